@@ -1,0 +1,26 @@
+"""Plain FP64 CPU oracle for spin-restricted CCSDT on full (unpacked) tensors.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) imports, links or calls this package; only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` do.
+It shares no code with the GPU path: its only input is the seeded data from
+``cct_inputs``.
+
+Modules
+-------
+rccsdt    The spin-free (non-orthogonally spin-adapted) RCCSD/RCCSDT working
+          equations of the paper's Appendix A (T1-dressed Hamiltonian, RCCSD
+          and RCCSDT intermediates, residuals R1/R2/R3 with the paired-index
+          permutation operator), the R3 post-processing (symmetrize, purify,
+          orthogonalize; Sec. "Removing redundancies"), the Jacobi update with
+          orbital-energy denominators, DIIS and the correlation energy.
+spinorb   Equation-free brute force in determinant space: FCI, spin-orbital
+          projective CC through exp(-T) H exp(T), and the spin-free <->
+          spin-orbital amplitude maps (Appendix A spin-free formalism and the
+          closed-shell T3 reconstruction formula of the UCCSDT appendix).
+elements  Element-by-element evaluation of R3 for sampled outputs at sizes
+          where the full tensor does not fit in host memory.
+counts    Closed-form multiply-add counts of the compact contractions
+          (Sec. "Total cost of RCCSDT contractions" and the RCCSDT operation
+          count table).
+"""
