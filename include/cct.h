@@ -1,0 +1,148 @@
+/*
+ * cct.h - compact-triples spin-restricted CCSDT on one MI355X (gfx950).
+ *
+ * The library evaluates the connected-triples residual R3 of spin-restricted,
+ * non-orthogonally spin-adapted CCSDT on compactly stored T3 (only occupied
+ * triples i <= j <= k are kept, each with its full v^3 virtual block), the
+ * T2*W driver terms, the T3 -> T1/T2 feedback, the RCCSD parts of R1/R2, the
+ * R3 post-processing, the Jacobi update with orbital-energy denominators,
+ * DIIS and the correlation energy.  Equations: the paper's Appendix A
+ * (T1-dressed formalism, RCCSD and RCCSDT working equations, Eq. resi-rccsdt);
+ * compact contractions: Sec. "Tensor contractions for compact amplitudes";
+ * post-processing: Sec. "Removing redundancies in RCC amplitudes"; Jacobi
+ * update: Appendix A "Coupled-cluster theory"; DIIS: Sec. "Distributed DIIS"
+ * (here on one device).
+ *
+ * Conventions
+ *   o = number of occupied, v = number of virtual spatial orbitals, n = o + v.
+ *   Every host array is FP64, C-contiguous, owned by the caller and copied in
+ *   or out before the call returns:
+ *     f    [n][n]            bare Fock matrix f^p_q (row p, column q)
+ *     B    [naux][n][n]      density-fitting factors, B[P][p][q] == B[P][q][p];
+ *                            (pq|rs) = sum_P B[P][p][q] B[P][r][s]
+ *     t1   [o][v]            t_i^a
+ *     t2   [o][o][v][v]      t_ij^ab, must satisfy t_ij^ab == t_ji^ba
+ *     t3p  [ntri][v][v][v]   packed T3, ntri = o(o+1)(o+2)/6, triples i<=j<=k in
+ *                            lexicographic order (cct_packed_index), block
+ *                            (i,j,k) holds t_ijk^abc for all a,b,c
+ *   The library owns its device memory (allocated at cct_create) and works on
+ *   the HIP stream passed at creation (NULL = the default stream).
+ *
+ * Errors: every int-returning function returns CCT_OK (0) or a negative code;
+ * nothing aborts.  cct_last_error() gives a message for the latest failure.
+ * A context is not thread-safe: one thread per context at a time.
+ */
+#ifndef CCT_H
+#define CCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CCT_OK = 0,
+  CCT_EINVAL = -1,    /* bad argument: dimension, NULL pointer, option */
+  CCT_ENOMEM = -2,    /* the memory plan does not fit the device */
+  CCT_EDEVICE = -3,   /* a HIP call failed (message in cct_last_error) */
+  CCT_ESTATE = -4,    /* call out of order (e.g. residual before integrals) */
+  CCT_ENUMERIC = -5,  /* NaN or Inf in a residual norm or the energy */
+  CCT_ENOTCONV = -6   /* cct_solve reached max_iter */
+};
+
+/* Precision of the particle-particle ladder and ring contractions (the
+ * dominant O(o^3 v^5) and O(o^4 v^4) terms).  Everything else (T1 dressing,
+ * RCCSD parts, feedback, drivers, Fock and hole-ladder terms, post-processing,
+ * update, DIIS, energy) is FP64 in every mode. */
+typedef enum {
+  CCT_FP64 = 0,   /* FP64 MFMA */
+  CCT_FP32 = 1,   /* FP32 operands, FP32 MFMA accumulation, FP64 flush per K block */
+  CCT_BF16X3 = 2  /* split BF16 (hi + lo) operands, three BF16 MFMA products,
+                     FP32 accumulation, FP64 flush per K block */
+} cct_precision;
+
+/* Residual term groups of Eq. resi-rccsdt (bit mask for cct_residual). */
+enum {
+  CCT_TERM_D1 = 1 << 0,   /* sum_d W^{ab}_{dj} t_ik^dc                 */
+  CCT_TERM_D2 = 1 << 1,   /* -sum_l W^{al}_{ij} t_lk^bc                */
+  CCT_TERM_F1 = 1 << 2,   /* 1/2 sum_d F^a_d t_ijk^dbc                 */
+  CCT_TERM_F2 = 1 << 3,   /* -1/2 sum_l F^l_i t_ljk^abc                */
+  CCT_TERM_RA = 1 << 4,   /* 1/4 sum_ld Wbar^{la}_{di} t~_{ljk}^{dbc}    */
+  CCT_TERM_RB = 1 << 5,   /* -1/2 sum_ld Wbar^{la}_{id} t_jlk^dbc      */
+  CCT_TERM_RC = 1 << 6,   /* -sum_ld Wbar^{lb}_{id} t_jlk^dac          */
+  CCT_TERM_HH = 1 << 7,   /* 1/2 sum_lm W^{lm}_{ij} t_lmk^abc          */
+  CCT_TERM_PP = 1 << 8,   /* 1/2 sum_de W^{ab}_{de} t_ijk^dec          */
+  CCT_TERM_ALL = 0x1ff
+};
+
+typedef struct cct_ctx cct_ctx;
+
+/* Create a context for o occupied / v virtual orbitals and naux fitting
+ * functions.  opts_json may be NULL or a JSON object with integer/string
+ * fields: "diis_space" (default 8), "diis_start" (default 2), "diis_t3"
+ * ("full" | "none", default "full"), "workspace_gb" (scratch budget, default
+ * 16).  hip_stream: a hipStream_t or NULL.  The memory plan is checked
+ * against free device memory here; CCT_ENOMEM if it does not fit. */
+int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json,
+               void* hip_stream, cct_ctx** out);
+/* Free the context and all device memory it owns.  NULL is ignored. */
+void cct_destroy(cct_ctx* ctx);
+
+/* Upload the bare Fock matrix f[n][n] (host).  Need not be diagonal; the
+ * orbital energies of the denominators are its diagonal. */
+int cct_set_fock(cct_ctx* ctx, const double* f);
+/* Upload the density-fitting factors B[naux][n][n] (host). */
+int cct_set_eri_df(cct_ctx* ctx, const double* B);
+
+/* T1 = 0, T2 = v^{ij}_{ab} / (e_i + e_j - e_a - e_b), T3 = 0; clears DIIS. */
+int cct_init_mp2(cct_ctx* ctx);
+/* Copy amplitudes in (host arrays; t3p == NULL means T3 = 0); clears DIIS. */
+int cct_set_amplitudes(cct_ctx* ctx, const double* t1, const double* t2, const double* t3p);
+/* Copy amplitudes out (host arrays; any pointer may be NULL). */
+int cct_get_amplitudes(cct_ctx* ctx, double* t1, double* t2, double* t3p);
+
+/* Evaluate the residuals at the current amplitudes.  term_mask selects R3
+ * term groups (CCT_TERM_*; R1 and R2 are always complete).  R3 is
+ * post-processed (symmetrize i=j<k / i<j=k blocks, zero i=j=k blocks,
+ * subtract the mean over virtual permutations).  Host outputs r1 [o][v],
+ * r2 [o][o][v][v], r3p [ntri][v][v][v] may be NULL.  norms (may be NULL)
+ * receives the squared full-tensor Frobenius norms |R1|^2, |R2|^2, |R3|^2
+ * (packed blocks weighted by the number of distinct orderings of i,j,k). */
+int cct_residual(cct_ctx* ctx, unsigned term_mask, double* r1, double* r2, double* r3p, double norms[3]);
+/* Copy count elements of the packed R3 of the latest cct_residual/cct_update,
+ * starting at flat element offset first (element (t,a,b,c) is at
+ * ((t*v + a)*v + b)*v + c), to host memory. */
+int cct_copy_r3(cct_ctx* ctx, int64_t first, int64_t count, double* out);
+
+/* One iteration: residuals, R3 post-processing, Jacobi update t += r / eps,
+ * DIIS extrapolation (if enabled by options), energy of the new amplitudes.
+ * e_corr and norms (squared, as in cct_residual) may be NULL.  Returns
+ * CCT_ENUMERIC if a norm or the energy is not finite. */
+int cct_update(cct_ctx* ctx, double* e_corr, double norms[3]);
+/* Correlation energy of the current amplitudes with the bare integrals. */
+int cct_energy(cct_ctx* ctx, double* e_corr);
+/* Iterate until sqrt(|R1|^2 + |R2|^2 + |R3|^2) < tol or max_iter.  Returns
+ * CCT_ENOTCONV (with the last energy and count filled in) if not converged. */
+int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters);
+
+/* Algorithmic multiply-add counts of the last residual per R3 term group
+ * (indices as the CCT_TERM_* bit positions, 9 entries) and device time in ms
+ * per phase (entries: 0 setup/dressing+CCSD, 1 feedback, 2 PP, 3 rings,
+ * 4 HH+F2, 5 drivers, 6 F1, 7 post+update, 8 DIIS+energy).  cap = length of
+ * both arrays provided; writes min(cap, 9). */
+int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap);
+
+/* Index of the packed triple (i,j,k), 0 <= i <= j <= k < nocc, in the
+ * lexicographic order; -1 if the arguments are out of range or unordered. */
+int64_t cct_packed_index(int nocc, int i, int j, int k);
+
+const char* cct_strerror(int code);
+const char* cct_last_error(const cct_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCT_H */

@@ -1,0 +1,195 @@
+"""ctypes binding of the libcct C ABI (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts numpy arrays
+to pointers and return codes to exceptions.  Names follow ``include/cct.h``.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcct.so")
+
+CCT_OK, CCT_EINVAL, CCT_ENOMEM, CCT_EDEVICE, CCT_ESTATE, CCT_ENUMERIC, CCT_ENOTCONV = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+TERMS = {"D1": 1 << 0, "D2": 1 << 1, "F1": 1 << 2, "F2": 1 << 3, "RA": 1 << 4, "RB": 1 << 5,
+         "RC": 1 << 6, "HH": 1 << 7, "PP": 1 << 8}
+TERM_ALL = 0x1FF
+PHASES = ("ccsd", "feedback", "pp", "rings", "hh_f2", "drivers", "f1", "post", "diis_energy")
+
+_lib = None
+
+
+class CCTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcct error {code}: {msg}")
+        self.code = code
+
+
+def load(path: str | None = None):
+    """Load libcct.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} not found: build it with `python -m paper_2607_00981_amd.build`")
+    lib = C.CDLL(p)
+    dp = C.POINTER(C.c_double)
+    vp = C.c_void_p
+    sig = {
+        "cct_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp, C.POINTER(vp)]),
+        "cct_destroy": (None, [vp]),
+        "cct_set_fock": (C.c_int, [vp, dp]),
+        "cct_set_eri_df": (C.c_int, [vp, dp]),
+        "cct_init_mp2": (C.c_int, [vp]),
+        "cct_set_amplitudes": (C.c_int, [vp, dp, dp, dp]),
+        "cct_get_amplitudes": (C.c_int, [vp, dp, dp, dp]),
+        "cct_residual": (C.c_int, [vp, C.c_uint, dp, dp, dp, dp]),
+        "cct_copy_r3": (C.c_int, [vp, C.c_int64, C.c_int64, dp]),
+        "cct_update": (C.c_int, [vp, dp, dp]),
+        "cct_energy": (C.c_int, [vp, dp]),
+        "cct_solve": (C.c_int, [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int)]),
+        "cct_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
+        "cct_packed_index": (C.c_int64, [C.c_int, C.c_int, C.c_int, C.c_int]),
+        "cct_strerror": (C.c_char_p, [C.c_int]),
+        "cct_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _in(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def packed_index(o, i, j, k):
+    return load().cct_packed_index(o, i, j, k)
+
+
+def ntri(o):
+    return o * (o + 1) * (o + 2) // 6
+
+
+class Engine:
+    """One CCSDT context on the current HIP device."""
+
+    def __init__(self, nocc, nvir, naux, precision="fp64", opts=None, stream=None):
+        import json
+
+        self.lib = load()
+        self.o, self.v, self.naux = nocc, nvir, naux
+        self.n = nocc + nvir
+        self.ntri = ntri(nocc)
+        js = json.dumps(opts).encode() if opts else None
+        h = C.c_void_p()
+        rc = self.lib.cct_create(nocc, nvir, naux, PRECISIONS[precision], js, stream, C.byref(h))
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc, ok=(CCT_OK,)):
+        if rc not in ok:
+            raise CCTError(rc, self.lib.cct_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cct_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # inputs -------------------------------------------------------------
+    def set_fock(self, f):
+        f = _in(f, (self.n, self.n))
+        self._check(self.lib.cct_set_fock(self.h, _ptr(f)))
+
+    def set_eri_df(self, B):
+        B = _in(B, (self.naux, self.n, self.n))
+        self._check(self.lib.cct_set_eri_df(self.h, _ptr(B)))
+
+    def init_mp2(self):
+        self._check(self.lib.cct_init_mp2(self.h))
+
+    def set_amplitudes(self, t1, t2, t3p=None):
+        o, v = self.o, self.v
+        t1 = _in(t1, (o, v))
+        t2 = _in(t2, (o, o, v, v))
+        t3p = None if t3p is None else _in(t3p, (self.ntri, v, v, v))
+        self._check(self.lib.cct_set_amplitudes(self.h, _ptr(t1), _ptr(t2), _ptr(t3p)))
+
+    def get_amplitudes(self, with_t3=True):
+        o, v = self.o, self.v
+        t1 = np.empty((o, v))
+        t2 = np.empty((o, o, v, v))
+        t3 = np.empty((self.ntri, v, v, v)) if with_t3 else None
+        self._check(self.lib.cct_get_amplitudes(self.h, _ptr(t1), _ptr(t2), _ptr(t3)))
+        return t1, t2, t3
+
+    # compute ------------------------------------------------------------
+    def residual(self, terms=TERM_ALL, want_r3=True):
+        o, v = self.o, self.v
+        mask = terms if isinstance(terms, int) else sum(TERMS[t] for t in terms)
+        r1 = np.empty((o, v))
+        r2 = np.empty((o, o, v, v))
+        r3 = np.empty((self.ntri, v, v, v)) if want_r3 else None
+        nr = np.empty(3)
+        self._check(self.lib.cct_residual(self.h, mask, _ptr(r1), _ptr(r2), _ptr(r3), _ptr(nr)))
+        return r1, r2, r3, nr
+
+    def copy_r3(self, first, count):
+        out = np.empty(count)
+        self._check(self.lib.cct_copy_r3(self.h, first, count, _ptr(out)))
+        return out
+
+    def update(self):
+        e = C.c_double()
+        nr = np.empty(3)
+        self._check(self.lib.cct_update(self.h, C.byref(e), _ptr(nr)))
+        return e.value, nr
+
+    def energy(self):
+        e = C.c_double()
+        self._check(self.lib.cct_energy(self.h, C.byref(e)))
+        return e.value
+
+    def solve(self, max_iter=100, tol=1e-8):
+        e = C.c_double()
+        it = C.c_int()
+        rc = self._check(self.lib.cct_solve(self.h, max_iter, tol, C.byref(e), C.byref(it)),
+                         ok=(CCT_OK, CCT_ENOTCONV))
+        return e.value, it.value, rc == CCT_OK
+
+    def counters(self):
+        macs = np.zeros(9)
+        ms = np.zeros(9)
+        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 9))
+        return dict(zip(TERMS.keys(), macs)), dict(zip(PHASES, ms))

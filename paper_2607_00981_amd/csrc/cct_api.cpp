@@ -1,0 +1,1427 @@
+// libcct host runtime: context, memory plan, the RCCSDT iteration and the C ABI.
+//
+// One residual evaluation (paper, Appendix A; compact contractions of Sec.
+// "Tensor contractions for compact amplitudes"):
+//   1. T1 dressing of the density-fitting factors and the Fock matrix, and the
+//      dressed integrals v~^{pq}_{rs} = sum_P B~^P_{pr} B~^P_{qs} (one GEMM).
+//   2. RCCSD intermediates, R1 and the RCCSD part of R2.
+//   3. RCCSDT intermediates W^{ab}_{dj}, W^{al}_{ij}, Wbar, W^{ab}_{de}.
+//   4. T3 feedback into R1, R2, W^{ab}_{dj}, W^{al}_{ij} from unpacked,
+//      spin-summed T3 slabs.
+//   5. R3 on packed i<=j<=k blocks: particle-particle ladder by direct
+//      traversal (three relabelled GEMMs over all stored blocks), Fock terms,
+//      hole ladder (+F_oo), the three ring types and the two T2*W drivers by
+//      tile unpacking -> GEMM -> output-stationary fold.
+//   6. R3 post-processing fused with the norm and the Jacobi update.
+#include "../../include/cct.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "contract.h"
+#include "internal.h"
+
+using namespace cct;
+
+namespace {
+
+struct Batch {
+  int slot0 = 0, nslots = 0;
+  int2* d_slots = nullptr;
+  FoldTask* d_tasks = nullptr;
+  int ntasks = 0;
+  FoldContrib* d_contribs = nullptr;
+};
+
+struct Job {
+  int nslot_total = 0;
+  int per_batch = 1;
+  std::vector<int2> slots;  // fixed occupied indices per slot
+  std::vector<Batch> batches;
+};
+
+enum Phase { PH_CCSD = 0, PH_FEED, PH_PP, PH_RING, PH_HH, PH_DRV, PH_F1, PH_POST, PH_DIIS, PH_N };
+
+const char* kErr[] = {"ok", "invalid argument", "out of device memory", "device error", "call out of order",
+                      "non-finite residual or energy", "not converged"};
+
+}  // namespace
+
+struct cct_ctx {
+  int o = 0, v = 0, n = 0, naux = 0;
+  long long ntri = 0, v3 = 0;
+  Prec prec = Prec::F64;
+  hipStream_t s = nullptr;
+  int diis_space = 8, diis_start = 2;
+  bool diis_on = true, diis_t3 = true;
+  double ws_gb = 16.0;
+  std::string err;
+  bool have_f = false, have_B = false, have_res = false;
+
+  std::vector<void*> owned;
+  // inputs
+  double *f = nullptr, *B = nullptr, *eps = nullptr, *fov = nullptr;
+  double *vbare_c = nullptr;  // 2 v^{ij}_{ab} - v^{ij}_{ba} (bare), [i][j][a][b]
+  double *vbare = nullptr;    // v^{ij}_{ab} (bare), [i][j][a][b]
+  // dressed quantities
+  double *Bt = nullptr, *ft = nullptr, *V = nullptr, *fG = nullptr, *G = nullptr, *cP = nullptr, *Dt = nullptr;
+  // amplitudes and residuals
+  double *t1 = nullptr, *t2 = nullptr, *t3 = nullptr, *r1 = nullptr, *r2 = nullptr, *r3 = nullptr, *X2 = nullptr;
+  double *zero_r1 = nullptr;
+  // intermediates
+  double *tau2 = nullptr, *VCoovv = nullptr, *VCovvo = nullptr, *VCovvv = nullptr, *VCoovo = nullptr;
+  double *Fvv = nullptr, *Foo = nullptr, *Woooo = nullptr, *Wh = nullptr, *Wovvo = nullptr, *Wovov = nullptr;
+  double *Wt = nullptr, *Wvooo = nullptr, *Wb1 = nullptr, *Wb2 = nullptr, *Wvvvv = nullptr;
+  double *tau_e = nullptr;
+  // tables
+  BlockRef* tbl = nullptr;
+  int4* tri = nullptr;
+  double* red = nullptr;  // reduction scratch
+  long long red_n = 0;
+  double* scal = nullptr;  // device scalars
+  // workspace
+  char* wsbuf = nullptr;
+  Arena ws;
+  // plans
+  Job ring[3], hh, d1, d2, feed1, feed12;
+  // DIIS
+  std::vector<double*> dvec, derr;
+  int diis_n = 0, diis_next = 0;
+  std::vector<std::vector<double>> Bmat;
+  double* diis_old = nullptr;
+  long long diis_len = 0;
+  // counters
+  double macs[9] = {0};
+  double ms[PH_N] = {0};
+  hipEvent_t ev[PH_N + 1] = {};
+  bool events = false;
+};
+
+namespace {
+
+#define HIPCK(expr)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                     \
+      return CCT_EDEVICE;                                                               \
+    }                                                                                   \
+  } while (0)
+
+#define STCK(expr)                                                                      \
+  do {                                                                                  \
+    Status st_ = (expr);                                                                \
+    if (!st_.ok()) {                                                                    \
+      ctx->err = st_.msg.empty() ? std::string(hipGetErrorString(st_.err)) : st_.msg;   \
+      ctx->err += std::string(" [") + #expr + "]";                                      \
+      return st_.msg.empty() ? CCT_EDEVICE : CCT_EINVAL;                                \
+    }                                                                                   \
+  } while (0)
+
+#define RCK(expr)              \
+  do {                         \
+    int r_ = (expr);           \
+    if (r_ != CCT_OK) return r_; \
+  } while (0)
+
+long long tri_count(int o) { return (long long)o * (o + 1) * (o + 2) / 6; }
+
+int dalloc(cct_ctx* ctx, double** p, long long n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(n, 1) * sizeof(double));
+  if (e != hipSuccess) {
+    ctx->err = std::string("hipMalloc of ") + std::to_string(n * 8) + " bytes: " + hipGetErrorString(e);
+    return CCT_ENOMEM;
+  }
+  ctx->owned.push_back(q);
+  *p = (double*)q;
+  return CCT_OK;
+}
+
+template <typename T>
+int dalloc_t(cct_ctx* ctx, T** p, long long n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(n, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    ctx->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    return CCT_ENOMEM;
+  }
+  ctx->owned.push_back(q);
+  *p = (T*)q;
+  return CCT_OK;
+}
+
+// --- options: a tiny reader for flat JSON objects ----------------------------
+bool json_find(const std::string& js, const std::string& key, std::string& val) {
+  const std::string pat = "\"" + key + "\"";
+  size_t p = js.find(pat);
+  if (p == std::string::npos) return false;
+  p = js.find(':', p + pat.size());
+  if (p == std::string::npos) return false;
+  ++p;
+  while (p < js.size() && (js[p] == ' ' || js[p] == '\t')) ++p;
+  if (p < js.size() && js[p] == '"') {
+    size_t q = js.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    val = js.substr(p + 1, q - p - 1);
+    return true;
+  }
+  size_t q = p;
+  while (q < js.size() && js[q] != ',' && js[q] != '}' && js[q] != ' ') ++q;
+  val = js.substr(p, q - p);
+  return true;
+}
+
+// --- views of the dressed integrals -----------------------------------------
+// v~^{pq}_{rs} is stored as V[p][r][q][s] (the GEMM over the fitting index).
+DT Vv(cct_ctx* c, const char* blk) {
+  const long long n = c->n;
+  long long off[4], dim[4];
+  for (int i = 0; i < 4; ++i) {
+    off[i] = blk[i] == 'o' ? 0 : c->o;
+    dim[i] = blk[i] == 'o' ? c->o : c->v;
+  }
+  DT t;
+  t.p = c->V + off[0] * n * n * n + off[2] * n * n + off[1] * n + off[3];
+  t.nd = 4;
+  for (int i = 0; i < 4; ++i) t.dim[i] = dim[i];
+  t.st[0] = n * n * n;
+  t.st[1] = n;
+  t.st[2] = n * n;
+  t.st[3] = 1;
+  return t;
+}
+
+DT fview(cct_ctx* c, double* base, char a, char b) {
+  const long long n = c->n;
+  const long long oa = a == 'o' ? 0 : c->o, ob = b == 'o' ? 0 : c->o;
+  return strided(base + oa * n + ob, {a == 'o' ? c->o : c->v, b == 'o' ? c->o : c->v}, {n, 1});
+}
+
+// Table of unpacked blocks: for every ordered (p,q,r) the stored block
+// sort(p,q,r) and the strides of the three virtual axes in the order of
+// (p,q,r) (the column symmetry carries the virtual labels along).
+void build_tables(int o, int v, std::vector<BlockRef>& tbl, std::vector<int4>& tri) {
+  std::map<std::array<int, 3>, int> index;
+  tri.clear();
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k) {
+        index[{i, j, k}] = (int)tri.size();
+        const int mult = (i == j && j == k) ? 1 : ((i == j || j == k) ? 3 : 6);
+        tri.push_back(int4{i, j, k, mult});
+      }
+  const long long v3 = (long long)v * v * v;
+  const int axis_stride[3] = {v * v, v, 1};
+  tbl.assign((size_t)o * o * o, BlockRef{});
+  for (int p = 0; p < o; ++p)
+    for (int q = 0; q < o; ++q)
+      for (int r = 0; r < o; ++r) {
+        const int occ[3] = {p, q, r};
+        int order[3] = {0, 1, 2};
+        std::stable_sort(order, order + 3, [&](int x, int y) { return occ[x] < occ[y]; });
+        BlockRef b{};
+        b.off = (long long)index[{occ[order[0]], occ[order[1]], occ[order[2]]}] * v3;
+        for (int nax = 0; nax < 3; ++nax) b.s[order[nax]] = axis_stride[nax];
+        tbl[((size_t)p * o + q) * o + r] = b;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Fold plans
+// ---------------------------------------------------------------------------
+struct Contrib {
+  int slot;
+  long long base;
+  long long sa, sb, sc;
+  double coef;
+};
+
+// Build the batches of a job: per batch, fold tasks grouping contributions by
+// output block.  contribs_of(t) lists the contributions of packed triple t.
+template <typename F>
+int build_job(cct_ctx* ctx, Job& job, long long slot_doubles, F contribs_of) {
+  const int S = job.per_batch;
+  const int nb = (job.nslot_total + S - 1) / S;
+  std::vector<std::vector<std::pair<int, FoldContrib>>> per_batch(nb);
+  for (long long t = 0; t < ctx->ntri; ++t) {
+    std::vector<Contrib> cs = contribs_of((int)t);
+    for (const Contrib& c : cs) {
+      if (c.slot < 0 || c.slot >= job.nslot_total) {
+        ctx->err = "fold plan: slot out of range";
+        return CCT_EINVAL;
+      }
+      const int b = c.slot / S;
+      const int ls = c.slot - b * S;
+      // every element read by this contribution must lie inside its slot
+      const long long vm = ctx->v - 1;
+      if (c.base < 0 || c.base + vm * (c.sa + c.sb + c.sc) >= slot_doubles) {
+        ctx->err = "fold plan: contribution exceeds its slot";
+        return CCT_EINVAL;
+      }
+      FoldContrib fc{(long long)ls * slot_doubles + c.base, c.sa, c.sb, c.sc, c.coef};
+      per_batch[b].push_back({(int)t, fc});
+    }
+  }
+  job.batches.clear();
+  for (int b = 0; b < nb; ++b) {
+    Batch B;
+    B.slot0 = b * S;
+    B.nslots = std::min(S, job.nslot_total - b * S);
+    auto& lst = per_batch[b];
+    std::stable_sort(lst.begin(), lst.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+    std::vector<FoldTask> tasks;
+    std::vector<FoldContrib> cons;
+    for (size_t i = 0; i < lst.size();) {
+      size_t j = i;
+      FoldTask tk{lst[i].first, 0, (int)cons.size(), 0};
+      while (j < lst.size() && lst[j].first == lst[i].first) {
+        cons.push_back(lst[j].second);
+        ++j;
+      }
+      tk.nc = (int)(j - i);
+      tasks.push_back(tk);
+      i = j;
+    }
+    B.ntasks = (int)tasks.size();
+    RCK(dalloc_t(ctx, &B.d_slots, B.nslots));
+    RCK(dalloc_t(ctx, &B.d_tasks, std::max<size_t>(tasks.size(), 1)));
+    RCK(dalloc_t(ctx, &B.d_contribs, std::max<size_t>(cons.size(), 1)));
+    HIPCK(hipMemcpy(B.d_slots, job.slots.data() + B.slot0, sizeof(int2) * B.nslots, hipMemcpyHostToDevice));
+    if (!tasks.empty()) {
+      HIPCK(hipMemcpy(B.d_tasks, tasks.data(), sizeof(FoldTask) * tasks.size(), hipMemcpyHostToDevice));
+      HIPCK(hipMemcpy(B.d_contribs, cons.data(), sizeof(FoldContrib) * cons.size(), hipMemcpyHostToDevice));
+    }
+    job.batches.push_back(B);
+  }
+  return CCT_OK;
+}
+
+const int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+int slots_per_batch(long long budget_doubles, long long per_slot, int nslots) {
+  long long s = budget_doubles / std::max<long long>(per_slot, 1);
+  if (s < 1) s = 1;
+  if (s > nslots) s = nslots;
+  if (s > 4096) s = 4096;
+  return (int)s;
+}
+
+int build_plans(cct_ctx* ctx) {
+  const int o = ctx->o, v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = v2 * v;
+  const long long ov3 = o * v3, o2v3 = (long long)o * o * v3;
+  std::vector<int4> tri;
+  std::vector<BlockRef> tbl;
+  build_tables(o, v, tbl, tri);
+  // scratch left for the planner's operand copies and unpacking of one slot
+  const long long budget = (long long)(ctx->ws.capacity() / sizeof(double)) - 4 * ov3 - 4 * o2v3;
+  if (budget < 2 * o2v3) {
+    ctx->err = "workspace too small for one unpacked slab";
+    return CCT_ENOMEM;
+  }
+  // ---- rings: slots are occupied pairs; A and B over q <= r, C over all (q, r)
+  std::map<std::pair<int, int>, int> pair_ab, pair_c;
+  for (int q = 0; q < o; ++q)
+    for (int r = q; r < o; ++r) {
+      pair_ab[{q, r}] = (int)ctx->ring[0].slots.size();
+      ctx->ring[0].slots.push_back(int2{q, r});
+    }
+  ctx->ring[1].slots = ctx->ring[0].slots;
+  for (int q = 0; q < o; ++q)
+    for (int r = 0; r < o; ++r) {
+      pair_c[{q, r}] = (int)ctx->ring[2].slots.size();
+      ctx->ring[2].slots.push_back(int2{q, r});
+    }
+  const double ring_coef[3] = {0.5, -0.5, -1.0};
+  for (int kind = 0; kind < 3; ++kind) {
+    Job& J = ctx->ring[kind];
+    J.nslot_total = (int)J.slots.size();
+    J.per_batch = slots_per_batch(budget, 2 * ov3, J.nslot_total);
+    const double cf = ring_coef[kind];
+    RCK(build_job(ctx, J, ov3, [&](int t) {
+      std::vector<Contrib> cs;
+      const int occ[3] = {tri[t].x, tri[t].y, tri[t].z};
+      if (kind < 2) {
+        // Y(p; q, r)[x; y, z] stored as Z[slot(q,r)][p][x][y][z]
+        // sigma1: (i; j,k)[a; b,c]   sigma2: (j; i,k)[b; a,c]   sigma3: (k; i,j)[c; a,b]
+        cs.push_back({pair_ab[{occ[1], occ[2]}], (long long)occ[0] * v3, v2, v, 1, cf});
+        cs.push_back({pair_ab[{occ[0], occ[2]}], (long long)occ[1] * v3, v, v2, 1, cf});
+        cs.push_back({pair_ab[{occ[0], occ[1]}], (long long)occ[2] * v3, v, 1, v2, cf});
+      } else {
+        // Y(p,q,r)[x,y,z] stored as Z[slot(q,r)][p][y][x][z]; six column permutations
+        for (int s = 0; s < 6; ++s) {
+          const int* pi = PERM3[s];
+          long long st[3];
+          st[pi[0]] = v;
+          st[pi[1]] = v2;
+          st[pi[2]] = 1;
+          cs.push_back({pair_c[{occ[pi[1]], occ[pi[2]]}], (long long)occ[pi[0]] * v3, st[0], st[1], st[2], cf});
+        }
+      }
+      return cs;
+    }));
+  }
+  // ---- hole ladder (+ F_oo): slots are r; Z[slot(r)][(p,q)][x][y][z]
+  {
+    Job& J = ctx->hh;
+    for (int r = 0; r < o; ++r) J.slots.push_back(int2{r, 0});
+    J.nslot_total = o;
+    J.per_batch = slots_per_batch(budget, 2 * o2v3, o);
+    RCK(build_job(ctx, J, o2v3, [&](int t) {
+      const int i = tri[t].x, j = tri[t].y, k = tri[t].z;
+      std::vector<Contrib> cs;
+      cs.push_back({k, ((long long)i * o + j) * v3, v2, v, 1, 1.0});  // (i,j;k)[a,b;c]
+      cs.push_back({j, ((long long)i * o + k) * v3, v2, 1, v, 1.0});  // (i,k;j)[a,c;b]
+      cs.push_back({i, ((long long)j * o + k) * v3, 1, v2, v, 1.0});  // (j,k;i)[b,c;a]
+      return cs;
+    }));
+  }
+  // ---- drivers
+  {
+    Job& J = ctx->d1;  // slots q; Z[slot(q)][(x,y)][(p,r,z)]
+    for (int q = 0; q < o; ++q) J.slots.push_back(int2{q, 0});
+    J.nslot_total = o;
+    J.per_batch = slots_per_batch(budget, o2v3, o);
+    const long long sx = (long long)o * o * v2, sy = (long long)o * o * v;
+    RCK(build_job(ctx, J, o2v3, [&](int t) {
+      const int occ[3] = {tri[t].x, tri[t].y, tri[t].z};
+      std::vector<Contrib> cs;
+      for (int s = 0; s < 6; ++s) {
+        const int* pi = PERM3[s];
+        long long st[3];
+        st[pi[0]] = sx;
+        st[pi[1]] = sy;
+        st[pi[2]] = 1;
+        const int p = occ[pi[0]], q = occ[pi[1]], r = occ[pi[2]];
+        cs.push_back({q, ((long long)p * o + r) * v, st[0], st[1], st[2], 1.0});
+      }
+      return cs;
+    }));
+  }
+  {
+    Job& J = ctx->d2;  // slots r; Z[slot(r)][(x,p,q)][(y,z)]
+    for (int r = 0; r < o; ++r) J.slots.push_back(int2{r, 0});
+    J.nslot_total = o;
+    J.per_batch = slots_per_batch(budget, o2v3, o);
+    const long long sx = (long long)o * o * v2;
+    RCK(build_job(ctx, J, o2v3, [&](int t) {
+      const int occ[3] = {tri[t].x, tri[t].y, tri[t].z};
+      std::vector<Contrib> cs;
+      for (int s = 0; s < 6; ++s) {
+        const int* pi = PERM3[s];
+        long long st[3];
+        st[pi[0]] = sx;
+        st[pi[1]] = v;
+        st[pi[2]] = 1;
+        const int p = occ[pi[0]], q = occ[pi[1]], r = occ[pi[2]];
+        cs.push_back({r, ((long long)p * o + q) * v2, st[0], st[1], st[2], -1.0});
+      }
+      return cs;
+    }));
+  }
+  // ---- feedback unpack batches (no fold)
+  for (Job* J : {&ctx->feed1, &ctx->feed12}) {
+    for (int f = 0; f < o; ++f) J->slots.push_back(int2{f, 0});
+    J->nslot_total = o;
+    J->per_batch = slots_per_batch(budget, o2v3, o);
+    const int S = J->per_batch;
+    for (int b = 0; b * S < o; ++b) {
+      Batch B;
+      B.slot0 = b * S;
+      B.nslots = std::min(S, o - b * S);
+      RCK(dalloc_t(ctx, &B.d_slots, B.nslots));
+      HIPCK(hipMemcpy(B.d_slots, J->slots.data() + B.slot0, sizeof(int2) * B.nslots, hipMemcpyHostToDevice));
+      J->batches.push_back(B);
+    }
+  }
+  RCK(dalloc_t(ctx, &ctx->tbl, (long long)tbl.size()));
+  RCK(dalloc_t(ctx, &ctx->tri, (long long)tri.size()));
+  HIPCK(hipMemcpy(ctx->tbl, tbl.data(), sizeof(BlockRef) * tbl.size(), hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(ctx->tri, tri.data(), sizeof(int4) * tri.size(), hipMemcpyHostToDevice));
+  return CCT_OK;
+}
+
+// Unpack terms: spin-summation combinations on the first column (S1) and on
+// the first two columns (S12), as linear combinations of virtual orders.
+void set_s1(UnpackArgs& a, const int occ[3]) {
+  const UnpackTerm t[3] = {{2.0, {occ[0], occ[1], occ[2]}, {0, 1, 2}},
+                           {-1.0, {occ[0], occ[1], occ[2]}, {1, 0, 2}},
+                           {-1.0, {occ[0], occ[1], occ[2]}, {2, 1, 0}}};
+  a.nterms = 3;
+  for (int i = 0; i < 3; ++i) a.terms[i] = t[i];
+}
+
+void set_s12(UnpackArgs& a, const int occ[3]) {
+  const double c[6] = {4.0, -2.0, -2.0, -2.0, 1.0, 1.0};
+  const int vp[6][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}, {0, 2, 1}, {2, 0, 1}, {1, 2, 0}};
+  a.nterms = 6;
+  for (int i = 0; i < 6; ++i) {
+    a.terms[i].coef = c[i];
+    for (int m = 0; m < 3; ++m) {
+      a.terms[i].occ[m] = occ[m];
+      a.terms[i].virt[m] = vp[i][m];
+    }
+  }
+}
+
+void set_ident(UnpackArgs& a, const int occ[3]) {
+  a.nterms = 1;
+  a.terms[0].coef = 1.0;
+  for (int m = 0; m < 3; ++m) {
+    a.terms[0].occ[m] = occ[m];
+    a.terms[0].virt[m] = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// timing helpers
+// ---------------------------------------------------------------------------
+void mark(cct_ctx* ctx, int ph) {
+  if (ctx->events) (void)hipEventRecord(ctx->ev[ph], ctx->s);
+}
+
+// ---------------------------------------------------------------------------
+// the residual
+// ---------------------------------------------------------------------------
+int dress(cct_ctx* ctx) {
+  const int o = ctx->o, v = ctx->v, n = ctx->n;
+  const long long naux = ctx->naux;
+  const long long n2 = (long long)n * n;
+  hipStream_t s = ctx->s;
+  // Bt = x B y^T per fitting index P; x = 1 - t1 (rows of virtuals), y^T = 1 + t1 (columns of occupied)
+  HIPCK(axpby(1.0, ctx->B, 0.0, ctx->Bt, (long long)naux * n2, s));
+  {
+    GemmArgs g{};  // Bt[P][o+a][q] -= sum_i t1[i][a] B[P][i][q]
+    g.M = v; g.N = n; g.K = o; g.batch = (int)naux;
+    g.A = ctx->t1; g.am = idx1(1); g.ak = idx1(v); g.a_batch = 0;
+    g.B = ctx->B; g.bk = idx1(n); g.bn = idx1(1); g.b_batch = n2;
+    g.C = ctx->Bt + (long long)o * n; g.cm = idx1(n); g.cn = idx1(1); g.c_batch = n2;
+    g.alpha = -1.0; g.beta = 1.0;
+    g.a_len = (long long)o * v; g.b_len = naux * n2; g.c_len = naux * n2 - (long long)o * n;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  {
+    GemmArgs g{};  // Bt[P][p][i] += sum_a Bt[P][p][o+a] t1[i][a]
+    g.M = n; g.N = o; g.K = v; g.batch = (int)naux;
+    g.A = ctx->Bt + o; g.am = idx1(n); g.ak = idx1(1); g.a_batch = n2;
+    g.B = ctx->t1; g.bk = idx1(1); g.bn = idx1(v); g.b_batch = 0;
+    g.C = ctx->Bt; g.cm = idx1(n); g.cn = idx1(1); g.c_batch = n2;
+    g.alpha = 1.0; g.beta = 1.0;
+    g.a_len = naux * n2 - o; g.b_len = (long long)o * v; g.c_len = naux * n2;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  // G_rs = 2 sum_P c_P B[P][r][s] - sum_{P,i} D[P][r][i] B[P][i][s],
+  // c_P = sum_ia B[P][i][o+a] t_ia, D[P][r][i] = sum_a B[P][r][o+a] t_ia
+  {
+    GemmArgs g{};
+    g.M = (int)naux; g.N = 1; g.K = o * v; g.batch = 1;
+    g.A = ctx->B + o; g.am = idx1(n2); g.ak = idx2(v, n, 1);
+    g.B = ctx->t1; g.bk = idx1(1); g.bn = idx1(0);
+    g.C = ctx->cP; g.cm = idx1(1); g.cn = idx1(0);
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = naux * n2 - o; g.b_len = (long long)o * v; g.c_len = naux;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  {
+    GemmArgs g{};
+    g.M = 1; g.N = (int)n2; g.K = (int)naux; g.batch = 1;
+    g.A = ctx->cP; g.am = idx1(0); g.ak = idx1(1);
+    g.B = ctx->B; g.bk = idx1(n2); g.bn = idx1(1);
+    g.C = ctx->G; g.cm = idx1(0); g.cn = idx1(1);
+    g.alpha = 2.0; g.beta = 0.0;
+    g.a_len = naux; g.b_len = naux * n2; g.c_len = n2;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  {
+    GemmArgs g{};
+    g.M = n; g.N = o; g.K = v; g.batch = (int)naux;
+    g.A = ctx->B + o; g.am = idx1(n); g.ak = idx1(1); g.a_batch = n2;
+    g.B = ctx->t1; g.bk = idx1(1); g.bn = idx1(v); g.b_batch = 0;
+    g.C = ctx->Dt; g.cm = idx1(o); g.cn = idx1(1); g.c_batch = (long long)n * o;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = naux * n2 - o; g.b_len = (long long)o * v; g.c_len = (long long)naux * n * o;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  {
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = (int)naux * o; g.batch = 1;
+    g.A = ctx->Dt; g.am = idx1(o); g.ak = idx2(o, (long long)n * o, 1);
+    g.B = ctx->B; g.bk = idx2(o, n2, n); g.bn = idx1(1);
+    g.C = ctx->G; g.cm = idx1(n); g.cn = idx1(1);
+    g.alpha = -1.0; g.beta = 1.0;
+    g.a_len = (long long)naux * n * o; g.b_len = naux * n2; g.c_len = n2;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  HIPCK(axpby(1.0, ctx->f, 0.0, ctx->fG, n2, s));
+  HIPCK(axpby(1.0, ctx->G, 1.0, ctx->fG, n2, s));
+  HIPCK(axpby(1.0, ctx->fG, 0.0, ctx->ft, n2, s));
+  {
+    GemmArgs g{};
+    g.M = v; g.N = n; g.K = o; g.batch = 1;
+    g.A = ctx->t1; g.am = idx1(1); g.ak = idx1(v);
+    g.B = ctx->fG; g.bk = idx1(n); g.bn = idx1(1);
+    g.C = ctx->ft + (long long)o * n; g.cm = idx1(n); g.cn = idx1(1);
+    g.alpha = -1.0; g.beta = 1.0;
+    g.a_len = (long long)o * v; g.b_len = n2; g.c_len = n2 - (long long)o * n;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  {
+    GemmArgs g{};
+    g.M = n; g.N = o; g.K = v; g.batch = 1;
+    g.A = ctx->ft + o; g.am = idx1(n); g.ak = idx1(1);
+    g.B = ctx->t1; g.bk = idx1(1); g.bn = idx1(v);
+    g.C = ctx->ft; g.cm = idx1(n); g.cn = idx1(1);
+    g.alpha = 1.0; g.beta = 1.0;
+    g.a_len = n2 - o; g.b_len = (long long)o * v; g.c_len = n2;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  // V[(p,r)][(q,s)] = sum_P Bt[P][p][r] Bt[P][q][s]
+  {
+    GemmArgs g{};
+    g.M = (int)n2; g.N = (int)n2; g.K = (int)naux; g.batch = 1;
+    g.A = ctx->Bt; g.am = idx1(1); g.ak = idx1(n2);
+    g.B = ctx->Bt; g.bk = idx1(n2); g.bn = idx1(1);
+    g.C = ctx->V; g.cm = idx1(n2); g.cn = idx1(1);
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = naux * n2; g.b_len = naux * n2; g.c_len = n2 * n2;
+    HIPCK(gemm(g, Prec::F64, s));
+  }
+  return CCT_OK;
+}
+
+int ccsd_part(cct_ctx* ctx) {
+  const int o = ctx->o, v = ctx->v;
+  hipStream_t s = ctx->s;
+  Arena& ws = ctx->ws;
+  const Prec F = Prec::F64;
+  DT t2 = dense(ctx->t2, {o, o, v, v});
+  DT tau = dense(ctx->tau2, {o, o, v, v});
+  STCK(accumulate(s, 2.0, t2, "ijab", 0.0, tau, "ijab"));
+  STCK(accumulate(s, -1.0, t2, "ijba", 1.0, tau, "ijab"));
+  // spin-summed integral blocks  2 v~^{pq}_{rs} - v~^{pq}_{sr}
+  struct VC { double* p; const char* blk; const char* sw; } vcs[4] = {
+      {ctx->VCoovv, "oovv", "oovv"}, {ctx->VCovvo, "ovvo", "ovov"}, {ctx->VCovvv, "ovvv", "ovvv"},
+      {ctx->VCoovo, "oovo", "ooov"}};
+  for (auto& c : vcs) {
+    DT src = Vv(ctx, c.blk), sw = Vv(ctx, c.sw);
+    DT d = dense(c.p, {src.dim[0], src.dim[1], src.dim[2], src.dim[3]});
+    STCK(accumulate(s, 2.0, src, "pqrs", 0.0, d, "pqrs"));
+    STCK(accumulate(s, -1.0, sw, "pqsr", 1.0, d, "pqrs"));
+  }
+  DT VCoovv = dense(ctx->VCoovv, {o, o, v, v}), VCovvo = dense(ctx->VCovvo, {o, v, v, o});
+  DT VCovvv = dense(ctx->VCovvv, {o, v, v, v}), VCoovo = dense(ctx->VCoovo, {o, o, v, o});
+  DT Fvv = dense(ctx->Fvv, {v, v}), Foo = dense(ctx->Foo, {o, o});
+  DT Woooo = dense(ctx->Woooo, {o, o, o, o}), Wovvo = dense(ctx->Wovvo, {o, v, v, o});
+  DT Wovov = dense(ctx->Wovov, {o, v, o, v});
+  // RCCSD intermediates
+  STCK(accumulate(s, 1.0, fview(ctx, ctx->ft, 'v', 'v'), "bc", 0.0, Fvv, "bc"));
+  STCK(contract(ws, s, F, -1.0, VCoovv, "kldc", t2, "kldb", 1.0, Fvv, "bc"));
+  STCK(accumulate(s, 1.0, fview(ctx, ctx->ft, 'o', 'o'), "kj", 0.0, Foo, "kj"));
+  STCK(contract(ws, s, F, 1.0, VCoovv, "lkcd", t2, "ljcd", 1.0, Foo, "kj"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oooo"), "klij", 0.0, Woooo, "klij"));
+  STCK(contract(ws, s, F, 1.0, Vv(ctx, "oovv"), "klcd", t2, "ijcd", 1.0, Woooo, "klij"));
+  STCK(accumulate(s, 1.0, VCovvo, "kaci", 0.0, Wovvo, "kaci"));
+  STCK(contract(ws, s, F, 0.5, VCoovv, "lkdc", tau, "lida", 1.0, Wovvo, "kaci"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "ovov"), "kaic", 0.0, Wovov, "kaic"));
+  STCK(contract(ws, s, F, -0.5, Vv(ctx, "oovv"), "lkcd", t2, "ilda", 1.0, Wovov, "kaic"));
+  // R1 (RCCSD part)
+  DT r1 = dense(ctx->r1, {o, v});
+  STCK(accumulate(s, 1.0, fview(ctx, ctx->ft, 'v', 'o'), "ai", 0.0, r1, "ia"));
+  STCK(contract(ws, s, F, 1.0, fview(ctx, ctx->ft, 'o', 'v'), "kc", tau, "ikac", 1.0, r1, "ia"));
+  STCK(contract(ws, s, F, 1.0, Vv(ctx, "vovv"), "akcd", tau, "ikcd", 1.0, r1, "ia"));
+  STCK(contract(ws, s, F, -1.0, Vv(ctx, "ooov"), "klic", tau, "klac", 1.0, r1, "ia"));
+  // R2 (RCCSD part) before P_(ia)(jb)
+  DT X2 = dense(ctx->X2, {o, o, v, v});
+  DT Wvvvv = dense(ctx->Wvvvv, {v, v, v, v});
+  STCK(accumulate(s, 0.5, Vv(ctx, "vvoo"), "abij", 0.0, X2, "ijab"));
+  STCK(contract(ws, s, F, 1.0, Fvv, "bc", t2, "ijac", 1.0, X2, "ijab"));
+  STCK(contract(ws, s, F, -1.0, Foo, "kj", t2, "ikab", 1.0, X2, "ijab"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "vvvv"), "abcd", 0.0, Wvvvv, "abcd"));
+  STCK(contract(ws, s, F, 0.5, Wvvvv, "abcd", t2, "ijcd", 1.0, X2, "ijab"));
+  STCK(contract(ws, s, F, 0.5, Woooo, "klij", t2, "klab", 1.0, X2, "ijab"));
+  STCK(contract(ws, s, F, 0.5, Wovvo, "kaci", tau, "kjcb", 1.0, X2, "ijab"));
+  STCK(contract(ws, s, F, -0.5, Wovov, "kaic", t2, "jkcb", 1.0, X2, "ijab"));
+  STCK(contract(ws, s, F, -1.0, Wovov, "kbic", t2, "jkca", 1.0, X2, "ijab"));
+  // RCCSDT intermediates (T2 parts)
+  DT Wt = dense(ctx->Wt, {v, o, v, v});  // [d][j][b][a] = W^{ab}_{dj}
+  STCK(accumulate(s, 1.0, Vv(ctx, "vvvo"), "abdj", 0.0, Wt, "djba"));
+  STCK(contract(ws, s, F, 0.5, VCovvv, "laed", tau, "ljeb", 1.0, Wt, "djba"));
+  STCK(contract(ws, s, F, -0.5, Vv(ctx, "ovvv"), "lade", t2, "jleb", 1.0, Wt, "djba"));
+  STCK(contract(ws, s, F, -1.0, Vv(ctx, "ovvv"), "lbde", t2, "jlea", 1.0, Wt, "djba"));
+  STCK(contract(ws, s, F, 1.0, Vv(ctx, "oovo"), "lmdj", t2, "lmab", 1.0, Wt, "djba"));
+  DT Wvooo = dense(ctx->Wvooo, {v, o, o, o});  // [a][l][i][j] = W^{al}_{ij}
+  STCK(accumulate(s, 1.0, Vv(ctx, "vooo"), "alij", 0.0, Wvooo, "alij"));
+  STCK(contract(ws, s, F, 1.0, fview(ctx, ctx->ft, 'o', 'v'), "ld", t2, "ijad", 1.0, Wvooo, "alij"));
+  STCK(contract(ws, s, F, 0.5, VCoovo, "mldj", tau, "mida", 1.0, Wvooo, "alij"));
+  STCK(contract(ws, s, F, -0.5, Vv(ctx, "ooov"), "mljd", t2, "imda", 1.0, Wvooo, "alij"));
+  STCK(contract(ws, s, F, -1.0, Vv(ctx, "ooov"), "mlid", t2, "jmda", 1.0, Wvooo, "alij"));
+  STCK(contract(ws, s, F, 1.0, Vv(ctx, "vovv"), "alde", t2, "ijde", 1.0, Wvooo, "alij"));
+  DT Wb1 = dense(ctx->Wb1, {o, v, v, o});  // Wbar^{la}_{di} [l][a][d][i]
+  STCK(accumulate(s, 1.0, Wovvo, "ladi", 0.0, Wb1, "ladi"));
+  STCK(contract(ws, s, F, 0.5, VCoovv, "mled", tau, "miea", 1.0, Wb1, "ladi"));
+  DT Wb2 = dense(ctx->Wb2, {o, v, o, v});  // Wbar^{la}_{id} [l][a][i][d]
+  STCK(accumulate(s, 1.0, Wovov, "laid", 0.0, Wb2, "laid"));
+  STCK(contract(ws, s, F, -0.5, Vv(ctx, "oovv"), "mlde", t2, "imea", 1.0, Wb2, "laid"));
+  STCK(contract(ws, s, F, 1.0, Vv(ctx, "oovv"), "lmde", t2, "lmab", 1.0, Wvvvv, "abde"));
+  return CCT_OK;
+}
+
+// T3 contributions to R1, R2 and to W^{ab}_{dj}, W^{al}_{ij}.
+int feedback(cct_ctx* ctx) {
+  const int o = ctx->o, v = ctx->v, n = ctx->n;
+  const long long v3 = ctx->v3, o2v3 = (long long)o * o * v3;
+  const long long n3 = (long long)n * n * n;
+  hipStream_t s = ctx->s;
+  Arena& ws = ctx->ws;
+  const Prec F = Prec::F64;
+  DT X2 = dense(ctx->X2, {o, o, v, v});
+  DT Wt = dense(ctx->Wt, {v, o, v, v});
+  DT Wvooo = dense(ctx->Wvooo, {v, o, o, o});
+  // single check on column 1: U_f[o1][o2][x][y][z] = t~_{f o1 o2}^{xyz}
+  for (const Batch& b : ctx->feed1.batches) {
+    const size_t mk = ws.mark();
+    double* U = ws.alloc((size_t)(b.nslots * o2v3));
+    if (!U) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
+    UnpackArgs ua{};
+    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
+    const int occ[3] = {0, 2, 3};
+    set_s1(ua, occ);
+    ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
+    ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
+    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, s));
+    // (a) 1/2 f~^k_c t~_{kij}^{cab}: k runs over the batch
+    {
+      DT fk = strided(ctx->ft + (long long)b.slot0 * n + o, {b.nslots, v}, {n, 1});
+      DT Ub = dense(U, {b.nslots, o, o, v, v, v});
+      STCK(contract(ws, s, F, 0.5, fk, "kc", Ub, "kijcab", 1.0, X2, "ijab"));
+    }
+    for (int ls = 0; ls < b.nslots; ++ls) {
+      const int f = b.slot0 + ls;
+      DT Uf = dense(U + ls * o2v3, {o, o, v, v, v});
+      // (b) sum_cd v~^{bk}_{cd} t~_{kij}^{dac}
+      DT vb = strided(ctx->V + (long long)o * n3 + (long long)o * n * n + (long long)f * n + o, {v, v, v},
+                      {n3, (long long)n * n, 1});
+      STCK(contract(ws, s, F, 1.0, vb, "bcd", Uf, "ijdac", 1.0, X2, "ijab"));
+      // (c) - sum_kc v~^{kl}_{jc} t~_{lik}^{cab}
+      DT vc = strided(ctx->V + (long long)f * n + o, {o, o, v}, {n3, (long long)n * n, 1});
+      STCK(contract(ws, s, F, -1.0, vc, "kjc", Uf, "ikcab", 1.0, X2, "ijab"));
+      // (d) W^{ab}_{dj} -= sum_le v~^{lm}_{de} t~_{mjl}^{eba}
+      DT vd = strided(ctx->V + (long long)o * n * n + (long long)f * n + o, {o, v, v}, {n3, (long long)n * n, 1});
+      STCK(contract(ws, s, F, -1.0, vd, "lde", Uf, "jleba", 1.0, Wt, "djba"));
+      // (e) W^{al}_{ij} += sum_de v~^{lm}_{de} t~_{mij}^{ead}
+      STCK(contract(ws, s, F, 1.0, vd, "lde", Uf, "ijead", 1.0, Wvooo, "alij"));
+    }
+    ws.reset(mk);
+  }
+  // double check on columns 1,2: U'_f[j][k][b][c][a] = t~_{j' k' f}^{b' c' a}
+  for (const Batch& b : ctx->feed12.batches) {
+    const size_t mk = ws.mark();
+    double* U = ws.alloc((size_t)(b.nslots * o2v3));
+    if (!U) { ctx->err = "workspace exhausted (feedback S12)"; return CCT_ENOMEM; }
+    UnpackArgs ua{};
+    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
+    const int occ[3] = {2, 3, 0};
+    set_s12(ua, occ);
+    ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
+    ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
+    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, s));
+    DT Ub = dense(U, {b.nslots, o, o, v, v, v});
+    DT r1b = strided(ctx->r1 + (long long)b.slot0 * v, {b.nslots, v}, {v, 1});
+    STCK(contract(ws, s, F, 0.5, Vv(ctx, "oovv"), "jkbc", Ub, "fjkbca", 1.0, r1b, "fa"));
+    ws.reset(mk);
+  }
+  return CCT_OK;
+}
+
+int r3_pp(cct_ctx* ctx) {
+  const int v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3;
+  const int M = (int)(ctx->ntri * v);
+  // term 3: R[t][x][y][z] += sum_de T[t][x][d][e] W[y][z][d][e]
+  // term 2: R[t][y][x][z] += sum_de T[t][d][x][e] W[y][z][d][e]
+  // term 1: R[t][y][z][x] += sum_de T[t][d][e][x] W[y][z][d][e]
+  const Idx2 am[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
+  const Idx2 ak[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
+  const Idx2 cn[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
+  for (int term = 0; term < 3; ++term) {
+    GemmArgs g{};
+    g.M = M; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+    g.A = ctx->t3; g.am = am[term]; g.ak = ak[term];
+    g.B = ctx->Wvvvv; g.bk = idx1(1); g.bn = idx1(v2);
+    g.C = ctx->r3; g.cm = am[term]; g.cn = cn[term];
+    g.alpha = 1.0; g.beta = 1.0;
+    g.a_len = ctx->ntri * v3; g.b_len = v2 * v2; g.c_len = ctx->ntri * v3;
+    HIPCK(gemm(g, ctx->prec, ctx->s));
+  }
+  return CCT_OK;
+}
+
+int r3_f1(cct_ctx* ctx) {
+  // sum_d F^a_d t^{dbc} + F^b_d t^{adc} + F^c_d t^{abd}, one GEMM per axis, batched over blocks
+  const int v = ctx->v;
+  const long long v2 = (long long)v * v;
+  const int nt = (int)ctx->ntri;
+  for (int start = 0; start < nt; start += 65535) {
+    const int nb = std::min(65535, nt - start);
+    const long long off = (long long)start * ctx->v3;
+    for (int axis = 0; axis < 3; ++axis) {
+      GemmArgs g{};
+      g.M = v; g.K = v; g.N = (int)v2; g.batch = nb;
+      g.A = ctx->Fvv; g.am = idx1(v); g.ak = idx1(1); g.a_batch = 0;
+      g.B = ctx->t3 + off; g.b_batch = ctx->v3;
+      g.C = ctx->r3 + off; g.c_batch = ctx->v3;
+      if (axis == 0) { g.bk = idx1(v2); g.bn = idx1(1); g.cm = idx1(v2); g.cn = idx1(1); }
+      if (axis == 1) { g.bk = idx1(v); g.bn = idx2(v, v2, 1); g.cm = idx1(v); g.cn = idx2(v, v2, 1); }
+      if (axis == 2) { g.bk = idx1(1); g.bn = idx1(v); g.cm = idx1(1); g.cn = idx1(v); }
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = v2; g.b_len = ctx->ntri * ctx->v3 - off; g.c_len = ctx->ntri * ctx->v3 - off;
+      HIPCK(gemm(g, Prec::F64, ctx->s));
+    }
+  }
+  return CCT_OK;
+}
+
+int r3_rings(cct_ctx* ctx, int kind) {
+  const int o = ctx->o, v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, ov3 = o * v3;
+  Arena& ws = ctx->ws;
+  for (const Batch& b : ctx->ring[kind].batches) {
+    const size_t mk = ws.mark();
+    double* U = ws.alloc((size_t)(b.nslots * ov3));
+    double* Z = ws.alloc((size_t)(b.nslots * ov3));
+    if (!U || !Z) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
+    UnpackArgs ua{};
+    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 1;
+    ua.s_slot = ov3; ua.s_free[0] = v3; ua.s_free[1] = 0; ua.s_x = v2; ua.s_y = v; ua.s_z = 1;
+    if (kind == 0) {
+      const int occ[3] = {2, 0, 1};  // S1 t~_{l q r}^{d y z}
+      set_s1(ua, occ);
+    } else if (kind == 1) {
+      ua.nterms = 2;  // t_{q l r}^{d y z} + t_{r l q}^{d z y}
+      ua.terms[0] = UnpackTerm{1.0, {0, 2, 1}, {0, 1, 2}};
+      ua.terms[1] = UnpackTerm{1.0, {1, 2, 0}, {0, 2, 1}};
+    } else {
+      const int occ[3] = {0, 2, 1};  // t_{q l r}^{d x z}
+      set_ident(ua, occ);
+    }
+    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
+    GemmArgs g{};
+    g.M = o * v; g.N = (int)v2; g.K = o * v; g.batch = b.nslots;
+    if (kind == 0) {  // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} = Wb1[l][x][d][p]
+      g.A = ctx->Wb1; g.am = idx2(v, 1, (long long)v * o); g.ak = idx2(v, v2 * o, o);
+    } else {          // A[(p,x)][(l,d)] = Wbar^{lx}_{pd} = Wb2[l][x][p][d]
+      g.A = ctx->Wb2; g.am = idx2(v, v, (long long)o * v); g.ak = idx2(v, v2 * o, 1);
+    }
+    g.a_batch = 0;
+    g.B = U; g.bk = idx1(v2); g.bn = idx1(1); g.b_batch = ov3;
+    g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = (long long)o * o * v2; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+    HIPCK(gemm(g, ctx->prec, ctx->s));
+    HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    ws.reset(mk);
+  }
+  return CCT_OK;
+}
+
+int r3_hh(cct_ctx* ctx, bool with_hh, bool with_f2) {
+  const int o = ctx->o, v = ctx->v;
+  const long long v3 = ctx->v3, o2v3 = (long long)o * o * v3, o4 = (long long)o * o * o * o;
+  // Wh = W^{lm}_{pq} - 1/2 (delta_mq F^l_p + delta_lp F^m_q)
+  if (with_hh) HIPCK(axpby(1.0, ctx->Woooo, 0.0, ctx->Wh, o4, ctx->s));
+  else HIPCK(fill(ctx->Wh, 0.0, o4, ctx->s));
+  if (with_f2) HIPCK(add_pair_diag(ctx->Wh, ctx->Foo, o, o, -0.5, ctx->s));
+  Arena& ws = ctx->ws;
+  for (const Batch& b : ctx->hh.batches) {
+    const size_t mk = ws.mark();
+    double* U = ws.alloc((size_t)(b.nslots * o2v3));
+    double* Z = ws.alloc((size_t)(b.nslots * o2v3));
+    if (!U || !Z) { ctx->err = "workspace exhausted (hole ladder)"; return CCT_ENOMEM; }
+    UnpackArgs ua{};
+    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
+    const int occ[3] = {2, 3, 0};  // t_{l m r}^{xyz}
+    set_ident(ua, occ);
+    ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
+    ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
+    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
+    GemmArgs g{};
+    g.M = o * o; g.N = (int)v3; g.K = o * o; g.batch = b.nslots;
+    g.A = ctx->Wh; g.am = idx1(1); g.ak = idx1((long long)o * o); g.a_batch = 0;
+    g.B = U; g.bk = idx1(v3); g.bn = idx1(1); g.b_batch = o2v3;
+    g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
+    HIPCK(gemm(g, Prec::F64, ctx->s));
+    HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    ws.reset(mk);
+  }
+  return CCT_OK;
+}
+
+int r3_drivers(cct_ctx* ctx, int which) {
+  const int o = ctx->o, v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, o2v3 = (long long)o * o * v3;
+  Arena& ws = ctx->ws;
+  const Job& J = which == 0 ? ctx->d1 : ctx->d2;
+  for (const Batch& b : J.batches) {
+    const size_t mk = ws.mark();
+    double* Z = ws.alloc((size_t)(b.nslots * o2v3));
+    if (!Z) { ctx->err = "workspace exhausted (drivers)"; return CCT_ENOMEM; }
+    GemmArgs g{};
+    g.batch = b.nslots;
+    if (which == 0) {
+      // Z[q][(x,y)][(p,r,z)] = sum_d W^{xy}_{dq} t_pr^dz ; Wt[d][q][y][x]
+      g.M = (int)v2; g.N = o * o * v; g.K = v;
+      g.A = ctx->Wt + (long long)b.slot0 * v2; g.am = idx2(v, 1, v); g.ak = idx1((long long)o * v2); g.a_batch = v2;
+      g.B = ctx->t2; g.bk = idx1(v); g.bn = idx2(v, v2, 1); g.b_batch = 0;
+      g.C = Z; g.cm = idx1((long long)o * o * v); g.cn = idx1(1); g.c_batch = o2v3;
+      g.a_len = v3 * o - (long long)b.slot0 * v2; g.b_len = (long long)o * o * v2;
+    } else {
+      // Z[r][(x,p,q)][(y,z)] = sum_l W^{xl}_{pq} t_lr^yz ; Wvooo[x][l][p][q]
+      g.M = v * o * o; g.N = (int)v2; g.K = o;
+      g.A = ctx->Wvooo; g.am = idx2(o * o, (long long)o * o * o, 1); g.ak = idx1((long long)o * o); g.a_batch = 0;
+      g.B = ctx->t2 + (long long)b.slot0 * v2; g.bk = idx1((long long)o * v2); g.bn = idx1(1); g.b_batch = v2;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = o2v3;
+      g.a_len = (long long)v * o * o * o; g.b_len = (long long)o * o * v2 - (long long)b.slot0 * v2;
+    }
+    g.c_len = b.nslots * o2v3;
+    g.alpha = 1.0; g.beta = 0.0;
+    HIPCK(gemm(g, Prec::F64, ctx->s));
+    HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    ws.reset(mk);
+  }
+  return CCT_OK;
+}
+
+void count_macs(cct_ctx* ctx, unsigned mask) {
+  const double t = (double)ctx->ntri, o = ctx->o, v = ctx->v;
+  const double full[9] = {6 * t * v * v * v * v, 6 * t * o * v * v * v, 3 * t * v * v * v * v, 3 * t * o * v * v * v,
+                          3 * t * o * v * v * v * v, 3 * t * o * v * v * v * v, 6 * t * o * v * v * v * v,
+                          3 * t * o * o * v * v * v, 3 * t * v * v * v * v * v};
+  for (int i = 0; i < 9; ++i) ctx->macs[i] = (mask & (1u << i)) ? full[i] : 0.0;
+}
+
+int finite_or_err(cct_ctx* ctx, double x) {
+  if (!std::isfinite(x)) {
+    ctx->err = "non-finite residual norm or energy";
+    return CCT_ENUMERIC;
+  }
+  return CCT_OK;
+}
+
+// Full residual evaluation; R3 post-processed; optionally T3 += R3 / eps.
+int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
+  if (!ctx->have_f || !ctx->have_B) {
+    ctx->err = "integrals not set (cct_set_fock / cct_set_eri_df)";
+    return CCT_ESTATE;
+  }
+  hipStream_t s = ctx->s;
+  mark(ctx, 0);
+  RCK(dress(ctx));
+  RCK(ccsd_part(ctx));
+  mark(ctx, 1);
+  RCK(feedback(ctx));
+  {
+    DT X2 = dense(ctx->X2, {ctx->o, ctx->o, ctx->v, ctx->v});
+    DT R2 = dense(ctx->r2, {ctx->o, ctx->o, ctx->v, ctx->v});
+    STCK(accumulate(s, 1.0, X2, "ijab", 0.0, R2, "ijab"));
+    STCK(accumulate(s, 1.0, X2, "jiba", 1.0, R2, "ijab"));
+  }
+  HIPCK(fill(ctx->r3, 0.0, ctx->ntri * ctx->v3, s));
+  mark(ctx, 2);
+  if (mask & CCT_TERM_PP) RCK(r3_pp(ctx));
+  mark(ctx, 3);
+  if (mask & CCT_TERM_RA) RCK(r3_rings(ctx, 0));
+  if (mask & CCT_TERM_RB) RCK(r3_rings(ctx, 1));
+  if (mask & CCT_TERM_RC) RCK(r3_rings(ctx, 2));
+  mark(ctx, 4);
+  if (mask & (CCT_TERM_HH | CCT_TERM_F2)) RCK(r3_hh(ctx, mask & CCT_TERM_HH, mask & CCT_TERM_F2));
+  mark(ctx, 5);
+  if (mask & CCT_TERM_D1) RCK(r3_drivers(ctx, 0));
+  if (mask & CCT_TERM_D2) RCK(r3_drivers(ctx, 1));
+  mark(ctx, 6);
+  if (mask & CCT_TERM_F1) RCK(r3_f1(ctx));
+  mark(ctx, 7);
+  PostArgs pa{ctx->o, ctx->v, (int)ctx->ntri, ctx->v3, update_t3 ? 1 : 0, 1};
+  int np = 0;
+  const long long part_max = ctx->red_n - 1024;
+  if (64LL * ctx->ntri > part_max) {
+    ctx->err = "reduction scratch too small";
+    return CCT_EDEVICE;
+  }
+  HIPCK(post_update(ctx->r3, ctx->t3, ctx->tri, ctx->eps, ctx->red + 1024, &np, pa, s));
+  HIPCK(reduce_sum(ctx->red + 1024, np, ctx->scal + 2, ctx->red, s));
+  HIPCK(dot(ctx->r1, ctx->r1, (long long)ctx->o * ctx->v, ctx->scal + 0, ctx->red, s));
+  HIPCK(dot(ctx->r2, ctx->r2, (long long)ctx->o * ctx->o * ctx->v * ctx->v, ctx->scal + 1, ctx->red, s));
+  mark(ctx, 8);
+  count_macs(ctx, mask);
+  double h[3];
+  HIPCK(hipMemcpyAsync(h, ctx->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (ctx->events) {
+    for (int i = 0; i < PH_DIIS; ++i) {
+      float msv = 0.f;
+      if (hipEventElapsedTime(&msv, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) ctx->ms[i] = msv;
+    }
+  }
+  ctx->have_res = true;
+  for (int i = 0; i < 3; ++i) {
+    if (norms) norms[i] = h[i];
+    RCK(finite_or_err(ctx, h[i]));
+  }
+  return CCT_OK;
+}
+
+int energy_dev(cct_ctx* ctx, double* e) {
+  const int o = ctx->o, v = ctx->v;
+  hipStream_t s = ctx->s;
+  // tau = t2 + t1 t1
+  DT tau = dense(ctx->tau_e, {o, o, v, v});
+  DT t1 = dense(ctx->t1, {o, v});
+  STCK(accumulate(s, 1.0, dense(ctx->t2, {o, o, v, v}), "ijab", 0.0, tau, "ijab"));
+  STCK(contract(ctx->ws, s, Prec::F64, 1.0, t1, "ia", t1, "jb", 1.0, tau, "ijab"));
+  HIPCK(dot(ctx->vbare_c, ctx->tau_e, (long long)o * o * v * v, ctx->scal + 4, ctx->red, s));
+  HIPCK(dot(ctx->fov, ctx->t1, (long long)o * v, ctx->scal + 5, ctx->red, s));
+  double h[2];
+  HIPCK(hipMemcpyAsync(h, ctx->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  *e = h[0] + 2.0 * h[1];
+  return finite_or_err(ctx, *e);
+}
+
+// --- DIIS ---------------------------------------------------------------
+long long diis_len(cct_ctx* ctx) {
+  const long long n12 = (long long)ctx->o * ctx->v + (long long)ctx->o * ctx->o * ctx->v * ctx->v;
+  return n12 + (ctx->diis_t3 ? ctx->ntri * ctx->v3 : 0);
+}
+
+int copy_amps_to(cct_ctx* ctx, double* dst) {
+  const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
+  HIPCK(hipMemcpyAsync(dst, ctx->t1, n1 * 8, hipMemcpyDeviceToDevice, ctx->s));
+  HIPCK(hipMemcpyAsync(dst + n1, ctx->t2, n2 * 8, hipMemcpyDeviceToDevice, ctx->s));
+  if (ctx->diis_t3) HIPCK(hipMemcpyAsync(dst + n1 + n2, ctx->t3, ctx->ntri * ctx->v3 * 8, hipMemcpyDeviceToDevice, ctx->s));
+  return CCT_OK;
+}
+
+int diis_dot(cct_ctx* ctx, const double* x, const double* y, double* out_dev) {
+  const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
+  HIPCK(dot(x, y, n1 + n2, out_dev, ctx->red, ctx->s));
+  if (ctx->diis_t3) {
+    HIPCK(weighted_dot_t3(x + n1 + n2, y + n1 + n2, ctx->tri, (int)ctx->ntri, ctx->v3, ctx->v3, out_dev + 1,
+                          ctx->red, ctx->s));
+  } else {
+    HIPCK(fill(out_dev + 1, 0.0, 1, ctx->s));
+  }
+  return CCT_OK;
+}
+
+void diis_reset(cct_ctx* ctx) {
+  ctx->diis_n = 0;
+  ctx->diis_next = 0;
+  ctx->Bmat.assign(ctx->diis_space, std::vector<double>(ctx->diis_space, 0.0));
+}
+
+// Called after the Jacobi step: T currently holds the Jacobi-updated amplitudes,
+// diis_old the amplitudes before it.
+int diis_step(cct_ctx* ctx) {
+  const long long L = ctx->diis_len;
+  const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
+  const int M = ctx->diis_space;
+  const int slot = ctx->diis_next;
+  double* vec = ctx->dvec[slot];
+  double* err = ctx->derr[slot];
+  RCK(copy_amps_to(ctx, vec));
+  HIPCK(axpby(1.0, vec, 0.0, err, L, ctx->s));
+  HIPCK(axpby(-1.0, ctx->diis_old, 1.0, err, L, ctx->s));
+  ctx->diis_next = (slot + 1) % M;
+  ctx->diis_n = std::min(ctx->diis_n + 1, M);
+  // new row of the overlap matrix (stored slots are 0..diis_n-1 in ring order)
+  std::vector<int> slots;
+  for (int k = 0; k < ctx->diis_n; ++k) slots.push_back(k);
+  for (int k : slots) {
+    RCK(diis_dot(ctx, err, ctx->derr[k], ctx->scal + 8 + 2 * k));
+  }
+  std::vector<double> h(2 * M);
+  HIPCK(hipMemcpyAsync(h.data(), ctx->scal + 8, 2 * M * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  for (int k : slots) {
+    const double b = h[2 * k] + h[2 * k + 1];
+    ctx->Bmat[slot][k] = ctx->Bmat[k][slot] = b;
+  }
+  if (ctx->diis_n < ctx->diis_start) return CCT_OK;
+  // order slots from oldest to newest
+  std::vector<int> order;
+  for (int k = 0; k < ctx->diis_n; ++k) order.push_back((ctx->diis_next - ctx->diis_n + k + M) % M);
+  while (true) {
+    const int m = (int)order.size();
+    std::vector<double> A((size_t)(m + 1) * (m + 1)), rhs(m + 1, 0.0);
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) A[a * (m + 1) + b] = ctx->Bmat[order[a]][order[b]];
+    for (int a = 0; a < m; ++a) { A[a * (m + 1) + m] = -1.0; A[m * (m + 1) + a] = -1.0; }
+    A[m * (m + 1) + m] = 0.0;
+    rhs[m] = -1.0;
+    // LU with partial pivoting
+    bool singular = false;
+    const int N = m + 1;
+    std::vector<int> piv(N);
+    for (int i = 0; i < N; ++i) piv[i] = i;
+    double amax = 0.0;
+    for (double x : A) amax = std::max(amax, std::fabs(x));
+    for (int c = 0; c < N && !singular; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < N; ++r)
+        if (std::fabs(A[r * N + c]) > std::fabs(A[pr * N + c])) pr = r;
+      if (std::fabs(A[pr * N + c]) <= 1e-300 || std::fabs(A[pr * N + c]) < 1e-15 * amax * 1e-10) { singular = true; break; }
+      if (pr != c) {
+        for (int k = 0; k < N; ++k) std::swap(A[pr * N + k], A[c * N + k]);
+        std::swap(rhs[pr], rhs[c]);
+      }
+      for (int r = c + 1; r < N; ++r) {
+        const double f = A[r * N + c] / A[c * N + c];
+        for (int k = c; k < N; ++k) A[r * N + k] -= f * A[c * N + k];
+        rhs[r] -= f * rhs[c];
+      }
+    }
+    std::vector<double> x(N);
+    if (!singular) {
+      for (int r = N - 1; r >= 0; --r) {
+        double acc = rhs[r];
+        for (int k = r + 1; k < N; ++k) acc -= A[r * N + k] * x[k];
+        x[r] = acc / A[r * N + r];
+        if (!std::isfinite(x[r])) singular = true;
+      }
+    }
+    if (singular) {
+      if (m <= 1) return CCT_OK;
+      order.erase(order.begin());
+      continue;
+    }
+    // T = sum_m c_m vec_m
+    double* t1 = ctx->t1;
+    double* t2 = ctx->t2;
+    for (int a = 0; a < m; ++a) {
+      const double* vp = ctx->dvec[order[a]];
+      const double b = a == 0 ? 0.0 : 1.0;
+      HIPCK(axpby(x[a], vp, b, t1, n1, ctx->s));
+      HIPCK(axpby(x[a], vp + n1, b, t2, n2, ctx->s));
+      if (ctx->diis_t3) HIPCK(axpby(x[a], vp + n1 + n2, b, ctx->t3, ctx->ntri * ctx->v3, ctx->s));
+    }
+    return CCT_OK;
+  }
+}
+
+int update(cct_ctx* ctx, double* e, double norms[3]) {
+  const bool use_diis = ctx->diis_on && ctx->diis_space > 0;
+  if (use_diis) RCK(copy_amps_to(ctx, ctx->diis_old));
+  double nr[3];
+  RCK(compute(ctx, CCT_TERM_ALL, true, nr));
+  HIPCK(jacobi_t1t2(ctx->t1, ctx->r1, ctx->t2, ctx->r2, ctx->eps, ctx->o, ctx->v, ctx->s));
+  mark(ctx, PH_DIIS);
+  if (use_diis) RCK(diis_step(ctx));
+  double en = 0.0;
+  RCK(energy_dev(ctx, &en));
+  mark(ctx, PH_N);
+  if (ctx->events) {
+    float msv = 0.f;
+    if (hipEventSynchronize(ctx->ev[PH_N]) == hipSuccess &&
+        hipEventElapsedTime(&msv, ctx->ev[PH_DIIS], ctx->ev[PH_N]) == hipSuccess)
+      ctx->ms[PH_DIIS] = msv;
+  }
+  if (e) *e = en;
+  if (norms) for (int i = 0; i < 3; ++i) norms[i] = nr[i];
+  return CCT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* cct_strerror(int code) {
+  if (code > 0 || code < -6) return "unknown error";
+  return kErr[-code];
+}
+
+const char* cct_last_error(const cct_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t cct_packed_index(int nocc, int i, int j, int k) {
+  if (nocc <= 0 || i < 0 || i > j || j > k || k >= nocc) return -1;
+  // triples before first index i, then pairs (j,k) before j within i, then k offset
+  const long long o = nocc;
+  auto c3 = [](long long x) { return x * (x + 1) * (x + 2) / 6; };
+  auto c2 = [](long long x) { return x * (x + 1) / 2; };
+  const long long m = o - i;
+  return c3(o) - c3(m) + c2(m) - c2(m - (j - i)) + (k - j);
+}
+
+void cct_destroy(cct_ctx* ctx) {
+  if (!ctx) return;
+  for (void* p : ctx->owned) (void)hipFree(p);
+  if (ctx->wsbuf) (void)hipFree(ctx->wsbuf);
+  for (int i = 0; i <= PH_N; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+}
+
+int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json, void* hip_stream,
+               cct_ctx** out) {
+  if (!out) return CCT_EINVAL;
+  *out = nullptr;
+  if (nocc < 1 || nvir < 1 || naux < 1 || nocc > 200 || nvir > 1200 || (int)prec < 0 || (int)prec > 2)
+    return CCT_EINVAL;
+  cct_ctx* ctx = new cct_ctx();
+  ctx->o = nocc;
+  ctx->v = nvir;
+  ctx->n = nocc + nvir;
+  ctx->naux = naux;
+  ctx->ntri = tri_count(nocc);
+  ctx->v3 = (long long)nvir * nvir * nvir;
+  ctx->prec = (Prec)prec;
+  ctx->s = (hipStream_t)hip_stream;
+  if (ctx->ntri > 65535) { delete ctx; return CCT_EINVAL; }
+  if (opts_json) {
+    std::string js(opts_json), val;
+    if (json_find(js, "diis_space", val)) ctx->diis_space = std::atoi(val.c_str());
+    if (json_find(js, "diis_start", val)) ctx->diis_start = std::atoi(val.c_str());
+    if (json_find(js, "diis_t3", val)) {
+      if (val == "none") ctx->diis_t3 = false;
+      else if (val == "full") ctx->diis_t3 = true;
+      else { delete ctx; return CCT_EINVAL; }
+    }
+    if (json_find(js, "diis", val)) ctx->diis_on = (val != "false" && val != "0" && val != "off");
+    if (json_find(js, "workspace_gb", val)) ctx->ws_gb = std::atof(val.c_str());
+    if (json_find(js, "timers", val)) ctx->events = (val == "true" || val == "1");
+    if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb <= 0) {
+      delete ctx;
+      return CCT_EINVAL;
+    }
+  }
+  const int o = nocc, v = nvir, n = ctx->n;
+  const long long n2 = (long long)n * n, n4 = n2 * n2;
+  const long long ov = (long long)o * v, o2v2 = ov * ov, v3 = ctx->v3, t3n = ctx->ntri * v3;
+  const long long o2v3 = (long long)o * o * v3;
+  // memory plan (doubles)
+  long long fixed = 3 * n2 + n + ov + 2 * o2v2 + (long long)naux * n2 * 2 + n4 + 2 * n2 + naux + (long long)naux * n * o;
+  fixed += 2 * ov + 3 * o2v2 + 2 * t3n;                       // t1 t2 t3 r1 r2 r3 X2
+  fixed += 2 * o2v2 + 2 * (long long)o * v * v * o + (long long)o * v * v * v + (long long)o * o * v * o;  // tau, VC*
+  fixed += v * v + o * o + 2LL * o * o * o * o + 4 * o2v2 + 2 * (long long)v * v * v * o + (long long)v * o * o * o;
+  fixed += (long long)v * v * v * v + o2v2 + ov;
+  const int M = ctx->diis_on ? ctx->diis_space : 0;
+  const long long dlen = ov + o2v2 + (ctx->diis_t3 ? t3n : 0);
+  fixed += (long long)(2 * M + 1) * dlen;
+  // workspace: enough for every job in one batch (two unpacked/contracted
+  // slabs per slot, o^2 slots for the rings), capped by the option
+  const long long need_ws = 4 * (long long)o * v3 + 4 * o2v3 + 2 * o2v3 * o + 1024;
+  long long ws_doubles = std::min<long long>(need_ws, (long long)(ctx->ws_gb * 1e9 / 8.0));
+  ws_doubles = std::max<long long>(ws_doubles, 4 * (long long)o * v3 + 6 * o2v3 + 1024);
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    ctx->err = "hipMemGetInfo failed (no HIP device?)";
+    *out = nullptr;
+    delete ctx;
+    return CCT_EDEVICE;
+  }
+  const double need_b = (double)(fixed + ws_doubles) * 8.0 + 64e6;
+  if (need_b > (double)free_b) {
+    delete ctx;
+    return CCT_ENOMEM;
+  }
+  int rc = CCT_OK;
+#define AL(ptr, cnt) if (rc == CCT_OK) rc = dalloc(ctx, &ctx->ptr, (cnt))
+  AL(f, n2); AL(B, (long long)naux * n2); AL(eps, n); AL(fov, ov);
+  AL(vbare_c, o2v2); AL(vbare, o2v2);
+  AL(Bt, (long long)naux * n2); AL(ft, n2); AL(V, n4); AL(fG, n2); AL(G, n2); AL(cP, naux);
+  AL(Dt, (long long)naux * n * o);
+  AL(t1, ov); AL(t2, o2v2); AL(t3, t3n); AL(r1, ov); AL(r2, o2v2); AL(r3, t3n); AL(X2, o2v2); AL(zero_r1, ov);
+  AL(tau2, o2v2); AL(VCoovv, o2v2); AL(VCovvo, (long long)o * v * v * o); AL(VCovvv, (long long)o * v * v * v);
+  AL(VCoovo, (long long)o * o * v * o);
+  AL(Fvv, (long long)v * v); AL(Foo, (long long)o * o); AL(Woooo, (long long)o * o * o * o);
+  AL(Wh, (long long)o * o * o * o); AL(Wovvo, o2v2); AL(Wovov, o2v2);
+  AL(Wt, (long long)v * v * v * o); AL(Wvooo, (long long)v * o * o * o); AL(Wb1, o2v2); AL(Wb2, o2v2);
+  AL(Wvvvv, (long long)v * v * v * v); AL(tau_e, o2v2);
+  AL(scal, 256);
+  ctx->red_n = 1024 + 64LL * ctx->ntri + 1024;
+  AL(red, ctx->red_n);
+  ctx->diis_len = diis_len(ctx);
+  if (M > 0) {
+    AL(diis_old, ctx->diis_len);
+    for (int k = 0; k < M && rc == CCT_OK; ++k) {
+      double *a = nullptr, *b = nullptr;
+      rc = dalloc(ctx, &a, ctx->diis_len);
+      if (rc == CCT_OK) rc = dalloc(ctx, &b, ctx->diis_len);
+      ctx->dvec.push_back(a);
+      ctx->derr.push_back(b);
+    }
+  }
+#undef AL
+  if (rc == CCT_OK) {
+    void* w = nullptr;
+    if (hipMalloc(&w, (size_t)ws_doubles * 8) != hipSuccess) rc = CCT_ENOMEM;
+    else {
+      ctx->wsbuf = (char*)w;
+      ctx->ws.init(ctx->wsbuf, (size_t)ws_doubles * 8);
+    }
+  }
+  if (rc == CCT_OK && ctx->events) {
+    for (int i = 0; i <= PH_N && rc == CCT_OK; ++i)
+      if (hipEventCreate(&ctx->ev[i]) != hipSuccess) rc = CCT_EDEVICE;
+  }
+  if (rc == CCT_OK) rc = build_plans(ctx);
+  if (rc == CCT_OK) {
+    if (fill(ctx->zero_r1, 0.0, ov, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+    if (fill(ctx->t1, 0.0, ov, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+    if (fill(ctx->t2, 0.0, o2v2, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+    if (fill(ctx->t3, 0.0, t3n, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+    if (hipStreamSynchronize(ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+  }
+  diis_reset(ctx);
+  if (rc != CCT_OK) {
+    cct_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return CCT_OK;
+}
+
+int cct_set_fock(cct_ctx* ctx, const double* f) {
+  if (!ctx || !f) return CCT_EINVAL;
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  HIPCK(hipMemcpyAsync(ctx->f, f, (size_t)n * n * 8, hipMemcpyHostToDevice, ctx->s));
+  std::vector<double> e(n), fo((size_t)o * v);
+  for (int p = 0; p < n; ++p) e[p] = f[(size_t)p * n + p];
+  for (int i = 0; i < o; ++i)
+    for (int a = 0; a < v; ++a) fo[(size_t)i * v + a] = f[(size_t)i * n + o + a];
+  HIPCK(hipMemcpyAsync(ctx->eps, e.data(), (size_t)n * 8, hipMemcpyHostToDevice, ctx->s));
+  HIPCK(hipMemcpyAsync(ctx->fov, fo.data(), fo.size() * 8, hipMemcpyHostToDevice, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  ctx->have_f = true;
+  return CCT_OK;
+}
+
+int cct_set_eri_df(cct_ctx* ctx, const double* B) {
+  if (!ctx || !B) return CCT_EINVAL;
+  const int n = ctx->n, o = ctx->o, v = ctx->v;
+  const long long naux = ctx->naux;
+  const long long n2 = (long long)n * n;
+  HIPCK(hipMemcpyAsync(ctx->B, B, (size_t)naux * n2 * 8, hipMemcpyHostToDevice, ctx->s));
+  // bare v^{ij}_{ab} = (ia|jb) = sum_P B[P][i][o+a] B[P][j][o+b], stored [i][j][a][b]
+  GemmArgs g{};
+  g.M = o * v; g.N = o * v; g.K = (int)naux; g.batch = 1;
+  g.A = ctx->B + o; g.am = idx2(v, n, 1); g.ak = idx1(n2);
+  g.B = ctx->B + o; g.bk = idx1(n2); g.bn = idx2(v, n, 1);
+  // C[(i,a)][(j,b)] -> vbare[i][j][a][b]
+  g.C = ctx->vbare; g.cm = idx2(v, (long long)o * v * v, v); g.cn = idx2(v, (long long)v * v, 1);
+  g.alpha = 1.0; g.beta = 0.0;
+  g.a_len = naux * n2 - o; g.b_len = naux * n2 - o; g.c_len = (long long)o * o * v * v;
+  HIPCK(gemm(g, Prec::F64, ctx->s));
+  DT vb = dense(ctx->vbare, {o, o, v, v}), vc = dense(ctx->vbare_c, {o, o, v, v});
+  STCK(accumulate(ctx->s, 2.0, vb, "ijab", 0.0, vc, "ijab"));
+  STCK(accumulate(ctx->s, -1.0, vb, "ijba", 1.0, vc, "ijab"));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  ctx->have_B = true;
+  return CCT_OK;
+}
+
+int cct_init_mp2(cct_ctx* ctx) {
+  if (!ctx) return CCT_EINVAL;
+  if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
+  const long long ov = (long long)ctx->o * ctx->v;
+  HIPCK(fill(ctx->t1, 0.0, ov, ctx->s));
+  HIPCK(fill(ctx->t2, 0.0, ov * ov, ctx->s));
+  HIPCK(fill(ctx->t3, 0.0, ctx->ntri * ctx->v3, ctx->s));
+  HIPCK(jacobi_t1t2(ctx->t1, ctx->zero_r1, ctx->t2, ctx->vbare, ctx->eps, ctx->o, ctx->v, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  diis_reset(ctx);
+  return CCT_OK;
+}
+
+int cct_set_amplitudes(cct_ctx* ctx, const double* t1, const double* t2, const double* t3p) {
+  if (!ctx || !t1 || !t2) return CCT_EINVAL;
+  const long long ov = (long long)ctx->o * ctx->v;
+  HIPCK(hipMemcpyAsync(ctx->t1, t1, ov * 8, hipMemcpyHostToDevice, ctx->s));
+  HIPCK(hipMemcpyAsync(ctx->t2, t2, ov * ov * 8, hipMemcpyHostToDevice, ctx->s));
+  if (t3p) HIPCK(hipMemcpyAsync(ctx->t3, t3p, ctx->ntri * ctx->v3 * 8, hipMemcpyHostToDevice, ctx->s));
+  else HIPCK(fill(ctx->t3, 0.0, ctx->ntri * ctx->v3, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  diis_reset(ctx);
+  return CCT_OK;
+}
+
+int cct_get_amplitudes(cct_ctx* ctx, double* t1, double* t2, double* t3p) {
+  if (!ctx) return CCT_EINVAL;
+  const long long ov = (long long)ctx->o * ctx->v;
+  if (t1) HIPCK(hipMemcpyAsync(t1, ctx->t1, ov * 8, hipMemcpyDeviceToHost, ctx->s));
+  if (t2) HIPCK(hipMemcpyAsync(t2, ctx->t2, ov * ov * 8, hipMemcpyDeviceToHost, ctx->s));
+  if (t3p) HIPCK(hipMemcpyAsync(t3p, ctx->t3, ctx->ntri * ctx->v3 * 8, hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  return CCT_OK;
+}
+
+int cct_residual(cct_ctx* ctx, unsigned term_mask, double* r1, double* r2, double* r3p, double norms[3]) {
+  if (!ctx) return CCT_EINVAL;
+  if (term_mask & ~(unsigned)CCT_TERM_ALL) { ctx->err = "bad term mask"; return CCT_EINVAL; }
+  double nr[3];
+  int rc = compute(ctx, term_mask, false, nr);
+  if (rc != CCT_OK && rc != CCT_ENUMERIC) return rc;
+  const long long ov = (long long)ctx->o * ctx->v;
+  if (r1) HIPCK(hipMemcpyAsync(r1, ctx->r1, ov * 8, hipMemcpyDeviceToHost, ctx->s));
+  if (r2) HIPCK(hipMemcpyAsync(r2, ctx->r2, ov * ov * 8, hipMemcpyDeviceToHost, ctx->s));
+  if (r3p) HIPCK(hipMemcpyAsync(r3p, ctx->r3, ctx->ntri * ctx->v3 * 8, hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  if (norms) for (int i = 0; i < 3; ++i) norms[i] = nr[i];
+  return rc;
+}
+
+int cct_copy_r3(cct_ctx* ctx, int64_t first, int64_t count, double* out) {
+  if (!ctx || !out || first < 0 || count < 0 || first + count > ctx->ntri * ctx->v3) return CCT_EINVAL;
+  if (!ctx->have_res) { ctx->err = "no residual computed yet"; return CCT_ESTATE; }
+  HIPCK(hipMemcpyAsync(out, ctx->r3 + first, (size_t)count * 8, hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
+  return CCT_OK;
+}
+
+int cct_update(cct_ctx* ctx, double* e_corr, double norms[3]) {
+  if (!ctx) return CCT_EINVAL;
+  return update(ctx, e_corr, norms);
+}
+
+int cct_energy(cct_ctx* ctx, double* e_corr) {
+  if (!ctx || !e_corr) return CCT_EINVAL;
+  if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
+  return energy_dev(ctx, e_corr);
+}
+
+int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters) {
+  if (!ctx || max_iter < 1 || !(tol > 0)) return CCT_EINVAL;
+  double e = 0.0, nr[3] = {0, 0, 0};
+  for (int it = 1; it <= max_iter; ++it) {
+    RCK(update(ctx, &e, nr));
+    if (e_corr) *e_corr = e;
+    if (iters) *iters = it;
+    if (std::sqrt(nr[0] + nr[1] + nr[2]) < tol) return CCT_OK;
+  }
+  ctx->err = "not converged";
+  return CCT_ENOTCONV;
+}
+
+int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap) {
+  if (!ctx || cap < 0) return CCT_EINVAL;
+  for (int i = 0; i < std::min(cap, 9); ++i) {
+    if (macs_by_term) macs_by_term[i] = ctx->macs[i];
+    if (ms_by_phase) ms_by_phase[i] = ctx->ms[i];
+  }
+  return CCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,476 @@
+// Strided, batched GEMM on CDNA4 matrix cores with two-level index maps.
+//
+// C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n), where every
+// index of every operand goes through an Idx2 map, so permuted views of packed
+// T3 blocks (the three relabelled operands of the particle-particle ladder)
+// and of the dressed integrals are read in place without transposed copies.
+//
+// Tiling: 256 threads = 4 waves of 64 lanes, BM x BN output tile, BK = 16.
+// Operand tiles are staged through LDS (double buffered); each wave owns a
+// (BM/2) x (BN/2) sub-tile of 16x16 MFMA blocks.  Global loads of the next K
+// tile are issued before the MFMAs of the current one, so their latency hides
+// behind the matrix-core work.  Loads follow the operand's unit-stride axis
+// (k-fast or m/n-fast mapping) so that a wave reads contiguous 128-byte runs.
+//
+// FP64:   v_mfma_f64_16x16x4_f64.  A lane l holds A(row l%16, k l/16) and
+//         B(k l/16, col l%16); the accumulator register r of lane l holds
+//         D(row 4r + l/16, col l%16).
+// FP32:   operands rounded to FP32 in LDS, v_mfma_f32_16x16x4_f32; the FP32
+//         accumulators are flushed into FP64 registers every K tile.
+// BF16X3: each operand x is split into hi = bf16(x), lo = bf16(x - hi); the
+//         product uses hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x32_bf16
+//         (A(row l%16, k 8*(l/16)+e), D(row 4*(l/16)+r, col l%16)); FP32
+//         accumulators are flushed into FP64 every K tile.
+#include "internal.h"
+
+#include <climits>
+
+namespace cct {
+namespace {
+
+constexpr int NT = 256;
+constexpr int BK = 16;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ long long map2(const Idx2& d, int i) {
+  if (d.inner == 0) return (long long)i * d.s_lo;
+  int hi = (int)((unsigned)i / (unsigned)d.inner);
+  int lo = i - hi * d.inner;
+  return (long long)hi * d.s_hi + (long long)lo * d.s_lo;
+}
+
+// Position of the tile handled by this workgroup.  Consecutive workgroup ids
+// land on different XCDs (round robin over 8); remap so that each XCD gets a
+// contiguous range of the tile order, and order tiles in groups of GM tile
+// rows so that concurrently running workgroups on one XCD share A and B
+// panels in that XCD's L2.
+__device__ __forceinline__ bool tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int nb = tiles_m * tiles_n;
+  const int per = (nb + 7) / 8;
+  const int bid = blockIdx.x;
+  const int pid = (bid % 8) * per + bid / 8;
+  if (pid >= nb) return false;
+  constexpr int GM = 8;
+  const int group = pid / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gsize = min(tiles_m - first_m, GM);
+  const int r = pid - group * GM * tiles_n;
+  tm = first_m + r % gsize;
+  tn = r / gsize;
+  return true;
+}
+
+template <int BM, int BN>
+struct Tiles {
+  static constexpr int TM = BM / 32;  // 16x16 blocks per wave along M
+  static constexpr int TN = BN / 32;
+  static constexpr int PADA = 2, PADB = 2;
+  static constexpr int LA = BM + PADA, LB = BN + PADB;
+  static constexpr int EA = BM * BK / NT;  // A elements loaded per thread per K tile
+  static constexpr int EB = BN * BK / NT;
+};
+
+// ---------------------------------------------------------------------------
+// operand staging: global (any Idx2 layout) -> registers -> LDS
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+struct Loader {
+  // Row (A) and column (B) parts of the operand addresses, one per tile row /
+  // column, kept in LDS (-1 marks rows/columns outside the matrix).
+  const long long* a_row;
+  const long long* b_col;
+  int a_k0, a_m0;
+  bool a_kfast;
+  int b_k0, b_n0;
+  bool b_nfast;
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ void load_tile(const GemmArgs& g, const double* __restrict__ A, const double* __restrict__ B,
+                                          const Loader<BM, BN>& L, int k0, double (&ra)[Tiles<BM, BN>::EA],
+                                          double (&rb)[Tiles<BM, BN>::EB]) {
+  using T = Tiles<BM, BN>;
+  if (L.a_kfast) {
+    const int k = k0 + L.a_k0;
+    const bool kok = k < g.K;
+    const long long ko = kok ? map2(g.ak, k) : 0;
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const long long r = L.a_row[L.a_m0 + e * (NT / BK)];
+      ra[e] = (kok && r >= 0) ? A[r + ko] : 0.0;
+    }
+  } else {
+    constexpr int step = NT / BM;
+    const long long r = L.a_row[L.a_m0];
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const int k = k0 + L.a_k0 + e * step;
+      ra[e] = (k < g.K && r >= 0) ? A[r + map2(g.ak, k)] : 0.0;
+    }
+  }
+  if (L.b_nfast) {
+    constexpr int step = NT / BN;
+    const long long c = L.b_col[L.b_n0];
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const int k = k0 + L.b_k0 + e * step;
+      rb[e] = (k < g.K && c >= 0) ? B[c + map2(g.bk, k)] : 0.0;
+    }
+  } else {
+    const int k = k0 + L.b_k0;
+    const bool kok = k < g.K;
+    const long long ko = kok ? map2(g.bk, k) : 0;
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const long long c = L.b_col[L.b_n0 + e * (NT / BK)];
+      rb[e] = (kok && c >= 0) ? B[c + ko] : 0.0;
+    }
+  }
+}
+
+template <int BM, int BN, typename S>
+__device__ __forceinline__ void store_tile(const Loader<BM, BN>& L, const double (&ra)[Tiles<BM, BN>::EA],
+                                           const double (&rb)[Tiles<BM, BN>::EB], S* As, S* Bs) {
+  using T = Tiles<BM, BN>;
+  if (L.a_kfast) {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) As[L.a_k0 * T::LA + L.a_m0 + e * (NT / BK)] = (S)ra[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) As[(L.a_k0 + e * (NT / BM)) * T::LA + L.a_m0] = (S)ra[e];
+  }
+  if (L.b_nfast) {
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) Bs[(L.b_k0 + e * (NT / BN)) * T::LB + L.b_n0] = (S)rb[e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) Bs[L.b_k0 * T::LB + L.b_n0 + e * (NT / BK)] = (S)rb[e];
+  }
+}
+
+// Fill the LDS offset tables (rows of A, columns of B) and choose the load
+// mappings.  Ends with a barrier.
+template <int BM, int BN>
+__device__ __forceinline__ void init_loader(const GemmArgs& g, int tm, int tn, long long a_off, long long b_off,
+                                            long long* rowA, long long* colB, Loader<BM, BN>& L) {
+  const int tid = threadIdx.x;
+  const int m_base = tm * BM, n_base = tn * BN;
+  for (int i = tid; i < BM; i += NT) {
+    const int m = m_base + i;
+    rowA[i] = (m < g.M) ? a_off + map2(g.am, m) : -1;
+  }
+  for (int i = tid; i < BN; i += NT) {
+    const int n = n_base + i;
+    colB[i] = (n < g.N) ? b_off + map2(g.bn, n) : -1;
+  }
+  L.a_row = rowA;
+  L.b_col = colB;
+  L.a_kfast = (g.ak.s_lo == 1);
+  if (L.a_kfast) { L.a_k0 = tid % BK; L.a_m0 = tid / BK; }
+  else { L.a_m0 = tid % BM; L.a_k0 = tid / BM; }
+  L.b_nfast = (g.bn.s_lo == 1);
+  if (L.b_nfast) { L.b_n0 = tid % BN; L.b_k0 = tid / BN; }
+  else { L.b_k0 = tid % BK; L.b_n0 = tid / BK; }
+  __syncthreads();
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ void store_c(const GemmArgs& g, int tm, int tn, long long c_off,
+                                        const double (&acc)[Tiles<BM, BN>::TM][Tiles<BM, BN>::TN][4],
+                                        int wm0, int wn0, bool f64_layout) {
+  using T = Tiles<BM, BN>;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = f64_layout ? (4 * r + lane / 16) : (4 * (lane / 16) + r);
+      const int m = tm * BM + wm0 + i * 16 + row;
+      if (m >= g.M) continue;
+      const long long mo = c_off + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * acc[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 kernel
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  using T = Tiles<BM, BN>;
+  __shared__ double As[2][BK * T::LA];
+  __shared__ double Bs[2][BK * T::LB];
+  __shared__ long long rowA[BM], colB[BN];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int b = blockIdx.z;
+  const double* A = (const double*)g.A;
+  const double* B = (const double*)g.B;
+  Loader<BM, BN> L;
+  init_loader<BM, BN>(g, tm, tn, (long long)b * g.a_batch, (long long)b * g.b_batch, rowA, colB, L);
+
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  d4 acc[T::TM][T::TN];
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[T::EA], rb[T::EB];
+  const int nk = (g.K + BK - 1) / BK;
+  load_tile<BM, BN>(g, A, B, L, 0, ra, rb);
+  store_tile<BM, BN, double>(L, ra, rb, As[0], Bs[0]);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_tile<BM, BN>(g, A, B, L, (kt + 1) * BK, ra, rb);
+    const double* as = As[cur];
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double af[T::TM], bf[T::TN];
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i) af[i] = as[kr * T::LA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j) bf[j] = bs[kr * T::LB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_tile<BM, BN, double>(L, ra, rb, As[cur ^ 1], Bs[cur ^ 1]);
+    __syncthreads();
+  }
+  double out[T::TM][T::TN][4];
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = acc[i][j][r];
+  store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, true);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 kernel (operands rounded to FP32, FP64 flush per K tile)
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 1) void gemm_f32_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  using T = Tiles<BM, BN>;
+  __shared__ float As[2][BK * T::LA];
+  __shared__ float Bs[2][BK * T::LB];
+  __shared__ long long rowA[BM], colB[BN];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int b = blockIdx.z;
+  const double* A = (const double*)g.A;
+  const double* B = (const double*)g.B;
+  Loader<BM, BN> L;
+  init_loader<BM, BN>(g, tm, tn, (long long)b * g.a_batch, (long long)b * g.b_batch, rowA, colB, L);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  double out[T::TM][T::TN][4];
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  double ra[T::EA], rb[T::EB];
+  const int nk = (g.K + BK - 1) / BK;
+  load_tile<BM, BN>(g, A, B, L, 0, ra, rb);
+  store_tile<BM, BN, float>(L, ra, rb, As[0], Bs[0]);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load_tile<BM, BN>(g, A, B, L, (kt + 1) * BK, ra, rb);
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+    f4 acc[T::TM][T::TN];
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      float af[T::TM], bf[T::TN];
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i) af[i] = as[kr * T::LA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j) bf[j] = bs[kr * T::LB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    if (kt + 1 < nk) store_tile<BM, BN, float>(L, ra, rb, As[cur ^ 1], Bs[cur ^ 1]);
+    __syncthreads();
+  }
+  store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, false);
+}
+
+// ---------------------------------------------------------------------------
+// split-BF16 kernel: x = hi + lo, A*B ~ Ahi*Bhi + Ahi*Blo + Alo*Bhi
+// K tile of 32 (one bf16 MFMA k-step); LDS holds hi and lo planes k-major in
+// groups of 8 consecutive k per lane.
+// ---------------------------------------------------------------------------
+constexpr int BK16 = 32;
+
+template <int BM, int BN>
+struct TilesB {
+  static constexpr int TM = BM / 32, TN = BN / 32;
+  static constexpr int EA = BM * BK16 / NT, EB = BN * BK16 / NT;
+  // LDS layout: [row][k] with k contiguous (row stride padded) so that a lane
+  // reads its 8 consecutive k values as one 16-byte vector.
+  static constexpr int LK = BK16 + 8;
+};
+
+__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
+  const float xf = (float)x;
+  hi = (__bf16)xf;
+  lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  using T = TilesB<BM, BN>;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * T::LK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * T::LK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN * T::LK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN * T::LK];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int b = blockIdx.z;
+  const double* A = (const double*)g.A;
+  const double* B = (const double*)g.B;
+  const long long a_off = (long long)b * g.a_batch, b_off = (long long)b * g.b_batch;
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int m_base = tm * BM, n_base = tn * BN;
+  // load mappings (single-buffered; this path trades peak speed for simplicity)
+  const bool a_kfast = (g.ak.s_lo == 1);
+  const bool b_nfast = (g.bn.s_lo == 1);
+  double out[T::TM][T::TN][4];
+#pragma unroll
+  for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  const int nk = (g.K + BK16 - 1) / BK16;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int k0 = kt * BK16;
+    // stage A
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      int mm, kk;
+      if (a_kfast) { kk = tid % BK16; mm = tid / BK16 + e * (NT / BK16); }
+      else { mm = tid % BM; kk = tid / BM + e * (NT / BM); }
+      const int m = m_base + mm, k = k0 + kk;
+      const double x = (m < g.M && k < g.K) ? A[a_off + map2(g.am, m) + map2(g.ak, k)] : 0.0;
+      __bf16 h, l;
+      split_bf16(x, h, l);
+      Ah[mm * T::LK + kk] = h;
+      Al[mm * T::LK + kk] = l;
+    }
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      int nn, kk;
+      if (b_nfast) { nn = tid % BN; kk = tid / BN + e * (NT / BN); }
+      else { kk = tid % BK16; nn = tid / BK16 + e * (NT / BK16); }
+      const int n = n_base + nn, k = k0 + kk;
+      const double x = (n < g.N && k < g.K) ? B[b_off + map2(g.bk, k) + map2(g.bn, n)] : 0.0;
+      __bf16 h, l;
+      split_bf16(x, h, l);
+      Bh[nn * T::LK + kk] = h;
+      Bl[nn * T::LK + kk] = l;
+    }
+    __syncthreads();
+    f4 acc[T::TM][T::TN];
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int kq = 8 * (lane / 16);
+    bf8 ah[T::TM], al[T::TM];
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i) {
+      const int row = wm0 + i * 16 + (lane & 15);
+      ah[i] = *(const bf8*)&Ah[row * T::LK + kq];
+      al[i] = *(const bf8*)&Al[row * T::LK + kq];
+    }
+#pragma unroll
+    for (int j = 0; j < T::TN; ++j) {
+      const int col = wn0 + j * 16 + (lane & 15);
+      const bf8 bh = *(const bf8*)&Bh[col * T::LK + kq];
+      const bf8 bl = *(const bf8*)&Bl[col * T::LK + kq];
+#pragma unroll
+      for (int i = 0; i < T::TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    __syncthreads();
+  }
+  store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, false);
+}
+
+template <int BM, int BN>
+hipError_t launch(const GemmArgs& g, Prec prec, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  if (prec == Prec::F64)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
+  else if (prec == Prec::F32)
+    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  const long long nb = g.batch - 1;
+  if (g.a_len > 0 && nb * g.a_batch + idx_max(g.am, g.M) + idx_max(g.ak, g.K) >= g.a_len) return hipErrorInvalidValue;
+  if (g.b_len > 0 && nb * g.b_batch + idx_max(g.bk, g.K) + idx_max(g.bn, g.N) >= g.b_len) return hipErrorInvalidValue;
+  if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  if (g.K <= 0) return g.beta == 1.0 ? hipSuccess : hipErrorInvalidValue;
+  const long long work = (long long)g.M * g.N * g.batch;
+  if (work >= (long long)256 * 128 * 128 * 2) return launch<128, 128>(g, prec, s);
+  return launch<64, 64>(g, prec, s);
+}
+
+}  // namespace cct

@@ -1,0 +1,126 @@
+// Internal declarations shared by the kernels and the host runtime of libcct.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace cct {
+
+// Two-level index map: i -> (i / inner) * s_hi + (i % inner) * s_lo.
+// inner == 0 means one level: i -> i * s_lo.
+struct Idx2 {
+  int inner;
+  long long s_hi, s_lo;
+};
+
+static inline Idx2 idx1(long long s) { return Idx2{0, 0, s}; }
+static inline Idx2 idx2(int inner, long long s_hi, long long s_lo) { return Idx2{inner, s_hi, s_lo}; }
+
+// C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n)
+struct GemmArgs {
+  int M, N, K, batch;
+  const void* A; Idx2 am, ak; long long a_batch;
+  const void* B; Idx2 bk, bn; long long b_batch;
+  double* C; Idx2 cm, cn; long long c_batch;
+  double alpha, beta;
+  // Elements addressable from A, B, C (0 = unchecked).  When set, the host
+  // verifies before launch that every index map stays inside the operand.
+  long long a_len, b_len, c_len;
+};
+
+// Largest offset reached by an index map over [0, n) (non-negative strides).
+static inline long long idx_max(const Idx2& d, long long n) {
+  if (n <= 0) return 0;
+  if (d.inner == 0) return (n - 1) * d.s_lo;
+  const long long hi = (n - 1) / d.inner;
+  long long best = hi * d.s_hi + ((n - 1) % d.inner) * d.s_lo;
+  if (hi >= 1) {
+    const long long alt = (hi - 1) * d.s_hi + (long long)(d.inner - 1) * d.s_lo;
+    if (alt > best) best = alt;
+  }
+  return best;
+}
+
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+
+hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s);
+
+// Y = alpha * X + beta * Y over an index space of up to 6 dimensions.
+struct PermArgs {
+  int nd;
+  long long dim[6];
+  long long sx[6], sy[6];
+  double alpha, beta;
+};
+hipError_t permute_add(const double* X, double* Y, const PermArgs& p, hipStream_t s);
+
+// Location of an unpacked T3 block: t_{pqr}^{u0 u1 u2} = T[off + u0*s0 + u1*s1 + u2*s2].
+struct BlockRef {
+  long long off;
+  int s[3];
+  int pad;
+};
+
+// One term of an unpacked element: coef * t_{occ}^{virt} where occ[m] selects
+// the occupied index at position m (0,1: the slot's fixed indices; 2,3: the
+// free indices) and virt[m] selects which of (x,y,z) sits at position m.
+struct UnpackTerm {
+  double coef;
+  int occ[3];
+  int virt[3];
+};
+
+struct UnpackArgs {
+  int o, v, nslots, nfree;
+  int nterms;
+  UnpackTerm terms[6];
+  long long s_free[2], s_x, s_y, s_z, s_slot;
+};
+// slots: device array of int2 (fixed occupied indices) per slot.
+hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out,
+                     const UnpackArgs& a, hipStream_t s);
+
+// Output-stationary accumulation of temporary Y blocks into packed R3:
+// R[t] (a,b,c) += sum_c coef * Z[base + a*sa + b*sb + c*sc].
+struct FoldContrib {
+  long long base, sa, sb, sc;
+  double coef;
+};
+struct FoldTask {
+  int t, nc, c0, pad;
+};
+hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTask* tasks, int ntasks,
+                   const FoldContrib* contribs, hipStream_t s);
+
+// R3 post-processing, norms and Jacobi update on packed blocks.
+struct PostArgs {
+  int o, v, ntri;
+  long long bs;
+  int do_update;   // 1: T += R / eps
+  int keep_r;      // 1: write post-processed R back
+};
+// tri: device int4 (i,j,k,mult) per packed triple; eps: device [n] orbital energies.
+// partial: device array of per-block partial sums (size >= gridDim used), filled with
+// weighted squared norms; returns the number of partials in *npartial.
+hipError_t post_update(double* R, double* T, const int4* tri, const double* eps, double* partial,
+                       int* npartial, const PostArgs& a, hipStream_t s);
+
+// Deterministic fixed-order sum of n doubles into out[0].
+hipError_t reduce_sum(const double* x, long long n, double* out, double* scratch, hipStream_t s);
+// Deterministic dot product sum_i w(i) x_i y_i with an optional packed-T3 weight.
+hipError_t dot(const double* x, const double* y, long long n, double* out, double* scratch, hipStream_t s);
+hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, int ntri, long long bs, long long v3,
+                           double* out, double* scratch, hipStream_t s);
+// y = a*x + b*y (elementwise, n elements)
+hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s);
+hipError_t fill(double* y, double val, long long n, hipStream_t s);
+// Jacobi update of T1 / T2 with denominators built from eps.
+hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r2, const double* eps, int o, int v,
+                       hipStream_t s);
+// W_diag: add c * F[a][d] on the (b == e) diagonal and c * F[b][e] on (a == d) for a [x][y][x][y] tensor.
+hipError_t add_pair_diag(double* W, const double* F, long long ldF, int nx, double c, hipStream_t s);
+
+}  // namespace cct

@@ -1,0 +1,367 @@
+// Bandwidth-bound kernels around the matrix-core contractions: strided
+// permute/accumulate, T3 unpacking (the paper's on-the-fly reconstruction of
+// off-triangle blocks from stored i<=j<=k blocks, with the spin-summed
+// combinations applied in the same pass), output-stationary folding of
+// contracted blocks into packed R3, the fused R3 post-processing / Jacobi
+// update, and deterministic reductions.
+#include "internal.h"
+
+namespace cct {
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned blocks_for(long long n, int per_block, unsigned cap = 1u << 20) {
+  long long b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------
+// permute / accumulate
+// ---------------------------------------------------------------------------
+__global__ void permute_add_kernel(const double* __restrict__ X, double* __restrict__ Y, PermArgs p, long long total) {
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    long long r = idx, ox = 0, oy = 0;
+    for (int d = p.nd - 1; d >= 0; --d) {
+      const long long c = r % p.dim[d];
+      r /= p.dim[d];
+      ox += c * p.sx[d];
+      oy += c * p.sy[d];
+    }
+    const double x = p.alpha * X[ox];
+    Y[oy] = (p.beta == 0.0) ? x : x + p.beta * Y[oy];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// T3 unpacking
+// ---------------------------------------------------------------------------
+// grid.y enumerates (slot, free indices); grid.x covers the v^3 virtual block.
+__global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __restrict__ tbl,
+                              const int2* __restrict__ slots, double* __restrict__ out, UnpackArgs a) {
+  const int o = a.o, v = a.v;
+  const int nfc = (a.nfree == 2) ? o * o : o;
+  const int sy_ = blockIdx.y;
+  const int slot = sy_ / nfc;
+  const int fc = sy_ - slot * nfc;
+  const int f0 = (a.nfree == 2) ? fc / o : fc;
+  const int f1 = (a.nfree == 2) ? fc - f0 * o : 0;
+  const int2 fx = slots[slot];
+  const int ids[4] = {fx.x, fx.y, f0, f1};
+  // per-term block references
+  const long long v3 = (long long)v * v * v;
+  BlockRef br[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    if (t < a.nterms) {
+      const int p = ids[a.terms[t].occ[0]], q = ids[a.terms[t].occ[1]], r = ids[a.terms[t].occ[2]];
+      br[t] = tbl[((long long)p * o + q) * o + r];
+    }
+  }
+  const long long obase = (long long)slot * a.s_slot + (long long)f0 * a.s_free[0] + (long long)f1 * a.s_free[1];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(e / ((long long)v * v));
+    const int rem = (int)(e - (long long)x * v * v);
+    const int y = rem / v;
+    const int z = rem - y * v;
+    const int xyz[3] = {x, y, z};
+    double val = 0.0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      if (t < a.nterms) {
+        const UnpackTerm& tm = a.terms[t];
+        const long long off = br[t].off + (long long)xyz[tm.virt[0]] * br[t].s[0] +
+                              (long long)xyz[tm.virt[1]] * br[t].s[1] + (long long)xyz[tm.virt[2]] * br[t].s[2];
+        val += tm.coef * T[off];
+      }
+    }
+    out[obase + (long long)x * a.s_x + (long long)y * a.s_y + (long long)z * a.s_z] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fold temporary blocks into packed R3 (one output block per task)
+// ---------------------------------------------------------------------------
+__global__ void fold_kernel(double* __restrict__ R, long long bs, int v, const double* __restrict__ Z,
+                            const FoldTask* __restrict__ tasks, const FoldContrib* __restrict__ contribs) {
+  const FoldTask tk = tasks[blockIdx.y];
+  const long long v3 = (long long)v * v * v;
+  double* Rt = R + (long long)tk.t * bs;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / ((long long)v * v));
+    const int rem = (int)(e - (long long)a * v * v);
+    const int b = rem / v;
+    const int c = rem - b * v;
+    double acc = Rt[e];
+    for (int i = 0; i < tk.nc; ++i) {
+      const FoldContrib fc = contribs[tk.c0 + i];
+      acc += fc.coef * Z[fc.base + (long long)a * fc.sa + (long long)b * fc.sb + (long long)c * fc.sc];
+    }
+    Rt[e] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// R3 post-processing + norm + Jacobi update.  One thread per orbit
+// {(a,b,c) and its permutations} with a <= b <= c.
+// ---------------------------------------------------------------------------
+__global__ void post_update_kernel(double* __restrict__ R, double* __restrict__ T, const int4* __restrict__ tri,
+                                   const double* __restrict__ eps, double* __restrict__ partial, PostArgs pa) {
+  __shared__ double red[TPB];
+  const int t = blockIdx.y;
+  const int4 ijk = tri[t];
+  const int o = pa.o, v = pa.v;
+  const long long v2 = (long long)v * v, v3 = v2 * v;
+  double* Rt = R + (long long)t * pa.bs;
+  double* Tt = T + (long long)t * pa.bs;
+  const bool ij = (ijk.x == ijk.y), jk = (ijk.y == ijk.z);
+  const double eocc = eps[ijk.x] + eps[ijk.y] + eps[ijk.z];
+  double nrm = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / v2);
+    const int rem = (int)(e - (long long)a * v2);
+    const int b = rem / v;
+    const int c = rem - b * v;
+    if (a > b || b > c) continue;
+    // the six placements of (a,b,c): p = 0:(a,b,c) 1:(a,c,b) 2:(b,a,c) 3:(b,c,a) 4:(c,a,b) 5:(c,b,a)
+    const int P[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
+    long long off[6];
+    double r[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      off[p] = (long long)P[p][0] * v2 + (long long)P[p][1] * v + P[p][2];
+      r[p] = Rt[off[p]];
+    }
+    // placement reached by swapping the first two / the last two positions
+    const int sw12[6] = {2, 4, 0, 5, 1, 3};
+    const int sw23[6] = {1, 0, 3, 2, 5, 4};
+    double s[6];
+    if (ij && jk) {
+#pragma unroll
+      for (int p = 0; p < 6; ++p) s[p] = 0.0;
+    } else if (ij) {
+#pragma unroll
+      for (int p = 0; p < 6; ++p) s[p] = 0.5 * (r[p] + r[sw12[p]]);
+    } else if (jk) {
+#pragma unroll
+      for (int p = 0; p < 6; ++p) s[p] = 0.5 * (r[p] + r[sw23[p]]);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 6; ++p) s[p] = r[p];
+    }
+    const double mean = (s[0] + s[1] + s[2] + s[3] + s[4] + s[5]) * (1.0 / 6.0);
+    // distinct placements: p is a duplicate if an earlier placement has the same offset
+    double part = 0.0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      bool dup = false;
+#pragma unroll
+      for (int q = 0; q < p; ++q) dup = dup || (off[q] == off[p]);
+      if (dup) continue;
+      const double x = s[p] - mean;
+      part += x * x;
+      if (pa.keep_r) Rt[off[p]] = x;
+      if (pa.do_update) {
+        const double den = eocc - eps[o + P[p][0]] - eps[o + P[p][1]] - eps[o + P[p][2]];
+        Tt[off[p]] += x / den;
+      }
+    }
+    nrm += part;
+  }
+  red[threadIdx.x] = nrm * (double)ijk.w;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// reductions (fixed grid, fixed order: bitwise reproducible)
+// ---------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  red[threadIdx.x] = x;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__ y, long long n,
+                                   double* __restrict__ part) {
+  __shared__ double red[TPB];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < n; i += (long long)gridDim.x * TPB)
+    acc += x[i] * (y ? y[i] : 1.0);
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void sum_kernel(const double* __restrict__ part, long long n, double* __restrict__ out) {
+  __shared__ double red[TPB];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += TPB) acc += part[i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void dot_t3_partial_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                      const int4* __restrict__ tri, long long bs, long long v3, double* __restrict__ part) {
+  __shared__ double red[TPB];
+  const int t = blockIdx.y;
+  const double* xt = x + (long long)t * bs;
+  const double* yt = y + (long long)t * bs;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < v3; i += (long long)gridDim.x * TPB)
+    acc += xt[i] * yt[i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(long long)t * gridDim.x + blockIdx.x] = s * (double)tri[t].w;
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = val;
+}
+
+__global__ void jacobi_kernel(double* __restrict__ t1, const double* __restrict__ r1, double* __restrict__ t2,
+                              const double* __restrict__ r2, const double* __restrict__ eps, int o, int v) {
+  const long long n1 = (long long)o * v, n2 = n1 * n1;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n1 + n2;
+       idx += (long long)gridDim.x * blockDim.x) {
+    if (idx < n1) {
+      const int i = (int)(idx / v), a = (int)(idx % v);
+      t1[idx] += r1[idx] / (eps[i] - eps[o + a]);
+    } else {
+      const long long k = idx - n1;
+      const int b = (int)(k % v);
+      const int a = (int)((k / v) % v);
+      const int j = (int)((k / ((long long)v * v)) % o);
+      const int i = (int)(k / ((long long)v * v * o));
+      t2[k] += r2[k] / (eps[i] + eps[j] - eps[o + a] - eps[o + b]);
+    }
+  }
+}
+
+// W[x][y][x'][y'] += c F[x][x'] (y == y')   (pass 0)   or   += c F[y][y'] (x == x')   (pass 1)
+__global__ void pair_diag_kernel(double* __restrict__ W, const double* __restrict__ F, long long ldF, int nx, double c,
+                                 int pass) {
+  const long long n3 = (long long)nx * nx * nx;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n3;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int u = (int)(idx / ((long long)nx * nx));
+    const int w = (int)((idx / nx) % nx);
+    const int d = (int)(idx % nx);
+    const long long nx2 = (long long)nx * nx;
+    if (pass == 0) {
+      // x = u, x' = w, y = y' = d
+      W[((long long)u * nx + d) * nx2 + (long long)w * nx + d] += c * F[(long long)u * ldF + w];
+    } else {
+      // y = u, y' = w, x = x' = d
+      W[((long long)d * nx + u) * nx2 + (long long)d * nx + w] += c * F[(long long)u * ldF + w];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t permute_add(const double* X, double* Y, const PermArgs& p, hipStream_t s) {
+  long long total = 1;
+  for (int d = 0; d < p.nd; ++d) total *= p.dim[d];
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(permute_add_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, X, Y, p, total);
+  return hipGetLastError();
+}
+
+hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out, const UnpackArgs& a,
+                     hipStream_t s) {
+  const long long v3 = (long long)a.v * a.v * a.v;
+  const long long ny = (long long)a.nslots * (a.nfree == 2 ? (long long)a.o * a.o : a.o);
+  if (ny <= 0 || v3 <= 0) return hipSuccess;
+  if (ny > 65535) return hipErrorInvalidValue;
+  dim3 grid(blocks_for(v3, TPB * 4, 4096), (unsigned)ny);
+  hipLaunchKernelGGL(unpack_kernel, grid, dim3(TPB), 0, s, T, tbl, slots, out, a);
+  return hipGetLastError();
+}
+
+hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTask* tasks, int ntasks,
+                   const FoldContrib* contribs, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (ntasks > 65535) return hipErrorInvalidValue;
+  const long long v3 = (long long)v * v * v;
+  dim3 grid(blocks_for(v3, TPB * 8, 4096), (unsigned)ntasks);
+  hipLaunchKernelGGL(fold_kernel, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs);
+  return hipGetLastError();
+}
+
+hipError_t post_update(double* R, double* T, const int4* tri, const double* eps, double* partial, int* npartial,
+                       const PostArgs& a, hipStream_t s) {
+  const long long v3 = (long long)a.v * a.v * a.v;
+  const unsigned gx = blocks_for(v3, TPB * 8, 64);
+  if (a.ntri > 65535) return hipErrorInvalidValue;
+  dim3 grid(gx, (unsigned)a.ntri);
+  hipLaunchKernelGGL(post_update_kernel, grid, dim3(TPB), 0, s, R, T, tri, eps, partial, a);
+  *npartial = (int)(gx * a.ntri);
+  return hipGetLastError();
+}
+
+hipError_t reduce_sum(const double* x, long long n, double* out, double* scratch, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(RED_BLOCKS), dim3(TPB), 0, s, x, (const double*)nullptr, n, scratch);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(TPB), 0, s, (const double*)scratch, (long long)RED_BLOCKS, out);
+  return hipGetLastError();
+}
+
+hipError_t dot(const double* x, const double* y, long long n, double* out, double* scratch, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(RED_BLOCKS), dim3(TPB), 0, s, x, y, n, scratch);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(TPB), 0, s, (const double*)scratch, (long long)RED_BLOCKS, out);
+  return hipGetLastError();
+}
+
+hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, int ntri, long long bs, long long v3,
+                           double* out, double* scratch, hipStream_t s) {
+  const unsigned gx = blocks_for(v3, TPB * 16, 16);
+  if (ntri > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dot_t3_partial_kernel, dim3(gx, (unsigned)ntri), dim3(TPB), 0, s, x, y, tri, bs, v3, scratch);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(TPB), 0, s, (const double*)scratch, (long long)gx * ntri, out);
+  return hipGetLastError();
+}
+
+hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t fill(double* y, double val, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, y, val, n);
+  return hipGetLastError();
+}
+
+hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r2, const double* eps, int o, int v,
+                       hipStream_t s) {
+  const long long n = (long long)o * v + (long long)o * o * v * v;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, t1, r1, t2, r2, eps, o, v);
+  return hipGetLastError();
+}
+
+hipError_t add_pair_diag(double* W, const double* F, long long ldF, int nx, double c, hipStream_t s) {
+  const long long n3 = (long long)nx * nx * nx;
+  hipLaunchKernelGGL(pair_diag_kernel, dim3(blocks_for(n3, TPB * 4)), dim3(TPB), 0, s, W, F, ldF, nx, c, 0);
+  hipLaunchKernelGGL(pair_diag_kernel, dim3(blocks_for(n3, TPB * 4)), dim3(TPB), 0, s, W, F, ldF, nx, c, 1);
+  return hipGetLastError();
+}
+
+}  // namespace cct

@@ -1,0 +1,62 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/cct.h, and its host-only entry points behave."""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2607_00981_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "cct.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cct_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = _declared()
+    assert len(names) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (cct_\w+)", out))
+    for name in names:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_packed_index_matches_enumeration():
+    for o in (1, 2, 5, 9):
+        idx = 0
+        for i in range(o):
+            for j in range(i, o):
+                for k in range(j, o):
+                    assert binding.packed_index(o, i, j, k) == idx
+                    idx += 1
+        assert idx == binding.ntri(o)
+    assert binding.packed_index(4, 2, 1, 3) == -1
+    assert binding.packed_index(4, 0, 0, 4) == -1
+    assert binding.packed_index(0, 0, 0, 0) == -1
+
+
+def test_strerror_codes():
+    lib = binding.load()
+    assert lib.cct_strerror(0) == b"ok"
+    assert lib.cct_strerror(-2) == b"out of device memory"
+    assert lib.cct_strerror(-6) == b"not converged"
+    assert lib.cct_strerror(5) == b"unknown error"
+
+
+def test_create_rejects_bad_arguments():
+    import ctypes as C
+    lib = binding.load()
+    h = C.c_void_p()
+    assert lib.cct_create(0, 10, 10, 0, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 7, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "bogus"}', None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, None, None, None) == binding.CCT_EINVAL
+    lib.cct_destroy(None)

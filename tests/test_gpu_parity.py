@@ -1,0 +1,143 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Inputs come from cct_inputs (seeded); expected values from oracle/ only.
+Tolerances: FP64 residuals agree to 1e-11 relative to the largest residual
+element (roundoff of a few-thousand-term sums is ~1e-14 relative); energies
+after 20 iterations to 1e-10 Eh.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import cct_inputs as ci
+from oracle import rccsdt as R
+from paper_2607_00981_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _system(o, v, seed, sigma=0.1, nondiag=True):
+    s = ci.make_system(o, v, 2 * (o + v), seed, sigma=sigma)
+    f = ci.random_fock(o, v, seed) if nondiag else s["f"]
+    return f, s["B"]
+
+
+def _amps(o, v, seed, s3=0.02):
+    t1, t2, _ = ci.random_amplitudes(o, v, seed, 0.02, 0.03, 0.0, triples=False)
+    t3p = ci.random_t3_packed(o, v, seed + 100, s3)
+    return t1, t2, t3p
+
+
+def _engine(o, v, naux, f, B, **kw):
+    eng = binding.Engine(o, v, naux, **kw)
+    eng.set_fock(f)
+    eng.set_eri_df(B)
+    return eng
+
+
+def _oracle_residual(f, B, o, t1, t2, t3p, terms=None):
+    V = R.eri_phys_from_B(B)
+    t3 = R.unpack_t3(t3p, o)
+    r1, r2, r3 = R.residuals(f, V, t1, t2, t3, o, terms=terms)
+    return r1, r2, R.pack_t3(R.postprocess_r3(r3))
+
+
+def _close(a, b, rel=1e-11):
+    scale = max(1.0, float(np.abs(b).max()))
+    err = float(np.abs(a - b).max())
+    return err <= rel * scale, err, scale
+
+
+@pytest.mark.parametrize("term", R.R3_TERMS)
+def test_each_r3_term_matches_oracle(term):
+    o, v, seed = 3, 7, 31
+    say(f"[term parity] term={term} o={o} v={v} seed={seed}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p, terms=(term,))
+    with _engine(o, v, B.shape[0], f, B) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, _ = eng.residual([term])
+    for name, a, b in (("R1", g1, e1), ("R2", g2, e2), ("R3", g3, e3)):
+        ok, err, scale = _close(a, b)
+        assert ok, f"{name} term {term}: max err {err:.3e} (scale {scale:.3e})"
+    assert np.abs(e3).max() > 1e-6
+
+
+@pytest.mark.parametrize("o,v,seed", [(1, 5, 3), (2, 3, 4), (3, 9, 5), (4, 20, 6), (5, 11, 7)])
+def test_full_residual_matches_oracle(o, v, seed):
+    say(f"[full parity] o={o} v={v} seed={seed}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
+    with _engine(o, v, B.shape[0], f, B) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, nr = eng.residual()
+    for name, a, b in (("R1", g1, e1), ("R2", g2, e2), ("R3", g3, e3)):
+        ok, err, scale = _close(a, b)
+        assert ok, f"{name}: max err {err:.3e} (scale {scale:.3e})"
+    w = np.array([R.multiplicity(*t) for t in R.packed_list(o)], dtype=float)
+    n3 = float(np.sum(w[:, None, None, None] * e3 * e3))
+    assert abs(nr[2] - n3) <= 1e-10 * max(1.0, n3)
+    assert abs(nr[0] - np.sum(e1 * e1)) <= 1e-10 * max(1.0, np.sum(e1 * e1))
+
+
+def test_mp2_guess_energy_anchor():
+    o, v, naux, seed = ci.CONFIGS["o4v20"]
+    say("[mp2 anchor]")
+    s = ci.make_system(o, v, naux, seed)
+    with _engine(o, v, naux, s["f"], s["B"]) as eng:
+        eng.init_mp2()
+        e = eng.energy()
+    V = R.eri_phys_from_B(s["B"])
+    t1, t2, _ = R.mp2_guess(s["f"], V, o)
+    assert abs(e - R.energy(s["f"], V, t1, t2, o)) < 1e-12
+
+
+def test_residual_is_bitwise_deterministic():
+    o, v, seed = 4, 13, 9
+    say("[determinism]")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    with _engine(o, v, B.shape[0], f, B) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        a = eng.residual()
+        b = eng.residual()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("diis", [True, False])
+def test_twenty_iterations_o4v20(diis):
+    """Twenty iterations from the MP2 guess on the o=4, v=20 workload (seed 1):
+    GPU energy after every iteration within 1e-10 Eh of the oracle."""
+    o, v, naux, seed = ci.CONFIGS["o4v20"]
+    niter = 20 if diis else 8
+    say(f"[iterations] diis={diis} niter={niter}")
+    s = ci.make_system(o, v, naux, seed)
+    f, B = s["f"], s["B"]
+    V = R.eri_phys_from_B(B)
+    t1, t2, t3 = R.mp2_guess(f, V, o)
+    d = R.DIIS() if diis else None
+    ref = []
+    for _ in range(niter):
+        t1, t2, t3, e, _ = R.iterate(f, V, t1, t2, t3, o, diis=d)
+        ref.append(e)
+    opts = {"diis": diis}
+    with _engine(o, v, naux, f, B, opts=opts) as eng:
+        eng.init_mp2()
+        got = []
+        for it in range(niter):
+            e, nr = eng.update()
+            got.append(e)
+            say(f"  it {it+1}: gpu {e:.14f} oracle {ref[it]:.14f} diff {e-ref[it]:.2e}")
+        g1, g2, g3 = eng.get_amplitudes()
+    assert np.max(np.abs(np.array(got) - np.array(ref))) < 1e-10
+    assert np.abs(g3 - R.pack_t3(t3)).max() < 1e-9
