@@ -154,3 +154,71 @@ def t3_block(v: int, seed: int, idx: int, ijk: tuple[int, int, int], scale: floa
     if j == k:
         return 0.5 * (g + g.transpose(0, 2, 1))
     return g
+
+
+# ---------------------------------------------------------------------------
+# Counter-based T3 for large sizes
+# ---------------------------------------------------------------------------
+# Element (block idx, flat offset e) of the packed T3 is a function of its
+# global counter c = idx * v^3 + e alone: the SplitMix64 output function
+# (Steele, Lea and Flood, OOPSLA 2014) applied to c and the seed gives a
+# 64-bit word whose top 53 bits make a uniform double u in [0, 1); the value
+# is scale * (2u - 1).  Any block can therefore be produced independently and
+# in parallel, and a host can regenerate just the blocks it needs.
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _splitmix_uniform(counter: np.ndarray, seed: int) -> np.ndarray:
+    z = counter + np.uint64(1)
+    with np.errstate(over="ignore"):
+        np.multiply(z, _GOLDEN, out=z)
+        np.add(z, np.uint64((seed * 0xD1B54A32D192ED03) % (1 << 64)), out=z)
+        np.bitwise_xor(z, z >> np.uint64(30), out=z)
+        np.multiply(z, _M1, out=z)
+        np.bitwise_xor(z, z >> np.uint64(27), out=z)
+        np.multiply(z, _M2, out=z)
+        np.bitwise_xor(z, z >> np.uint64(31), out=z)
+    np.right_shift(z, np.uint64(11), out=z)
+    return z.view(np.int64).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def hashed_t3_block(v: int, seed: int, idx: int, ijk: tuple[int, int, int], scale: float = 0.01) -> np.ndarray:
+    """Block idx = (i,j,k) of the counter-based packed T3, with the symmetry
+    that equal occupied indices force (as in :func:`t3_block`)."""
+    i, j, k = ijk
+    v3 = v * v * v
+    cnt = np.arange(v3, dtype=np.uint64) + np.uint64(idx * v3)
+    g = (scale * (2.0 * _splitmix_uniform(cnt, seed) - 1.0)).reshape(v, v, v)
+    if i == j == k:
+        s = np.zeros_like(g)
+        for p in _col_perms(3):
+            s += g.transpose(p)
+        s /= 6.0
+        a, b, c = np.meshgrid(np.arange(v), np.arange(v), np.arange(v), indexing="ij")
+        srt = np.sort(np.stack([a, b, c]), axis=0)
+        return s[srt[0], srt[1], srt[2]]
+    if i == j:
+        return 0.5 * (g + g.transpose(1, 0, 2))
+    if j == k:
+        return 0.5 * (g + g.transpose(0, 2, 1))
+    return g
+
+
+def hashed_t3_packed(o: int, v: int, seed: int, scale: float = 0.01, out: np.ndarray | None = None,
+                     threads: int = 8) -> np.ndarray:
+    """Whole counter-based packed T3 (ntri, v, v, v), blocks filled in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    tri = packed_triples(o)
+    if out is None:
+        out = np.empty((len(tri), v, v, v))
+
+    def work(n):
+        out[n] = hashed_t3_block(v, seed, n, tri[n], scale)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        list(ex.map(work, range(len(tri))))
+    return out

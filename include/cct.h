@@ -82,8 +82,11 @@ typedef struct cct_ctx cct_ctx;
 /* Create a context for o occupied / v virtual orbitals and naux fitting
  * functions.  opts_json may be NULL or a JSON object with integer/string
  * fields: "diis_space" (default 8), "diis_start" (default 2), "diis_t3"
- * ("full" | "none", default "full"), "workspace_gb" (scratch budget, default
- * 16).  hip_stream: a hipStream_t or NULL.  The memory plan is checked
+ * ("full" | "none", default "full"), "diis" (true/false, default true),
+ * "workspace_gb" (cap on the scratch buffer; default: enough for every
+ * unpacked slab in one batch, limited by free device memory), "timers"
+ * (true: per-phase device times for cct_get_counters).  hip_stream: a
+ * hipStream_t or NULL.  The memory plan is checked
  * against free device memory here; CCT_ENOMEM if it does not fit. */
 int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json,
                void* hip_stream, cct_ctx** out);

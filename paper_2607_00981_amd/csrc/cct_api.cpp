@@ -62,7 +62,7 @@ struct cct_ctx {
   hipStream_t s = nullptr;
   int diis_space = 8, diis_start = 2;
   bool diis_on = true, diis_t3 = true;
-  double ws_gb = 16.0;
+  double ws_gb = 0.0;  // 0: size the workspace from free device memory
   std::string err;
   bool have_f = false, have_B = false, have_res = false;
 
@@ -322,8 +322,8 @@ int build_plans(cct_ctx* ctx) {
   std::vector<int4> tri;
   std::vector<BlockRef> tbl;
   build_tables(o, v, tbl, tri);
-  // scratch left for the planner's operand copies and unpacking of one slot
-  const long long budget = (long long)(ctx->ws.capacity() / sizeof(double)) - 4 * ov3 - 4 * o2v3;
+  // scratch left after the planner's operand copies (at most a few o*v^3 blocks)
+  const long long budget = (long long)(ctx->ws.capacity() / sizeof(double)) - 4 * ov3 - (1 << 20);
   if (budget < 2 * o2v3) {
     ctx->err = "workspace too small for one unpacked slab";
     return CCT_ENOMEM;
@@ -1202,7 +1202,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (json_find(js, "diis", val)) ctx->diis_on = (val != "false" && val != "0" && val != "off");
     if (json_find(js, "workspace_gb", val)) ctx->ws_gb = std::atof(val.c_str());
     if (json_find(js, "timers", val)) ctx->events = (val == "true" || val == "1");
-    if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb <= 0) {
+    if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb < 0) {
       delete ctx;
       return CCT_EINVAL;
     }
@@ -1222,9 +1222,8 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   fixed += (long long)(2 * M + 1) * dlen;
   // workspace: enough for every job in one batch (two unpacked/contracted
   // slabs per slot, o^2 slots for the rings), capped by the option
-  const long long need_ws = 4 * (long long)o * v3 + 4 * o2v3 + 2 * o2v3 * o + 1024;
-  long long ws_doubles = std::min<long long>(need_ws, (long long)(ctx->ws_gb * 1e9 / 8.0));
-  ws_doubles = std::max<long long>(ws_doubles, 4 * (long long)o * v3 + 6 * o2v3 + 1024);
+  const long long ws_min = 4 * (long long)o * v3 + 2 * o2v3 + (1 << 20);
+  const long long need_ws = 4 * (long long)o * v3 + 2 * o2v3 * o + (1 << 20);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     ctx->err = "hipMemGetInfo failed (no HIP device?)";
@@ -1232,6 +1231,13 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     delete ctx;
     return CCT_EDEVICE;
   }
+  // workspace: everything in one batch if it fits, else what is left of the
+  // device after the fixed allocations (minus a margin), capped by the option
+  const double margin = 2e9;
+  const long long avail = (long long)(((double)free_b - (double)fixed * 8.0 - margin) / 8.0);
+  long long ws_doubles = std::min<long long>(need_ws, avail);
+  if (ctx->ws_gb > 0) ws_doubles = std::min<long long>(ws_doubles, (long long)(ctx->ws_gb * 1e9 / 8.0));
+  ws_doubles = std::max<long long>(ws_doubles, ws_min);
   const double need_b = (double)(fixed + ws_doubles) * 8.0 + 64e6;
   if (need_b > (double)free_b) {
     delete ctx;

@@ -267,3 +267,35 @@ def test_mac_counts_reduce_to_paper_leading_terms():
     assert abs(exact / lead - 1.0) < 0.02
     assert counts.r3_macs_total(4, 20) == 387840000
     assert abs(counts.r3_macs_total(20, 180) - 1.288e15) / 1.288e15 < 1e-3
+
+
+def test_block_oracle_matches_full_oracle_pp():
+    """oracle.blocks (used where the full tensor does not fit) reproduces the
+    full-tensor oracle's particle-particle ladder block by block."""
+    from oracle import blocks
+
+    o, v, seed = 3, 5, 17
+    s = ci.make_system(o, v, 2 * (o + v), seed, sigma=0.1)
+    f = ci.random_fock(o, v, seed)
+    V = R.eri_phys_from_B(s["B"])
+    t1, t2, _ = ci.random_amplitudes(o, v, seed, 0.03, 0.03, 0.0, triples=False)
+    t3p = ci.hashed_t3_packed(o, v, seed, 0.02, threads=2)
+    ref = R.pack_t3(R.postprocess_r3(R.residuals(f, V, t1, t2, R.unpack_t3(t3p, o), o, terms=("PP",))[2]))
+    W = blocks.w_vvvv(blocks.dressed_factors(s["B"], t1), t2, o)
+    for n, ijk in enumerate(ci.packed_triples(o)):
+        got = blocks.postprocess_block(blocks.pp_block(W, t3p[n], ijk), ijk)
+        assert np.abs(got - ref[n]).max() < 1e-15
+
+
+def test_hashed_t3_symmetry_and_determinism():
+    o, v = 3, 6
+    a = ci.hashed_t3_packed(o, v, 5, threads=3)
+    b = ci.hashed_t3_packed(o, v, 5, threads=1)
+    assert np.array_equal(a, b)
+    for idx, (i, j, k) in enumerate(ci.packed_triples(o)):
+        blk = a[idx]
+        if i == j:
+            assert np.array_equal(blk, blk.transpose(1, 0, 2))
+        if j == k:
+            assert np.array_equal(blk, blk.transpose(0, 2, 1))
+    assert abs(a.std() - 0.01 / np.sqrt(3)) < 2e-3
