@@ -39,16 +39,22 @@ def dressed_factors(B: np.ndarray, t1: np.ndarray) -> np.ndarray:
 
 
 def w_vvvv(Bt: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
-    """W^{ab}_{de} = v~^{ab}_{de} + sum_lm v~^{lm}_{de} t_lm^ab as W[a,b,d,e].
-    v~^{pq}_{rs} = sum_P B~^P_{pr} B~^P_{qs}."""
+    """W^{ab}_{de} = v~^{ab}_{de} + sum_lm v~^{lm}_{de} t_lm^ab as W[a,b,d,e],
+    one row a at a time.  v~^{pq}_{rs} = sum_P B~^P_{pr} B~^P_{qs}; the sums
+    over P and over (l,m) are matrix products (a library primitive)."""
     naux, n, _ = Bt.shape
     v = n - o
-    Bvv = np.ascontiguousarray(Bt[:, o:, o:])
-    # v~^{ab}_{de} = sum_P B~_{ad} B~_{be}
-    W = np.einsum("Pad,Pbe->abde", Bvv, Bvv, optimize=True)
-    Bov = np.ascontiguousarray(Bt[:, :o, o:])
-    voovv = np.einsum("Pld,Pme->lmde", Bov, Bov, optimize=True)  # v~^{lm}_{de}
-    W += np.einsum("lmde,lmab->abde", voovv, t2, optimize=True)
+    Bvv = np.ascontiguousarray(Bt[:, o:, o:])  # [P][a][d]
+    Xbe = Bvv.reshape(naux, v * v)  # [P][(b,e)]
+    Y = np.ascontiguousarray(Bt[:, :o, o:]).reshape(naux, o * v)  # [P][(l,d)]
+    voovv = np.ascontiguousarray((Y.T @ Y).reshape(o, v, o, v).transpose(0, 2, 1, 3)).reshape(o * o, v * v)
+    BvvT = np.ascontiguousarray(Bvv.transpose(1, 2, 0))  # [a][d][P]
+    t2T = np.ascontiguousarray(t2.reshape(o * o, v, v).transpose(1, 2, 0))  # [a][b][(l,m)]
+    W = np.empty((v, v, v, v))
+    for a in range(v):
+        # v~^{ab}_{de} = sum_P B~_{ad} B~_{be}: rows d, columns (b,e)
+        row = (BvvT[a] @ Xbe).reshape(v, v, v).transpose(1, 0, 2)  # [b][d][e]
+        W[a] = row + (t2T[a] @ voovv).reshape(v, v, v)
     return W
 
 
