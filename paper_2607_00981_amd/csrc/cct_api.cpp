@@ -91,7 +91,7 @@ struct cct_ctx {
   char* wsbuf = nullptr;
   Arena ws;
   // plans
-  Job ring[3], hh, d1, d2, feed1, feed12;
+  Job ring[3], hh, d1, d2, feed1;
   // DIIS
   std::vector<double*> dvec, derr;
   int diis_n = 0, diis_next = 0;
@@ -323,7 +323,7 @@ int build_plans(cct_ctx* ctx) {
   std::vector<BlockRef> tbl;
   build_tables(o, v, tbl, tri);
   // scratch left after the planner's operand copies (at most a few o*v^3 blocks)
-  const long long budget = (long long)(ctx->ws.capacity() / sizeof(double)) - 4 * ov3 - (1 << 20);
+  const long long budget = (long long)(ctx->ws.capacity() / sizeof(double)) - 6 * ov3 - (1 << 22);
   if (budget < 2 * o2v3) {
     ctx->err = "workspace too small for one unpacked slab";
     return CCT_ENOMEM;
@@ -429,7 +429,7 @@ int build_plans(cct_ctx* ctx) {
     }));
   }
   // ---- feedback unpack batches (no fold)
-  for (Job* J : {&ctx->feed1, &ctx->feed12}) {
+  for (Job* J : {&ctx->feed1}) {
     for (int f = 0; f < o; ++f) J->slots.push_back(int2{f, 0});
     J->nslot_total = o;
     J->per_batch = slots_per_batch(budget, o2v3, o);
@@ -665,38 +665,56 @@ int ccsd_part(cct_ctx* ctx) {
   STCK(contract(ws, s, F, -0.5, Vv(ctx, "ooov"), "mljd", t2, "imda", 1.0, Wvooo, "alij"));
   STCK(contract(ws, s, F, -1.0, Vv(ctx, "ooov"), "mlid", t2, "jmda", 1.0, Wvooo, "alij"));
   STCK(contract(ws, s, F, 1.0, Vv(ctx, "vovv"), "alde", t2, "ijde", 1.0, Wvooo, "alij"));
-  DT Wb1 = dense(ctx->Wb1, {o, v, v, o});  // Wbar^{la}_{di} [l][a][d][i]
-  STCK(accumulate(s, 1.0, Wovvo, "ladi", 0.0, Wb1, "ladi"));
-  STCK(contract(ws, s, F, 0.5, VCoovv, "mled", tau, "miea", 1.0, Wb1, "ladi"));
-  DT Wb2 = dense(ctx->Wb2, {o, v, o, v});  // Wbar^{la}_{id} [l][a][i][d]
-  STCK(accumulate(s, 1.0, Wovov, "laid", 0.0, Wb2, "laid"));
-  STCK(contract(ws, s, F, -0.5, Vv(ctx, "oovv"), "mlde", t2, "imea", 1.0, Wb2, "laid"));
+  // Wbar^{la}_{di} and Wbar^{la}_{id}, both stored [i][a][l][d]: the ring
+  // contractions read them as (i,a) x (l,d) row-major matrices
+  DT Wb1 = dense(ctx->Wb1, {o, v, o, v});
+  STCK(accumulate(s, 1.0, Wovvo, "ladi", 0.0, Wb1, "iald"));
+  STCK(contract(ws, s, F, 0.5, VCoovv, "mled", tau, "miea", 1.0, Wb1, "iald"));
+  DT Wb2 = dense(ctx->Wb2, {o, v, o, v});
+  STCK(accumulate(s, 1.0, Wovov, "laid", 0.0, Wb2, "iald"));
+  STCK(contract(ws, s, F, -0.5, Vv(ctx, "oovv"), "mlde", t2, "imea", 1.0, Wb2, "iald"));
   STCK(contract(ws, s, F, 1.0, Vv(ctx, "oovv"), "lmde", t2, "lmab", 1.0, Wvvvv, "abde"));
   return CCT_OK;
 }
 
-// T3 contributions to R1, R2 and to W^{ab}_{dj}, W^{al}_{ij}.
+// T3 contributions to R1, R2 and to W^{ab}_{dj}, W^{al}_{ij} (RCCSDT
+// appendix).  For each batch of first-column indices f the spin-summed slab
+// U_f[o1][o2][x][y][z] = t~_{f o1 o2}^{xyz} (single check on column 1) is
+// unpacked once and contracted five ways; R1's double check is rebuilt from
+// the same slab: t~_{j'k'i}^{b'c'a} = 2 U_j[k][i][b][c][a] - U_j[k][i][b][a][c].
 int feedback(cct_ctx* ctx) {
   const int o = ctx->o, v = ctx->v, n = ctx->n;
-  const long long v3 = ctx->v3, o2v3 = (long long)o * o * v3;
-  const long long n3 = (long long)n * n * n;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, o2v3 = (long long)o * o * v3;
   hipStream_t s = ctx->s;
   Arena& ws = ctx->ws;
   const Prec F = Prec::F64;
   DT X2 = dense(ctx->X2, {o, o, v, v});
   DT Wt = dense(ctx->Wt, {v, o, v, v});
   DT Wvooo = dense(ctx->Wvooo, {v, o, o, o});
-  // single check on column 1: U_f[o1][o2][x][y][z] = t~_{f o1 o2}^{xyz}
+  const size_t mk0 = ws.mark();
+  // contiguous integral slices, one row per fixed occupied index f
+  double* Vb = ws.alloc((size_t)(o * v3));                 // [k][b][c][d] = v~^{bk}_{cd}
+  double* Vc = ws.alloc((size_t)o * o * o * v);            // [f][j][k][c] = v~^{kf}_{jc}
+  double* Vd = ws.alloc((size_t)o * o * v2);               // [f][d][l][e] = v~^{lf}_{de}
+  double* Ve = ws.alloc((size_t)o * o * v2);               // [f][l][d][e] = v~^{lf}_{de}
+  double* vv = ws.alloc((size_t)o * o * v2);               // [j][k][b][c] = v~^{jk}_{bc}
+  if (!Vb || !Vc || !Vd || !Ve || !vv) { ctx->err = "workspace exhausted (feedback slices)"; return CCT_ENOMEM; }
+  STCK(accumulate(s, 1.0, Vv(ctx, "vovv"), "bkcd", 0.0, dense(Vb, {o, v, v, v}), "kbcd"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "ooov"), "kfjc", 0.0, dense(Vc, {o, o, o, v}), "fjkc"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(Vd, {o, v, o, v}), "fdle"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(Ve, {o, o, v, v}), "flde"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "jkbc", 0.0, dense(vv, {o, o, v, v}), "jkbc"));
   for (const Batch& b : ctx->feed1.batches) {
     const size_t mk = ws.mark();
     double* U = ws.alloc((size_t)(b.nslots * o2v3));
-    if (!U) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
+    double* part = ws.alloc((size_t)b.nslots * o * o * v);
+    if (!U || !part) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
     UnpackArgs ua{};
     ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
     const int occ[3] = {0, 2, 3};
     set_s1(ua, occ);
     ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
-    ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
+    ua.s_x = v2; ua.s_y = v; ua.s_z = 1;
     HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, s));
     // (a) 1/2 f~^k_c t~_{kij}^{cab}: k runs over the batch
     {
@@ -708,37 +726,36 @@ int feedback(cct_ctx* ctx) {
       const int f = b.slot0 + ls;
       DT Uf = dense(U + ls * o2v3, {o, o, v, v, v});
       // (b) sum_cd v~^{bk}_{cd} t~_{kij}^{dac}
-      DT vb = strided(ctx->V + (long long)o * n3 + (long long)o * n * n + (long long)f * n + o, {v, v, v},
-                      {n3, (long long)n * n, 1});
-      STCK(contract(ws, s, F, 1.0, vb, "bcd", Uf, "ijdac", 1.0, X2, "ijab"));
+      STCK(contract(ws, s, F, 1.0, dense(Vb + (long long)f * v3, {v, v, v}), "bcd", Uf, "ijdac", 1.0, X2, "ijab"));
       // (c) - sum_kc v~^{kl}_{jc} t~_{lik}^{cab}
-      DT vc = strided(ctx->V + (long long)f * n + o, {o, o, v}, {n3, (long long)n * n, 1});
-      STCK(contract(ws, s, F, -1.0, vc, "kjc", Uf, "ikcab", 1.0, X2, "ijab"));
+      STCK(contract(ws, s, F, -1.0, dense(Vc + (long long)f * o * o * v, {o, o, v}), "jkc", Uf, "ikcab", 1.0, X2,
+                    "ijab"));
       // (d) W^{ab}_{dj} -= sum_le v~^{lm}_{de} t~_{mjl}^{eba}
-      DT vd = strided(ctx->V + (long long)o * n * n + (long long)f * n + o, {o, v, v}, {n3, (long long)n * n, 1});
-      STCK(contract(ws, s, F, -1.0, vd, "lde", Uf, "jleba", 1.0, Wt, "djba"));
+      STCK(contract(ws, s, F, -1.0, dense(Vd + (long long)f * o * v2, {v, o, v}), "dle", Uf, "jleba", 1.0, Wt,
+                    "djba"));
       // (e) W^{al}_{ij} += sum_de v~^{lm}_{de} t~_{mij}^{ead}
-      STCK(contract(ws, s, F, 1.0, vd, "lde", Uf, "ijead", 1.0, Wvooo, "alij"));
+      STCK(contract(ws, s, F, 1.0, dense(Ve + (long long)f * o * v2, {o, v, v}), "lde", Uf, "ijead", 1.0, Wvooo,
+                    "alij"));
+    }
+    // R1 += 1/2 sum_jkbc v~^{jk}_{bc} (2 U_j[k][i][b][c][a] - U_j[k][i][b][a][c]), as partial sums
+    // over (j,k) pairs: part[(j,k)][(i,a)]
+    {
+      GemmArgs g{};
+      g.M = 1; g.N = o * v; g.K = (int)v2; g.batch = b.nslots * o;
+      g.A = vv + (long long)b.slot0 * o * v2; g.am = idx1(0); g.ak = idx1(1); g.a_batch = v2;
+      g.B = U; g.bk = idx1(v); g.bn = idx2(v, v3, 1); g.b_batch = (long long)o * v3;
+      g.C = part; g.cm = idx1(0); g.cn = idx1(1); g.c_batch = (long long)o * v;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = (long long)(o - b.slot0) * o * v2; g.b_len = b.nslots * o2v3; g.c_len = (long long)b.nslots * o * o * v;
+      HIPCK(gemm(g, F, s));
+      g.bk = idx2(v, v2, 1); g.bn = idx2(v, v3, v);
+      g.alpha = -0.5; g.beta = 1.0;
+      HIPCK(gemm(g, F, s));
+      HIPCK(add_rows(part, b.nslots * o, (long long)o * v, ctx->r1, s));
     }
     ws.reset(mk);
   }
-  // double check on columns 1,2: U'_f[j][k][b][c][a] = t~_{j' k' f}^{b' c' a}
-  for (const Batch& b : ctx->feed12.batches) {
-    const size_t mk = ws.mark();
-    double* U = ws.alloc((size_t)(b.nslots * o2v3));
-    if (!U) { ctx->err = "workspace exhausted (feedback S12)"; return CCT_ENOMEM; }
-    UnpackArgs ua{};
-    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
-    const int occ[3] = {2, 3, 0};
-    set_s12(ua, occ);
-    ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
-    ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
-    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, s));
-    DT Ub = dense(U, {b.nslots, o, o, v, v, v});
-    DT r1b = strided(ctx->r1 + (long long)b.slot0 * v, {b.nslots, v}, {v, 1});
-    STCK(contract(ws, s, F, 0.5, Vv(ctx, "oovv"), "jkbc", Ub, "fjkbca", 1.0, r1b, "fa"));
-    ws.reset(mk);
-  }
+  ws.reset(mk0);
   return CCT_OK;
 }
 
@@ -816,11 +833,9 @@ int r3_rings(cct_ctx* ctx, int kind) {
     HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
     GemmArgs g{};
     g.M = o * v; g.N = (int)v2; g.K = o * v; g.batch = b.nslots;
-    if (kind == 0) {  // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} = Wb1[l][x][d][p]
-      g.A = ctx->Wb1; g.am = idx2(v, 1, (long long)v * o); g.ak = idx2(v, v2 * o, o);
-    } else {          // A[(p,x)][(l,d)] = Wbar^{lx}_{pd} = Wb2[l][x][p][d]
-      g.A = ctx->Wb2; g.am = idx2(v, v, (long long)o * v); g.ak = idx2(v, v2 * o, 1);
-    }
+    // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
+    g.A = kind == 0 ? ctx->Wb1 : ctx->Wb2;
+    g.am = idx1((long long)o * v); g.ak = idx1(1);
     g.a_batch = 0;
     g.B = U; g.bk = idx1(v2); g.bn = idx1(1); g.b_batch = ov3;
     g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
@@ -1222,8 +1237,8 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   fixed += (long long)(2 * M + 1) * dlen;
   // workspace: enough for every job in one batch (two unpacked/contracted
   // slabs per slot, o^2 slots for the rings), capped by the option
-  const long long ws_min = 4 * (long long)o * v3 + 2 * o2v3 + (1 << 20);
-  const long long need_ws = 4 * (long long)o * v3 + 2 * o2v3 * o + (1 << 20);
+  const long long ws_min = 6 * (long long)o * v3 + 2 * o2v3 + (1 << 22);
+  const long long need_ws = 6 * (long long)o * v3 + 2 * o2v3 * o + (1 << 22);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     ctx->err = "hipMemGetInfo failed (no HIP device?)";

@@ -117,6 +117,8 @@ hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, in
 // y = a*x + b*y (elementwise, n elements)
 hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s);
 hipError_t fill(double* y, double val, long long n, hipStream_t s);
+// out[i] += sum_r in[r * n + i] for r = 0..rows-1 (fixed order).
+hipError_t add_rows(const double* in, int rows, long long n, double* out, hipStream_t s);
 // Jacobi update of T1 / T2 with denominators built from eps.
 hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r2, const double* eps, int o, int v,
                        hipStream_t s);

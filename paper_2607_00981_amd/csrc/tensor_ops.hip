@@ -236,6 +236,14 @@ __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
     y[i] = val;
 }
 
+__global__ void add_rows_kernel(const double* __restrict__ in, int rows, long long n, double* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double acc = out[i];
+    for (int r = 0; r < rows; ++r) acc += in[(long long)r * n + i];
+    out[i] = acc;
+  }
+}
+
 __global__ void jacobi_kernel(double* __restrict__ t1, const double* __restrict__ r1, double* __restrict__ t2,
                               const double* __restrict__ r2, const double* __restrict__ eps, int o, int v) {
   const long long n1 = (long long)o * v, n2 = n1 * n1;
@@ -347,6 +355,12 @@ hipError_t axpby(double a, const double* x, double b, double* y, long long n, hi
 hipError_t fill(double* y, double val, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, y, val, n);
+  return hipGetLastError();
+}
+
+hipError_t add_rows(const double* in, int rows, long long n, double* out, hipStream_t s) {
+  if (n <= 0 || rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_rows_kernel, dim3(blocks_for(n, TPB)), dim3(TPB), 0, s, in, rows, n, out);
   return hipGetLastError();
 }
 
