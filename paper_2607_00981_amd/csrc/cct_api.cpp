@@ -759,26 +759,72 @@ int feedback(cct_ctx* ctx) {
   return CCT_OK;
 }
 
+// Particle-particle ladder by direct traversal of the stored blocks (paper,
+// Sec. "RCCSDT contractions without unpacking"): for each stored (i,j,k)
+//   R[abc] += sum_de W^{ab}_{de} t^{dec} + W^{ac}_{de} t^{dbe} + W^{bc}_{de} t^{ade},
+// i.e. three GEMMs over all blocks at once with M = (block, free virtual),
+// N = (two output virtuals), K = (d,e), W shared.  In FP64 each term reads a
+// K-contiguous copy of T3 (term 3 reads T3 itself; terms 2 and 1 a copy with
+// the block axes swapped or rotated) through the NT matrix-core kernel.
 int r3_pp(cct_ctx* ctx) {
   const int v = ctx->v;
-  const long long v2 = (long long)v * v, v3 = ctx->v3;
-  const int M = (int)(ctx->ntri * v);
-  // term 3: R[t][x][y][z] += sum_de T[t][x][d][e] W[y][z][d][e]
-  // term 2: R[t][y][x][z] += sum_de T[t][d][x][e] W[y][z][d][e]
-  // term 1: R[t][y][z][x] += sum_de T[t][d][e][x] W[y][z][d][e]
-  const Idx2 am[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
-  const Idx2 ak[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
+  const long long v2 = (long long)v * v, v3 = ctx->v3, nt = ctx->ntri;
+  const int M = (int)(nt * v);
+  // output maps of the three terms: C[(t,x)][(y,z)] -> R[t][..]
+  const Idx2 cm[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
   const Idx2 cn[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
-  for (int term = 0; term < 3; ++term) {
-    GemmArgs g{};
-    g.M = M; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
-    g.A = ctx->t3; g.am = am[term]; g.ak = ak[term];
-    g.B = ctx->Wvvvv; g.bk = idx1(1); g.bn = idx1(v2);
-    g.C = ctx->r3; g.cm = am[term]; g.cn = cn[term];
-    g.alpha = 1.0; g.beta = 1.0;
-    g.a_len = ctx->ntri * v3; g.b_len = v2 * v2; g.c_len = ctx->ntri * v3;
-    HIPCK(gemm(g, ctx->prec, ctx->s));
+  if (ctx->prec != Prec::F64 || (v2 & 1)) {
+    // generic strided kernel reading T3 in place
+    const Idx2 am[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
+    const Idx2 ak[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
+    for (int term = 0; term < 3; ++term) {
+      GemmArgs g{};
+      g.M = M; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+      g.A = ctx->t3; g.am = am[term]; g.ak = ak[term];
+      g.B = ctx->Wvvvv; g.bk = idx1(1); g.bn = idx1(v2);
+      g.C = ctx->r3; g.cm = cm[term]; g.cn = cn[term];
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = nt * v3; g.b_len = v2 * v2; g.c_len = nt * v3;
+      HIPCK(gemm(g, ctx->prec, ctx->s));
+    }
+    return CCT_OK;
   }
+  // term 3 straight from T3 ([t][x][(d,e)] is already K-contiguous)
+  {
+    NtArgs g{};
+    g.M = M; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+    g.A = ctx->t3; g.lda = v2;
+    g.B = ctx->Wvvvv; g.ldb = v2;
+    g.C = ctx->r3; g.cm = idx1(v2); g.cn = idx1(1);
+    g.alpha = 1.0; g.beta = 1.0;
+    g.a_len = nt * v3; g.b_len = v2 * v2; g.c_len = nt * v3;
+    HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+  }
+  // terms 2 and 1 from relabelled copies, in chunks of blocks that fit the workspace
+  Arena& ws = ctx->ws;
+  const size_t mk = ws.mark();
+  long long chunk = (long long)(ws.available() / sizeof(double) / (size_t)v3) - 1;
+  if (chunk < 1) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
+  if (chunk > nt) chunk = nt;
+  double* Tc = ws.alloc((size_t)(chunk * v3));
+  if (!Tc) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
+  for (int term = 1; term >= 0; --term) {
+    for (long long t0 = 0; t0 < nt; t0 += chunk) {
+      const long long nb = std::min(chunk, nt - t0);
+      const double* src = ctx->t3 + t0 * v3;
+      if (term == 1) HIPCK(swap01_batched(src, Tc, nb, v, v, v, ctx->s));       // [t][x][d][e] = T[t][d][x][e]
+      else HIPCK(transpose_batched(src, Tc, nb, (int)v2, v, ctx->s));          // [t][x][(d,e)] = T[t][(d,e)][x]
+      NtArgs g{};
+      g.M = (int)(nb * v); g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+      g.A = Tc; g.lda = v2;
+      g.B = ctx->Wvvvv; g.ldb = v2;
+      g.C = ctx->r3 + t0 * v3; g.cm = cm[term]; g.cn = cn[term];
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = nb * v3; g.b_len = v2 * v2; g.c_len = (nt - t0) * v3;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+    }
+  }
+  ws.reset(mk);
   return CCT_OK;
 }
 
@@ -807,10 +853,19 @@ int r3_f1(cct_ctx* ctx) {
   return CCT_OK;
 }
 
+// Rings (paper, Sec. "RCCSDT contractions with unpacking" and the compact
+// ring expansions of the operation-count table).  For a batch of occupied
+// pairs (q,r) the unpacked, spin-combined operand U[(q,r)][(y,z)][(l,d)] is
+// built once; one batched GEMM gives Z[(q,r)][(p,x)][(y,z)] =
+// sum_(l,d) Wbar[(p,x)][(l,d)] U[(q,r)][(y,z)][(l,d)] for every p, and an
+// output-stationary fold adds each Z block into the packed R3 blocks it
+// belongs to with the right virtual permutation and coefficient.
 int r3_rings(cct_ctx* ctx, int kind) {
   const int o = ctx->o, v = ctx->v;
   const long long v2 = (long long)v * v, v3 = ctx->v3, ov3 = o * v3;
+  const long long ov = (long long)o * v;
   Arena& ws = ctx->ws;
+  const bool nt = (ctx->prec == Prec::F64) && !(ov & 1);
   for (const Batch& b : ctx->ring[kind].batches) {
     const size_t mk = ws.mark();
     double* U = ws.alloc((size_t)(b.nslots * ov3));
@@ -818,7 +873,9 @@ int r3_rings(cct_ctx* ctx, int kind) {
     if (!U || !Z) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
     UnpackArgs ua{};
     ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 1;
-    ua.s_slot = ov3; ua.s_free[0] = v3; ua.s_free[1] = 0; ua.s_x = v2; ua.s_y = v; ua.s_z = 1;
+    // U[s][(y,z)][(l,d)]: (x, y, z) of the unpack are (d, y, z); d runs fastest
+    ua.s_slot = ov3; ua.s_free[0] = v; ua.s_free[1] = 0;
+    ua.s_x = 1; ua.s_y = ov * v; ua.s_z = ov; ua.fast = 2;
     if (kind == 0) {
       const int occ[3] = {2, 0, 1};  // S1 t~_{l q r}^{d y z}
       set_s1(ua, occ);
@@ -831,17 +888,27 @@ int r3_rings(cct_ctx* ctx, int kind) {
       set_ident(ua, occ);
     }
     HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
-    GemmArgs g{};
-    g.M = o * v; g.N = (int)v2; g.K = o * v; g.batch = b.nslots;
     // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
-    g.A = kind == 0 ? ctx->Wb1 : ctx->Wb2;
-    g.am = idx1((long long)o * v); g.ak = idx1(1);
-    g.a_batch = 0;
-    g.B = U; g.bk = idx1(v2); g.bn = idx1(1); g.b_batch = ov3;
-    g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
-    g.alpha = 1.0; g.beta = 0.0;
-    g.a_len = (long long)o * o * v2; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
-    HIPCK(gemm(g, ctx->prec, ctx->s));
+    const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
+    if (nt) {
+      NtArgs g{};
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
+      g.A = Aw; g.lda = ov; g.a_batch = 0;
+      g.B = U; g.ldb = ov; g.b_batch = ov3;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+    } else {
+      GemmArgs g{};
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
+      g.A = Aw; g.am = idx1(ov); g.ak = idx1(1); g.a_batch = 0;
+      g.B = U; g.bk = idx1(1); g.bn = idx1(ov); g.b_batch = ov3;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      HIPCK(gemm(g, ctx->prec, ctx->s));
+    }
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }

@@ -474,3 +474,173 @@ hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s) {
 }
 
 }  // namespace cct
+
+// ===========================================================================
+// K-contiguous ("NT") GEMM: both operands are row-major with the contracted
+// index fastest, so a K tile of 16 doubles is one 128-byte line per row.
+// Loads are 16-byte vectors (two doubles), rows outside the matrix are
+// clamped to a valid row and zeroed, and the main loop carries no index
+// arithmetic beyond pointer increments.  Tile BM x BN with WM x WN waves.
+// ===========================================================================
+namespace cct {
+namespace {
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int BM, int BN, int WM, int WN>
+struct NtCfg {
+  static constexpr int NTH = 64 * WM * WN;
+  static constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  static constexpr int LA = BM + 2, LB = BN + 2;
+  static constexpr int SA = BM * (BK / 2) / NTH;  // 16-byte segments of A per thread per K tile
+  static constexpr int SB = BN * (BK / 2) / NTH;
+};
+
+template <int BM, int BN, int WM, int WN, int OCC>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g, int tiles_m, int tiles_n) {
+  using C = NtCfg<BM, BN, WM, WN>;
+  __shared__ double As[2][BK * C::LA];
+  __shared__ double Bs[2][BK * C::LB];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.z;
+  const double* A = g.A + (long long)b * g.a_batch;
+  const double* B = g.B + (long long)b * g.b_batch;
+  // per-thread source rows (clamped) and validity
+  const double* pa[C::SA];
+  const double* pb[C::SB];
+  int ka[C::SA], kb[C::SB];
+  bool va[C::SA], vb[C::SB];
+#pragma unroll
+  for (int i = 0; i < C::SA; ++i) {
+    const int seg = tid + i * C::NTH;
+    const int row = seg / (BK / 2);
+    ka[i] = 2 * (seg % (BK / 2));
+    const int m = tm * BM + row;
+    va[i] = m < g.M;
+    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
+  }
+#pragma unroll
+  for (int i = 0; i < C::SB; ++i) {
+    const int seg = tid + i * C::NTH;
+    const int row = seg / (BK / 2);
+    kb[i] = 2 * (seg % (BK / 2));
+    const int n = tn * BN + row;
+    vb[i] = n < g.N;
+    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+  }
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  d4 acc[C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  dbl2 ra[C::SA], rb[C::SB];
+  const int nk = (g.K + BK - 1) / BK;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < C::SA; ++i) {
+      const bool ok = va[i] && (k0 + ka[i] < g.K);
+      const dbl2 x = *(const dbl2*)(pa[i] + (ok ? k0 : 0));
+      ra[i] = ok ? x : dbl2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int i = 0; i < C::SB; ++i) {
+      const bool ok = vb[i] && (k0 + kb[i] < g.K);
+      const dbl2 x = *(const dbl2*)(pb[i] + (ok ? k0 : 0));
+      rb[i] = ok ? x : dbl2{0.0, 0.0};
+    }
+  };
+  auto store = [&](double* as, double* bs) {
+#pragma unroll
+    for (int i = 0; i < C::SA; ++i) {
+      const int row = (tid + i * C::NTH) / (BK / 2);
+      as[ka[i] * C::LA + row] = ra[i].x;
+      as[(ka[i] + 1) * C::LA + row] = ra[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < C::SB; ++i) {
+      const int row = (tid + i * C::NTH) / (BK / 2);
+      bs[kb[i] * C::LB + row] = rb[i].x;
+      bs[(kb[i] + 1) * C::LB + row] = rb[i].y;
+    }
+  };
+  load(0);
+  store(As[0], Bs[0]);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    const double* as = As[cur];
+    const double* bs = Bs[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double af[C::TM], bf[C::TN];
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i) af[i] = as[kr * C::LA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) bf[j] = bs[kr * C::LB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(As[cur ^ 1], Bs[cur ^ 1]);
+    __syncthreads();
+  }
+  // epilogue: accumulator register r of lane l holds row 4r + l/16, column l%16
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * r + lane / 16;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * acc[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WM, int WN, int OCC>
+hipError_t launch_nt(const NtArgs& g, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_nt_f64_kernel<BM, BN, WM, WN, OCC>), dim3((unsigned)grid_x, 1, (unsigned)g.batch),
+                     dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (prec != Prec::F64) return hipErrorInvalidValue;
+  if (g.K <= 0 || (g.K & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_batch & 1) || (g.b_batch & 1) ||
+      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15))
+    return hipErrorInvalidValue;
+  const long long nb = g.batch - 1;
+  if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
+  if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
+  if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  switch (g.variant) {
+    case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
+    case 2: return launch_nt<256, 128, 4, 2, 2>(g, s);
+    case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);
+    default: return launch_nt<128, 128, 2, 2, 2>(g, s);
+  }
+}
+
+}  // namespace cct

@@ -48,6 +48,21 @@ enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s);
 
+// C[b](m,n) = alpha * sum_k A[b][m*lda + k] * B[b][n*ldb + k] + beta * C[b](m,n):
+// both operands K-contiguous (row-major M x K and N x K), the output through
+// two-level index maps.  Requires K, lda, ldb even and 16-byte aligned A, B
+// (checked; hipErrorInvalidValue otherwise).
+struct NtArgs {
+  int M, N, K, batch;
+  const double* A; long long lda, a_batch;
+  const double* B; long long ldb, b_batch;
+  double* C; Idx2 cm, cn; long long c_batch;
+  double alpha, beta;
+  long long a_len, b_len, c_len;  // bounds for the host check (0 = unchecked)
+  int variant;                    // tile variant (0 = default)
+};
+hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s);
+
 // Y = alpha * X + beta * Y over an index space of up to 6 dimensions.
 struct PermArgs {
   int nd;
@@ -75,6 +90,7 @@ struct UnpackTerm {
 
 struct UnpackArgs {
   int o, v, nslots, nfree;
+  int fast;  // axis running fastest across threads: 0 = z, 1 = y, 2 = x (the output's unit-stride axis)
   int nterms;
   UnpackTerm terms[6];
   long long s_free[2], s_x, s_y, s_z, s_slot;
@@ -82,6 +98,11 @@ struct UnpackArgs {
 // slots: device array of int2 (fixed occupied indices) per slot.
 hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out,
                      const UnpackArgs& a, hipStream_t s);
+
+// out[b][j][i] = in[b][i][j] for a batch of R x C matrices (row-major).
+hipError_t transpose_batched(const double* in, double* out, long long batch, int R, int C, hipStream_t s);
+// out[b][i][j][k] = in[b][j][i][k] for a batch of n0 x n1 x n2 tensors (swap of the two outer axes).
+hipError_t swap01_batched(const double* in, double* out, long long batch, int n0, int n1, int n2, hipStream_t s);
 
 // Output-stationary accumulation of temporary Y blocks into packed R3:
 // R[t] (a,b,c) += sum_c coef * Z[base + a*sa + b*sb + c*sc].

@@ -63,11 +63,16 @@ __global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __re
   }
   const long long obase = (long long)slot * a.s_slot + (long long)f0 * a.s_free[0] + (long long)f1 * a.s_free[1];
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(e / ((long long)v * v));
-    const int rem = (int)(e - (long long)x * v * v);
-    const int y = rem / v;
-    const int z = rem - y * v;
-    const int xyz[3] = {x, y, z};
+    const int i0 = (int)(e / ((long long)v * v));
+    const int rem = (int)(e - (long long)i0 * v * v);
+    const int i1 = rem / v;
+    const int i2 = rem - i1 * v;
+    // i2 runs fastest across threads; it is z (fast 0), y (fast 1) or x (fast 2)
+    int xyz[3];
+    if (a.fast == 0) { xyz[0] = i0; xyz[1] = i1; xyz[2] = i2; }
+    else if (a.fast == 1) { xyz[0] = i0; xyz[2] = i1; xyz[1] = i2; }
+    else { xyz[1] = i0; xyz[2] = i1; xyz[0] = i2; }
+    const int x = xyz[0], y = xyz[1], z = xyz[2];
     double val = 0.0;
 #pragma unroll
     for (int t = 0; t < 6; ++t) {
@@ -236,6 +241,39 @@ __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
     y[i] = val;
 }
 
+// 32 x 32 tiles through LDS: reads and writes both coalesced.
+__global__ void transpose_kernel(const double* __restrict__ in, double* __restrict__ out, int R, int C) {
+  __shared__ double tile[32][33];
+  const long long b = blockIdx.z;
+  const double* src = in + b * (long long)R * C;
+  double* dst = out + b * (long long)R * C;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < R && c < C) tile[k][tx] = src[(long long)r * C + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < R && c < C) dst[(long long)c * R + r] = tile[tx][k];
+  }
+}
+
+__global__ void swap01_kernel(const double* __restrict__ in, double* __restrict__ out, long long rows, int n0, int n1,
+                              int n2) {
+  // one (b, i, j) row of n2 elements per (y, z) block index
+  const long long row = blockIdx.y + (long long)blockIdx.z * 65535;
+  if (row >= rows) return;
+  const long long per = (long long)n0 * n1;
+  const long long b = row / per;
+  const int ij = (int)(row - b * per);
+  const int i = ij / n1, j = ij - i * n1;  // out[b][i][j][:] = in[b][j][i][:]
+  const double* src = in + ((b * n1 + j) * n0 + i) * (long long)n2;
+  double* dst = out + ((b * n0 + i) * n1 + j) * (long long)n2;
+  for (int k = threadIdx.x; k < n2; k += blockDim.x) dst[k] = src[k];
+}
+
 __global__ void add_rows_kernel(const double* __restrict__ in, int rows, long long n, double* __restrict__ out) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     double acc = out[i];
@@ -355,6 +393,28 @@ hipError_t axpby(double a, const double* x, double b, double* y, long long n, hi
 hipError_t fill(double* y, double val, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, y, val, n);
+  return hipGetLastError();
+}
+
+hipError_t transpose_batched(const double* in, double* out, long long batch, int R, int C, hipStream_t s) {
+  if (batch <= 0 || R <= 0 || C <= 0) return hipSuccess;
+  for (long long b0 = 0; b0 < batch; b0 += 65535) {
+    const long long nb = batch - b0 < 65535 ? batch - b0 : 65535;
+    const long long off = b0 * (long long)R * C;
+    dim3 grid((C + 31) / 32, (R + 31) / 32, (unsigned)nb);
+    if (grid.y > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, in + off, out + off, R, C);
+  }
+  return hipGetLastError();
+}
+
+hipError_t swap01_batched(const double* in, double* out, long long batch, int n0, int n1, int n2, hipStream_t s) {
+  const long long rows = batch * n0 * n1;
+  if (rows <= 0 || n2 <= 0) return hipSuccess;
+  const long long gz = (rows + 65534) / 65535;
+  if (gz > 65535) return hipErrorInvalidValue;
+  const unsigned gy = (unsigned)(rows < 65535 ? rows : 65535);
+  hipLaunchKernelGGL(swap01_kernel, dim3(1, gy, (unsigned)gz), dim3(256), 0, s, in, out, rows, n0, n1, n2);
   return hipGetLastError();
 }
 

@@ -55,9 +55,12 @@ def _close(a, b, rel=1e-11):
     return err <= rel * scale, err, scale
 
 
+@pytest.mark.parametrize("shape", [(3, 7, 31), (3, 8, 32)], ids=["odd_v", "even_v"])
 @pytest.mark.parametrize("term", R.R3_TERMS)
-def test_each_r3_term_matches_oracle(term):
-    o, v, seed = 3, 7, 31
+def test_each_r3_term_matches_oracle(term, shape):
+    """Each term group alone; odd v runs the generic strided kernels, even v
+    the K-contiguous matrix-core path."""
+    o, v, seed = shape
     say(f"[term parity] term={term} o={o} v={v} seed={seed}")
     f, B = _system(o, v, seed)
     t1, t2, t3p = _amps(o, v, seed)
