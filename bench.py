@@ -159,7 +159,8 @@ def main():
         "phase_ms": {k: x / args.steps for k, x in phase_ms.items()},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": f"gemm_{'f64' if args.precision == 'fp64' else args.precision}_kernel<128,128> "
+                     "kernel": ("gemm_nt_f64_kernel<128,256> " if args.precision == "fp64" else
+                                f"gemm_{args.precision}_kernel<128,128> ") +
                                "(particle-particle ladder, one of 3 relabelled GEMMs)"},
         "energy": e,
     }

@@ -537,34 +537,36 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
     for (int j = 0; j < C::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  // Raw loads go to registers; masking is applied when they are written to
+  // LDS after the matrix-core work, so the wait for the loads lands there
+  // and not right after the loads are issued.
   dbl2 ra[C::SA], rb[C::SB];
+  bool oa[C::SA], ob[C::SB];
   const int nk = (g.K + BK - 1) / BK;
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < C::SA; ++i) {
-      const bool ok = va[i] && (k0 + ka[i] < g.K);
-      const dbl2 x = *(const dbl2*)(pa[i] + (ok ? k0 : 0));
-      ra[i] = ok ? x : dbl2{0.0, 0.0};
+      oa[i] = va[i] && (k0 + ka[i] < g.K);
+      ra[i] = *(const dbl2*)(pa[i] + (oa[i] ? k0 : 0));
     }
 #pragma unroll
     for (int i = 0; i < C::SB; ++i) {
-      const bool ok = vb[i] && (k0 + kb[i] < g.K);
-      const dbl2 x = *(const dbl2*)(pb[i] + (ok ? k0 : 0));
-      rb[i] = ok ? x : dbl2{0.0, 0.0};
+      ob[i] = vb[i] && (k0 + kb[i] < g.K);
+      rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0));
     }
   };
   auto store = [&](double* as, double* bs) {
 #pragma unroll
     for (int i = 0; i < C::SA; ++i) {
       const int row = (tid + i * C::NTH) / (BK / 2);
-      as[ka[i] * C::LA + row] = ra[i].x;
-      as[(ka[i] + 1) * C::LA + row] = ra[i].y;
+      as[ka[i] * C::LA + row] = oa[i] ? ra[i].x : 0.0;
+      as[(ka[i] + 1) * C::LA + row] = oa[i] ? ra[i].y : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < C::SB; ++i) {
       const int row = (tid + i * C::NTH) / (BK / 2);
-      bs[kb[i] * C::LB + row] = rb[i].x;
-      bs[(kb[i] + 1) * C::LB + row] = rb[i].y;
+      bs[kb[i] * C::LB + row] = ob[i] ? rb[i].x : 0.0;
+      bs[(kb[i] + 1) * C::LB + row] = ob[i] ? rb[i].y : 0.0;
     }
   };
   load(0);
@@ -635,7 +637,15 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
-  switch (g.variant) {
+  int variant = g.variant;
+  if (variant == 0) {
+    // 128 x 256 tiles (8 waves of 64 x 64) once there are enough of them to
+    // fill the chip twice; 128 x 128 below that; 64 x 64 for small outputs
+    const long long t256 = (long long)((g.M + 127) / 128) * ((g.N + 255) / 256) * g.batch;
+    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+    variant = t256 >= 512 ? 1 : (t128 >= 256 ? 4 : 3);
+  }
+  switch (variant) {
     case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
     case 2: return launch_nt<256, 128, 4, 2, 2>(g, s);
     case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);
