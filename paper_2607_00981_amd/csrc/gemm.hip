@@ -654,3 +654,291 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
 }
 
 }  // namespace cct
+
+// ===========================================================================
+// Mixed-precision K-contiguous kernels.  Operands are read as FP64 and
+// rounded when they are written to LDS.
+//   FP32:   v_mfma_f32_16x16x4_f32, FP32 accumulation within a K tile,
+//           flushed into FP64 registers after every K tile.
+//   BF16X3: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each product
+//           is hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16),
+//           FP32 accumulation within a K tile of 32, flushed into FP64.
+// ===========================================================================
+namespace cct {
+namespace {
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 1) void gemm_nt_f32_kernel(NtArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, LA = BM + 4, LB = BN + 4;
+  constexpr int SA = BM * (BK / 2) / NTH, SB = BN * (BK / 2) / NTH;
+  __shared__ float As[2][BK * LA];
+  __shared__ float Bs[2][BK * LB];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const double* A = g.A + (long long)b * g.a_batch;
+  const double* B = g.B + (long long)b * g.b_batch;
+  const double* pa[SA];
+  const double* pb[SB];
+  int ka[SA], kb[SB];
+  bool va[SA], vb[SB];
+#pragma unroll
+  for (int i = 0; i < SA; ++i) {
+    const int seg = tid + i * NTH, row = seg / (BK / 2);
+    ka[i] = 2 * (seg % (BK / 2));
+    const int m = tm * BM + row;
+    va[i] = m < g.M;
+    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int seg = tid + i * NTH, row = seg / (BK / 2);
+    kb[i] = 2 * (seg % (BK / 2));
+    const int n = tn * BN + row;
+    vb[i] = n < g.N;
+    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+  }
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  double out[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  dbl2 ra[SA], rb[SB];
+  bool oa[SA], ob[SB];
+  const int nk = (g.K + BK - 1) / BK;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const dbl2*)(pa[i] + (oa[i] ? k0 : 0)); }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0)); }
+  };
+  auto store = [&](float* as, float* bs) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) {
+      const int row = (tid + i * NTH) / (BK / 2);
+      as[ka[i] * LA + row] = oa[i] ? (float)ra[i].x : 0.f;
+      as[(ka[i] + 1) * LA + row] = oa[i] ? (float)ra[i].y : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+      const int row = (tid + i * NTH) / (BK / 2);
+      bs[kb[i] * LB + row] = ob[i] ? (float)rb[i].x : 0.f;
+      bs[(kb[i] + 1) * LB + row] = ob[i] ? (float)rb[i].y : 0.f;
+    }
+  };
+  load(0);
+  store(As[0], Bs[0]);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = as[kr * LA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = bs[kr * LB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    if (kt + 1 < nk) store(As[cur ^ 1], Bs[cur ^ 1]);
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * out[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 1) void gemm_nt_bf16x3_kernel(NtArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LK = KB + 8;
+  constexpr int SA = BM * (KB / 2) / NTH, SB = BN * (KB / 2) / NTH;
+  // [buffer][plane hi/lo][row][k], k contiguous so a lane reads 8 consecutive k as 16 bytes
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM * LK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN * LK];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const double* A = g.A + (long long)b * g.a_batch;
+  const double* B = g.B + (long long)b * g.b_batch;
+  const double* pa[SA];
+  const double* pb[SB];
+  int ka[SA], kb[SB], rowa[SA], rowb[SB];
+  bool va[SA], vb[SB];
+#pragma unroll
+  for (int i = 0; i < SA; ++i) {
+    const int seg = tid + i * NTH;
+    rowa[i] = seg / (KB / 2);
+    ka[i] = 2 * (seg % (KB / 2));
+    const int m = tm * BM + rowa[i];
+    va[i] = m < g.M;
+    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int seg = tid + i * NTH;
+    rowb[i] = seg / (KB / 2);
+    kb[i] = 2 * (seg % (KB / 2));
+    const int n = tn * BN + rowb[i];
+    vb[i] = n < g.N;
+    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+  }
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  double out[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  dbl2 ra[SA], rb[SB];
+  bool oa[SA], ob[SB];
+  const int nk = (g.K + KB - 1) / KB;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const dbl2*)(pa[i] + (oa[i] ? k0 : 0)); }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0)); }
+  };
+  auto put = [&](__bf16* hi, __bf16* lo, int off, double x0, double x1) {
+    __bf16 h0, l0, h1, l1;
+    split_bf16(x0, h0, l0);
+    split_bf16(x1, h1, l1);
+    hi[off] = h0; hi[off + 1] = h1;
+    lo[off] = l0; lo[off + 1] = l1;
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i)
+      put(As[buf][0], As[buf][1], rowa[i] * LK + ka[i], oa[i] ? ra[i].x : 0.0, oa[i] ? ra[i].y : 0.0);
+#pragma unroll
+    for (int i = 0; i < SB; ++i)
+      put(Bs[buf][0], Bs[buf][1], rowb[i] * LK + kb[i], ob[i] ? rb[i].x : 0.0, ob[i] ? rb[i].y : 0.0);
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  const int kq = 8 * (lane / 16);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm0 + i * 16 + (lane & 15);
+      ah[i] = *(const bf8*)&As[cur][0][row * LK + kq];
+      al[i] = *(const bf8*)&As[cur][1][row * LK + kq];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = wn0 + j * 16 + (lane & 15);
+      const bf8 bh = *(const bf8*)&Bs[cur][0][col * LK + kq];
+      const bf8 bl = *(const bf8*)&Bs[cur][1][col * LK + kq];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * out[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN>
+hipError_t launch_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  if (prec == Prec::F32)
+    hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_nt_bf16x3_kernel<BM, BN>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (prec == Prec::F64) return gemm_nt(g, prec, s);
+  if (g.K <= 0 || (g.K & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_batch & 1) || (g.b_batch & 1) ||
+      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15))
+    return hipErrorInvalidValue;
+  const long long nb = g.batch - 1;
+  if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
+  if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
+  if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  if (t128 >= 256) return launch_nt_mixed<128, 128>(g, prec, s);
+  return launch_nt_mixed<64, 64>(g, prec, s);
+}
+
+}  // namespace cct

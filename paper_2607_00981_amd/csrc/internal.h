@@ -62,6 +62,9 @@ struct NtArgs {
   int variant;                    // tile variant (0 = default)
 };
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s);
+// The same product in FP32 or split-BF16 (FP64 operands rounded in LDS, FP64
+// output); Prec::F64 forwards to gemm_nt.
+hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s);
 
 // Y = alpha * X + beta * Y over an index space of up to 6 dimensions.
 struct PermArgs {
