@@ -759,6 +759,52 @@ int feedback(cct_ctx* ctx) {
   return CCT_OK;
 }
 
+// Low-precision operand storage: FP32 values, or split BF16 as two planes
+// (hi, lo); both take four bytes per element.
+int lp_width(Prec p) { return p == Prec::F32 ? 4 : 8; }
+int lp_fmt(Prec p) { return p == Prec::F32 ? OUT_F32 : OUT_BF16X2; }
+void* alloc_lp(Arena& ws, long long n) { return ws.alloc((size_t)((n + 1) / 2)); }
+
+// Ladder with operands stored in the working precision: W converted once,
+// then per chunk of blocks the three K-contiguous views of T3 (plain,
+// axes 0/1 swapped, (d,e) rotated to the back) are written in that precision
+// and multiplied by the low-precision K-contiguous kernel (FP64 output).
+int r3_pp_lp(cct_ctx* ctx, const Idx2 cm[3], const Idx2 cn[3]) {
+  const int v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, v4 = v2 * v2, nt = ctx->ntri;
+  const int fmt = lp_fmt(ctx->prec);
+  Arena& ws = ctx->ws;
+  const size_t mk = ws.mark();
+  void* Wl = alloc_lp(ws, v4);
+  if (!Wl) { ctx->err = "workspace exhausted (ladder W)"; return CCT_ENOMEM; }
+  HIPCK(convert(ctx->Wvvvv, OutSpec{Wl, fmt, v4}, v4, ctx->s));
+  long long chunk = (long long)(ws.available() / 4 / (size_t)v3) - 1;
+  if (chunk < 1) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
+  if (chunk > nt) chunk = nt;
+  void* Tc = alloc_lp(ws, chunk * v3);
+  if (!Tc) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
+  for (long long t0 = 0; t0 < nt; t0 += chunk) {
+    const long long nb = std::min(chunk, nt - t0);
+    const double* src = ctx->t3 + t0 * v3;
+    const OutSpec os{Tc, fmt, nb * v3};
+    for (int term = 2; term >= 0; --term) {
+      if (term == 2) HIPCK(convert(src, os, nb * v3, ctx->s));
+      else if (term == 1) HIPCK(swap01_batched(src, os, nb, v, v, v, ctx->s));
+      else HIPCK(transpose_batched(src, os, nb, (int)v2, v, ctx->s));
+      NtLpArgs g{};
+      g.M = (int)(nb * v); g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+      g.A = Tc; g.lda = v2; g.a_plane = nb * v3;
+      g.B = Wl; g.ldb = v2; g.b_plane = v4;
+      g.C = ctx->r3 + t0 * v3; g.cm = cm[term]; g.cn = cn[term];
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = nb * v3; g.b_len = v4; g.c_len = (nt - t0) * v3;
+      HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
+    }
+  }
+  ws.reset(mk);
+  return CCT_OK;
+}
+
 // Particle-particle ladder by direct traversal of the stored blocks (paper,
 // Sec. "RCCSDT contractions without unpacking"): for each stored (i,j,k)
 //   R[abc] += sum_de W^{ab}_{de} t^{dec} + W^{ac}_{de} t^{dbe} + W^{bc}_{de} t^{ade},
@@ -773,7 +819,9 @@ int r3_pp(cct_ctx* ctx) {
   // output maps of the three terms: C[(t,x)][(y,z)] -> R[t][..]
   const Idx2 cm[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
   const Idx2 cn[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
-  if (ctx->prec != Prec::F64 || (v2 & 1)) {
+  const bool lp = ctx->prec != Prec::F64;
+  if (lp && v2 % lp_width(ctx->prec) == 0) return r3_pp_lp(ctx, cm, cn);
+  if (lp || (v2 & 1)) {
     // generic strided kernel reading T3 in place
     const Idx2 am[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
     const Idx2 ak[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
@@ -812,8 +860,9 @@ int r3_pp(cct_ctx* ctx) {
     for (long long t0 = 0; t0 < nt; t0 += chunk) {
       const long long nb = std::min(chunk, nt - t0);
       const double* src = ctx->t3 + t0 * v3;
-      if (term == 1) HIPCK(swap01_batched(src, Tc, nb, v, v, v, ctx->s));       // [t][x][d][e] = T[t][d][x][e]
-      else HIPCK(transpose_batched(src, Tc, nb, (int)v2, v, ctx->s));          // [t][x][(d,e)] = T[t][(d,e)][x]
+      const OutSpec os{Tc, OUT_F64, 0};
+      if (term == 1) HIPCK(swap01_batched(src, os, nb, v, v, v, ctx->s));  // [t][x][d][e] = T[t][d][x][e]
+      else HIPCK(transpose_batched(src, os, nb, (int)v2, v, ctx->s));      // [t][x][(d,e)] = T[t][(d,e)][x]
       NtArgs g{};
       g.M = (int)(nb * v); g.N = (int)v2; g.K = (int)v2; g.batch = 1;
       g.A = Tc; g.lda = v2;
@@ -865,10 +914,21 @@ int r3_rings(cct_ctx* ctx, int kind) {
   const long long v2 = (long long)v * v, v3 = ctx->v3, ov3 = o * v3;
   const long long ov = (long long)o * v;
   Arena& ws = ctx->ws;
-  const bool nt = (ctx->prec == Prec::F64) && !(ov & 1);
+  const bool f64 = ctx->prec == Prec::F64;
+  const bool nt = f64 && !(ov & 1);
+  const bool lp = !f64 && ov % lp_width(ctx->prec) == 0;
+  // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
+  const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
+  const size_t mk0 = ws.mark();
+  void* Al = nullptr;
+  if (lp) {
+    Al = alloc_lp(ws, ov * ov);
+    if (!Al) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
+    HIPCK(convert(Aw, OutSpec{Al, lp_fmt(ctx->prec), ov * ov}, ov * ov, ctx->s));
+  }
   for (const Batch& b : ctx->ring[kind].batches) {
     const size_t mk = ws.mark();
-    double* U = ws.alloc((size_t)(b.nslots * ov3));
+    void* U = lp ? alloc_lp(ws, b.nslots * ov3) : (void*)ws.alloc((size_t)(b.nslots * ov3));
     double* Z = ws.alloc((size_t)(b.nslots * ov3));
     if (!U || !Z) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
     UnpackArgs ua{};
@@ -887,14 +947,22 @@ int r3_rings(cct_ctx* ctx, int kind) {
       const int occ[3] = {0, 2, 1};  // t_{q l r}^{d x z}
       set_ident(ua, occ);
     }
-    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
-    // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
-    const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
-    if (nt) {
+    const OutSpec uo{U, lp ? lp_fmt(ctx->prec) : OUT_F64, b.nslots * ov3};
+    HIPCK(unpack_t3_fmt(ctx->t3, ctx->tbl, b.d_slots, uo, ua, ctx->s));
+    if (lp) {
+      NtLpArgs g{};
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
+      g.A = Al; g.lda = ov; g.a_batch = 0; g.a_plane = ov * ov;
+      g.B = U; g.ldb = ov; g.b_batch = ov3; g.b_plane = b.nslots * ov3;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
+    } else if (nt) {
       NtArgs g{};
       g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
       g.A = Aw; g.lda = ov; g.a_batch = 0;
-      g.B = U; g.ldb = ov; g.b_batch = ov3;
+      g.B = (const double*)U; g.ldb = ov; g.b_batch = ov3;
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
@@ -903,7 +971,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
       GemmArgs g{};
       g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
       g.A = Aw; g.am = idx1(ov); g.ak = idx1(1); g.a_batch = 0;
-      g.B = U; g.bk = idx1(1); g.bn = idx1(ov); g.b_batch = ov3;
+      g.B = (const double*)U; g.bk = idx1(1); g.bn = idx1(ov); g.b_batch = ov3;
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
@@ -912,6 +980,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }
+  ws.reset(mk0);
   return CCT_OK;
 }
 
@@ -1007,6 +1076,7 @@ int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
     return CCT_ESTATE;
   }
   hipStream_t s = ctx->s;
+  ctx->ws.reset(0);  // the arena holds only per-evaluation scratch; drop what a failed call left
   mark(ctx, 0);
   RCK(dress(ctx));
   RCK(ccsd_part(ctx));

@@ -942,3 +942,304 @@ hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
 }
 
 }  // namespace cct
+
+// ===========================================================================
+// K-contiguous kernels on low-precision operands stored in memory.
+//   FP32 operands: 16-byte loads of 4 floats, K tile of 32, FP32 MFMA with
+//   FP32 accumulation inside the K tile and an FP64 flush after it.
+//   Split-BF16 operands: hi and lo planes, 16-byte loads of 8 bf16 per plane,
+//   K tile of 32 (one bf16 MFMA step), three products per tile, FP32
+//   accumulation flushed into FP64 after every K tile.
+// ===========================================================================
+namespace cct {
+namespace {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LA = BM + 4, LB = BN + 4;
+  constexpr int SA = BM * (KB / 4) / NTH, SB = BN * (KB / 4) / NTH;  // 16-byte segments per thread
+  __shared__ float As[2][KB * LA];
+  __shared__ float Bs[2][KB * LB];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const float* A = (const float*)g.A + (long long)b * g.a_batch;
+  const float* B = (const float*)g.B + (long long)b * g.b_batch;
+  const float* pa[SA];
+  const float* pb[SB];
+  int ka[SA], kb[SB];
+  bool va[SA], vb[SB];
+#pragma unroll
+  for (int i = 0; i < SA; ++i) {
+    const int seg = tid + i * NTH, row = seg / (KB / 4);
+    ka[i] = 4 * (seg % (KB / 4));
+    const int m = tm * BM + row;
+    va[i] = m < g.M;
+    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int seg = tid + i * NTH, row = seg / (KB / 4);
+    kb[i] = 4 * (seg % (KB / 4));
+    const int n = tn * BN + row;
+    vb[i] = n < g.N;
+    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+  }
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  double out[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  flt4 ra[SA], rb[SB];
+  bool oa[SA], ob[SB];
+  const int nk = (g.K + KB - 1) / KB;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const flt4*)(pa[i] + (oa[i] ? k0 : 0)); }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const flt4*)(pb[i] + (ob[i] ? k0 : 0)); }
+  };
+  auto store = [&](float* as, float* bs) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) {
+      const int row = (tid + i * NTH) / (KB / 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) as[(ka[i] + q) * LA + row] = oa[i] ? ra[i][q] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+      const int row = (tid + i * NTH) / (KB / 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bs[(kb[i] + q) * LB + row] = ob[i] ? rb[i][q] : 0.f;
+    }
+  };
+  load(0);
+  store(As[0], Bs[0]);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = as[kr * LA + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = bs[kr * LB + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    if (kt + 1 < nk) store(As[cur ^ 1], Bs[cur ^ 1]);
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * out[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LK = KB + 8;
+  constexpr int SA = BM * (KB / 8) / NTH, SB = BN * (KB / 8) / NTH;  // 16-byte segments per plane per thread
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM * LK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN * LK];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const __bf16* A = (const __bf16*)g.A + (long long)b * g.a_batch;
+  const __bf16* B = (const __bf16*)g.B + (long long)b * g.b_batch;
+  const __bf16* pa[SA];
+  const __bf16* pb[SB];
+  int ka[SA], kb[SB], rowa[SA], rowb[SB];
+  bool va[SA], vb[SB];
+#pragma unroll
+  for (int i = 0; i < SA; ++i) {
+    const int seg = tid + i * NTH;
+    rowa[i] = seg / (KB / 8);
+    ka[i] = 8 * (seg % (KB / 8));
+    const int m = tm * BM + rowa[i];
+    va[i] = m < g.M;
+    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    const int seg = tid + i * NTH;
+    rowb[i] = seg / (KB / 8);
+    kb[i] = 8 * (seg % (KB / 8));
+    const int n = tn * BN + rowb[i];
+    vb[i] = n < g.N;
+    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+  }
+  const int wave = tid / 64, lane = tid & 63;
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  double out[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  u32x4 rah[SA], ral[SA], rbh[SB], rbl[SB];
+  bool oa[SA], ob[SB];
+  const int nk = (g.K + KB - 1) / KB;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) {
+      oa[i] = va[i] && (k0 + ka[i] < g.K);
+      const __bf16* p = pa[i] + (oa[i] ? k0 : 0);
+      rah[i] = *(const u32x4*)p;
+      ral[i] = *(const u32x4*)(p + g.a_plane);
+    }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+      ob[i] = vb[i] && (k0 + kb[i] < g.K);
+      const __bf16* p = pb[i] + (ob[i] ? k0 : 0);
+      rbh[i] = *(const u32x4*)p;
+      rbl[i] = *(const u32x4*)(p + g.b_plane);
+    }
+  };
+  const u32x4 zero4 = {0u, 0u, 0u, 0u};
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) {
+      *(u32x4*)&As[buf][0][rowa[i] * LK + ka[i]] = oa[i] ? rah[i] : zero4;
+      *(u32x4*)&As[buf][1][rowa[i] * LK + ka[i]] = oa[i] ? ral[i] : zero4;
+    }
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+      *(u32x4*)&Bs[buf][0][rowb[i] * LK + kb[i]] = ob[i] ? rbh[i] : zero4;
+      *(u32x4*)&Bs[buf][1][rowb[i] * LK + kb[i]] = ob[i] ? rbl[i] : zero4;
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  const int kq = 8 * (lane / 16);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * KB);
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm0 + i * 16 + (lane & 15);
+      ah[i] = *(const bf8*)&As[cur][0][row * LK + kq];
+      al[i] = *(const bf8*)&As[cur][1][row * LK + kq];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = wn0 + j * 16 + (lane & 15);
+      const bf8 bh = *(const bf8*)&Bs[cur][0][col * LK + kq];
+      const bf8 bl = *(const bf8*)&Bs[cur][1][col * LK + kq];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * out[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN, int OCC>
+hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  if (prec == Prec::F32)
+    hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, OCC>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, OCC>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (prec == Prec::F64) return hipErrorInvalidValue;
+  // operands: K, leading dimensions and batch strides multiples of the vector width, 16-byte aligned
+  const int w = prec == Prec::F32 ? 4 : 8;
+  if (g.K <= 0 || g.K % w || g.lda % w || g.ldb % w || g.a_batch % w || g.b_batch % w || ((uintptr_t)g.A & 15) ||
+      ((uintptr_t)g.B & 15))
+    return hipErrorInvalidValue;
+  if (prec == Prec::BF16X3 && (g.a_plane % w || g.b_plane % w || g.a_plane <= 0 || g.b_plane <= 0))
+    return hipErrorInvalidValue;
+  const long long nb = g.batch - 1;
+  if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
+  if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
+  if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  if (t128 >= 256) return launch_lp<128, 128, 1>(g, prec, s);
+  return launch_lp<64, 64, 2>(g, prec, s);
+}
+
+}  // namespace cct

@@ -82,6 +82,16 @@ struct BlockRef {
   int pad;
 };
 
+// Element formats of operands written by the bandwidth kernels:
+//   OUT_F64: double; OUT_F32: float; OUT_BF16X2: two bf16 planes (hi at
+//   out[i], lo at out[plane + i], hi = bf16(x), lo = bf16(x - hi)).
+enum OutFmt { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+struct OutSpec {
+  void* p;
+  int fmt;
+  long long plane;  // element offset of the lo plane (OUT_BF16X2)
+};
+
 // One term of an unpacked element: coef * t_{occ}^{virt} where occ[m] selects
 // the occupied index at position m (0,1: the slot's fixed indices; 2,3: the
 // free indices) and virt[m] selects which of (x,y,z) sits at position m.
@@ -101,11 +111,28 @@ struct UnpackArgs {
 // slots: device array of int2 (fixed occupied indices) per slot.
 hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out,
                      const UnpackArgs& a, hipStream_t s);
+hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots, OutSpec out, const UnpackArgs& a,
+                         hipStream_t s);
 
 // out[b][j][i] = in[b][i][j] for a batch of R x C matrices (row-major).
-hipError_t transpose_batched(const double* in, double* out, long long batch, int R, int C, hipStream_t s);
+hipError_t transpose_batched(const double* in, OutSpec out, long long batch, int R, int C, hipStream_t s);
 // out[b][i][j][k] = in[b][j][i][k] for a batch of n0 x n1 x n2 tensors (swap of the two outer axes).
-hipError_t swap01_batched(const double* in, double* out, long long batch, int n0, int n1, int n2, hipStream_t s);
+hipError_t swap01_batched(const double* in, OutSpec out, long long batch, int n0, int n1, int n2, hipStream_t s);
+// out[i] = in[i] in the requested format.
+hipError_t convert(const double* in, OutSpec out, long long n, hipStream_t s);
+
+// K-contiguous GEMM on low-precision operands (FP32, or split BF16 planes),
+// FP64 output through two-level maps.  lda/ldb/batch strides in elements of
+// the operand format; a_plane/b_plane: offset of the lo plane (BF16X3).
+struct NtLpArgs {
+  int M, N, K, batch;
+  const void* A; long long lda, a_batch, a_plane;
+  const void* B; long long ldb, b_batch, b_plane;
+  double* C; Idx2 cm, cn; long long c_batch;
+  double alpha, beta;
+  long long a_len, b_len, c_len;
+};
+hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s);
 
 // Output-stationary accumulation of temporary Y blocks into packed R3:
 // R[t] (a,b,c) += sum_c coef * Z[base + a*sa + b*sb + c*sc].

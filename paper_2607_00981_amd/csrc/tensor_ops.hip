@@ -18,6 +18,19 @@ inline unsigned blocks_for(long long n, int per_block, unsigned cap = 1u << 20) 
   return (unsigned)b;
 }
 
+__device__ __forceinline__ void put_out(const OutSpec& o, long long i, double x) {
+  if (o.fmt == OUT_F64) {
+    ((double*)o.p)[i] = x;
+  } else if (o.fmt == OUT_F32) {
+    ((float*)o.p)[i] = (float)x;
+  } else {
+    const __bf16 hi = (__bf16)(float)x;
+    const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+    ((__bf16*)o.p)[i] = hi;
+    ((__bf16*)o.p)[o.plane + i] = lo;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // permute / accumulate
 // ---------------------------------------------------------------------------
@@ -41,7 +54,7 @@ __global__ void permute_add_kernel(const double* __restrict__ X, double* __restr
 // ---------------------------------------------------------------------------
 // grid.y enumerates (slot, free indices); grid.x covers the v^3 virtual block.
 __global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __restrict__ tbl,
-                              const int2* __restrict__ slots, double* __restrict__ out, UnpackArgs a) {
+                              const int2* __restrict__ slots, OutSpec out, UnpackArgs a) {
   const int o = a.o, v = a.v;
   const int nfc = (a.nfree == 2) ? o * o : o;
   const int sy_ = blockIdx.y;
@@ -83,7 +96,7 @@ __global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __re
         val += tm.coef * T[off];
       }
     }
-    out[obase + (long long)x * a.s_x + (long long)y * a.s_y + (long long)z * a.s_z] = val;
+    put_out(out, obase + (long long)x * a.s_x + (long long)y * a.s_y + (long long)z * a.s_z, val);
   }
 }
 
@@ -242,11 +255,11 @@ __global__ void fill_kernel(double* __restrict__ y, double val, long long n) {
 }
 
 // 32 x 32 tiles through LDS: reads and writes both coalesced.
-__global__ void transpose_kernel(const double* __restrict__ in, double* __restrict__ out, int R, int C) {
+__global__ void transpose_kernel(const double* __restrict__ in, OutSpec out, long long b0, int R, int C) {
   __shared__ double tile[32][33];
-  const long long b = blockIdx.z;
+  const long long b = blockIdx.z + b0;
   const double* src = in + b * (long long)R * C;
-  double* dst = out + b * (long long)R * C;
+  const long long dbase = b * (long long)R * C;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
   for (int k = ty; k < 32; k += 8) {
@@ -256,12 +269,11 @@ __global__ void transpose_kernel(const double* __restrict__ in, double* __restri
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
     const int c = c0 + k, r = r0 + tx;
-    if (r < R && c < C) dst[(long long)c * R + r] = tile[tx][k];
+    if (r < R && c < C) put_out(out, dbase + (long long)c * R + r, tile[tx][k]);
   }
 }
 
-__global__ void swap01_kernel(const double* __restrict__ in, double* __restrict__ out, long long rows, int n0, int n1,
-                              int n2) {
+__global__ void swap01_kernel(const double* __restrict__ in, OutSpec out, long long rows, int n0, int n1, int n2) {
   // one (b, i, j) row of n2 elements per (y, z) block index
   const long long row = blockIdx.y + (long long)blockIdx.z * 65535;
   if (row >= rows) return;
@@ -270,8 +282,13 @@ __global__ void swap01_kernel(const double* __restrict__ in, double* __restrict_
   const int ij = (int)(row - b * per);
   const int i = ij / n1, j = ij - i * n1;  // out[b][i][j][:] = in[b][j][i][:]
   const double* src = in + ((b * n1 + j) * n0 + i) * (long long)n2;
-  double* dst = out + ((b * n0 + i) * n1 + j) * (long long)n2;
-  for (int k = threadIdx.x; k < n2; k += blockDim.x) dst[k] = src[k];
+  const long long dst = ((b * n0 + i) * n1 + j) * (long long)n2;
+  for (int k = threadIdx.x; k < n2; k += blockDim.x) put_out(out, dst + k, src[k]);
+}
+
+__global__ void convert_kernel(const double* __restrict__ in, OutSpec out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    put_out(out, i, in[i]);
 }
 
 __global__ void add_rows_kernel(const double* __restrict__ in, int rows, long long n, double* __restrict__ out) {
@@ -331,8 +348,8 @@ hipError_t permute_add(const double* X, double* Y, const PermArgs& p, hipStream_
   return hipGetLastError();
 }
 
-hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out, const UnpackArgs& a,
-                     hipStream_t s) {
+hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots, OutSpec out, const UnpackArgs& a,
+                         hipStream_t s) {
   const long long v3 = (long long)a.v * a.v * a.v;
   const long long ny = (long long)a.nslots * (a.nfree == 2 ? (long long)a.o * a.o : a.o);
   if (ny <= 0 || v3 <= 0) return hipSuccess;
@@ -340,6 +357,11 @@ hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, do
   dim3 grid(blocks_for(v3, TPB * 4, 4096), (unsigned)ny);
   hipLaunchKernelGGL(unpack_kernel, grid, dim3(TPB), 0, s, T, tbl, slots, out, a);
   return hipGetLastError();
+}
+
+hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out, const UnpackArgs& a,
+                     hipStream_t s) {
+  return unpack_t3_fmt(T, tbl, slots, OutSpec{out, OUT_F64, 0}, a, s);
 }
 
 hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTask* tasks, int ntasks,
@@ -396,25 +418,30 @@ hipError_t fill(double* y, double val, long long n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t transpose_batched(const double* in, double* out, long long batch, int R, int C, hipStream_t s) {
+hipError_t transpose_batched(const double* in, OutSpec out, long long batch, int R, int C, hipStream_t s) {
   if (batch <= 0 || R <= 0 || C <= 0) return hipSuccess;
+  if ((R + 31) / 32 > 65535) return hipErrorInvalidValue;
   for (long long b0 = 0; b0 < batch; b0 += 65535) {
     const long long nb = batch - b0 < 65535 ? batch - b0 : 65535;
-    const long long off = b0 * (long long)R * C;
     dim3 grid((C + 31) / 32, (R + 31) / 32, (unsigned)nb);
-    if (grid.y > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, in + off, out + off, R, C);
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, in, out, b0, R, C);
   }
   return hipGetLastError();
 }
 
-hipError_t swap01_batched(const double* in, double* out, long long batch, int n0, int n1, int n2, hipStream_t s) {
+hipError_t swap01_batched(const double* in, OutSpec out, long long batch, int n0, int n1, int n2, hipStream_t s) {
   const long long rows = batch * n0 * n1;
   if (rows <= 0 || n2 <= 0) return hipSuccess;
   const long long gz = (rows + 65534) / 65535;
   if (gz > 65535) return hipErrorInvalidValue;
   const unsigned gy = (unsigned)(rows < 65535 ? rows : 65535);
   hipLaunchKernelGGL(swap01_kernel, dim3(1, gy, (unsigned)gz), dim3(256), 0, s, in, out, rows, n0, n1, n2);
+  return hipGetLastError();
+}
+
+hipError_t convert(const double* in, OutSpec out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(convert_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, in, out, n);
   return hipGetLastError();
 }
 

@@ -3,7 +3,11 @@
 Inputs come from cct_inputs (seeded); expected values from oracle/ only.
 Tolerances: FP64 residuals agree to 1e-11 relative to the largest residual
 element (roundoff of a few-thousand-term sums is ~1e-14 relative); energies
-after 20 iterations to 1e-10 Eh.
+after 20 iterations to 1e-10 Eh.  Mixed modes (ladder and ring contractions
+on FP32 or split-BF16 operands, FP32 accumulation inside a K tile of 32):
+operand rounding is 2^-24 (FP32) or about 2^-17 (hi+lo BF16) relative, so
+R3 is held to 2e-6 (FP32) and 5e-5 (BF16X3) of its largest element, and the
+energy after 20 DIIS iterations to 1e-6 Eh of the FP64 oracle.
 """
 
 import sys
@@ -144,3 +148,53 @@ def test_twenty_iterations_o4v20(diis):
         g1, g2, g3 = eng.get_amplitudes()
     assert np.max(np.abs(np.array(got) - np.array(ref))) < 1e-10
     assert np.abs(g3 - R.pack_t3(t3)).max() < 1e-9
+
+
+MIXED_TOL = {"fp32": 2e-6, "bf16x3": 5e-5}
+
+
+@pytest.mark.parametrize("shape", [(3, 7, 31), (3, 8, 32), (2, 12, 41)], ids=["odd_v", "even_v", "v12"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_residual_close_to_oracle(prec, shape):
+    """v=8 and v=12 take the low-precision operand kernels (K multiple of the
+    vector width), v=7 the generic strided kernels with operands rounded at
+    the LDS store.  R1 and R2 stay FP64."""
+    o, v, seed = shape
+    say(f"[mixed parity] prec={prec} o={o} v={v} seed={seed}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
+    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, _ = eng.residual()
+    for name, a, b, rel in (("R1", g1, e1, 1e-11), ("R2", g2, e2, 1e-11), ("R3", g3, e3, MIXED_TOL[prec])):
+        ok, err, scale = _close(a, b, rel)
+        say(f"  {name}: max err {err:.3e} scale {scale:.3e}")
+        assert ok, f"{prec} {name}: max err {err:.3e} (scale {scale:.3e})"
+    # the rounding is really there: FP32/BF16 operands do not reproduce FP64 bit for bit
+    assert not np.array_equal(g3, e3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_twenty_iterations_o4v20(prec):
+    """Twenty DIIS iterations from the MP2 guess at o=4, v=20 in a mixed mode:
+    the energy stays within 1e-6 Eh of the FP64 oracle at every iteration."""
+    o, v, naux, seed = ci.CONFIGS["o4v20"]
+    say(f"[mixed iterations] prec={prec}")
+    s = ci.make_system(o, v, naux, seed)
+    f, B = s["f"], s["B"]
+    V = R.eri_phys_from_B(B)
+    t1, t2, t3 = R.mp2_guess(f, V, o)
+    d = R.DIIS()
+    ref = []
+    for _ in range(20):
+        t1, t2, t3, e, _ = R.iterate(f, V, t1, t2, t3, o, diis=d)
+        ref.append(e)
+    with _engine(o, v, naux, f, B, precision=prec) as eng:
+        eng.init_mp2()
+        got = []
+        for it in range(20):
+            e, nr = eng.update()
+            got.append(e)
+            say(f"  it {it+1}: gpu {e:.14f} oracle {ref[it]:.14f} diff {e-ref[it]:.2e}")
+    assert np.max(np.abs(np.array(got) - np.array(ref))) < 1e-6
