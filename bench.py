@@ -82,50 +82,85 @@ def cpu_baseline(o, v, naux, seed):
     }
 
 
+def run_mode(binding, s, o, v, naux, prec, steps, warmup):
+    """Warmup + timed iterations from the MP2 guess in one precision mode."""
+    eng = binding.Engine(o, v, naux, precision=prec,
+                         opts={"timers": True, "diis_t3": "none" if o >= 20 else "full"})
+    try:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        # every cct_update ends with a synchronisation of the library's stream
+        # (the energy and norms are read back), so the host clock brackets
+        # exactly the device work of the timed steps.
+        for w in range(warmup):
+            e, nr = eng.update()
+            log(f"[bench] {prec} warmup {w}: E={e:.10f}")
+        phase_ms = {k: 0.0 for k in binding.PHASES}
+        t0 = time.perf_counter()
+        for st in range(steps):
+            e, nr = eng.update()
+            macs, ms = eng.counters()
+            for k in phase_ms:
+                phase_ms[k] += ms[k]
+            log(f"[bench] {prec} step {st}: E={e:.10f} |R|={np.sqrt(nr.sum()):.3e}")
+        wall = time.perf_counter() - t0
+    finally:
+        eng.close()
+    r3_macs = sum(macs.values())
+    r3_ms = sum(phase_ms[k] for k in ("pp", "rings", "hh_f2", "drivers", "f1")) / steps
+    return {
+        "ms_per_step": 1000.0 * wall / steps,
+        "energy": e,
+        "macs": macs,
+        "r3_macs": r3_macs,
+        "r3_tflops": 2.0 * r3_macs / (r3_ms / 1000.0) / 1e12,
+        "phase_ms": {k: x / steps for k, x in phase_ms.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=list(PEAK))
+    ap.add_argument("--precision", default="fp64", choices=list(PEAK),
+                    help="mode whose rate is the reported value")
+    ap.add_argument("--compare", default="fp32,bf16x3",
+                    help="further modes run from the same start for speedup and dE ('' for none)")
     ap.add_argument("--workload", default="o20v180", choices=list(ci.CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
                                    "design only, sharded by packed triples)"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+
+        n = args.calibrate_copy // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        assert bool((b[-1] == 1.0).item())
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
 
     from paper_2607_00981_amd import binding
 
     o, v, naux, seed = ci.CONFIGS[args.workload]
     s = ci.make_system(o, v, naux, seed)
     log(f"[bench] o={o} v={v} naux={naux} seed={seed} precision={args.precision}")
-    eng = binding.Engine(o, v, naux, precision=args.precision,
-                         opts={"timers": True, "diis_t3": "none" if o >= 20 else "full"})
-    eng.set_fock(s["f"])
-    eng.set_eri_df(s["B"])
-    eng.init_mp2()
-    # every cct_update ends with a synchronisation of the library's stream
-    # (the energy and norms are read back), so the host clock brackets
-    # exactly the device work of the timed steps.
-    for w in range(args.warmup):
-        e, nr = eng.update()
-        log(f"[bench] warmup {w}: E={e:.10f}")
-    phase_ms = {k: 0.0 for k in binding.PHASES}
-    t0 = time.perf_counter()
-    for st in range(args.steps):
-        e, nr = eng.update()
-        macs, ms = eng.counters()
-        for k in phase_ms:
-            phase_ms[k] += ms[k]
-        log(f"[bench] step {st}: E={e:.10f} |R|={np.sqrt(nr.sum()):.3e}")
-    wall = time.perf_counter() - t0
-    ms_step = 1000.0 * wall / args.steps
-    r3_macs = sum(macs.values())
-    value = 2.0 * r3_macs / (ms_step / 1000.0) / 1e12
-    # dominant kernel: PP ladder GEMM, 3 launches per step
-    pp_ms_launch = phase_ms["pp"] / args.steps / 3.0
+    main_run = run_mode(binding, s, o, v, naux, args.precision, args.steps, args.warmup)
+    macs, phase_ms, ms_step, e = main_run["macs"], main_run["phase_ms"], main_run["ms_per_step"], main_run["energy"]
+    value = 2.0 * main_run["r3_macs"] / (ms_step / 1000.0) / 1e12
+    # dominant kernel: the particle-particle ladder GEMM, 3 launches per step;
+    # the phase also holds the relabelling copies of T3 (under 0.5 % of it)
+    pp_ms_launch = phase_ms["pp"] / 3.0
     pp_flop_launch = 2.0 * macs["PP"] / 3.0
     achieved = pp_flop_launch / (pp_ms_launch / 1000.0) / 1e12
     peak = PEAK[args.precision]
@@ -137,7 +172,14 @@ def main():
                 traffic = tf.get("bytes_per_launch")
         except Exception:
             traffic = None
-    r3_ms = sum(phase_ms[k] for k in ("pp", "rings", "hh_f2", "drivers", "f1")) / args.steps
+    modes = {args.precision: {"s_per_iteration": ms_step / 1000.0, "r3_tflops": main_run["r3_tflops"],
+                              "energy": e, "speedup": 1.0, "dE": 0.0, "dE_rel": 0.0}}
+    for prec in [m for m in args.compare.split(",") if m and m != args.precision]:
+        r = run_mode(binding, s, o, v, naux, prec, args.steps, args.warmup)
+        modes[prec] = {"s_per_iteration": r["ms_per_step"] / 1000.0, "r3_tflops": r["r3_tflops"],
+                       "energy": r["energy"], "speedup": ms_step / r["ms_per_step"],
+                       "dE": r["energy"] - e, "dE_rel": (r["energy"] - e) / max(abs(e), 1e-300),
+                       "phase_ms": r["phase_ms"]}
     out = {
         "metric": "T3-residual TFLOP/s + s/CCSDT iteration, FP64 vs mixed, o=20 v=180, dE vs oracle",
         "value": value,
@@ -154,17 +196,20 @@ def main():
         "config": {"workload": f"RCCSDT iteration o={o} v={v} naux={naux} seed={seed}, compact T3 "
                                f"({o*(o+1)*(o+2)//6} triples x {v}^3), MP2 start, DIIS on T1/T2",
                    "precision": args.precision},
-        "s_per_iteration": wall / args.steps,
-        "r3_tflops": 2.0 * r3_macs / (r3_ms / 1000.0) / 1e12,
-        "phase_ms": {k: x / args.steps for k, x in phase_ms.items()},
+        "s_per_iteration": ms_step / 1000.0,
+        "r3_tflops": main_run["r3_tflops"],
+        "phase_ms": phase_ms,
+        "modes": modes,
+        "modes_note": ("each mode runs warmup+steps iterations from the same MP2 guess; dE = E(mode) - "
+                       f"E({args.precision}) after the last step; the {args.precision} path is the one held to "
+                       "the oracle"),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": ("gemm_nt_f64_kernel<128,256> " if args.precision == "fp64" else
-                                f"gemm_{args.precision}_kernel<128,128> ") +
+                                f"gemm_lp_{args.precision.replace('fp32', 'f32')}_kernel<128,128> ") +
                                "(particle-particle ladder, one of 3 relabelled GEMMs)"},
         "energy": e,
     }
-    eng.close()
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)
