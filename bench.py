@@ -119,6 +119,41 @@ def run_mode(binding, s, o, v, naux, prec, steps, warmup):
     }
 
 
+def run_batched(binding, niter, modes):
+    """The 64-system batch (o uniform in 3..8, v in 20..60, seeded): niter
+    iterations from the MP2 guess per mode, one graph replay per iteration.
+    Rate: system-iterations per second over the timed iterations (the first,
+    which records the graph, is excluded)."""
+    sizes = ci.batched_sizes()
+    # variance-scaled integrals: with sigma = 0.05 the largest members (naux up
+    # to 136) diverge from the MP2 guess and their dE would measure chaos
+    systems = [ci.make_system(o, v, na, seed, sigma=ci.scaled_sigma(na)) for o, v, na, seed in sizes]
+    out = {}
+    e_ref = None
+    for prec in modes:
+        with binding.Batch([(o, v, na) for o, v, na, _ in sizes], precision=prec) as b:
+            for k, s in enumerate(systems):
+                b.set_system(k, s["f"], s["B"])
+            b.iterate(1)
+            t0 = time.perf_counter()
+            e, nr = b.iterate(niter - 1)
+            dt = time.perf_counter() - t0
+        rec = {"systems_per_s": len(sizes) * (niter - 1) / dt, "s_per_batch_iteration": dt / (niter - 1)}
+        if e_ref is None:
+            e_ref = e
+        else:
+            d = e - e_ref
+            rec["dE_max_abs"] = float(np.abs(d).max())
+            rec["dE_rel_max"] = float(np.abs(d / e_ref).max())
+        out[prec] = rec
+        log(f"[bench] batched {prec}: {rec}")
+    return {"workload": f"{len(sizes)} systems, o in [3,8], v in [20,60], naux=2(o+v), seeds 4000+s, "
+                        "B entries N(0, 0.05 sqrt(48/naux)); "
+                        f"{niter} iterations from MP2 (DIIS), first excluded from the rate",
+            "unit": "system-iterations/s", "modes": out,
+            "note": f"dE: energy after {niter} iterations minus the {modes[0]} batch's, per system"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +165,8 @@ def main():
                     help="further modes run from the same start for speedup and dE ('' for none)")
     ap.add_argument("--workload", default="o20v180", choices=list(ci.CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-iters", type=int, default=5,
+                    help="iterations of the 64-system batch per mode (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -210,6 +247,9 @@ def main():
                                "(particle-particle ladder, one of 3 relabelled GEMMs)"},
         "energy": e,
     }
+    if args.batched_iters > 1:
+        out["batched"] = run_batched(binding, args.batched_iters,
+                                     [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision])
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)

@@ -18,6 +18,13 @@ orbitals (n = o + v), ``naux`` fitting functions and a seed::
 so that (pq|rs) = sum_P B[P,p,q] B[P,r,s].  The paper's workloads are
 molecules; these synthetic systems stand in for them at the paper's
 occupied/virtual ratios.
+
+With sigma fixed at 0.05 the exchange-type integrals (ia|ia) ~ naux sigma^2
+grow with naux (0.12 / 0.50 / 1.00 at naux = 48 / 200 / 400) and the larger
+named systems have no coupled-cluster solution reachable from the MP2 guess.
+``scaled_sigma(naux)`` = 0.05 sqrt(48 / naux) keeps every (pq|rs) at the
+variance of the o=4, v=20 system; the "-scaled" variants of the named
+workloads (``make_named``) use it where a converged energy is needed.
 """
 
 from __future__ import annotations
@@ -29,6 +36,8 @@ import numpy as np
 __all__ = [
     "CONFIGS",
     "make_system",
+    "make_named",
+    "scaled_sigma",
     "batched_sizes",
     "random_fock",
     "random_amplitudes",
@@ -43,6 +52,20 @@ CONFIGS = {
     "o20v180": (20, 180, 400, 3),
     "o50v400": (50, 400, 900, 5),
 }
+
+
+def scaled_sigma(naux: int) -> float:
+    """Entry standard deviation giving (pq|rs) the variance of naux = 48, sigma = 0.05."""
+    return 0.05 * float(np.sqrt(48.0 / naux))
+
+
+def make_named(name: str) -> dict:
+    """A named workload ("o10v90"), or its variance-scaled variant ("o10v90-scaled")."""
+    base, _, variant = name.partition("-")
+    o, v, naux, seed = CONFIGS[base]
+    if variant not in ("", "scaled"):
+        raise ValueError(f"unknown workload variant {variant!r}")
+    return make_system(o, v, naux, seed, sigma=scaled_sigma(naux) if variant else 0.05)
 
 
 def make_system(o: int, v: int, naux: int | None = None, seed: int = 0, sigma: float = 0.05) -> dict:

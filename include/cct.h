@@ -144,6 +144,39 @@ int64_t cct_packed_index(int nocc, int i, int j, int k);
 const char* cct_strerror(int code);
 const char* cct_last_error(const cct_ctx* ctx);
 
+/* ---- batches of independent systems ------------------------------------
+ * Many small closed-shell systems iterated together (the same equations as
+ * a single context, one context per system).  The device part of one
+ * iteration of every system (DIIS save, residual, Jacobi steps) is recorded
+ * once into a HIP graph and replayed once per iteration; norm read-back,
+ * DIIS extrapolation and energy follow per system on the host side. */
+typedef struct cct_batch cct_batch;
+
+/* nsys systems with sizes nocc[s], nvir[s], naux[s] (host arrays), all in
+ * precision prec.  opts_json: "streams" (1..4, default 4: systems are spread
+ * round-robin over that many streams, which the graph forks and joins),
+ * "graph" (true by default; false enqueues every iteration eagerly, the same
+ * kernels in the same order), and the per-system keys of cct_create
+ * ("diis", "diis_space", "diis_start", "diis_t3", "workspace_gb").
+ * Errors: CCT_EINVAL (sizes, options), CCT_ENOMEM, CCT_EDEVICE. */
+int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux, cct_precision prec,
+                     const char* opts_json, cct_batch** out);
+/* Upload system s's bare Fock f[n][n] and factors B[naux][n][n] (host) and
+ * start it from the MP2 guess.  Does not invalidate a recorded graph (the
+ * device buffers keep their addresses). */
+int cct_batch_set_system(cct_batch* b, int s, const double* f, const double* B);
+/* niter iterations of every system.  e_corr [nsys] and norms [nsys][3]
+ * (squared norms of R1, R2, R3) after the last one; either may be NULL.
+ * CCT_ESTATE if a system has no integrals; per-system errors as for
+ * cct_update, with the system named in cct_batch_last_error. */
+int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms);
+/* The context of system s (owned by the batch; valid until
+ * cct_batch_destroy), for cct_get_amplitudes, cct_energy, cct_get_counters.
+ * NULL if s is out of range. */
+cct_ctx* cct_batch_system(cct_batch* b, int s);
+const char* cct_batch_last_error(const cct_batch* b);
+void cct_batch_destroy(cct_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,13 @@ def load(path: str | None = None):
         "cct_packed_index": (C.c_int64, [C.c_int, C.c_int, C.c_int, C.c_int]),
         "cct_strerror": (C.c_char_p, [C.c_int]),
         "cct_last_error": (C.c_char_p, [vp]),
+        "cct_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.c_int, C.c_char_p, C.POINTER(vp)]),
+        "cct_batch_set_system": (C.c_int, [vp, C.c_int, dp, dp]),
+        "cct_batch_iterate": (C.c_int, [vp, C.c_int, dp, dp]),
+        "cct_batch_system": (vp, [vp, C.c_int]),
+        "cct_batch_last_error": (C.c_char_p, [vp]),
+        "cct_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -193,3 +200,76 @@ class Engine:
         ms = np.zeros(9)
         self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 9))
         return dict(zip(TERMS.keys(), macs)), dict(zip(PHASES, ms))
+
+
+class _SystemView(Engine):
+    """A batch member's context, used through the single-system methods
+    (not owned: closing it does nothing)."""
+
+    def __init__(self, lib, h, o, v, naux):
+        self.lib, self.h = lib, h
+        self.o, self.v, self.naux = o, v, naux
+        self.n = o + v
+        self.ntri = ntri(o)
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Independent systems iterated together (one graph launch per iteration)."""
+
+    def __init__(self, sizes, precision="fp64", opts=None):
+        import json
+
+        self.lib = load()
+        self.sizes = [(int(o), int(v), int(na)) for o, v, na in sizes]
+        n = len(self.sizes)
+        arr = lambda k: (C.c_int * n)(*[s[k] for s in self.sizes])  # noqa: E731
+        js = json.dumps(opts).encode() if opts else None
+        h = C.c_void_p()
+        rc = self.lib.cct_batch_create(n, arr(0), arr(1), arr(2), PRECISIONS[precision], js, C.byref(h))
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cct_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_system(self, s, f, B):
+        o, v, na = self.sizes[s]
+        f = _in(f, (o + v, o + v))
+        B = _in(B, (na, o + v, o + v))
+        self._check(self.lib.cct_batch_set_system(self.h, s, _ptr(f), _ptr(B)))
+
+    def iterate(self, niter=1):
+        n = len(self.sizes)
+        e = np.empty(n)
+        nr = np.empty((n, 3))
+        self._check(self.lib.cct_batch_iterate(self.h, niter, _ptr(e), _ptr(nr)))
+        return e, nr
+
+    def system(self, s):
+        o, v, na = self.sizes[s]
+        h = self.lib.cct_batch_system(self.h, s)
+        if not h:
+            raise IndexError(s)
+        return _SystemView(self.lib, C.c_void_p(h), o, v, na)

@@ -1070,7 +1070,10 @@ int finite_or_err(cct_ctx* ctx, double x) {
 }
 
 // Full residual evaluation; R3 post-processed; optionally T3 += R3 / eps.
-int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
+// Enqueue one residual evaluation (and, with update_t3, the T3 Jacobi step)
+// on the context's stream.  No host synchronisation and no allocation: the
+// squared norms are left in scal[0..2].  Safe to record into a HIP graph.
+int enqueue_residual(cct_ctx* ctx, unsigned mask, bool update_t3) {
   if (!ctx->have_f || !ctx->have_B) {
     ctx->err = "integrals not set (cct_set_fock / cct_set_eri_df)";
     return CCT_ESTATE;
@@ -1116,9 +1119,14 @@ int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
   HIPCK(dot(ctx->r2, ctx->r2, (long long)ctx->o * ctx->o * ctx->v * ctx->v, ctx->scal + 1, ctx->red, s));
   mark(ctx, 8);
   count_macs(ctx, mask);
+  return CCT_OK;
+}
+
+// Wait for an enqueued residual, read the squared norms back, check them.
+int finish_residual(cct_ctx* ctx, double norms[3]) {
   double h[3];
-  HIPCK(hipMemcpyAsync(h, ctx->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCK(hipStreamSynchronize(s));
+  HIPCK(hipMemcpyAsync(h, ctx->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
   if (ctx->events) {
     for (int i = 0; i < PH_DIIS; ++i) {
       float msv = 0.f;
@@ -1131,6 +1139,11 @@ int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
     RCK(finite_or_err(ctx, h[i]));
   }
   return CCT_OK;
+}
+
+int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
+  RCK(enqueue_residual(ctx, mask, update_t3));
+  return finish_residual(ctx, norms);
 }
 
 int energy_dev(cct_ctx* ctx, double* e) {
@@ -1158,9 +1171,9 @@ long long diis_len(cct_ctx* ctx) {
 
 int copy_amps_to(cct_ctx* ctx, double* dst) {
   const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
-  HIPCK(hipMemcpyAsync(dst, ctx->t1, n1 * 8, hipMemcpyDeviceToDevice, ctx->s));
-  HIPCK(hipMemcpyAsync(dst + n1, ctx->t2, n2 * 8, hipMemcpyDeviceToDevice, ctx->s));
-  if (ctx->diis_t3) HIPCK(hipMemcpyAsync(dst + n1 + n2, ctx->t3, ctx->ntri * ctx->v3 * 8, hipMemcpyDeviceToDevice, ctx->s));
+  HIPCK(axpby(1.0, ctx->t1, 0.0, dst, n1, ctx->s));
+  HIPCK(axpby(1.0, ctx->t2, 0.0, dst + n1, n2, ctx->s));
+  if (ctx->diis_t3) HIPCK(axpby(1.0, ctx->t3, 0.0, dst + n1 + n2, ctx->ntri * ctx->v3, ctx->s));
   return CCT_OK;
 }
 
@@ -1271,12 +1284,20 @@ int diis_step(cct_ctx* ctx) {
   }
 }
 
-int update(cct_ctx* ctx, double* e, double norms[3]) {
-  const bool use_diis = ctx->diis_on && ctx->diis_space > 0;
-  if (use_diis) RCK(copy_amps_to(ctx, ctx->diis_old));
-  double nr[3];
-  RCK(compute(ctx, CCT_TERM_ALL, true, nr));
+// Device part of one iteration: save the amplitudes for DIIS, residual, T3
+// and T1/T2 Jacobi steps.  No host synchronisation (graph-capturable).
+int enqueue_iteration(cct_ctx* ctx) {
+  if (ctx->diis_on && ctx->diis_space > 0) RCK(copy_amps_to(ctx, ctx->diis_old));
+  RCK(enqueue_residual(ctx, CCT_TERM_ALL, true));
   HIPCK(jacobi_t1t2(ctx->t1, ctx->r1, ctx->t2, ctx->r2, ctx->eps, ctx->o, ctx->v, ctx->s));
+  return CCT_OK;
+}
+
+// Host part after enqueue_iteration: norms, DIIS extrapolation, energy.
+int finish_iteration(cct_ctx* ctx, double* e, double norms[3]) {
+  const bool use_diis = ctx->diis_on && ctx->diis_space > 0;
+  double nr[3];
+  RCK(finish_residual(ctx, nr));
   mark(ctx, PH_DIIS);
   if (use_diis) RCK(diis_step(ctx));
   double en = 0.0;
@@ -1291,6 +1312,11 @@ int update(cct_ctx* ctx, double* e, double norms[3]) {
   if (e) *e = en;
   if (norms) for (int i = 0; i < 3; ++i) norms[i] = nr[i];
   return CCT_OK;
+}
+
+int update(cct_ctx* ctx, double* e, double norms[3]) {
+  RCK(enqueue_iteration(ctx));
+  return finish_iteration(ctx, e, norms);
 }
 
 }  // namespace
@@ -1581,5 +1607,197 @@ int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, in
   }
   return CCT_OK;
 }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches of independent systems
+//
+// Each system is an ordinary context.  The device part of an iteration
+// (amplitude save for DIIS, residual, T3 and T1/T2 Jacobi steps) of every
+// system is recorded once into a HIP graph, forked over a few streams so
+// that independent systems can overlap, and replayed once per iteration:
+// one graph launch per batch residual.  The host part (norm read-back, DIIS
+// extrapolation, energy) follows per system after the replay.
+// ===========================================================================
+struct cct_batch {
+  std::vector<cct_ctx*> sys;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+  std::string err;
+};
+
+namespace {
+
+int batch_enqueue_all(cct_batch* b) {
+  for (cct_ctx* c : b->sys) {
+    const int rc = enqueue_iteration(c);
+    if (rc != CCT_OK) {
+      b->err = c->err;
+      return rc;
+    }
+  }
+  return CCT_OK;
+}
+
+// Record the device part of one iteration of every system into a graph.
+int batch_capture(cct_batch* b) {
+  hipStream_t s0 = b->streams[0];
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    b->err = "hipStreamBeginCapture failed";
+    return CCT_EDEVICE;
+  }
+  int rc = CCT_OK;
+  if (hipEventRecord(b->fork, s0) != hipSuccess) rc = CCT_EDEVICE;
+  for (size_t i = 1; i < b->streams.size() && rc == CCT_OK; ++i)
+    if (hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess) rc = CCT_EDEVICE;
+  if (rc == CCT_OK) rc = batch_enqueue_all(b);
+  for (size_t i = 1; i < b->streams.size() && rc == CCT_OK; ++i) {
+    if (hipEventRecord(b->join[i], b->streams[i]) != hipSuccess || hipStreamWaitEvent(s0, b->join[i], 0) != hipSuccess)
+      rc = CCT_EDEVICE;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(s0, &g);
+  if (rc == CCT_OK && ee != hipSuccess) {
+    b->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ee);
+    rc = CCT_EDEVICE;
+  }
+  if (rc != CCT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    if (b->err.empty()) b->err = "graph capture failed";
+    return rc;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    b->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ie);
+    return CCT_EDEVICE;
+  }
+  b->graph = g;
+  b->exec = ex;
+  return CCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cct_batch_destroy(cct_batch* b) {
+  if (!b) return;
+  for (hipStream_t s : b->streams)
+    if (s) (void)hipStreamSynchronize(s);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (cct_ctx* c : b->sys) cct_destroy(c);
+  for (hipEvent_t e : b->join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipStream_t s : b->streams)
+    if (s) (void)hipStreamDestroy(s);
+  delete b;
+}
+
+int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux, cct_precision prec,
+                     const char* opts_json, cct_batch** out) {
+  if (!out) return CCT_EINVAL;
+  *out = nullptr;
+  if (nsys < 1 || nsys > 4096 || !nocc || !nvir || !naux) return CCT_EINVAL;
+  int nstreams = 4;
+  bool use_graph = true;
+  std::string sys_opts = "{\"timers\": false";
+  if (opts_json) {
+    std::string js(opts_json), val;
+    if (json_find(js, "streams", val)) nstreams = std::atoi(val.c_str());
+    if (json_find(js, "graph", val)) use_graph = (val == "true" || val == "1");
+    for (const char* key : {"diis_space", "diis_start", "diis", "workspace_gb"})
+      if (json_find(js, key, val)) sys_opts += std::string(", \"") + key + "\": " + val;
+    if (json_find(js, "diis_t3", val)) sys_opts += ", \"diis_t3\": \"" + val + "\"";
+  }
+  sys_opts += "}";
+  if (nstreams < 1 || nstreams > 4) return CCT_EINVAL;
+  cct_batch* b = new cct_batch();
+  b->use_graph = use_graph;
+  int rc = CCT_OK;
+  for (int i = 0; i < nstreams && rc == CCT_OK; ++i) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) rc = CCT_EDEVICE;
+    b->streams.push_back(s);
+    hipEvent_t e = nullptr;
+    if (rc == CCT_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = CCT_EDEVICE;
+    b->join.push_back(e);
+  }
+  if (rc == CCT_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) rc = CCT_EDEVICE;
+  for (int i = 0; i < nsys && rc == CCT_OK; ++i) {
+    cct_ctx* c = nullptr;
+    rc = cct_create(nocc[i], nvir[i], naux[i], prec, sys_opts.c_str(), b->streams[i % nstreams], &c);
+    if (rc == CCT_OK) b->sys.push_back(c);
+  }
+  if (rc != CCT_OK) {
+    cct_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return CCT_OK;
+}
+
+cct_ctx* cct_batch_system(cct_batch* b, int s) {
+  if (!b || s < 0 || s >= (int)b->sys.size()) return nullptr;
+  return b->sys[s];
+}
+
+int cct_batch_set_system(cct_batch* b, int s, const double* f, const double* B) {
+  if (!b || s < 0 || s >= (int)b->sys.size()) return CCT_EINVAL;
+  cct_ctx* c = b->sys[s];
+  int rc = cct_set_fock(c, f);
+  if (rc == CCT_OK) rc = cct_set_eri_df(c, B);
+  if (rc == CCT_OK) rc = cct_init_mp2(c);
+  if (rc != CCT_OK) b->err = c->err;
+  return rc;
+}
+
+int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms) {
+  if (!b || niter < 0) return CCT_EINVAL;
+  for (cct_ctx* c : b->sys)
+    if (!c->have_f || !c->have_B) {
+      b->err = "integrals not set for every system (cct_batch_set_system)";
+      return CCT_ESTATE;
+    }
+  if (b->use_graph && !b->exec) RCK(batch_capture(b));
+  const int ns = (int)b->sys.size();
+  for (int it = 0; it < niter; ++it) {
+    if (b->use_graph) {
+      const hipError_t e = hipGraphLaunch(b->exec, b->streams[0]);
+      if (e != hipSuccess) {
+        b->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+        return CCT_EDEVICE;
+      }
+      if (hipStreamSynchronize(b->streams[0]) != hipSuccess) {
+        b->err = "stream synchronisation after graph launch failed";
+        return CCT_EDEVICE;
+      }
+    } else {
+      RCK(batch_enqueue_all(b));
+    }
+    for (int s = 0; s < ns; ++s) {
+      double e = 0.0, nr[3] = {0, 0, 0};
+      const int rc = finish_iteration(b->sys[s], &e, nr);
+      if (rc != CCT_OK) {
+        b->err = "system " + std::to_string(s) + ": " + b->sys[s]->err;
+        return rc;
+      }
+      if (e_corr) e_corr[s] = e;
+      if (norms)
+        for (int k = 0; k < 3; ++k) norms[3 * s + k] = nr[k];
+    }
+  }
+  return CCT_OK;
+}
+
+const char* cct_batch_last_error(const cct_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"

@@ -1,0 +1,76 @@
+"""Converged energies in every precision mode (GPU, through the C ABI).
+
+o=4, v=20 (seed 1): the oracle is iterated to a residual norm below 1e-10
+(DIIS on T1, T2, T3); the GPU FP64 energy must agree within 1e-10 Eh and the
+FP32 and split-BF16 energies within 1 microhartree.
+
+o=10, v=90 (seed 2) with the variance-scaled integrals (the literal recipe
+has no solution reachable from MP2 at this size): the full oracle is out of
+reach of a test, so GPU FP64 (held to the oracle residual by residual in the
+parity tests) converges to 1e-8 and is the reference for the mixed modes,
+which must land within 1 microhartree of it.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import cct_inputs as ci
+from oracle import rccsdt as R
+from paper_2607_00981_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _converge(s, o, v, naux, prec, tol, max_iter):
+    with binding.Engine(o, v, naux, precision=prec) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        hist = []
+        for it in range(max_iter):
+            e, nr = eng.update()
+            n = float(np.sqrt(nr.sum()))
+            hist.append((e, n))
+            if n < tol:
+                break
+    return hist
+
+
+def test_converged_o4v20_all_modes_vs_oracle():
+    o, v, naux, seed = ci.CONFIGS["o4v20"]
+    s = ci.make_system(o, v, naux, seed)
+    f, B = s["f"], s["B"]
+    V = R.eri_phys_from_B(B)
+    t1, t2, t3 = R.mp2_guess(f, V, o)
+    d = R.DIIS()
+    for it in range(200):
+        t1, t2, t3, e_ref, nr = R.iterate(f, V, t1, t2, t3, o, diis=d)
+        if np.sqrt(np.sum(nr)) < 1e-10:
+            break
+    say(f"[converged o4v20] oracle E={e_ref:.12f} after {it+1} iterations")
+    for prec, tol_e in (("fp64", 1e-10), ("fp32", 1e-6), ("bf16x3", 1e-6)):
+        hist = _converge(s, o, v, naux, prec, 1e-10 if prec == "fp64" else 1e-9, 200)
+        e, n = hist[-1]
+        say(f"  {prec}: E={e:.12f} |R|={n:.2e} after {len(hist)} iterations, dE={e - e_ref:.3e}")
+        assert abs(e - e_ref) <= tol_e
+
+
+def test_converged_o10v90_scaled_mixed_vs_fp64():
+    s = ci.make_named("o10v90-scaled")
+    o, v, naux = s["o"], s["v"], s["naux"]
+    ref = _converge(s, o, v, naux, "fp64", 1e-8, 150)
+    e_ref, n_ref = ref[-1]
+    say(f"[converged o10v90-scaled] fp64 E={e_ref:.12f} |R|={n_ref:.2e} after {len(ref)} iterations")
+    assert n_ref < 1e-8
+    for prec in ("fp32", "bf16x3"):
+        hist = _converge(s, o, v, naux, prec, 1e-8, len(ref) + 30)
+        e, n = hist[-1]
+        say(f"  {prec}: E={e:.12f} |R|={n:.2e} after {len(hist)} iterations, dE={e - e_ref:.3e}")
+        assert abs(e - e_ref) <= 1e-6
