@@ -1,5 +1,8 @@
 """Block-level FP64 oracle for large systems (test oracle only).
 
+Test infrastructure: only tests, the smoke check and the CPU baseline of the
+benchmark use this module; the HIP library never does.
+
 At o=20, v=180 the full T3 tensor (o^3 v^3 doubles, 373 GB) does not fit in
 host memory, so the plain full-tensor oracle of ``rccsdt`` cannot run.  This
 module evaluates one output block R3[i,j,k,:,:,:] of the particle-particle
@@ -96,3 +99,50 @@ def postprocess_block(r: np.ndarray, ijk: tuple[int, int, int]) -> np.ndarray:
         r = 0.5 * (r + r.transpose(0, 2, 1))
     m = sum(r.transpose(p) for p in PERMS3) / 6.0
     return r - m
+
+
+def _sum_perms(term_of_occ, ijk):
+    """sum over the six simultaneous column permutations sigma of
+    X_{sigma(ijk)}^{sigma(abc)}, where term_of_occ(occ) returns X_{occ}^{xyz}
+    as an array [x][y][z] (Eq. rcc-perm-op written out)."""
+    out = None
+    for p in PERMS3:
+        occ = tuple(ijk[s] for s in p)
+        y = term_of_occ(occ)
+        inv = [p.index(s) for s in range(3)]
+        out = y.transpose(inv) if out is None else out + y.transpose(inv)
+    return out
+
+
+def f1_block(Fvv: np.ndarray, stored: np.ndarray, ijk) -> np.ndarray:
+    """Raw F^a_d part of the Fock term of R3 for packed block (i,j,k):
+    P[1/2 sum_d F^a_d t_{ijk}^{dbc}] (Eq. resi-rccsdt), Fvv[a][d]."""
+    return _sum_perms(lambda occ: 0.5 * np.einsum("xd,dyz->xyz", Fvv, unpack_block(stored, occ)), ijk)
+
+
+def d1_block(Wvvvo: np.ndarray, t2: np.ndarray, ijk) -> np.ndarray:
+    """Raw T2 driver P[sum_d W^{ab}_{dj} t_{ik}^{dc}] for packed block (i,j,k);
+    Wvvvo[a][b][d][j], t2[i][k][d][c] (Eq. resi-rccsdt)."""
+    return _sum_perms(lambda occ: np.einsum("xyd,dz->xyz", Wvvvo[:, :, :, occ[1]], t2[occ[0], occ[2]]), ijk)
+
+
+def d2_block(Wvooo: np.ndarray, t2: np.ndarray, ijk) -> np.ndarray:
+    """Raw T2 driver P[-sum_l W^{al}_{ij} t_{lk}^{bc}] for packed block (i,j,k);
+    Wvooo[a][l][i][j], t2[l][k][b][c] (Eq. resi-rccsdt)."""
+    return _sum_perms(lambda occ: -np.einsum("xl,lyz->xyz", Wvooo[:, :, occ[0], occ[1]], t2[:, occ[2]]), ijk)
+
+
+def local_terms_block(W, Fvv, Wvvvo, Wvooo, t2, stored, ijk, terms=("PP", "F1", "D1", "D2")):
+    """Post-processed sum of the R3 terms that need only this block of T3
+    (particle-particle ladder, F_vv term, both T2 drivers)."""
+    v = stored.shape[0]
+    r = np.zeros((v, v, v))
+    if "PP" in terms:
+        r += pp_block(W, stored, ijk)
+    if "F1" in terms:
+        r += f1_block(Fvv, stored, ijk)
+    if "D1" in terms:
+        r += d1_block(Wvvvo, t2, ijk)
+    if "D2" in terms:
+        r += d2_block(Wvooo, t2, ijk)
+    return postprocess_block(r, ijk)

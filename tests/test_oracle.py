@@ -287,6 +287,39 @@ def test_block_oracle_matches_full_oracle_pp():
         assert np.abs(got - ref[n]).max() < 1e-15
 
 
+def test_block_oracle_local_terms_match_full_oracle():
+    """The block forms of the F_vv term and the two T2 drivers reproduce the
+    full-tensor oracle's terms (same intermediates) block by block, including
+    blocks with repeated occupied indices."""
+    from oracle import blocks
+
+    o, v = 3, 5
+    rng = np.random.default_rng(23)
+    t2 = rng.normal(0, 0.05, (o, o, v, v))
+    t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
+    t3p = ci.hashed_t3_packed(o, v, 31, 0.02, threads=2)
+    t3 = R.unpack_t3(t3p, o)
+    ims = {"Fvv": rng.normal(0, 0.1, (v, v)), "Foo": rng.normal(0, 0.1, (o, o)),
+           "Woooo": rng.normal(0, 0.1, (o, o, o, o))}
+    ims3 = {"Wvvvo": rng.normal(0, 0.1, (v, v, v, o)), "Wvooo": rng.normal(0, 0.1, (v, o, o, o)),
+            "Wbar_ovvo": rng.normal(0, 0.1, (o, v, v, o)), "Wbar_ovov": rng.normal(0, 0.1, (o, v, o, v)),
+            "Wvvvv": rng.normal(0, 0.1, (v, v, v, v))}
+    parts = R.r3_terms(t2, t3, ims, ims3)
+    for name, fn in (("F1", lambda ijk, n: blocks.f1_block(ims["Fvv"], t3p[n], ijk)),
+                     ("D1", lambda ijk, n: blocks.d1_block(ims3["Wvvvo"], t2, ijk)),
+                     ("D2", lambda ijk, n: blocks.d2_block(ims3["Wvooo"], t2, ijk)),
+                     ("PP", lambda ijk, n: blocks.pp_block(ims3["Wvvvv"], t3p[n], ijk))):
+        full = R.perm_sym3(parts[name])
+        for n, (i, j, k) in enumerate(ci.packed_triples(o)):
+            got = fn((i, j, k), n)
+            assert np.abs(got - full[i, j, k]).max() < 1e-14, (name, (i, j, k))
+    # the combined local sum is the post-processed sum of the four
+    full = R.postprocess_r3(sum(R.perm_sym3(parts[k]) for k in ("PP", "F1", "D1", "D2")))
+    for n, (i, j, k) in enumerate(ci.packed_triples(o)):
+        got = blocks.local_terms_block(ims3["Wvvvv"], ims["Fvv"], ims3["Wvvvo"], ims3["Wvooo"], t2, t3p[n], (i, j, k))
+        assert np.abs(got - full[i, j, k]).max() < 1e-14
+
+
 def test_hashed_t3_symmetry_and_determinism():
     o, v = 3, 6
     a = ci.hashed_t3_packed(o, v, 5, threads=3)
