@@ -177,6 +177,51 @@ cct_ctx* cct_batch_system(cct_batch* b, int s);
 const char* cct_batch_last_error(const cct_batch* b);
 void cct_batch_destroy(cct_batch* b);
 
+/* ---- slab of packed triples ---------------------------------------------
+ * The R3 terms that need only the locally stored T3 blocks, for packed
+ * triples [first, first + count) of an nocc-occupied system: the
+ * particle-particle ladder (paper, Sec. "RCCSDT contractions without
+ * unpacking"), the F_vv part of the Fock term and the two T2*W drivers of
+ * Eq. resi-rccsdt, followed by the R3 post-processing of Sec. "Removing
+ * redundancies in RCC amplitudes".  This is one process's share of a run
+ * sharded by packed triples; T1, T2 and the intermediates are replicated
+ * inputs.  W^{ab}_{de} = sum_P B~^P_{ad} B~^P_{be} + sum_lm v~^{lm}_{de}
+ * t_lm^ab is rebuilt in panels of opts "panel" rows a (default 8) and never
+ * stored whole.  Ladder operands in the working precision (FP32, or hi+lo
+ * BF16 when v^2 is a multiple of 4 or 8; FP64 otherwise); F_vv term and
+ * drivers in FP64; R3 in FP64. */
+typedef struct cct_slab cct_slab;
+
+/* first + count <= nocc(nocc+1)(nocc+2)/6, count <= 65535.  opts_json:
+ * "panel" (rows a per W panel, 1..nvir), "timers" (true: per-phase times
+ * in cct_slab_get_counters).  Errors: CCT_EINVAL, CCT_ENOMEM. */
+int cct_slab_create(int nocc, int nvir, int naux, int first, int count, cct_precision prec, const char* opts_json,
+                    void* hip_stream, cct_slab** out);
+/* Replicated inputs (host arrays, copied in): Bt = T1-dressed factors
+ * B~[naux][n][n] (Appendix A, "T1-dressed formalism"), t2 [o][o][v][v]
+ * (t_ij^ab = t_ji^ba), Fvv [a][d] = F^a_d, Wt [j][a][b][d] = W^{ab}_{dj},
+ * Wvooo [a][l][i][j] = W^{al}_{ij}. */
+int cct_slab_set_intermediates(cct_slab* sl, const double* Bt, const double* t2, const double* Fvv,
+                               const double* Wt, const double* Wvooo);
+/* The slab's stored T3 blocks, t3slab [count][v][v][v] (host). */
+int cct_slab_set_t3(cct_slab* sl, const double* t3slab);
+/* R3 of the slab for term_mask within CCT_TERM_PP | CCT_TERM_F1 |
+ * CCT_TERM_D1 | CCT_TERM_D2 (CCT_EINVAL otherwise; F1 here is the F_vv part
+ * only), post-processed.  r3slab [count][v][v][v] (host, may be NULL);
+ * norm2 = sum over the slab of multiplicity x squared elements.
+ * CCT_ESTATE before both setters, CCT_ENUMERIC on a non-finite norm. */
+int cct_slab_residual(cct_slab* sl, unsigned term_mask, double* r3slab, double* norm2);
+/* Copy count elements of the slab's R3 from element offset first (host). */
+int cct_slab_copy_r3(cct_slab* sl, int64_t first, int64_t count, double* out);
+/* Multiply-adds of the last residual: [0] ladder 3 count v^5, [1] W rebuild
+ * (naux + o^2) v^4, [2] F_vv 3 count v^4, [3] W^{ab}_{dj} driver 6 count v^4,
+ * [4] W^{al}_{ij} driver 6 count o v^3, [5] 0; milliseconds (with "timers"):
+ * [0] T3 relabelling, [1] W rebuild, [2] ladder GEMMs, [3] F_vv, [4] drivers,
+ * [5] post-processing.  Writes min(cap, 6) of each. */
+int cct_slab_get_counters(cct_slab* sl, double* macs, double* ms, int cap);
+const char* cct_slab_last_error(const cct_slab* sl);
+void cct_slab_destroy(cct_slab* sl);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,15 @@ def load(path: str | None = None):
         "cct_batch_system": (vp, [vp, C.c_int]),
         "cct_batch_last_error": (C.c_char_p, [vp]),
         "cct_batch_destroy": (None, [vp]),
+        "cct_slab_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp,
+                                      C.POINTER(vp)]),
+        "cct_slab_set_intermediates": (C.c_int, [vp, dp, dp, dp, dp, dp]),
+        "cct_slab_set_t3": (C.c_int, [vp, dp]),
+        "cct_slab_residual": (C.c_int, [vp, C.c_uint, dp, dp]),
+        "cct_slab_copy_r3": (C.c_int, [vp, C.c_int64, C.c_int64, dp]),
+        "cct_slab_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
+        "cct_slab_last_error": (C.c_char_p, [vp]),
+        "cct_slab_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +282,77 @@ class Batch:
         if not h:
             raise IndexError(s)
         return _SystemView(self.lib, C.c_void_p(h), o, v, na)
+
+
+SLAB_MACS = ("ladder", "w_rebuild", "f_vv", "driver_vvvo", "driver_vooo")
+SLAB_PHASES = ("views", "w_rebuild", "ladder", "f_vv", "drivers", "post")
+
+
+class Slab:
+    """The block-local R3 terms for packed triples [first, first + count)."""
+
+    def __init__(self, nocc, nvir, naux, first, count, precision="fp64", opts=None, stream=None):
+        import json
+
+        self.lib = load()
+        self.o, self.v, self.naux, self.first, self.count = nocc, nvir, naux, first, count
+        self.n = nocc + nvir
+        js = json.dumps(opts).encode() if opts else None
+        h = C.c_void_p()
+        rc = self.lib.cct_slab_create(nocc, nvir, naux, first, count, PRECISIONS[precision], js, stream, C.byref(h))
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_slab_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cct_slab_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_intermediates(self, Bt, t2, Fvv, Wt, Wvooo):
+        o, v, n = self.o, self.v, self.n
+        Bt = _in(Bt, (self.naux, n, n))
+        t2 = _in(t2, (o, o, v, v))
+        Fvv = _in(Fvv, (v, v))
+        Wt = _in(Wt, (o, v, v, v))
+        Wvooo = _in(Wvooo, (v, o, o, o))
+        self._check(self.lib.cct_slab_set_intermediates(self.h, _ptr(Bt), _ptr(t2), _ptr(Fvv), _ptr(Wt),
+                                                        _ptr(Wvooo)))
+
+    def set_t3(self, t3slab):
+        t3slab = _in(t3slab, (self.count, self.v, self.v, self.v))
+        self._check(self.lib.cct_slab_set_t3(self.h, _ptr(t3slab)))
+
+    def residual(self, terms=("PP", "F1", "D1", "D2"), want_r3=True):
+        mask = terms if isinstance(terms, int) else sum(TERMS[t] for t in terms)
+        r3 = np.empty((self.count, self.v, self.v, self.v)) if want_r3 else None
+        n2 = C.c_double()
+        self._check(self.lib.cct_slab_residual(self.h, mask, _ptr(r3), C.byref(n2)))
+        return r3, n2.value
+
+    def copy_r3(self, first, count):
+        out = np.empty(count)
+        self._check(self.lib.cct_slab_copy_r3(self.h, first, count, _ptr(out)))
+        return out
+
+    def counters(self):
+        macs = np.zeros(6)
+        ms = np.zeros(6)
+        self._check(self.lib.cct_slab_get_counters(self.h, _ptr(macs), _ptr(ms), 6))
+        return dict(zip(SLAB_MACS, macs)), dict(zip(SLAB_PHASES, ms))
