@@ -154,6 +154,48 @@ def run_batched(binding, niter, modes):
             "note": f"dE: energy after {niter} iterations minus the {modes[0]} batch's, per system"}
 
 
+SLAB = {"o": 50, "v": 400, "naux": 900, "seed": 5, "first": 0, "count": 64}
+
+
+def run_slab(binding, modes, panel):
+    """One process's share of a run sharded by packed triples: the block-local
+    R3 terms (ladder with W^{ab}_{de} rebuilt in panels from the factors,
+    F_vv term, T2 drivers, post-processing) for packed triples 0..63 at
+    o=50, v=400, naux=900."""
+    o, v, naux, seed = SLAB["o"], SLAB["v"], SLAB["naux"], SLAB["seed"]
+    first, count = SLAB["first"], SLAB["count"]
+    threads = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8)
+    t0 = time.time()
+    s = ci.make_system(o, v, naux, seed)
+    Bt = s["B"]  # T1 = 0: the dressed factors are the bare ones
+    _, t2, _ = ci.random_amplitudes(o, v, seed, 0.0, 0.01, 0.0, triples=False)
+    Fvv = ci.hashed_uniform((v, v), seed * 7 + 1, 0.1, threads)
+    Wt = ci.hashed_uniform((o, v, v, v), seed * 7 + 2, 0.01, threads)
+    Wvooo = ci.hashed_uniform((v, o, o, o), seed * 7 + 3, 0.01, threads)
+    t3 = ci.hashed_t3_slab(o, v, seed, first, count, 0.01, threads)
+    log(f"[bench] slab inputs ready in {time.time() - t0:.1f} s")
+    out = {}
+    for prec in modes:
+        with binding.Slab(o, v, naux, first, count, precision=prec, opts={"panel": panel, "timers": True}) as sl:
+            t1_ = time.time()
+            sl.set_intermediates(Bt, t2, Fvv, Wt, Wvooo)
+            sl.set_t3(t3)
+            log(f"[bench] slab {prec}: inputs uploaded in {time.time() - t1_:.1f} s; residual ...")
+            tr = time.perf_counter()
+            _, n2 = sl.residual(want_r3=False)
+            wall = time.perf_counter() - tr
+            macs, ms = sl.counters()
+        step_macs = macs["ladder"] + macs["f_vv"] + macs["driver_vvvo"] + macs["driver_vooo"]
+        rec = {"s_per_residual": wall, "tflops": 2.0 * step_macs / wall / 1e12,
+               "tflops_with_rebuild": 2.0 * (step_macs + macs["w_rebuild"]) / wall / 1e12,
+               "ladder_tflops": 2.0 * macs["ladder"] / (ms["ladder"] / 1000.0) / 1e12,
+               "peak": PEAK[prec], "phase_ms": ms, "norm2": n2}
+        rec["ladder_frac"] = rec["ladder_tflops"] / PEAK[prec]
+        out[prec] = rec
+        log(f"[bench] slab {prec}: {rec}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +211,9 @@ def main():
                     help="iterations of the 64-system batch per mode (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (reference for the HBM byte counters)")
+    ap.add_argument("--slab", action="store_true",
+                    help="only the block-local terms of a 64-triple slab at o=50 v=400 (FP32 and split-BF16)")
+    ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
@@ -188,6 +233,28 @@ def main():
         return
 
     from paper_2607_00981_amd import binding
+
+    if args.slab:
+        modes = [m for m in ("fp32", "bf16x3") if m in [args.precision] + args.compare.split(",")]
+        res = run_slab(binding, modes, args.panel)
+        best = max(res, key=lambda m: res[m]["tflops"])
+        r = res[best]
+        ladder_ms = r["phase_ms"]["ladder"]
+        print(json.dumps({
+            "metric": "slab step (iv) TFLOP/s vs matrix peak, o=50 v=400, 64 packed triples",
+            "value": r["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1000.0 * r["s_per_residual"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
+            "config": {"workload": "block-local R3 terms (ladder with W^ab_de rebuilt in panels, F_vv, T2 drivers, "
+                                   "post-processing) for packed triples 0..63 of o=50 v=400 naux=900 seed 5",
+                       "precision": best, "panel": args.panel},
+            "modes": res,
+            "roofline": {"bound": "mfma", "achieved": r["ladder_tflops"], "peak": r["peak"], "unit": "TFLOP/s",
+                         "frac": r["ladder_frac"], "traffic": None,
+                         "kernel": f"gemm_lp_{best.replace('fp32', 'f32')}_kernel (ladder GEMMs, "
+                                   f"{ladder_ms:.0f} ms over all panels)"},
+        }), flush=True)
+        return
 
     o, v, naux, seed = ci.CONFIGS[args.workload]
     s = ci.make_system(o, v, naux, seed)
