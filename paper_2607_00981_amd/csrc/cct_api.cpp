@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -432,7 +433,7 @@ int build_plans(cct_ctx* ctx) {
   for (Job* J : {&ctx->feed1}) {
     for (int f = 0; f < o; ++f) J->slots.push_back(int2{f, 0});
     J->nslot_total = o;
-    J->per_batch = slots_per_batch(budget, o2v3, o);
+    J->per_batch = slots_per_batch(budget, 2 * o2v3, o);
     const int S = J->per_batch;
     for (int b = 0; b * S < o; ++b) {
       Batch B;
@@ -682,77 +683,114 @@ int ccsd_part(cct_ctx* ctx) {
 // U_f[o1][o2][x][y][z] = t~_{f o1 o2}^{xyz} (single check on column 1) is
 // unpacked once and contracted five ways; R1's double check is rebuilt from
 // the same slab: t~_{j'k'i}^{b'c'a} = 2 U_j[k][i][b][c][a] - U_j[k][i][b][a][c].
+// K-contiguous product C = alpha A B^T + beta C (A: M x K rows of lda, B: N x K
+// rows of ldb): the matrix-core NT kernel when its alignment rules hold, the
+// generic strided kernel otherwise.
+int nt_or_generic(cct_ctx* ctx, int M, int N, long long K, const double* A, long long lda, long long a_len,
+                  const double* B, long long ldb, long long b_len, double* C, Idx2 cm, Idx2 cn, long long c_len,
+                  double alpha, double beta) {
+  const bool even = !(K & 1) && !(lda & 1) && !(ldb & 1) && !((uintptr_t)A & 15) && !((uintptr_t)B & 15);
+  if (K > INT_MAX) { ctx->err = "contraction length exceeds int"; return CCT_EINVAL; }
+  if (even) {
+    NtArgs g{};
+    g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+    g.C = C; g.cm = cm; g.cn = cn;
+    g.alpha = alpha; g.beta = beta;
+    g.a_len = a_len; g.b_len = b_len; g.c_len = c_len;
+    HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+  } else {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
+    g.A = A; g.am = idx1(lda); g.ak = idx1(1);
+    g.B = B; g.bk = idx1(1); g.bn = idx1(ldb);
+    g.C = C; g.cm = cm; g.cn = cn;
+    g.alpha = alpha; g.beta = beta;
+    g.a_len = a_len; g.b_len = b_len; g.c_len = c_len;
+    HIPCK(gemm(g, Prec::F64, ctx->s));
+  }
+  return CCT_OK;
+}
+
+// T3 -> R1, R2, W^{ab}_{dj}, W^{al}_{ij} (Eq. resi-rccsdt feedback terms and
+// the T3 parts of the two RCCSDT intermediates).  For a batch of S slots f,
+// the single-check spin-summed amplitudes t~_{f..}^{...} are unpacked twice,
+// in the two layouts that make every contraction one K-contiguous GEMM with
+// the slot index folded into K:
+//   UA[(i,j,a)][f][(p,q)] = t~_{fij}^{q a p}   (K = f, two virtuals)
+//   UB[(i,a,b)][f][(k,c)] = t~_{fik}^{c a b}   (K = f, occupied, virtual)
+// and
+//   X2[ij][ab] +=  sum_{fcd} v~^{bf}_{cd} t~_{fij}^{dac} + 1/2 sum_{fc} f~^f_c t~_{fij}^{cab}   (UA, one GEMM:
+//                  the Fock term rides on the diagonal p = b of the integral rows)
+//   X2[ij][ab] -=  sum_{fkc} v~^{kf}_{jc} t~_{fik}^{cab}                                         (UB)
+//   W^{ab}_{dj} -= sum_{fle} v~^{lf}_{de} t~_{fjl}^{eba}                                         (UB)
+//   W^{al}_{ij} += sum_{fde} v~^{lf}_{de} t~_{fij}^{ead}                                         (UA)
+//   R1[ia]      += 1/2 sum v~^{jk}_{bc} (2 t~_{jki}^{bca} - t~_{jki}^{bac})                        (UA, reduction kernel)
 int feedback(cct_ctx* ctx) {
   const int o = ctx->o, v = ctx->v, n = ctx->n;
   const long long v2 = (long long)v * v, v3 = ctx->v3, o2v3 = (long long)o * o * v3;
+  const long long ov = (long long)o * v, o2v2 = ov * ov;
   hipStream_t s = ctx->s;
   Arena& ws = ctx->ws;
-  const Prec F = Prec::F64;
-  DT X2 = dense(ctx->X2, {o, o, v, v});
-  DT Wt = dense(ctx->Wt, {v, o, v, v});
-  DT Wvooo = dense(ctx->Wvooo, {v, o, o, o});
   const size_t mk0 = ws.mark();
-  // contiguous integral slices, one row per fixed occupied index f
-  double* Vb = ws.alloc((size_t)(o * v3));                 // [k][b][c][d] = v~^{bk}_{cd}
-  double* Vc = ws.alloc((size_t)o * o * o * v);            // [f][j][k][c] = v~^{kf}_{jc}
-  double* Vd = ws.alloc((size_t)o * o * v2);               // [f][d][l][e] = v~^{lf}_{de}
-  double* Ve = ws.alloc((size_t)o * o * v2);               // [f][l][d][e] = v~^{lf}_{de}
-  double* vv = ws.alloc((size_t)o * o * v2);               // [j][k][b][c] = v~^{jk}_{bc}
-  if (!Vb || !Vc || !Vd || !Ve || !vv) { ctx->err = "workspace exhausted (feedback slices)"; return CCT_ENOMEM; }
-  STCK(accumulate(s, 1.0, Vv(ctx, "vovv"), "bkcd", 0.0, dense(Vb, {o, v, v, v}), "kbcd"));
-  STCK(accumulate(s, 1.0, Vv(ctx, "ooov"), "kfjc", 0.0, dense(Vc, {o, o, o, v}), "fjkc"));
-  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(Vd, {o, v, o, v}), "fdle"));
-  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(Ve, {o, o, v, v}), "flde"));
-  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "jkbc", 0.0, dense(vv, {o, o, v, v}), "jkbc"));
+  // integral slices with the summed slot index next to the contracted pair
+  double* VbT = ws.alloc((size_t)(o * v3));            // [b][f][c][d] = v~^{bf}_{cd} (+ 1/2 f~ on c = b)
+  double* VcT = ws.alloc((size_t)o * o * o * v);       // [j][f][k][c] = v~^{kf}_{jc}
+  double* VdT = ws.alloc((size_t)o2v2);                // [d][f][l][e] = v~^{lf}_{de}
+  double* VeT = ws.alloc((size_t)o2v2);                // [l][f][d][e] = v~^{lf}_{de}
+  double* vvT = ws.alloc((size_t)o2v2);                // [j][k][c][b] = v~^{jk}_{bc}
+  if (!VbT || !VcT || !VdT || !VeT || !vvT) { ctx->err = "workspace exhausted (feedback slices)"; return CCT_ENOMEM; }
+  STCK(accumulate(s, 1.0, Vv(ctx, "vovv"), "bfcd", 0.0, dense(VbT, {v, o, v, v}), "bfcd"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "ooov"), "kfjc", 0.0, dense(VcT, {o, o, o, v}), "jfkc"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(VdT, {v, o, o, v}), "dfle"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "lfde", 0.0, dense(VeT, {o, o, v, v}), "lfde"));
+  STCK(accumulate(s, 1.0, Vv(ctx, "oovv"), "jkbc", 0.0, dense(vvT, {o, o, v, v}), "jkcb"));
+  // VbT[b][f][b][q] += 1/2 f~^f_{v_q}
+  HIPCK(add_diag_rows(VbT, ctx->ft + o, v, o, v, (long long)o * v2, v2, v, 1, n, 0.5, s));
   for (const Batch& b : ctx->feed1.batches) {
     const size_t mk = ws.mark();
-    double* U = ws.alloc((size_t)(b.nslots * o2v3));
-    double* part = ws.alloc((size_t)b.nslots * o * o * v);
-    if (!U || !part) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
-    UnpackArgs ua{};
-    ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
-    const int occ[3] = {0, 2, 3};
-    set_s1(ua, occ);
-    ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
-    ua.s_x = v2; ua.s_y = v; ua.s_z = 1;
-    HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, s));
-    // (a) 1/2 f~^k_c t~_{kij}^{cab}: k runs over the batch
+    const int S = b.nslots, f0 = b.slot0;
+    const long long slab = (long long)S * o2v3;
+    double* UA = ws.alloc((size_t)slab);
+    double* UB = ws.alloc((size_t)slab);
+    if (!UA || !UB) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
+    const int occ[3] = {0, 2, 3};  // t~_{f, free0, free1}
     {
-      DT fk = strided(ctx->ft + (long long)b.slot0 * n + o, {b.nslots, v}, {n, 1});
-      DT Ub = dense(U, {b.nslots, o, o, v, v, v});
-      STCK(contract(ws, s, F, 0.5, fk, "kc", Ub, "kijcab", 1.0, X2, "ijab"));
+      UnpackArgs ua{};
+      ua.o = o; ua.v = v; ua.nslots = S; ua.nfree = 2;
+      set_s1(ua, occ);
+      const long long row = (long long)S * v2;  // one (i,j,a) row
+      ua.s_slot = v2; ua.s_free[0] = (long long)o * v * row; ua.s_free[1] = v * row;
+      ua.s_x = 1; ua.s_y = row; ua.s_z = v; ua.fast = 2;  // (x,y,z) = (q,a,p)
+      HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, UA, ua, s));
     }
-    for (int ls = 0; ls < b.nslots; ++ls) {
-      const int f = b.slot0 + ls;
-      DT Uf = dense(U + ls * o2v3, {o, o, v, v, v});
-      // (b) sum_cd v~^{bk}_{cd} t~_{kij}^{dac}
-      STCK(contract(ws, s, F, 1.0, dense(Vb + (long long)f * v3, {v, v, v}), "bcd", Uf, "ijdac", 1.0, X2, "ijab"));
-      // (c) - sum_kc v~^{kl}_{jc} t~_{lik}^{cab}
-      STCK(contract(ws, s, F, -1.0, dense(Vc + (long long)f * o * o * v, {o, o, v}), "jkc", Uf, "ikcab", 1.0, X2,
-                    "ijab"));
-      // (d) W^{ab}_{dj} -= sum_le v~^{lm}_{de} t~_{mjl}^{eba}
-      STCK(contract(ws, s, F, -1.0, dense(Vd + (long long)f * o * v2, {v, o, v}), "dle", Uf, "jleba", 1.0, Wt,
-                    "djba"));
-      // (e) W^{al}_{ij} += sum_de v~^{lm}_{de} t~_{mij}^{ead}
-      STCK(contract(ws, s, F, 1.0, dense(Ve + (long long)f * o * v2, {o, v, v}), "lde", Uf, "ijead", 1.0, Wvooo,
-                    "alij"));
-    }
-    // R1 += 1/2 sum_jkbc v~^{jk}_{bc} (2 U_j[k][i][b][c][a] - U_j[k][i][b][a][c]), as partial sums
-    // over (j,k) pairs: part[(j,k)][(i,a)]
     {
-      GemmArgs g{};
-      g.M = 1; g.N = o * v; g.K = (int)v2; g.batch = b.nslots * o;
-      g.A = vv + (long long)b.slot0 * o * v2; g.am = idx1(0); g.ak = idx1(1); g.a_batch = v2;
-      g.B = U; g.bk = idx1(v); g.bn = idx2(v, v3, 1); g.b_batch = (long long)o * v3;
-      g.C = part; g.cm = idx1(0); g.cn = idx1(1); g.c_batch = (long long)o * v;
-      g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = (long long)(o - b.slot0) * o * v2; g.b_len = b.nslots * o2v3; g.c_len = (long long)b.nslots * o * o * v;
-      HIPCK(gemm(g, F, s));
-      g.bk = idx2(v, v2, 1); g.bn = idx2(v, v3, v);
-      g.alpha = -0.5; g.beta = 1.0;
-      HIPCK(gemm(g, F, s));
-      HIPCK(add_rows(part, b.nslots * o, (long long)o * v, ctx->r1, s));
+      UnpackArgs ua{};
+      ua.o = o; ua.v = v; ua.nslots = S; ua.nfree = 2;
+      set_s1(ua, occ);
+      const long long row = (long long)S * ov;  // one (i,a,b) row
+      ua.s_slot = ov; ua.s_free[0] = v2 * row; ua.s_free[1] = v;
+      ua.s_x = 1; ua.s_y = v * row; ua.s_z = row; ua.fast = 2;  // (x,y,z) = (c,a,b)
+      HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, UB, ua, s));
     }
+    const long long KA = (long long)S * v2, KB = (long long)S * ov;
+    // X2[(i,j,a)][b] += UA[(i,j,a)][K] VbT[b][f0.. K]
+    RCK(nt_or_generic(ctx, (int)((long long)o * o * v), v, KA, UA, KA, slab, VbT + (long long)f0 * v2,
+                      (long long)o * v2, (long long)o * v3 - (long long)f0 * v2, ctx->X2, idx1(v), idx1(1), o2v2,
+                      1.0, 1.0));
+    // W^{al}_{ij}: C[l][(i,j,a)] = VeT[l][f0.. K] UA[(i,j,a)][K], stored [a][l][i][j]
+    RCK(nt_or_generic(ctx, o, (int)((long long)o * o * v), KA, VeT + (long long)f0 * v2, (long long)o * v2,
+                      o2v2 - (long long)f0 * v2, UA, KA, slab, ctx->Wvooo, idx1((long long)o * o),
+                      idx2(v, 1, (long long)o * o * o), (long long)v * o * o * o, 1.0, 1.0));
+    // X2[(i,a,b)][j] -= UB[(i,a,b)][K] VcT[j][f0.. K]
+    RCK(nt_or_generic(ctx, (int)(o * v2), o, KB, UB, KB, slab, VcT + (long long)f0 * ov, (long long)o * ov,
+                      (long long)o * o * ov - (long long)f0 * ov, ctx->X2, idx2((int)v2, (long long)o * v2, 1),
+                      idx1(v2), o2v2, -1.0, 1.0));
+    // W^{ab}_{dj}: C[d][(j,b,a)] -= VdT[d][f0.. K] UB[(j,b,a)][K], stored [d][j][b][a]
+    RCK(nt_or_generic(ctx, v, (int)(o * v2), KB, VdT + (long long)f0 * ov, (long long)o * ov,
+                      o2v2 - (long long)f0 * ov, UB, KB, slab, ctx->Wt, idx1((long long)o * v2), idx1(1),
+                      (long long)v * o * v2, -1.0, 1.0));
+    HIPCK(feedback_r1(UA, vvT, ctx->r1, o, v, S, f0, s));
     ws.reset(mk);
   }
   ws.reset(mk0);

@@ -168,6 +168,12 @@ hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, in
 // y = a*x + b*y (elementwise, n elements)
 hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s);
 hipError_t fill(double* y, double val, long long n, hipStream_t s);
+// R1[i][a] += 1/2 sum_{j in [f0, f0+S), k, b, c} vvT[j][k][c][b] (2 U[(k,i,c)][j-f0][a][b] - U[(k,i,a)][j-f0][c][b])
+// with U[(k,i,x)][j'][p][q] the single-check spin-summed slab t~_{j k i}^{q x p} (one block per (i,a)).
+hipError_t feedback_r1(const double* U, const double* vvT, double* r1, int o, int v, int S, int f0, hipStream_t s);
+// Y[b*sb + f*sf + b*sp + q*sq] += alpha * X[f*xf + q] for b < nb, f < nf, q < nq.
+hipError_t add_diag_rows(double* Y, const double* X, int nb, int nf, int nq, long long sb, long long sf, long long sp,
+                         long long sq, long long xf, double alpha, hipStream_t s);
 // out[i] += sum_r in[r * n + i] for r = 0..rows-1 (fixed order).
 hipError_t add_rows(const double* in, int rows, long long n, double* out, hipStream_t s);
 // Jacobi update of T1 / T2 with denominators built from eps.

@@ -458,6 +458,71 @@ hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// T3 -> R1 feedback from one batch of spin-summed slabs (see feedback_r1)
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void r1_feedback_kernel(const double* __restrict__ U, const double* __restrict__ vvT,
+                                   double* __restrict__ r1, int o, int v, int S, int f0) {
+  __shared__ double red[TPB];
+  const int ia = blockIdx.x;
+  const int i = ia / v, a = ia - (ia / v) * v;
+  const long long v2 = (long long)v * v, rowS = (long long)S * v2;
+  double acc = 0.0;
+  for (int jj = 0; jj < S; ++jj) {
+    for (int k = 0; k < o; ++k) {
+      const double* M = vvT + ((long long)(f0 + jj) * o + k) * v2;            // [c][b]
+      const double* U1 = U + ((long long)(k * o + i) * v) * rowS + jj * v2 + (long long)a * v;  // + c rowS + b
+      const double* U2 = U + ((long long)(k * o + i) * v + a) * rowS + jj * v2;              // + c v + b
+      for (long long e = threadIdx.x; e < v2; e += TPB) {
+        const int c = (int)(e / v), b = (int)(e - (long long)c * v);
+        acc += M[e] * (2.0 * U1[(long long)c * rowS + b] - U2[e]);
+      }
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) r1[ia] += 0.5 * red[0];
+}
+
+// Y[b*sb + f*sf + b*sp + q*sq] += alpha * X[f*xf + q] for b < nb, f < nf, q < nq.
+__global__ void add_diag_rows_kernel(double* __restrict__ Y, const double* __restrict__ X, int nb, int nf, int nq,
+                                     long long sb, long long sf, long long sp, long long sq, long long xf,
+                                     double alpha) {
+  const long long total = (long long)nb * nf * nq;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(e % nq);
+    const long long r = e / nq;
+    const int f = (int)(r % nf);
+    const int b = (int)(r / nf);
+    Y[b * (sb + sp) + f * sf + q * sq] += alpha * X[f * xf + q];
+  }
+}
+
+}  // namespace
+
+hipError_t feedback_r1(const double* U, const double* vvT, double* r1, int o, int v, int S, int f0,
+                       hipStream_t s) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(r1_feedback_kernel, dim3((unsigned)(o * v)), dim3(TPB), 0, s, U, vvT, r1, o, v, S, f0);
+  return hipGetLastError();
+}
+
+hipError_t add_diag_rows(double* Y, const double* X, int nb, int nf, int nq, long long sb, long long sf, long long sp,
+                         long long sq, long long xf, double alpha, hipStream_t s) {
+  const long long total = (long long)nb * nf * nq;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(add_diag_rows_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, Y, X, nb, nf, nq, sb,
+                     sf, sp, sq, xf, alpha);
+  return hipGetLastError();
+}
+
 hipError_t add_pair_diag(double* W, const double* F, long long ldF, int nx, double c, hipStream_t s) {
   const long long n3 = (long long)nx * nx * nx;
   hipLaunchKernelGGL(pair_diag_kernel, dim3(blocks_for(n3, TPB * 4)), dim3(TPB), 0, s, W, F, ldF, nx, c, 0);
