@@ -52,9 +52,22 @@ __global__ void permute_add_kernel(const double* __restrict__ X, double* __restr
 // ---------------------------------------------------------------------------
 // T3 unpacking
 // ---------------------------------------------------------------------------
-// grid.y enumerates (slot, free indices); grid.x covers the v^3 virtual block.
-__global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __restrict__ tbl,
-                              const int2* __restrict__ slots, OutSpec out, UnpackArgs a) {
+// grid.y enumerates (slot, free indices); grid.x enumerates tiles of the v^3 virtual block.
+// LDS-staged unpack.  One workgroup builds one UT x UT x UT tile of one
+// output block.  Each term is gathered with the threads running along the
+// axis that is unit-stride in that term's stored block (coalesced 128-byte
+// row segments whatever the virtual permutation) and accumulated into the
+// LDS tile; the tile is then written with the threads running along the
+// output's unit-stride axis.
+constexpr int UT = 16;
+constexpr int UP_Z = UT + 1;            // pitch of y rows in the LDS tile
+constexpr int UP_X = UT * UP_Z + 1;     // pitch of x planes
+
+__global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restrict__ T,
+                                                           const BlockRef* __restrict__ tbl,
+                                                           const int2* __restrict__ slots, OutSpec out,
+                                                           UnpackArgs a, int nt) {
+  __shared__ double L[UT * UP_X];
   const int o = a.o, v = a.v;
   const int nfc = (a.nfree == 2) ? o * o : o;
   const int sy_ = blockIdx.y;
@@ -64,61 +77,120 @@ __global__ void unpack_kernel(const double* __restrict__ T, const BlockRef* __re
   const int f1 = (a.nfree == 2) ? fc - f0 * o : 0;
   const int2 fx = slots[slot];
   const int ids[4] = {fx.x, fx.y, f0, f1};
-  // per-term block references
-  const long long v3 = (long long)v * v * v;
-  BlockRef br[6];
-#pragma unroll
-  for (int t = 0; t < 6; ++t) {
-    if (t < a.nterms) {
-      const int p = ids[a.terms[t].occ[0]], q = ids[a.terms[t].occ[1]], r = ids[a.terms[t].occ[2]];
-      br[t] = tbl[((long long)p * o + q) * o + r];
-    }
-  }
+  const int tile = blockIdx.x;
+  const int t2 = tile % nt, t1 = (tile / nt) % nt, t0 = tile / (nt * nt);
+  const int base[3] = {t0 * UT, t1 * UT, t2 * UT};  // x, y, z origins
   const long long obase = (long long)slot * a.s_slot + (long long)f0 * a.s_free[0] + (long long)f1 * a.s_free[1];
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
-    const int i0 = (int)(e / ((long long)v * v));
-    const int rem = (int)(e - (long long)i0 * v * v);
-    const int i1 = rem / v;
-    const int i2 = rem - i1 * v;
-    // i2 runs fastest across threads; it is z (fast 0), y (fast 1) or x (fast 2)
-    int xyz[3];
-    if (a.fast == 0) { xyz[0] = i0; xyz[1] = i1; xyz[2] = i2; }
-    else if (a.fast == 1) { xyz[0] = i0; xyz[2] = i1; xyz[1] = i2; }
-    else { xyz[1] = i0; xyz[2] = i1; xyz[0] = i2; }
-    const int x = xyz[0], y = xyz[1], z = xyz[2];
-    double val = 0.0;
+  for (int t = 0; t < a.nterms; ++t) {
+    const UnpackTerm& tm = a.terms[t];
+    const int p = ids[tm.occ[0]], q = ids[tm.occ[1]], r = ids[tm.occ[2]];
+    const BlockRef br = tbl[((long long)p * o + q) * o + r];
+    // output axis read by the unit-stride stored axis
+    int u = 2;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      if (t < a.nterms) {
-        const UnpackTerm& tm = a.terms[t];
-        const long long off = br[t].off + (long long)xyz[tm.virt[0]] * br[t].s[0] +
-                              (long long)xyz[tm.virt[1]] * br[t].s[1] + (long long)xyz[tm.virt[2]] * br[t].s[2];
-        val += tm.coef * T[off];
-      }
+    for (int m = 0; m < 3; ++m)
+      if (br.s[m] == 1) u = tm.virt[m];
+    const int ua = (u + 1) % 3, ub = (u + 2) % 3;
+    // stride of each output axis in the stored block
+    long long st[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) st[tm.virt[m]] = br.s[m];
+    // all loads of this thread first (independent, in flight together), then the LDS updates
+    constexpr int PER = UT * UT * UT / 256;
+    double vals[PER];
+    int lds[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * 256;
+      int c[3];
+      c[u] = e % UT;
+      c[ua] = (e / UT) % UT;
+      c[ub] = e / (UT * UT);
+      const int x = base[0] + c[0], y = base[1] + c[1], z = base[2] + c[2];
+      const bool ok = x < v && y < v && z < v;
+      lds[it] = ok ? c[0] * UP_X + c[1] * UP_Z + c[2] : -1;
+      vals[it] = ok ? T[br.off + x * st[0] + y * st[1] + z * st[2]] : 0.0;
     }
-    put_out(out, obase + (long long)x * a.s_x + (long long)y * a.s_y + (long long)z * a.s_z, val);
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      if (lds[it] < 0) continue;
+      const double val = tm.coef * vals[it];
+      L[lds[it]] = (t == 0) ? val : L[lds[it]] + val;
+    }
+    __syncthreads();
+  }
+  // write the tile along the output's unit-stride axis (fast: 0 = z, 1 = y, 2 = x)
+  const int w = a.fast == 0 ? 2 : (a.fast == 1 ? 1 : 0);
+  const int wa = (w + 1) % 3, wb = (w + 2) % 3;
+  const long long so[3] = {a.s_x, a.s_y, a.s_z};
+  for (int e = threadIdx.x; e < UT * UT * UT; e += blockDim.x) {
+    int c[3];
+    c[w] = e % UT;
+    c[wa] = (e / UT) % UT;
+    c[wb] = e / (UT * UT);
+    const int x = base[0] + c[0], y = base[1] + c[1], z = base[2] + c[2];
+    if (x >= v || y >= v || z >= v) continue;
+    put_out(out, obase + x * so[0] + y * so[1] + z * so[2], L[c[0] * UP_X + c[1] * UP_Z + c[2]]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // fold temporary blocks into packed R3 (one output block per task)
 // ---------------------------------------------------------------------------
-__global__ void fold_kernel(double* __restrict__ R, long long bs, int v, const double* __restrict__ Z,
-                            const FoldTask* __restrict__ tasks, const FoldContrib* __restrict__ contribs) {
+// One workgroup per UT^3 tile of one output block: the R tile is staged in
+// LDS, each contribution is added with the threads running along the axis
+// that is unit-stride in Z for that contribution (coalesced reads for any
+// virtual permutation), and the tile is written back along c.
+__global__ __launch_bounds__(256) void fold_tiled_kernel(double* __restrict__ R, long long bs, int v,
+                                                         const double* __restrict__ Z,
+                                                         const FoldTask* __restrict__ tasks,
+                                                         const FoldContrib* __restrict__ contribs, int nt) {
+  __shared__ double L[UT * UP_X];
+  constexpr int PER = UT * UT * UT / 256;
   const FoldTask tk = tasks[blockIdx.y];
-  const long long v3 = (long long)v * v * v;
+  const long long v2 = (long long)v * v;
   double* Rt = R + (long long)tk.t * bs;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
-    const int a = (int)(e / ((long long)v * v));
-    const int rem = (int)(e - (long long)a * v * v);
-    const int b = rem / v;
-    const int c = rem - b * v;
-    double acc = Rt[e];
-    for (int i = 0; i < tk.nc; ++i) {
-      const FoldContrib fc = contribs[tk.c0 + i];
-      acc += fc.coef * Z[fc.base + (long long)a * fc.sa + (long long)b * fc.sb + (long long)c * fc.sc];
+  const int tile = blockIdx.x;
+  const int t2 = tile % nt, t1 = (tile / nt) % nt, t0 = tile / (nt * nt);
+  const int base[3] = {t0 * UT, t1 * UT, t2 * UT};  // a, b, c origins
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int c2 = e % UT, c1 = (e / UT) % UT, c0 = e / (UT * UT);
+    const int a = base[0] + c0, b = base[1] + c1, c = base[2] + c2;
+    if (a < v && b < v && c < v) L[c0 * UP_X + c1 * UP_Z + c2] = Rt[a * v2 + (long long)b * v + c];
+  }
+  __syncthreads();
+  for (int i = 0; i < tk.nc; ++i) {
+    const FoldContrib fc = contribs[tk.c0 + i];
+    const long long st[3] = {fc.sa, fc.sb, fc.sc};
+    const int u = fc.sa == 1 ? 0 : (fc.sb == 1 ? 1 : 2);
+    const int ua = (u + 1) % 3, ub = (u + 2) % 3;
+    double vals[PER];
+    int lds[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * 256;
+      int cc[3];
+      cc[u] = e % UT;
+      cc[ua] = (e / UT) % UT;
+      cc[ub] = e / (UT * UT);
+      const int a = base[0] + cc[0], b = base[1] + cc[1], c = base[2] + cc[2];
+      const bool ok = a < v && b < v && c < v;
+      lds[it] = ok ? cc[0] * UP_X + cc[1] * UP_Z + cc[2] : -1;
+      vals[it] = ok ? Z[fc.base + a * st[0] + b * st[1] + c * st[2]] : 0.0;
     }
-    Rt[e] = acc;
+#pragma unroll
+    for (int it = 0; it < PER; ++it)
+      if (lds[it] >= 0) L[lds[it]] += fc.coef * vals[it];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int c2 = e % UT, c1 = (e / UT) % UT, c0 = e / (UT * UT);
+    const int a = base[0] + c0, b = base[1] + c1, c = base[2] + c2;
+    if (a < v && b < v && c < v) Rt[a * v2 + (long long)b * v + c] = L[c0 * UP_X + c1 * UP_Z + c2];
   }
 }
 
@@ -354,8 +426,10 @@ hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots
   const long long ny = (long long)a.nslots * (a.nfree == 2 ? (long long)a.o * a.o : a.o);
   if (ny <= 0 || v3 <= 0) return hipSuccess;
   if (ny > 65535) return hipErrorInvalidValue;
-  dim3 grid(blocks_for(v3, TPB * 4, 4096), (unsigned)ny);
-  hipLaunchKernelGGL(unpack_kernel, grid, dim3(TPB), 0, s, T, tbl, slots, out, a);
+  if (a.nterms < 1 || a.nterms > 6) return hipErrorInvalidValue;
+  const int nt = (a.v + UT - 1) / UT;
+  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ny);
+  hipLaunchKernelGGL(unpack_tiled_kernel, grid, dim3(TPB), 0, s, T, tbl, slots, out, a, nt);
   return hipGetLastError();
 }
 
@@ -368,9 +442,9 @@ hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTa
                    const FoldContrib* contribs, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   if (ntasks > 65535) return hipErrorInvalidValue;
-  const long long v3 = (long long)v * v * v;
-  dim3 grid(blocks_for(v3, TPB * 8, 4096), (unsigned)ntasks);
-  hipLaunchKernelGGL(fold_kernel, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs);
+  const int nt = (v + UT - 1) / UT;
+  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ntasks);
+  hipLaunchKernelGGL(fold_tiled_kernel, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
   return hipGetLastError();
 }
 
