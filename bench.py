@@ -82,14 +82,27 @@ def cpu_baseline(o, v, naux, seed):
     }
 
 
-def run_mode(binding, s, o, v, naux, prec, steps, warmup):
-    """Warmup + timed iterations from the MP2 guess in one precision mode."""
+NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64,64,2,2,2>", 4: "<128,128,2,2,2>"}
+LP_TILES = {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"}
+
+
+def kernel_name(prec, variant):
+    if prec == "fp64":
+        return "gemm_nt_f64_kernel" + NT_TILES.get(variant, str(variant))
+    return f"gemm_lp_{prec.replace('fp32', 'f32')}_kernel" + LP_TILES.get(variant, str(variant))
+
+
+def run_mode(binding, s, o, v, naux, prec, steps, warmup, tune_ms=0.0):
+    """Warmup + timed iterations from the MP2 guess in one precision mode
+    (tile variants autotuned first when tune_ms > 0, outside the timed steps)."""
     eng = binding.Engine(o, v, naux, precision=prec,
                          opts={"timers": True, "diis_t3": "none" if o >= 20 else "full"})
     try:
         eng.set_fock(s["f"])
         eng.set_eri_df(s["B"])
         eng.init_mp2()
+        variants = eng.autotune(tune_ms) if tune_ms > 0 else (0, 0)
+        log(f"[bench] {prec}: tile variants ladder={variants[0]} rings={variants[1]}")
         # every cct_update ends with a synchronisation of the library's stream
         # (the energy and norms are read back), so the host clock brackets
         # exactly the device work of the timed steps.
@@ -116,10 +129,11 @@ def run_mode(binding, s, o, v, naux, prec, steps, warmup):
         "r3_macs": r3_macs,
         "r3_tflops": 2.0 * r3_macs / (r3_ms / 1000.0) / 1e12,
         "phase_ms": {k: x / steps for k, x in phase_ms.items()},
+        "tile_variants": {"ladder": variants[0], "rings": variants[1]},
     }
 
 
-def run_batched(binding, niter, modes):
+def run_batched(binding, niter, modes, tune_ms=0.0):
     """The 64-system batch (o uniform in 3..8, v in 20..60, seeded): niter
     iterations from the MP2 guess per mode, one graph replay per iteration.
     Rate: system-iterations per second over the timed iterations (the first,
@@ -134,6 +148,8 @@ def run_batched(binding, niter, modes):
         with binding.Batch([(o, v, na) for o, v, na, _ in sizes], precision=prec) as b:
             for k, s in enumerate(systems):
                 b.set_system(k, s["f"], s["B"])
+            if tune_ms > 0:
+                b.autotune(tune_ms)
             b.iterate(1)
             t0 = time.perf_counter()
             e, nr = b.iterate(niter - 1)
@@ -207,6 +223,8 @@ def main():
                     help="further modes run from the same start for speedup and dE ('' for none)")
     ap.add_argument("--workload", default="o20v180", choices=list(ci.CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune-ms", type=float, default=3000.0,
+                    help="tile autotuning budget per mode before the timed steps (0: size-based defaults)")
     ap.add_argument("--batched-iters", type=int, default=5,
                     help="iterations of the 64-system batch per mode (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -259,7 +277,7 @@ def main():
     o, v, naux, seed = ci.CONFIGS[args.workload]
     s = ci.make_system(o, v, naux, seed)
     log(f"[bench] o={o} v={v} naux={naux} seed={seed} precision={args.precision}")
-    main_run = run_mode(binding, s, o, v, naux, args.precision, args.steps, args.warmup)
+    main_run = run_mode(binding, s, o, v, naux, args.precision, args.steps, args.warmup, args.autotune_ms)
     macs, phase_ms, ms_step, e = main_run["macs"], main_run["phase_ms"], main_run["ms_per_step"], main_run["energy"]
     value = 2.0 * main_run["r3_macs"] / (ms_step / 1000.0) / 1e12
     # dominant kernel: the particle-particle ladder GEMM, 3 launches per step;
@@ -277,13 +295,14 @@ def main():
         except Exception:
             traffic = None
     modes = {args.precision: {"s_per_iteration": ms_step / 1000.0, "r3_tflops": main_run["r3_tflops"],
-                              "energy": e, "speedup": 1.0, "dE": 0.0, "dE_rel": 0.0}}
+                              "energy": e, "speedup": 1.0, "dE": 0.0, "dE_rel": 0.0,
+                              "tile_variants": main_run["tile_variants"]}}
     for prec in [m for m in args.compare.split(",") if m and m != args.precision]:
-        r = run_mode(binding, s, o, v, naux, prec, args.steps, args.warmup)
+        r = run_mode(binding, s, o, v, naux, prec, args.steps, args.warmup, args.autotune_ms)
         modes[prec] = {"s_per_iteration": r["ms_per_step"] / 1000.0, "r3_tflops": r["r3_tflops"],
                        "energy": r["energy"], "speedup": ms_step / r["ms_per_step"],
                        "dE": r["energy"] - e, "dE_rel": (r["energy"] - e) / max(abs(e), 1e-300),
-                       "phase_ms": r["phase_ms"]}
+                       "phase_ms": r["phase_ms"], "tile_variants": r["tile_variants"]}
     out = {
         "metric": "T3-residual TFLOP/s + s/CCSDT iteration, FP64 vs mixed, o=20 v=180, dE vs oracle",
         "value": value,
@@ -309,14 +328,14 @@ def main():
                        "the oracle"),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": ("gemm_nt_f64_kernel<128,256> " if args.precision == "fp64" else
-                                f"gemm_lp_{args.precision.replace('fp32', 'f32')}_kernel<128,128> ") +
-                               "(particle-particle ladder, one of 3 relabelled GEMMs)"},
+                     "kernel": kernel_name(args.precision, main_run["tile_variants"]["ladder"]) +
+                               " (particle-particle ladder, one of 3 relabelled GEMMs)"},
         "energy": e,
     }
     if args.batched_iters > 1:
         out["batched"] = run_batched(binding, args.batched_iters,
-                                     [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision])
+                                     [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision],
+                                     args.autotune_ms)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)

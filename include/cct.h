@@ -137,6 +137,17 @@ int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters
  * both arrays provided; writes min(cap, 9). */
 int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap);
 
+/* Tile autotuner: times every tile variant of the particle-particle ladder
+ * GEMM (on a truncated M of this context's shape, scratch output) and of the
+ * ring GEMM (one batch of occupied pairs) in the context's precision and uses
+ * the fastest from then on (results are the same to rounding in every
+ * variant).  budget_ms bounds the timing (at least one variant per class is
+ * timed).  The choice is also stored in the flat JSON file named by the
+ * CCT_TUNE_CACHE environment variable (if set; keys "o<o>_v<v>_<prec>_ladder"
+ * and "..._rings"), which cct_create reads.  variants (may be NULL) receives
+ * {ladder variant, ring variant}.  Does not touch amplitudes or residuals. */
+int cct_autotune(cct_ctx* ctx, double budget_ms, int* variants);
+
 /* Index of the packed triple (i,j,k), 0 <= i <= j <= k < nocc, in the
  * lexicographic order; -1 if the arguments are out of range or unordered. */
 int64_t cct_packed_index(int nocc, int i, int j, int k);
@@ -174,6 +185,10 @@ int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms);
  * cct_batch_destroy), for cct_get_amplitudes, cct_energy, cct_get_counters.
  * NULL if s is out of range. */
 cct_ctx* cct_batch_system(cct_batch* b, int s);
+/* Tunes one system of each distinct (nocc, nvir) with cct_autotune (budget
+ * split evenly) and gives its choice to every system of that size; the
+ * recorded graph is dropped and recorded again by the next cct_batch_iterate. */
+int cct_batch_autotune(cct_batch* b, double budget_ms);
 const char* cct_batch_last_error(const cct_batch* b);
 void cct_batch_destroy(cct_batch* b);
 

@@ -55,6 +55,8 @@ def load(path: str | None = None):
         "cct_energy": (C.c_int, [vp, dp]),
         "cct_solve": (C.c_int, [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int)]),
         "cct_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
+        "cct_autotune": (C.c_int, [vp, C.c_double, C.POINTER(C.c_int)]),
+        "cct_batch_autotune": (C.c_int, [vp, C.c_double]),
         "cct_packed_index": (C.c_int64, [C.c_int, C.c_int, C.c_int, C.c_int]),
         "cct_strerror": (C.c_char_p, [C.c_int]),
         "cct_last_error": (C.c_char_p, [vp]),
@@ -204,6 +206,12 @@ class Engine:
                          ok=(CCT_OK, CCT_ENOTCONV))
         return e.value, it.value, rc == CCT_OK
 
+    def autotune(self, budget_ms=2000.0):
+        """Time the ladder and ring GEMM tile variants; returns (ladder, rings)."""
+        var = (C.c_int * 2)()
+        self._check(self.lib.cct_autotune(self.h, float(budget_ms), var))
+        return var[0], var[1]
+
     def counters(self):
         macs = np.zeros(9)
         ms = np.zeros(9)
@@ -275,6 +283,9 @@ class Batch:
         nr = np.empty((n, 3))
         self._check(self.lib.cct_batch_iterate(self.h, niter, _ptr(e), _ptr(nr)))
         return e, nr
+
+    def autotune(self, budget_ms=2000.0):
+        self._check(self.lib.cct_batch_autotune(self.h, float(budget_ms)))
 
     def system(self, s):
         o, v, na = self.sizes[s]

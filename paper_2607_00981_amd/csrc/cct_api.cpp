@@ -22,6 +22,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -64,6 +65,7 @@ struct cct_ctx {
   int diis_space = 8, diis_start = 2;
   bool diis_on = true, diis_t3 = true;
   double ws_gb = 0.0;  // 0: size the workspace from free device memory
+  int tune_ladder = 0, tune_rings = 0;  // GEMM tile variants chosen by cct_autotune (0 = size-based default)
   std::string err;
   bool have_f = false, have_B = false, have_res = false;
 
@@ -836,6 +838,7 @@ int r3_pp_lp(cct_ctx* ctx, const Idx2 cm[3], const Idx2 cn[3]) {
       g.C = ctx->r3 + t0 * v3; g.cm = cm[term]; g.cn = cn[term];
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = nb * v3; g.b_len = v4; g.c_len = (nt - t0) * v3;
+      g.variant = ctx->tune_ladder;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     }
   }
@@ -884,6 +887,7 @@ int r3_pp(cct_ctx* ctx) {
     g.C = ctx->r3; g.cm = idx1(v2); g.cn = idx1(1);
     g.alpha = 1.0; g.beta = 1.0;
     g.a_len = nt * v3; g.b_len = v2 * v2; g.c_len = nt * v3;
+    g.variant = ctx->tune_ladder;
     HIPCK(gemm_nt(g, Prec::F64, ctx->s));
   }
   // terms 2 and 1 from relabelled copies, in chunks of blocks that fit the workspace
@@ -908,6 +912,7 @@ int r3_pp(cct_ctx* ctx) {
       g.C = ctx->r3 + t0 * v3; g.cm = cm[term]; g.cn = cn[term];
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = nb * v3; g.b_len = v2 * v2; g.c_len = (nt - t0) * v3;
+      g.variant = ctx->tune_ladder;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     }
   }
@@ -995,6 +1000,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      g.variant = ctx->tune_rings;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     } else if (nt) {
       NtArgs g{};
@@ -1004,6 +1010,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      g.variant = ctx->tune_rings;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     } else {
       GemmArgs g{};
@@ -1357,6 +1364,180 @@ int update(cct_ctx* ctx, double* e, double norms[3]) {
   return finish_iteration(ctx, e, norms);
 }
 
+// --- autotuner ------------------------------------------------------------
+// The ladder and ring GEMMs are timed in each available tile variant on this
+// context's own shapes (the ladder on a truncated M, writing scratch output);
+// the fastest variant of each class is used from then on.  Choices persist in
+// a flat JSON file named by the CCT_TUNE_CACHE environment variable, keyed by
+// (o, v, precision, class).
+const char* prec_name(Prec p) { return p == Prec::F64 ? "fp64" : (p == Prec::F32 ? "fp32" : "bf16x3"); }
+
+std::string tune_key(const cct_ctx* ctx, const char* cls) {
+  return "o" + std::to_string(ctx->o) + "_v" + std::to_string(ctx->v) + "_" + prec_name(ctx->prec) + "_" + cls;
+}
+
+std::map<std::string, int> read_tune_cache() {
+  std::map<std::string, int> m;
+  const char* path = std::getenv("CCT_TUNE_CACHE");
+  if (!path || !*path) return m;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return m;
+  std::string js;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) js.append(buf, k);
+  std::fclose(f);
+  size_t p = 0;
+  while ((p = js.find('"', p)) != std::string::npos) {
+    const size_t q = js.find('"', p + 1);
+    if (q == std::string::npos) break;
+    const std::string key = js.substr(p + 1, q - p - 1);
+    const size_t c = js.find(':', q);
+    if (c == std::string::npos) break;
+    m[key] = std::atoi(js.c_str() + c + 1);
+    p = c + 1;
+  }
+  return m;
+}
+
+void write_tune_cache(const std::map<std::string, int>& m) {
+  const char* path = std::getenv("CCT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  std::fprintf(f, "{");
+  bool first = true;
+  for (const auto& kv : m) {
+    std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n}\n");
+  std::fclose(f);
+}
+
+void apply_tune_cache(cct_ctx* ctx) {
+  const auto m = read_tune_cache();
+  auto it = m.find(tune_key(ctx, "ladder"));
+  if (it != m.end()) ctx->tune_ladder = it->second;
+  it = m.find(tune_key(ctx, "rings"));
+  if (it != m.end()) ctx->tune_rings = it->second;
+}
+
+// Time one launch after a warm-up launch; -1 if the variant cannot run.
+template <typename F>
+float time_launch(hipStream_t s, F launch) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.f;
+  float ms = -1.f;
+  if (launch() == hipSuccess && hipEventRecord(e0, s) == hipSuccess && launch() == hipSuccess &&
+      hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+  }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
+  const int o = ctx->o, v = ctx->v;
+  const long long v2 = (long long)v * v, v4 = v2 * v2, ov = (long long)o * v, ov3 = o * ctx->v3;
+  const bool f64 = ctx->prec == Prec::F64;
+  Arena& ws = ctx->ws;
+  ws.reset(0);
+  double used = 0.0;
+  auto pick = [&](std::vector<int> cands, auto run) -> int {
+    int best = 0;
+    float tbest = 0.f;
+    for (int c : cands) {
+      if (used > budget_ms && best != 0) break;
+      const float t = time_launch(ctx->s, [&] { return run(c); });
+      if (t < 0.f) continue;
+      used += 2.0 * t;
+      if (best == 0 || t < tbest) { best = c; tbest = t; }
+    }
+    return best;
+  };
+  // ---- ladder: one relabelled term on the first Mt rows of the stored blocks
+  const bool lad_lp = !f64 && v2 % lp_width(ctx->prec) == 0, lad_nt = f64 && !(v2 & 1);
+  if (lad_lp || lad_nt) {
+    const long long M = ctx->ntri * v;
+    const long long Mt = std::min(M, std::max<long long>(1024, (long long)(2e9 / 8.0 / (double)v2)));
+    const size_t mk = ws.mark();
+    double* C = ws.alloc((size_t)(Mt * v2));
+    if (!C) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
+    if (lad_nt) {
+      ctx->tune_ladder = pick({1, 2, 3, 4}, [&](int var) {
+        NtArgs g{};
+        g.M = (int)Mt; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+        g.A = ctx->t3; g.lda = v2; g.B = ctx->Wvvvv; g.ldb = v2;
+        g.C = C; g.cm = idx1(v2); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+        g.a_len = ctx->ntri * ctx->v3; g.b_len = v4; g.c_len = Mt * v2; g.variant = var;
+        return gemm_nt(g, Prec::F64, ctx->s);
+      });
+    } else {
+      void* Al = alloc_lp(ws, Mt * v2);
+      void* Bl = alloc_lp(ws, v4);
+      if (!Al || !Bl) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
+      const int fmt = lp_fmt(ctx->prec);
+      HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * v2}, Mt * v2, ctx->s));
+      HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, v4}, v4, ctx->s));
+      ctx->tune_ladder = pick({1, 2, 3}, [&](int var) {
+        NtLpArgs g{};
+        g.M = (int)Mt; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
+        g.A = Al; g.lda = v2; g.a_plane = Mt * v2; g.B = Bl; g.ldb = v2; g.b_plane = v4;
+        g.C = C; g.cm = idx1(v2); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+        g.a_len = Mt * v2; g.b_len = v4; g.c_len = Mt * v2; g.variant = var;
+        return gemm_nt_lp(g, ctx->prec, ctx->s);
+      });
+    }
+    ws.reset(mk);
+  }
+  // ---- rings: one batch of occupied pairs with the planned batch size (at most 8)
+  const bool ring_lp = !f64 && ov % lp_width(ctx->prec) == 0, ring_nt = f64 && !(ov & 1);
+  if ((ring_lp || ring_nt) && !ctx->ring[0].batches.empty()) {
+    const int S = std::min(8, ctx->ring[0].per_batch);
+    const size_t mk = ws.mark();
+    double* Z = ws.alloc((size_t)(S * ov3));
+    void* U = ring_lp ? alloc_lp(ws, S * ov3) : (void*)ws.alloc((size_t)(S * ov3));
+    void* Al = ring_lp ? alloc_lp(ws, ov * ov) : nullptr;
+    if (!Z || !U || (ring_lp && !Al)) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
+    if (ring_lp) {
+      const int fmt = lp_fmt(ctx->prec);
+      HIPCK(convert(ctx->t3, OutSpec{U, fmt, S * ov3}, std::min<long long>(S * ov3, ctx->ntri * ctx->v3), ctx->s));
+      HIPCK(convert(ctx->Wb1, OutSpec{Al, fmt, ov * ov}, ov * ov, ctx->s));
+    } else {
+      HIPCK(fill((double*)U, 0.01, S * ov3, ctx->s));
+    }
+    ctx->tune_rings = pick(ring_lp ? std::vector<int>{1, 2, 3} : std::vector<int>{1, 2, 3, 4}, [&](int var) {
+      if (ring_lp) {
+        NtLpArgs g{};
+        g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = S;
+        g.A = Al; g.lda = ov; g.a_batch = 0; g.a_plane = ov * ov;
+        g.B = U; g.ldb = ov; g.b_batch = ov3; g.b_plane = S * ov3;
+        g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3; g.alpha = 1.0; g.beta = 0.0;
+        g.a_len = ov * ov; g.b_len = S * ov3; g.c_len = S * ov3; g.variant = var;
+        return gemm_nt_lp(g, ctx->prec, ctx->s);
+      }
+      NtArgs g{};
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = S;
+      g.A = ctx->Wb1; g.lda = ov; g.a_batch = 0;
+      g.B = (const double*)U; g.ldb = ov; g.b_batch = ov3;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3; g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = ov * ov; g.b_len = S * ov3; g.c_len = S * ov3; g.variant = var;
+      return gemm_nt(g, Prec::F64, ctx->s);
+    });
+    ws.reset(mk);
+  }
+  HIPCK(hipStreamSynchronize(ctx->s));
+  auto m = read_tune_cache();
+  m[tune_key(ctx, "ladder")] = ctx->tune_ladder;
+  m[tune_key(ctx, "rings")] = ctx->tune_rings;
+  write_tune_cache(m);
+  if (spent) *spent = used;
+  return CCT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1500,6 +1681,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
       if (hipEventCreate(&ctx->ev[i]) != hipSuccess) rc = CCT_EDEVICE;
   }
   if (rc == CCT_OK) rc = build_plans(ctx);
+  if (rc == CCT_OK) apply_tune_cache(ctx);
   if (rc == CCT_OK) {
     if (fill(ctx->zero_r1, 0.0, ov, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
     if (fill(ctx->t1, 0.0, ov, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
@@ -1635,6 +1817,16 @@ int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters
   }
   ctx->err = "not converged";
   return CCT_ENOTCONV;
+}
+
+int cct_autotune(cct_ctx* ctx, double budget_ms, int* variants) {
+  if (!ctx || !(budget_ms >= 0.0)) return CCT_EINVAL;
+  RCK(autotune(ctx, budget_ms, nullptr));
+  if (variants) {
+    variants[0] = ctx->tune_ladder;
+    variants[1] = ctx->tune_rings;
+  }
+  return CCT_OK;
 }
 
 int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap) {
@@ -1833,6 +2025,29 @@ int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms) {
         for (int k = 0; k < 3; ++k) norms[3 * s + k] = nr[k];
     }
   }
+  return CCT_OK;
+}
+
+int cct_batch_autotune(cct_batch* b, double budget_ms) {
+  if (!b || !(budget_ms >= 0.0)) return CCT_EINVAL;
+  // one tuning per distinct size, shared by the systems of that size
+  std::map<std::pair<int, int>, cct_ctx*> tuned;
+  for (cct_ctx* c : b->sys) tuned[{c->o, c->v}] = nullptr;
+  const double per = budget_ms / (double)tuned.size();
+  for (cct_ctx* c : b->sys) {
+    cct_ctx*& t = tuned[{c->o, c->v}];
+    if (!t) {
+      const int rc = autotune(c, per, nullptr);
+      if (rc != CCT_OK) { b->err = c->err; return rc; }
+      t = c;
+    } else {
+      c->tune_ladder = t->tune_ladder;
+      c->tune_rings = t->tune_rings;
+    }
+  }
+  // the recorded graph holds the old launches: record again on the next iterate
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return CCT_OK;
 }
 

@@ -946,20 +946,23 @@ hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
 // ===========================================================================
 // K-contiguous kernels on low-precision operands stored in memory.
 //   FP32 operands: 16-byte loads of 4 floats, K tile of 32, FP32 MFMA with
-//   FP32 accumulation inside the K tile and an FP64 flush after it.
+//   FP32 accumulation over LP_FLUSH K tiles and an FP64 flush after them.
 //   Split-BF16 operands: hi and lo planes, 16-byte loads of 8 bf16 per plane,
 //   K tile of 32 (one bf16 MFMA step), three products per tile, FP32
-//   accumulation flushed into FP64 after every K tile.
+//   accumulation flushed into FP64 after every LP_FLUSH K tiles.
 // ===========================================================================
 namespace cct {
 namespace {
 
+// K tiles accumulated in FP32 before the FP64 flush (K = 4 x 32 = 128 products)
+constexpr int LP_FLUSH = 4;
+
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int OCC>
-__global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
-  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LA = BM + 4, LB = BN + 4;
+template <int BM, int BN, int WM, int WN, int OCC>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LA = BM + 4, LB = BN + 4;
   constexpr int SA = BM * (KB / 4) / NTH, SB = BN * (KB / 4) / NTH;  // 16-byte segments per thread
   __shared__ float As[2][KB * LA];
   __shared__ float Bs[2][KB * LB];
@@ -989,7 +992,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int t
     pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
   }
   const int wave = tid / 64, lane = tid & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
   double out[TM][TN][4];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -1023,16 +1026,18 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int t
   load(0);
   store(As[0], Bs[0]);
   __syncthreads();
+  f4 acc[TM][TN];
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * KB);
     const float* as = As[cur];
     const float* bs = Bs[cur];
-    f4 acc[TM][TN];
+    if (kt % LP_FLUSH == 0) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
     for (int ks = 0; ks < KB / 4; ++ks) {
       const int kr = ks * 4 + lane / 16;
@@ -1046,12 +1051,14 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int t
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
+    if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+          for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    }
     if (kt + 1 < nk) store(As[cur ^ 1], Bs[cur ^ 1]);
     __syncthreads();
   }
@@ -1074,9 +1081,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int t
     }
 }
 
-template <int BM, int BN, int OCC>
-__global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
-  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LK = KB + 8;
+template <int BM, int BN, int WM, int WN, int OCC>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LK = KB + 8;
   constexpr int SA = BM * (KB / 8) / NTH, SB = BN * (KB / 8) / NTH;  // 16-byte segments per plane per thread
   __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM * LK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN * LK];
@@ -1108,7 +1115,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, in
     pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
   }
   const int wave = tid / 64, lane = tid & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
   double out[TM][TN][4];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -1152,14 +1159,16 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, in
   store(0);
   __syncthreads();
   const int kq = 8 * (lane / 16);
+  f4 acc[TM][TN];
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * KB);
-    f4 acc[TM][TN];
+    if (kt % LP_FLUSH == 0) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
     bf8 ah[TM], al[TM];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -1179,12 +1188,14 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, in
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
       }
     }
+    if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+          for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
@@ -1207,7 +1218,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, in
     }
 }
 
-template <int BM, int BN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC>
 hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   const long long nb = (long long)tiles_m * tiles_n;
@@ -1215,9 +1226,10 @@ hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
   if (prec == Prec::F32)
-    hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, OCC>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+    hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, OCC>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
+    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
+                       tiles_n);
   return hipGetLastError();
 }
 
@@ -1237,9 +1249,18 @@ hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
-  const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-  if (t128 >= 256) return launch_lp<128, 128, 1>(g, prec, s);
-  return launch_lp<64, 64, 2>(g, prec, s);
+  int variant = g.variant;
+  if (variant == 0) {
+    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+    // 128 x 128 tiles of 8 waves (64 x 32 each, two waves per SIMD) once
+    // there are enough of them; 64 x 64 below that
+    variant = t128 >= 256 ? 2 : 3;
+  }
+  switch (variant) {
+    case 1: return launch_lp<128, 128, 2, 2, 1>(g, prec, s);
+    case 2: return launch_lp<128, 128, 2, 4, 2>(g, prec, s);
+    default: return launch_lp<64, 64, 2, 2, 2>(g, prec, s);
+  }
 }
 
 }  // namespace cct

@@ -131,6 +131,7 @@ struct NtLpArgs {
   double* C; Idx2 cm, cn; long long c_batch;
   double alpha, beta;
   long long a_len, b_len, c_len;
+  int variant;  // tile variant (0 = size-based default)
 };
 hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s);
 

@@ -81,3 +81,21 @@ def test_batch_mixed_close_to_fp64(prec):
     d = np.abs(got - ref).max()
     say(f"[batch {prec}] max |dE| vs fp64 over {NIT} iterations: {d:.3e}")
     assert d < 1e-6
+
+
+def test_batch_autotune_then_graph_matches_eager():
+    """After tuning, the re-recorded graph still reproduces eager enqueueing."""
+    systems = _systems(SMALL)
+    ref = _batch_energies(SMALL, systems, graph=False)
+    out = []
+    with binding.Batch([(o, v, na) for o, v, na, _ in SMALL], opts={"graph": True}) as b:
+        for k, s in enumerate(systems):
+            b.set_system(k, s["f"], s["B"])
+        b.iterate(1)
+        out.append(None)
+        b.autotune(200.0)
+        for _ in range(NIT - 1):
+            e, _ = b.iterate(1)
+            out.append(e.copy())
+    got = np.array(out[1:])
+    assert np.abs(got - ref[1:]).max() < 1e-12

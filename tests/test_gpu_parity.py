@@ -198,3 +198,31 @@ def test_mixed_twenty_iterations_o4v20(prec):
             got.append(e)
             say(f"  it {it+1}: gpu {e:.14f} oracle {ref[it]:.14f} diff {e-ref[it]:.2e}")
     assert np.max(np.abs(np.array(got) - np.array(ref))) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_autotune_keeps_results_and_writes_cache(prec, tmp_path, monkeypatch):
+    """Tuned tile variants give the untuned residual to rounding, the choice
+    lands in the cache file, and a new context picks it up from there."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("CCT_TUNE_CACHE", str(cache))
+    o, v, seed = 3, 16, 21
+    say(f"[autotune] prec={prec}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        a = eng.residual()
+        lad, rng = eng.autotune(500.0)
+        say(f"  variants ladder={lad} rings={rng}")
+        b = eng.residual()
+    for x, y in zip(a[:3], b[:3]):
+        assert np.abs(x - y).max() <= 1e-12 * max(1.0, np.abs(x).max())
+    import json
+    js = json.loads(cache.read_text())
+    assert js[f"o{o}_v{v}_{prec}_ladder"] == lad and js[f"o{o}_v{v}_{prec}_rings"] == rng
+    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        c = eng.residual()
+    for x, y in zip(b[:3], c[:3]):
+        assert np.array_equal(x, y)
