@@ -801,7 +801,6 @@ int feedback(cct_ctx* ctx) {
 
 // Low-precision operand storage: FP32 values, or split BF16 as two planes
 // (hi, lo); both take four bytes per element.
-int lp_width(Prec p) { return p == Prec::F32 ? 4 : 8; }
 int lp_fmt(Prec p) { return p == Prec::F32 ? OUT_F32 : OUT_BF16X2; }
 void* alloc_lp(Arena& ws, long long n) { return ws.alloc((size_t)((n + 1) / 2)); }
 
@@ -860,9 +859,8 @@ int r3_pp(cct_ctx* ctx) {
   // output maps of the three terms: C[(t,x)][(y,z)] -> R[t][..]
   const Idx2 cm[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
   const Idx2 cn[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
-  const bool lp = ctx->prec != Prec::F64;
-  if (lp && v2 % lp_width(ctx->prec) == 0) return r3_pp_lp(ctx, cm, cn);
-  if (lp || (v2 & 1)) {
+  if (ctx->prec != Prec::F64) return r3_pp_lp(ctx, cm, cn);
+  if (v2 & 1) {
     // generic strided kernel reading T3 in place
     const Idx2 am[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
     const Idx2 ak[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
@@ -959,7 +957,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
   Arena& ws = ctx->ws;
   const bool f64 = ctx->prec == Prec::F64;
   const bool nt = f64 && !(ov & 1);
-  const bool lp = !f64 && ov % lp_width(ctx->prec) == 0;
+  const bool lp = !f64;
   // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
   const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
   const size_t mk0 = ws.mark();
@@ -1459,7 +1457,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     return best;
   };
   // ---- ladder: one relabelled term on the first Mt rows of the stored blocks
-  const bool lad_lp = !f64 && v2 % lp_width(ctx->prec) == 0, lad_nt = f64 && !(v2 & 1);
+  const bool lad_lp = !f64, lad_nt = f64 && !(v2 & 1);
   if (lad_lp || lad_nt) {
     const long long M = ctx->ntri * v;
     const long long Mt = std::min(M, std::max<long long>(1024, (long long)(2e9 / 8.0 / (double)v2)));
@@ -1494,7 +1492,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     ws.reset(mk);
   }
   // ---- rings: one batch of occupied pairs with the planned batch size (at most 8)
-  const bool ring_lp = !f64 && ov % lp_width(ctx->prec) == 0, ring_nt = f64 && !(ov & 1);
+  const bool ring_lp = !f64, ring_nt = f64 && !(ov & 1);
   if ((ring_lp || ring_nt) && !ctx->ring[0].batches.empty()) {
     const int S = std::min(8, ctx->ring[0].per_batch);
     const size_t mk = ws.mark();

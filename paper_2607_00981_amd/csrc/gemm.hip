@@ -960,7 +960,7 @@ constexpr int LP_FLUSH = 4;
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
   constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LA = BM + 4, LB = BN + 4;
   constexpr int SA = BM * (KB / 4) / NTH, SB = BN * (KB / 4) / NTH;  // 16-byte segments per thread
@@ -1004,10 +1004,26 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs
   bool oa[SA], ob[SB];
   const int nk = (g.K + KB - 1) / KB;
   auto load = [&](int k0) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const flt4*)(pa[i] + (oa[i] ? k0 : 0)); }
+      for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const flt4*)(pa[i] + (oa[i] ? k0 : 0)); }
 #pragma unroll
-    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const flt4*)(pb[i] + (ob[i] ? k0 : 0)); }
+      for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const flt4*)(pb[i] + (ob[i] ? k0 : 0)); }
+    } else {
+      // any K, leading dimension and alignment: element loads, masked per element
+#pragma unroll
+      for (int i = 0; i < SA; ++i) {
+        oa[i] = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ra[i][q] = (va[i] && k0 + ka[i] + q < g.K) ? pa[i][k0 + q] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        ob[i] = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rb[i][q] = (vb[i] && k0 + kb[i] + q < g.K) ? pb[i][k0 + q] : 0.f;
+      }
+    }
   };
   auto store = [&](float* as, float* bs) {
 #pragma unroll
@@ -1081,7 +1097,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
   constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LK = KB + 8;
   constexpr int SA = BM * (KB / 8) / NTH, SB = BN * (KB / 8) / NTH;  // 16-byte segments per plane per thread
@@ -1127,19 +1143,52 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
   bool oa[SA], ob[SB];
   const int nk = (g.K + KB - 1) / KB;
   auto load = [&](int k0) {
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < SA; ++i) {
-      oa[i] = va[i] && (k0 + ka[i] < g.K);
-      const __bf16* p = pa[i] + (oa[i] ? k0 : 0);
-      rah[i] = *(const u32x4*)p;
-      ral[i] = *(const u32x4*)(p + g.a_plane);
-    }
+      for (int i = 0; i < SA; ++i) {
+        oa[i] = va[i] && (k0 + ka[i] < g.K);
+        const __bf16* p = pa[i] + (oa[i] ? k0 : 0);
+        rah[i] = *(const u32x4*)p;
+        ral[i] = *(const u32x4*)(p + g.a_plane);
+      }
 #pragma unroll
-    for (int i = 0; i < SB; ++i) {
-      ob[i] = vb[i] && (k0 + kb[i] < g.K);
-      const __bf16* p = pb[i] + (ob[i] ? k0 : 0);
-      rbh[i] = *(const u32x4*)p;
-      rbl[i] = *(const u32x4*)(p + g.b_plane);
+      for (int i = 0; i < SB; ++i) {
+        ob[i] = vb[i] && (k0 + kb[i] < g.K);
+        const __bf16* p = pb[i] + (ob[i] ? k0 : 0);
+        rbh[i] = *(const u32x4*)p;
+        rbl[i] = *(const u32x4*)(p + g.b_plane);
+      }
+    } else {
+      // any K, leading dimension and alignment: element loads, masked per element
+      const __bf16 z = (__bf16)0.f;
+#pragma unroll
+      for (int i = 0; i < SA; ++i) {
+        oa[i] = true;
+        __bf16 h[8], l[8];
+        const __bf16* p = pa[i] + k0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool ok = va[i] && k0 + ka[i] + q < g.K;
+          h[q] = ok ? p[q] : z;
+          l[q] = ok ? p[q + g.a_plane] : z;
+        }
+        __builtin_memcpy(&rah[i], h, 16);
+        __builtin_memcpy(&ral[i], l, 16);
+      }
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        ob[i] = true;
+        __bf16 h[8], l[8];
+        const __bf16* p = pb[i] + k0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool ok = vb[i] && k0 + kb[i] + q < g.K;
+          h[q] = ok ? p[q] : z;
+          l[q] = ok ? p[q + g.b_plane] : z;
+        }
+        __builtin_memcpy(&rbh[i], h, 16);
+        __builtin_memcpy(&rbl[i], l, 16);
+      }
     }
   };
   const u32x4 zero4 = {0u, 0u, 0u, 0u};
@@ -1218,7 +1267,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC>
 hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   const long long nb = (long long)tiles_m * tiles_n;
@@ -1226,9 +1275,9 @@ hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
   if (prec == Prec::F32)
-    hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+    hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, WM, WN, OCC, VEC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
+    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC, VEC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
                        tiles_n);
   return hipGetLastError();
 }
@@ -1237,29 +1286,30 @@ hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
 
 hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (prec == Prec::F64) return hipErrorInvalidValue;
-  // operands: K, leading dimensions and batch strides multiples of the vector width, 16-byte aligned
-  const int w = prec == Prec::F32 ? 4 : 8;
-  if (g.K <= 0 || g.K % w || g.lda % w || g.ldb % w || g.a_batch % w || g.b_batch % w || ((uintptr_t)g.A & 15) ||
-      ((uintptr_t)g.B & 15))
-    return hipErrorInvalidValue;
-  if (prec == Prec::BF16X3 && (g.a_plane % w || g.b_plane % w || g.a_plane <= 0 || g.b_plane <= 0))
-    return hipErrorInvalidValue;
+  if (prec == Prec::F64 || g.K <= 0) return hipErrorInvalidValue;
+  if (prec == Prec::BF16X3 && (g.a_plane <= 0 || g.b_plane <= 0)) return hipErrorInvalidValue;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  // 16-byte vector loads need K, leading dimensions, batch strides and planes
+  // in multiples of the vector width and 16-byte aligned bases
+  const int w = prec == Prec::F32 ? 4 : 8;
+  const bool vec = !(g.K % w || g.lda % w || g.ldb % w || g.a_batch % w || g.b_batch % w ||
+                     ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15) ||
+                     (prec == Prec::BF16X3 && (g.a_plane % w || g.b_plane % w)));
+  if (!vec) return launch_lp<64, 64, 2, 2, 2, false>(g, prec, s);
   int variant = g.variant;
   if (variant == 0) {
-    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
     // 128 x 128 tiles of 8 waves (64 x 32 each, two waves per SIMD) once
     // there are enough of them; 64 x 64 below that
+    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
     variant = t128 >= 256 ? 2 : 3;
   }
   switch (variant) {
-    case 1: return launch_lp<128, 128, 2, 2, 1>(g, prec, s);
-    case 2: return launch_lp<128, 128, 2, 4, 2>(g, prec, s);
-    default: return launch_lp<64, 64, 2, 2, 2>(g, prec, s);
+    case 1: return launch_lp<128, 128, 2, 2, 1, true>(g, prec, s);
+    case 2: return launch_lp<128, 128, 2, 4, 2, true>(g, prec, s);
+    default: return launch_lp<64, 64, 2, 2, 2, true>(g, prec, s);
   }
 }
 

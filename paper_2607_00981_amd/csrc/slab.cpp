@@ -110,10 +110,7 @@ void mark(cct_slab* sl, int i) {
   if (sl->timers) (void)hipEventRecord(sl->ev[i], sl->s);
 }
 
-bool lp_ok(const cct_slab* sl) {
-  const long long v2 = (long long)sl->v * sl->v;
-  return sl->prec != Prec::F64 && v2 % (sl->prec == Prec::F32 ? 4 : 8) == 0;
-}
+bool lp_ok(const cct_slab* sl) { return sl->prec != Prec::F64; }
 bool nt_ok(const cct_slab* sl) { return sl->prec == Prec::F64 && ((long long)sl->v * sl->v) % 2 == 0; }
 
 // The ladder's three relabelled terms, each a GEMM C[(t,x)][(y,z)] with K = (d,e):
