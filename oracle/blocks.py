@@ -146,3 +146,73 @@ def local_terms_block(W, Fvv, Wvvvo, Wvooo, t2, stored, ijk, terms=("PP", "F1", 
     if "D2" in terms:
         r += d2_block(Wvooo, t2, ijk)
     return postprocess_block(r, ijk)
+
+
+def occ_virt_gram(Bt: np.ndarray, o: int) -> np.ndarray:
+    """G[l][d][m][e] = v~^{lm}_{de} = sum_P B~^P_{ld} B~^P_{me} (a matrix product
+    over the fitting index)."""
+    naux, n, _ = Bt.shape
+    v = n - o
+    Y = np.ascontiguousarray(Bt[:, :o, o:]).reshape(naux, o * v)
+    return (Y.T @ Y).reshape(o, v, o, v)
+
+
+def local_terms_elements(Bt, t2, Fvv, Wvvvo, Wvooo, stored, ijk, abcs, G):
+    """Post-processed values R3[ijk][a][b][c] of the block-local terms (ladder,
+    F_vv term, both T2 drivers) for the listed (a,b,c), by definition: the raw
+    value of every member of the (a,b,c) orbit as the sum over the six
+    simultaneous column permutations, each W^{xy}_{de} row built on demand
+    from the dressed factors, then the post-processing of the orbit.  For
+    sizes where neither W nor a whole block's ladder fits a check."""
+    o = t2.shape[0]
+    v = stored.shape[0]
+    rows = {}
+
+    def wrow(x, y):
+        if (x, y) not in rows:
+            bx = Bt[:, o + x, o:]
+            by = Bt[:, o + y, o:]
+            rows[(x, y)] = bx.T @ by + np.einsum("lm,ldme->de", t2[:, :, x, y], G)
+        return rows[(x, y)]
+
+    views = {}
+
+    def tview(occ):
+        if occ not in views:
+            views[occ] = unpack_block(stored, occ)
+        return views[occ]
+
+    def raw(abc):
+        total = 0.0
+        for p in PERMS3:
+            p_, q_, r_ = (ijk[s] for s in p)
+            x, y, z = (abc[s] for s in p)
+            t = tview((p_, q_, r_))
+            total += 0.5 * float(np.sum(wrow(x, y) * t[:, :, z]))                 # ladder
+            total += 0.5 * float(Fvv[x] @ t[:, y, z])                             # F_vv
+            total += float(Wvvvo[x, y, :, q_] @ t2[p_, r_, :, z])                 # W^{xy}_{dq} t_{pr}^{dz}
+            total -= float(Wvooo[x, :, p_, q_] @ t2[:, r_, y, z])                 # W^{xl}_{pq} t_{lr}^{yz}
+        return total
+
+    i, j, k = ijk
+    out = []
+    for abc in abcs:
+        if i == j == k:
+            out.append(0.0)
+            continue
+        orbit = {}
+        for p in PERMS3:
+            m = tuple(abc[s] for s in p)
+            if m not in orbit:
+                orbit[m] = raw(m)
+
+        def sym(m):
+            if i == j:
+                return 0.5 * (orbit[m] + orbit[(m[1], m[0], m[2])])
+            if j == k:
+                return 0.5 * (orbit[m] + orbit[(m[0], m[2], m[1])])
+            return orbit[m]
+
+        mean = sum(sym(tuple(abc[s] for s in p)) for p in PERMS3) / 6.0
+        out.append(sym(tuple(abc)) - mean)
+    return np.array(out)

@@ -320,6 +320,31 @@ def test_block_oracle_local_terms_match_full_oracle():
         assert np.abs(got - full[i, j, k]).max() < 1e-14
 
 
+def test_element_oracle_matches_block_oracle():
+    """The element-wise local-terms oracle (W rows on demand, orbit
+    post-processing) equals the whole-block oracle on every element of
+    several blocks, including repeated occupied and virtual indices."""
+    from oracle import blocks
+
+    o, v, naux = 3, 5, 16
+    rng = np.random.default_rng(29)
+    s = ci.make_system(o, v, naux, 29, sigma=0.1)
+    t1, t2, _ = ci.random_amplitudes(o, v, 29, 0.03, 0.03, 0.0, triples=False)
+    Bt = blocks.dressed_factors(s["B"], t1)
+    Fvv = rng.normal(0, 0.1, (v, v))
+    Wvvvo = rng.normal(0, 0.1, (v, v, v, o))
+    Wvooo = rng.normal(0, 0.1, (v, o, o, o))
+    t3p = ci.hashed_t3_packed(o, v, 30, 0.02, threads=2)
+    W = blocks.w_vvvv(Bt, t2, o)
+    G = blocks.occ_virt_gram(Bt, o)
+    tri = ci.packed_triples(o)
+    abcs = [(a, b, c) for a in range(v) for b in range(v) for c in range(v)]
+    for n in (0, 1, 4, 5, len(tri) - 1):
+        ref = blocks.local_terms_block(W, Fvv, Wvvvo, Wvooo, t2, t3p[n], tri[n])
+        got = blocks.local_terms_elements(Bt, t2, Fvv, Wvvvo, Wvooo, t3p[n], tri[n], abcs, G)
+        assert np.abs(got - ref.reshape(-1)).max() < 1e-14, tri[n]
+
+
 def test_hashed_t3_symmetry_and_determinism():
     o, v = 3, 6
     a = ci.hashed_t3_packed(o, v, 5, threads=3)
