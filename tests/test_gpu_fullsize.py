@@ -64,3 +64,54 @@ def test_pp_ladder_blocks_o20v180():
             assert np.abs(got[n]).max() == 0.0
         else:
             assert err <= 1e-11 * scale
+
+
+def test_slab_o50v400_sampled_elements():
+    """Slab of packed triples 0..63 at o=50, v=400, naux=900 (the slab
+    measurement's shape, split-BF16 ladder, panels of 8 rows): sampled
+    post-processed elements against the element-wise oracle (W^{ab}_{de}
+    rows built on demand; the full W would be 205 GB).  Inputs: the named
+    recipe's factors (T1 = 0), pair-symmetric T2, counter-based
+    intermediates and T3.  Tolerance 1e-4 of the largest sampled value."""
+    o, v, naux, seed = ci.CONFIGS["o50v400"]
+    first, count = 0, 64
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    s = ci.make_system(o, v, naux, seed)
+    Bt = s["B"]
+    _, t2, _ = ci.random_amplitudes(o, v, seed, 0.0, 0.01, 0.0, triples=False)
+    Fvv = ci.hashed_uniform((v, v), seed * 7 + 1, 0.1, threads)
+    Wt = ci.hashed_uniform((o, v, v, v), seed * 7 + 2, 0.01, threads)
+    Wvooo = ci.hashed_uniform((v, o, o, o), seed * 7 + 3, 0.01, threads)
+    t3 = ci.hashed_t3_slab(o, v, seed, first, count, 0.01, threads)
+    say(f"[slab fullsize] inputs in {time.time() - t0:.1f} s; GPU slab (bf16x3) ...")
+    tri = ci.packed_triples(o)
+    rng = np.random.default_rng(7)
+    picks = {0: [(0, 0, 0), (3, 5, 7)], 1: [(0, 0, 1), (399, 17, 17), (5, 200, 399)], 50: [(1, 2, 3), (100, 100, 4)],
+             63: [(398, 0, 211)]}
+    for t in (17, 40):
+        picks[t] = [tuple(int(x) for x in rng.integers(0, v, 3)) for _ in range(2)]
+    v3 = v ** 3
+    with binding.Slab(o, v, naux, first, count, precision="bf16x3", opts={"panel": 8}) as sl:
+        sl.set_intermediates(Bt, t2, Fvv, Wt, Wvooo)
+        sl.set_t3(t3)
+        t0 = time.time()
+        _, n2 = sl.residual(want_r3=False)
+        say(f"[slab fullsize] GPU residual {time.time() - t0:.1f} s, norm2 {n2:.6e}")
+        got = {t: [sl.copy_r3(t * v3 + a * v * v + b * v + c, 1)[0] for (a, b, c) in abcs]
+               for t, abcs in picks.items()}
+    t0 = time.time()
+    G = blocks.occ_virt_gram(Bt, o)
+    Wv = Wt.transpose(1, 2, 3, 0)  # W^{ab}_{dj} as a [a][b][d][j] view
+    say(f"[slab fullsize] oracle setup {time.time() - t0:.1f} s")
+    refs = {}
+    for t, abcs in picks.items():
+        refs[t] = blocks.local_terms_elements(Bt, t2, Fvv, Wv, Wvooo, t3[t - first], tri[t], abcs, G)
+    scale = max(float(np.abs(r).max()) for r in refs.values())
+    for t, abcs in picks.items():
+        for (abc, g, r) in zip(abcs, got[t], refs[t]):
+            say(f"  block {t} {tri[t]} {abc}: gpu {g:.9e} oracle {r:.9e}")
+            if tri[t][0] == tri[t][1] == tri[t][2]:
+                assert g == 0.0
+            else:
+                assert abs(g - r) <= 1e-4 * scale
