@@ -299,7 +299,16 @@ Status contract(Arena& ws, hipStream_t s, Prec prec, double alpha, const DT& A, 
   if (k_tot == 0) {
     g.K = 0;
   }
+  // scratch for a split-K launch: what is left of the arena, up to 64 M doubles
+  const size_t split_mark = ws.mark();
+  const size_t avail = ws.available() / sizeof(double);
+  const long long cap = (long long)std::min<size_t>(avail > 4096 ? avail - 4096 : 0, (size_t)1 << 26);
+  if (cap > 0) {
+    g.split_ws = ws.alloc((size_t)cap);
+    g.split_cap = g.split_ws ? cap : 0;
+  }
   st.err = gemm(g, prec, s);
+  ws.reset(split_mark);
   if (st.err != hipSuccess) { ws.reset(mark); return st; }
   if (tempC) {
     PermArgs p{};

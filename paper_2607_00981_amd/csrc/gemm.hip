@@ -24,6 +24,7 @@
 #include "internal.h"
 
 #include <climits>
+#include <numeric>
 
 namespace cct {
 namespace {
@@ -206,8 +207,11 @@ __device__ __forceinline__ void store_c(const GemmArgs& g, int tm, int tn, long 
 // ---------------------------------------------------------------------------
 // FP64 kernel
 // ---------------------------------------------------------------------------
+// kchunk > 0: this workgroup covers K range [blockIdx.y * kchunk, + kchunk) and
+// writes its raw partial sums to part[((b * splits + y) * M + m) * N + n].
 template <int BM, int BN>
-__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n, int kchunk,
+                                                         double* __restrict__ part) {
   using T = Tiles<BM, BN>;
   __shared__ double As[2][BK * T::LA];
   __shared__ double Bs[2][BK * T::LB];
@@ -215,6 +219,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
   int tm, tn;
   if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
   const int b = blockIdx.z;
+  constexpr bool can_split = (BM == 64);  // the split path exists for the small-tile kernel only
+  if (can_split && kchunk > 0) {
+    // K sub-range of this split: shift A and B by its start, shorten K
+    const int k_begin = blockIdx.y * kchunk;
+    g.K = min(g.K, k_begin + kchunk) - k_begin;
+    g.A = (const double*)g.A + map2(g.ak, k_begin);
+    g.B = (const double*)g.B + map2(g.bk, k_begin);
+  }
   const double* A = (const double*)g.A;
   const double* B = (const double*)g.B;
   Loader<BM, BN> L;
@@ -261,7 +273,41 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
     for (int j = 0; j < T::TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) out[i][j][r] = acc[i][j][r];
+  if (can_split && kchunk > 0) {
+    const int lane_ = threadIdx.x & 63;
+    double* P = part + ((long long)b * gridDim.y + blockIdx.y) * (long long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = tm * BM + wm0 + i * 16 + 4 * r + lane_ / 16;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) {
+          const int n = tn * BN + wn0 + j * 16 + (lane_ & 15);
+          if (n < g.N) P[(long long)m * g.N + n] = out[i][j][r];
+        }
+      }
+    return;
+  }
   store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, true);
+}
+
+// C(m,n) = alpha * sum_y part[b][y][m][n] + beta * C(m,n), splits added in order.
+__global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits, GemmArgs g) {
+  const long long mn = (long long)g.M * g.N;
+  const long long total = mn * g.batch;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / mn, r = e - b * mn;
+    const int m = (int)(r / g.N), n = (int)(r - (long long)m * g.N);
+    const double* p = part + b * splits * mn + r;
+    double acc = 0.0;
+    for (int y = 0; y < splits; ++y) acc += p[y * mn];
+    double* c = g.C + b * g.c_batch + map2(g.cm, m) + map2(g.cn, n);
+    const double x = g.alpha * acc;
+    *c = (g.beta == 0.0) ? x : x + g.beta * *c;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -450,8 +496,42 @@ hipError_t launch(const GemmArgs& g, Prec prec, hipStream_t s) {
   const long long grid_x = ((nb + 7) / 8) * 8;
   if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
   dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
-  if (prec == Prec::F64)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
+  if (prec == Prec::F64) {
+    // few output tiles and a long K: split K so that the chip fills
+    int splits = 1;
+    const long long tiles = nb * g.batch;
+    const long long mn = (long long)g.M * g.N * g.batch;
+    if (BM == 64 && g.split_ws && tiles < 128 && g.K >= 8 * BK) {
+      splits = (int)std::min<long long>((256 + tiles - 1) / tiles, g.K / (4 * BK));
+      splits = (int)std::min<long long>(splits, g.split_cap / std::max<long long>(mn, 1));
+      splits = std::min(splits, 64);
+    }
+    // a split starts at a multiple of BK and of both operands' inner K extents,
+    // so that each operand's K map shifts by a constant
+    long long unit = BK;
+    for (int inner : {g.ak.inner, g.bk.inner})
+      if (inner > 0) unit = std::lcm(unit, (long long)inner);
+    if (splits >= 2 && unit < g.K) {
+      const long long per = (g.K + splits - 1) / splits;
+      const int kchunk = (int)(((per + unit - 1) / unit) * unit);
+      splits = (g.K + kchunk - 1) / kchunk;
+    } else {
+      splits = 1;
+    }
+    if (splits >= 2) {
+      const long long per = (g.K + splits - 1) / splits;
+      const int kchunk = (int)(((per + unit - 1) / unit) * unit);
+      grid.y = (unsigned)splits;
+      hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n, kchunk, g.split_ws);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const long long total = mn;
+      const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 4096);
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const double*)g.split_ws, splits, g);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n, 0, (double*)nullptr);
+  }
   else if (prec == Prec::F32)
     hipLaunchKernelGGL((gemm_f32_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
   else

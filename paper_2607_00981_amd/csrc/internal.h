@@ -29,6 +29,11 @@ struct GemmArgs {
   // Elements addressable from A, B, C (0 = unchecked).  When set, the host
   // verifies before launch that every index map stays inside the operand.
   long long a_len, b_len, c_len;
+  // Optional scratch for splitting a long K over workgroups when the output
+  // has few tiles (FP64 only): partial products go to split_ws (split_cap
+  // doubles) and a fixed-order reduction adds them into C.  nullptr: no split.
+  double* split_ws;
+  long long split_cap;
 };
 
 // Largest offset reached by an index map over [0, n) (non-negative strides).
