@@ -164,8 +164,9 @@ const char* cct_last_error(const cct_ctx* ctx);
 typedef struct cct_batch cct_batch;
 
 /* nsys systems with sizes nocc[s], nvir[s], naux[s] (host arrays), all in
- * precision prec.  opts_json: "streams" (1..4, default 4: systems are spread
- * round-robin over that many streams, which the graph forks and joins),
+ * precision prec.  opts_json: "streams" (1..16, default 4: systems are spread
+ * over that many streams, largest triples work first onto the least loaded
+ * stream; the graph forks and joins them),
  * "graph" (true by default; false enqueues every iteration eagerly, the same
  * kernels in the same order), and the per-system keys of cct_create
  * ("diis", "diis_space", "diis_start", "diis_t3", "workspace_gb").

@@ -1947,7 +1947,7 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
     if (json_find(js, "diis_t3", val)) sys_opts += ", \"diis_t3\": \"" + val + "\"";
   }
   sys_opts += "}";
-  if (nstreams < 1 || nstreams > 4) return CCT_EINVAL;
+  if (nstreams < 1 || nstreams > 16) return CCT_EINVAL;
   cct_batch* b = new cct_batch();
   b->use_graph = use_graph;
   int rc = CCT_OK;
@@ -1960,9 +1960,28 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
     b->join.push_back(e);
   }
   if (rc == CCT_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) rc = CCT_EDEVICE;
+  // spread the systems over the streams by longest-processing-time-first on
+  // the leading triples work (ladder 3 ntri v^5 + rings 12 ntri o v^4)
+  std::vector<int> stream_of(nsys, 0);
+  {
+    std::vector<double> cost(nsys);
+    for (int i = 0; i < nsys; ++i) {
+      const double o = nocc[i], v = nvir[i], nt = o * (o + 1) * (o + 2) / 6.0;
+      cost[i] = 3.0 * nt * std::pow(v, 5) + 12.0 * nt * o * std::pow(v, 4);
+    }
+    std::vector<int> order(nsys);
+    for (int i = 0; i < nsys; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nstreams, 0.0);
+    for (int i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      stream_of[i] = k;
+      load[k] += cost[i];
+    }
+  }
   for (int i = 0; i < nsys && rc == CCT_OK; ++i) {
     cct_ctx* c = nullptr;
-    rc = cct_create(nocc[i], nvir[i], naux[i], prec, sys_opts.c_str(), b->streams[i % nstreams], &c);
+    rc = cct_create(nocc[i], nvir[i], naux[i], prec, sys_opts.c_str(), b->streams[stream_of[i]], &c);
     if (rc == CCT_OK) b->sys.push_back(c);
   }
   if (rc != CCT_OK) {
