@@ -921,22 +921,59 @@ int r3_pp(cct_ctx* ctx) {
 int r3_f1(cct_ctx* ctx) {
   // sum_d F^a_d t^{dbc} + F^b_d t^{adc} + F^c_d t^{abd}, one GEMM per axis, batched over blocks
   const int v = ctx->v;
-  const long long v2 = (long long)v * v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, nt3 = ctx->ntri * v3;
   const int nt = (int)ctx->ntri;
+  if (!(v & 1)) {
+    // matrix-core kernel: axis 0 reads the block as [K][N], axis 2 as [M][K]
+    for (int start = 0; start < nt; start += 65535) {
+      const int nb = std::min(65535, nt - start);
+      const long long off = (long long)start * v3;
+      NtArgs g{};
+      g.M = v; g.N = (int)v2; g.K = v; g.batch = nb;  // C[a][(b,c)] += F[a][d] T[d][(b,c)]
+      g.A = ctx->Fvv; g.lda = v; g.a_batch = 0;
+      g.B = ctx->t3 + off; g.ldb = v2; g.b_batch = v3; g.b_kn = 1;
+      g.C = ctx->r3 + off; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = v3;
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = v2; g.b_len = nt3 - off; g.c_len = nt3 - off;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+      NtArgs h{};
+      h.M = (int)v2; h.N = v; h.K = v; h.batch = nb;  // C[(a,b)][c] += T[(a,b)][d] F[c][d]
+      h.A = ctx->t3 + off; h.lda = v; h.a_batch = v3;
+      h.B = ctx->Fvv; h.ldb = v; h.b_batch = 0;
+      h.C = ctx->r3 + off; h.cm = idx1(v); h.cn = idx1(1); h.c_batch = v3;
+      h.alpha = 1.0; h.beta = 1.0;
+      h.a_len = nt3 - off; h.b_len = v2; h.c_len = nt3 - off;
+      HIPCK(gemm_nt(h, Prec::F64, ctx->s));
+    }
+    // axis 1 (strided in the block): generic kernel, batched over blocks
+    for (int start = 0; start < nt; start += 65535) {
+      const int nb = std::min(65535, nt - start);
+      const long long off = (long long)start * v3;
+      GemmArgs g{};
+      g.M = v; g.K = v; g.N = (int)v2; g.batch = nb;
+      g.A = ctx->Fvv; g.am = idx1(v); g.ak = idx1(1); g.a_batch = 0;
+      g.B = ctx->t3 + off; g.bk = idx1(v); g.bn = idx2(v, v2, 1); g.b_batch = v3;
+      g.C = ctx->r3 + off; g.cm = idx1(v); g.cn = idx2(v, v2, 1); g.c_batch = v3;
+      g.alpha = 1.0; g.beta = 1.0;
+      g.a_len = v2; g.b_len = nt3 - off; g.c_len = nt3 - off;
+      HIPCK(gemm(g, Prec::F64, ctx->s));
+    }
+    return CCT_OK;
+  }
   for (int start = 0; start < nt; start += 65535) {
     const int nb = std::min(65535, nt - start);
-    const long long off = (long long)start * ctx->v3;
+    const long long off = (long long)start * v3;
     for (int axis = 0; axis < 3; ++axis) {
       GemmArgs g{};
       g.M = v; g.K = v; g.N = (int)v2; g.batch = nb;
       g.A = ctx->Fvv; g.am = idx1(v); g.ak = idx1(1); g.a_batch = 0;
-      g.B = ctx->t3 + off; g.b_batch = ctx->v3;
-      g.C = ctx->r3 + off; g.c_batch = ctx->v3;
+      g.B = ctx->t3 + off; g.b_batch = v3;
+      g.C = ctx->r3 + off; g.c_batch = v3;
       if (axis == 0) { g.bk = idx1(v2); g.bn = idx1(1); g.cm = idx1(v2); g.cn = idx1(1); }
       if (axis == 1) { g.bk = idx1(v); g.bn = idx2(v, v2, 1); g.cm = idx1(v); g.cn = idx2(v, v2, 1); }
       if (axis == 2) { g.bk = idx1(1); g.bn = idx1(v); g.cm = idx1(1); g.cn = idx1(v); }
       g.alpha = 1.0; g.beta = 1.0;
-      g.a_len = v2; g.b_len = ctx->ntri * ctx->v3 - off; g.c_len = ctx->ntri * ctx->v3 - off;
+      g.a_len = v2; g.b_len = nt3 - off; g.c_len = nt3 - off;
       HIPCK(gemm(g, Prec::F64, ctx->s));
     }
   }
@@ -1035,6 +1072,13 @@ int r3_hh(cct_ctx* ctx, bool with_hh, bool with_f2) {
   else HIPCK(fill(ctx->Wh, 0.0, o4, ctx->s));
   if (with_f2) HIPCK(add_pair_diag(ctx->Wh, ctx->Foo, o, o, -0.5, ctx->s));
   Arena& ws = ctx->ws;
+  const size_t mk0 = ws.mark();
+  // W~ transposed, [(p,q)][(l,m)]: the K-contiguous operand of the matrix-core kernel
+  const long long o2 = (long long)o * o;
+  const bool nt = !(o2 & 1) && !(v3 & 1);
+  double* WhT = nt ? ws.alloc((size_t)o4) : nullptr;
+  if (nt && !WhT) { ctx->err = "workspace exhausted (hole ladder)"; return CCT_ENOMEM; }
+  if (nt) HIPCK(transpose_batched(ctx->Wh, OutSpec{WhT, OUT_F64, 0}, 1, (int)o2, (int)o2, ctx->s));
   for (const Batch& b : ctx->hh.batches) {
     const size_t mk = ws.mark();
     double* U = ws.alloc((size_t)(b.nslots * o2v3));
@@ -1047,17 +1091,30 @@ int r3_hh(cct_ctx* ctx, bool with_hh, bool with_f2) {
     ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
     ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
     HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
-    GemmArgs g{};
-    g.M = o * o; g.N = (int)v3; g.K = o * o; g.batch = b.nslots;
-    g.A = ctx->Wh; g.am = idx1(1); g.ak = idx1((long long)o * o); g.a_batch = 0;
-    g.B = U; g.bk = idx1(v3); g.bn = idx1(1); g.b_batch = o2v3;
-    g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
-    g.alpha = 1.0; g.beta = 0.0;
-    g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
-    HIPCK(gemm(g, Prec::F64, ctx->s));
+    if (nt) {
+      // Z[r][(p,q)][xyz] = sum_(l,m) WhT[(p,q)][(l,m)] U[r][(l,m)][xyz], U stored [K][N]
+      NtArgs g{};
+      g.M = (int)o2; g.N = (int)v3; g.K = (int)o2; g.batch = b.nslots;
+      g.A = WhT; g.lda = o2; g.a_batch = 0;
+      g.B = U; g.ldb = v3; g.b_batch = o2v3; g.b_kn = 1;
+      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+    } else {
+      GemmArgs g{};
+      g.M = o * o; g.N = (int)v3; g.K = o * o; g.batch = b.nslots;
+      g.A = ctx->Wh; g.am = idx1(1); g.ak = idx1((long long)o * o); g.a_batch = 0;
+      g.B = U; g.bk = idx1(v3); g.bn = idx1(1); g.b_batch = o2v3;
+      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
+      HIPCK(gemm(g, Prec::F64, ctx->s));
+    }
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }
+  ws.reset(mk0);
   return CCT_OK;
 }
 
@@ -1066,10 +1123,36 @@ int r3_drivers(cct_ctx* ctx, int which) {
   const long long v2 = (long long)v * v, v3 = ctx->v3, o2v3 = (long long)o * o * v3;
   Arena& ws = ctx->ws;
   const Job& J = which == 0 ? ctx->d1 : ctx->d2;
+  const size_t mk0 = ws.mark();
+  // K-contiguous copies for the matrix-core kernel (driver 1, even v):
+  //   WtT[q][(x,y)][d] = W^{xy}_{dq},  t2T[(p,r,z)][d] = t_pr^dz
+  const bool nt = which == 0 && !(v & 1);
+  double *WtT = nullptr, *t2T = nullptr;
+  if (nt) {
+    WtT = ws.alloc((size_t)(o * v3));
+    t2T = ws.alloc((size_t)o * o * v2);
+    if (!WtT || !t2T) { ctx->err = "workspace exhausted (drivers)"; return CCT_ENOMEM; }
+    STCK(accumulate(ctx->s, 1.0, dense(ctx->Wt, {v, o, v, v}), "dqyx", 0.0, dense(WtT, {o, v, v, v}), "qxyd"));
+    STCK(accumulate(ctx->s, 1.0, dense(ctx->t2, {o, o, v, v}), "prdz", 0.0, dense(t2T, {o, o, v, v}), "przd"));
+  }
   for (const Batch& b : J.batches) {
     const size_t mk = ws.mark();
     double* Z = ws.alloc((size_t)(b.nslots * o2v3));
     if (!Z) { ctx->err = "workspace exhausted (drivers)"; return CCT_ENOMEM; }
+    if (nt) {
+      // Z[q][(x,y)][(p,r,z)] = sum_d WtT[q][(x,y)][d] t2T[(p,r,z)][d]
+      NtArgs g{};
+      g.M = (int)v2; g.N = o * o * v; g.K = v; g.batch = b.nslots;
+      g.A = WtT + (long long)b.slot0 * v3; g.lda = v; g.a_batch = v3;
+      g.B = t2T; g.ldb = v; g.b_batch = 0;
+      g.C = Z; g.cm = idx1((long long)o * o * v); g.cn = idx1(1); g.c_batch = o2v3;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = (long long)(o - b.slot0) * v3; g.b_len = (long long)o * o * v2; g.c_len = b.nslots * o2v3;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+      HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+      ws.reset(mk);
+      continue;
+    }
     GemmArgs g{};
     g.batch = b.nslots;
     if (which == 0) {
@@ -1093,6 +1176,7 @@ int r3_drivers(cct_ctx* ctx, int which) {
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }
+  ws.reset(mk0);
   return CCT_OK;
 }
 

@@ -576,7 +576,7 @@ struct NtCfg {
   static constexpr int SB = BN * (BK / 2) / NTH;
 };
 
-template <int BM, int BN, int WM, int WN, int OCC>
+template <int BM, int BN, int WM, int WN, int OCC, bool BKN>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g, int tiles_m, int tiles_n) {
   using C = NtCfg<BM, BN, WM, WN>;
   __shared__ double As[2][BK * C::LA];
@@ -604,11 +604,19 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g
 #pragma unroll
   for (int i = 0; i < C::SB; ++i) {
     const int seg = tid + i * C::NTH;
-    const int row = seg / (BK / 2);
-    kb[i] = 2 * (seg % (BK / 2));
-    const int n = tn * BN + row;
-    vb[i] = n < g.N;
-    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+    if constexpr (BKN) {
+      // B[k][n]: segments of two consecutive n in one k row
+      kb[i] = seg / (BN / 2);
+      const int n = tn * BN + 2 * (seg % (BN / 2));
+      vb[i] = n < g.N;
+      pb[i] = B + (long long)kb[i] * g.ldb + (vb[i] ? n : 0);
+    } else {
+      const int row = seg / (BK / 2);
+      kb[i] = 2 * (seg % (BK / 2));
+      const int n = tn * BN + row;
+      vb[i] = n < g.N;
+      pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
+    }
   }
   const int wave = tid / 64, lane = tid & 63;
   const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
@@ -632,7 +640,8 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g
 #pragma unroll
     for (int i = 0; i < C::SB; ++i) {
       ob[i] = vb[i] && (k0 + kb[i] < g.K);
-      rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0));
+      if constexpr (BKN) rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? (long long)k0 * g.ldb : 0));
+      else rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0));
     }
   };
   auto store = [&](double* as, double* bs) {
@@ -644,9 +653,15 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g
     }
 #pragma unroll
     for (int i = 0; i < C::SB; ++i) {
-      const int row = (tid + i * C::NTH) / (BK / 2);
-      bs[kb[i] * C::LB + row] = ob[i] ? rb[i].x : 0.0;
-      bs[(kb[i] + 1) * C::LB + row] = ob[i] ? rb[i].y : 0.0;
+      if constexpr (BKN) {
+        const int col = 2 * ((tid + i * C::NTH) % (BN / 2));
+        bs[kb[i] * C::LB + col] = ob[i] ? rb[i].x : 0.0;
+        bs[kb[i] * C::LB + col + 1] = ob[i] ? rb[i].y : 0.0;
+      } else {
+        const int row = (tid + i * C::NTH) / (BK / 2);
+        bs[kb[i] * C::LB + row] = ob[i] ? rb[i].x : 0.0;
+        bs[(kb[i] + 1) * C::LB + row] = ob[i] ? rb[i].y : 0.0;
+      }
     }
   };
   load(0);
@@ -700,8 +715,13 @@ hipError_t launch_nt(const NtArgs& g, hipStream_t s) {
   const long long nb = (long long)tiles_m * tiles_n;
   const long long grid_x = ((nb + 7) / 8) * 8;
   if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_nt_f64_kernel<BM, BN, WM, WN, OCC>), dim3((unsigned)grid_x, 1, (unsigned)g.batch),
-                     dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+  const dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  if (g.b_kn)
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<BM, BN, WM, WN, OCC, true>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
+                       tiles_n);
+  else
+    hipLaunchKernelGGL((gemm_nt_f64_kernel<BM, BN, WM, WN, OCC, false>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
+                       tiles_n);
   return hipGetLastError();
 }
 
@@ -710,12 +730,16 @@ hipError_t launch_nt(const NtArgs& g, hipStream_t s) {
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (prec != Prec::F64) return hipErrorInvalidValue;
+  // 16-byte loads: A rows (and B rows, or B's N for [K][N] storage) in pairs, 16-byte aligned
   if (g.K <= 0 || (g.K & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_batch & 1) || (g.b_batch & 1) ||
-      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15))
+      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15) || (g.b_kn && (g.N & 1)))
     return hipErrorInvalidValue;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
-  if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
+  if (g.b_len > 0 && !g.b_kn && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len)
+    return hipErrorInvalidValue;
+  if (g.b_len > 0 && g.b_kn && nb * g.b_batch + (long long)(g.K - 1) * g.ldb + g.N > g.b_len)
+    return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
   int variant = g.variant;
   if (variant == 0) {

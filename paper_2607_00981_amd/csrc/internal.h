@@ -65,6 +65,7 @@ struct NtArgs {
   double alpha, beta;
   long long a_len, b_len, c_len;  // bounds for the host check (0 = unchecked)
   int variant;                    // tile variant (0 = default)
+  int b_kn;                       // 1: B is stored [K][N] (row stride ldb, N contiguous) instead of [N][K]
 };
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s);
 // The same product in FP32 or split-BF16 (FP64 operands rounded in LDS, FP64
