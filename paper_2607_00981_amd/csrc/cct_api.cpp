@@ -87,6 +87,7 @@ struct cct_ctx {
   // tables
   BlockRef* tbl = nullptr;
   int4* tri = nullptr;
+  int* pair_rows = nullptr;  // p*o + q for the ordered pairs p <= q (hole ladder rows)
   double* red = nullptr;  // reduction scratch
   long long red_n = 0;
   double* scal = nullptr;  // device scalars
@@ -373,20 +374,29 @@ int build_plans(cct_ctx* ctx) {
       return cs;
     }));
   }
-  // ---- hole ladder (+ F_oo): slots are r; Z[slot(r)][(p,q)][x][y][z]
+  // ---- hole ladder (+ F_oo): slots are r; Z[slot(r)][pair(p<=q)][x][y][z]
+  //      (every contribution of a packed triple has its first two occupied
+  //      indices in order, so only the o(o+1)/2 ordered pairs are formed)
   {
     Job& J = ctx->hh;
+    const long long npair = (long long)o * (o + 1) / 2;
+    auto pidx = [o](int p, int q) { return (long long)p * o - (long long)p * (p - 1) / 2 + (q - p); };
     for (int r = 0; r < o; ++r) J.slots.push_back(int2{r, 0});
     J.nslot_total = o;
-    J.per_batch = slots_per_batch(budget, 2 * o2v3, o);
-    RCK(build_job(ctx, J, o2v3, [&](int t) {
+    J.per_batch = slots_per_batch(budget, o2v3 + npair * v3, o);
+    RCK(build_job(ctx, J, npair * v3, [&](int t) {
       const int i = tri[t].x, j = tri[t].y, k = tri[t].z;
       std::vector<Contrib> cs;
-      cs.push_back({k, ((long long)i * o + j) * v3, v2, v, 1, 1.0});  // (i,j;k)[a,b;c]
-      cs.push_back({j, ((long long)i * o + k) * v3, v2, 1, v, 1.0});  // (i,k;j)[a,c;b]
-      cs.push_back({i, ((long long)j * o + k) * v3, 1, v2, v, 1.0});  // (j,k;i)[b,c;a]
+      cs.push_back({k, pidx(i, j) * v3, v2, v, 1, 1.0});  // (i,j;k)[a,b;c]
+      cs.push_back({j, pidx(i, k) * v3, v2, 1, v, 1.0});  // (i,k;j)[a,c;b]
+      cs.push_back({i, pidx(j, k) * v3, 1, v2, v, 1.0});  // (j,k;i)[b,c;a]
       return cs;
     }));
+    std::vector<int> rows;
+    for (int p_ = 0; p_ < o; ++p_)
+      for (int q = p_; q < o; ++q) rows.push_back(p_ * o + q);
+    RCK(dalloc_t(ctx, &ctx->pair_rows, (long long)rows.size()));
+    HIPCK(hipMemcpy(ctx->pair_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice));
   }
   // ---- drivers
   {
@@ -1067,22 +1077,24 @@ int r3_rings(cct_ctx* ctx, int kind) {
 int r3_hh(cct_ctx* ctx, bool with_hh, bool with_f2) {
   const int o = ctx->o, v = ctx->v;
   const long long v3 = ctx->v3, o2v3 = (long long)o * o * v3, o4 = (long long)o * o * o * o;
+  const long long o2 = (long long)o * o, npair = (long long)o * (o + 1) / 2;
   // Wh = W^{lm}_{pq} - 1/2 (delta_mq F^l_p + delta_lp F^m_q)
   if (with_hh) HIPCK(axpby(1.0, ctx->Woooo, 0.0, ctx->Wh, o4, ctx->s));
   else HIPCK(fill(ctx->Wh, 0.0, o4, ctx->s));
   if (with_f2) HIPCK(add_pair_diag(ctx->Wh, ctx->Foo, o, o, -0.5, ctx->s));
   Arena& ws = ctx->ws;
   const size_t mk0 = ws.mark();
-  // W~ transposed, [(p,q)][(l,m)]: the K-contiguous operand of the matrix-core kernel
-  const long long o2 = (long long)o * o;
+  // A[pair(p<=q)][(l,m)] = Wh[(l,m)][(p,q)]: transpose, then keep the ordered pairs
+  double* WhT = ws.alloc((size_t)o4);
+  double* WhP = ws.alloc((size_t)(npair * o2));
+  if (!WhT || !WhP) { ctx->err = "workspace exhausted (hole ladder)"; return CCT_ENOMEM; }
+  HIPCK(transpose_batched(ctx->Wh, OutSpec{WhT, OUT_F64, 0}, 1, (int)o2, (int)o2, ctx->s));
+  HIPCK(gather_rows(WhT, o2, ctx->pair_rows, (int)npair, o2, WhP, o2, ctx->s));
   const bool nt = !(o2 & 1) && !(v3 & 1);
-  double* WhT = nt ? ws.alloc((size_t)o4) : nullptr;
-  if (nt && !WhT) { ctx->err = "workspace exhausted (hole ladder)"; return CCT_ENOMEM; }
-  if (nt) HIPCK(transpose_batched(ctx->Wh, OutSpec{WhT, OUT_F64, 0}, 1, (int)o2, (int)o2, ctx->s));
   for (const Batch& b : ctx->hh.batches) {
     const size_t mk = ws.mark();
     double* U = ws.alloc((size_t)(b.nslots * o2v3));
-    double* Z = ws.alloc((size_t)(b.nslots * o2v3));
+    double* Z = ws.alloc((size_t)(b.nslots * npair * v3));
     if (!U || !Z) { ctx->err = "workspace exhausted (hole ladder)"; return CCT_ENOMEM; }
     UnpackArgs ua{};
     ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 2;
@@ -1091,24 +1103,24 @@ int r3_hh(cct_ctx* ctx, bool with_hh, bool with_f2) {
     ua.s_slot = o2v3; ua.s_free[0] = (long long)o * v3; ua.s_free[1] = v3;
     ua.s_x = (long long)v * v; ua.s_y = v; ua.s_z = 1;
     HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, U, ua, ctx->s));
+    // Z[r][pair][xyz] = sum_(l,m) WhP[pair][(l,m)] U[r][(l,m)][xyz]
     if (nt) {
-      // Z[r][(p,q)][xyz] = sum_(l,m) WhT[(p,q)][(l,m)] U[r][(l,m)][xyz], U stored [K][N]
       NtArgs g{};
-      g.M = (int)o2; g.N = (int)v3; g.K = (int)o2; g.batch = b.nslots;
-      g.A = WhT; g.lda = o2; g.a_batch = 0;
+      g.M = (int)npair; g.N = (int)v3; g.K = (int)o2; g.batch = b.nslots;
+      g.A = WhP; g.lda = o2; g.a_batch = 0;
       g.B = U; g.ldb = v3; g.b_batch = o2v3; g.b_kn = 1;
-      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
+      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = npair * v3;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
+      g.a_len = npair * o2; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * npair * v3;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     } else {
       GemmArgs g{};
-      g.M = o * o; g.N = (int)v3; g.K = o * o; g.batch = b.nslots;
-      g.A = ctx->Wh; g.am = idx1(1); g.ak = idx1((long long)o * o); g.a_batch = 0;
+      g.M = (int)npair; g.N = (int)v3; g.K = (int)o2; g.batch = b.nslots;
+      g.A = WhP; g.am = idx1(o2); g.ak = idx1(1); g.a_batch = 0;
       g.B = U; g.bk = idx1(v3); g.bn = idx1(1); g.b_batch = o2v3;
-      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = o2v3;
+      g.C = Z; g.cm = idx1(v3); g.cn = idx1(1); g.c_batch = npair * v3;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = o4; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * o2v3;
+      g.a_len = npair * o2; g.b_len = b.nslots * o2v3; g.c_len = b.nslots * npair * v3;
       HIPCK(gemm(g, Prec::F64, ctx->s));
     }
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));

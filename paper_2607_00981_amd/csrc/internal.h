@@ -178,6 +178,9 @@ hipError_t fill(double* y, double val, long long n, hipStream_t s);
 // R1[i][a] += 1/2 sum_{j in [f0, f0+S), k, b, c} vvT[j][k][c][b] (2 U[(k,i,c)][j-f0][a][b] - U[(k,i,a)][j-f0][c][b])
 // with U[(k,i,x)][j'][p][q] the single-check spin-summed slab t~_{j k i}^{q x p} (one block per (i,a)).
 hipError_t feedback_r1(const double* U, const double* vvT, double* r1, int o, int v, int S, int f0, hipStream_t s);
+// out[r * ld_out + c] = in[rows[r] * ld_in + c] for r < nrows, c < ncols (rows: device array).
+hipError_t gather_rows(const double* in, long long ld_in, const int* rows, int nrows, long long ncols, double* out,
+                       long long ld_out, hipStream_t s);
 // Y[b*sb + f*sf + b*sp + q*sq] += alpha * X[f*xf + q] for b < nb, f < nf, q < nq.
 hipError_t add_diag_rows(double* Y, const double* X, int nb, int nf, int nq, long long sb, long long sf, long long sp,
                          long long sq, long long xf, double alpha, hipStream_t s);

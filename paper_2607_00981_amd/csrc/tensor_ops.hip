@@ -565,6 +565,16 @@ __global__ void r1_feedback_kernel(const double* __restrict__ U, const double* _
 }
 
 // Y[b*sb + f*sf + b*sp + q*sq] += alpha * X[f*xf + q] for b < nb, f < nf, q < nq.
+__global__ void gather_rows_kernel(const double* __restrict__ in, long long ld_in, const int* __restrict__ rows,
+                                   int nrows, long long ncols, double* __restrict__ out, long long ld_out) {
+  const long long total = (long long)nrows * ncols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / ncols, c = e - r * ncols;
+    out[r * ld_out + c] = in[(long long)rows[r] * ld_in + c];
+  }
+}
+
 __global__ void add_diag_rows_kernel(double* __restrict__ Y, const double* __restrict__ X, int nb, int nf, int nq,
                                      long long sb, long long sf, long long sp, long long sq, long long xf,
                                      double alpha) {
@@ -585,6 +595,15 @@ hipError_t feedback_r1(const double* U, const double* vvT, double* r1, int o, in
                        hipStream_t s) {
   if (S <= 0) return hipSuccess;
   hipLaunchKernelGGL(r1_feedback_kernel, dim3((unsigned)(o * v)), dim3(TPB), 0, s, U, vvT, r1, o, v, S, f0);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows(const double* in, long long ld_in, const int* rows, int nrows, long long ncols, double* out,
+                       long long ld_out, hipStream_t s) {
+  const long long total = (long long)nrows * ncols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, in, ld_in, rows, nrows,
+                     ncols, out, ld_out);
   return hipGetLastError();
 }
 
