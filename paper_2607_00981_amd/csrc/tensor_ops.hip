@@ -6,6 +6,8 @@
 // update, and deterministic reductions.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace cct {
 namespace {
 
@@ -195,71 +197,128 @@ __global__ __launch_bounds__(256) void fold_tiled_kernel(double* __restrict__ R,
 }
 
 // ---------------------------------------------------------------------------
-// R3 post-processing + norm + Jacobi update.  One thread per orbit
-// {(a,b,c) and its permutations} with a <= b <= c.
+// R3 post-processing + norm + Jacobi update.  The virtual block is cut into
+// PT^3 tiles; a workgroup takes an orbit of tiles {(A,B,C) and its
+// permutations}, A <= B <= C, stages those (at most six) R tiles in LDS with
+// row-contiguous loads, post-processes every element orbit
+// {(a,b,c) and its permutations} inside LDS, and writes R back and updates T
+// with row-contiguous accesses.  Each element is read and written once.
 // ---------------------------------------------------------------------------
-__global__ void post_update_kernel(double* __restrict__ R, double* __restrict__ T, const int4* __restrict__ tri,
-                                   const double* __restrict__ eps, double* __restrict__ partial, PostArgs pa) {
+constexpr int PT = 8;
+constexpr int PT3 = PT * PT * PT;
+
+__device__ __forceinline__ void decode_tile_orbit(int idx, int nt, int& A, int& B, int& C) {
+  A = 0;
+  while (true) {
+    const int cnt = (nt - A) * (nt - A + 1) / 2;
+    if (idx < cnt) break;
+    idx -= cnt;
+    ++A;
+  }
+  B = A;
+  while (idx >= nt - B) {
+    idx -= nt - B;
+    ++B;
+  }
+  C = B + idx;
+}
+
+__global__ __launch_bounds__(256) void post_update_kernel(double* __restrict__ R, double* __restrict__ T,
+                                                          const int4* __restrict__ tri,
+                                                          const double* __restrict__ eps,
+                                                          double* __restrict__ partial, PostArgs pa, int nt,
+                                                          int norbit) {
+  __shared__ double L[6 * PT3];
   __shared__ double red[TPB];
   const int t = blockIdx.y;
   const int4 ijk = tri[t];
   const int o = pa.o, v = pa.v;
-  const long long v2 = (long long)v * v, v3 = v2 * v;
+  const long long v2 = (long long)v * v;
   double* Rt = R + (long long)t * pa.bs;
   double* Tt = T + (long long)t * pa.bs;
   const bool ij = (ijk.x == ijk.y), jk = (ijk.y == ijk.z);
   const double eocc = eps[ijk.x] + eps[ijk.y] + eps[ijk.z];
+  // placements p of (x,y,z): 0:(x,y,z) 1:(x,z,y) 2:(y,x,z) 3:(y,z,x) 4:(z,x,y) 5:(z,y,x)
+  const int sw12[6] = {2, 4, 0, 5, 1, 3};
+  const int sw23[6] = {1, 0, 3, 2, 5, 4};
   double nrm = 0.0;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < v3; e += (long long)gridDim.x * blockDim.x) {
-    const int a = (int)(e / v2);
-    const int rem = (int)(e - (long long)a * v2);
-    const int b = rem / v;
-    const int c = rem - b * v;
-    if (a > b || b > c) continue;
-    // the six placements of (a,b,c): p = 0:(a,b,c) 1:(a,c,b) 2:(b,a,c) 3:(b,c,a) 4:(c,a,b) 5:(c,b,a)
-    const int P[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
-    long long off[6];
-    double r[6];
+  for (int orb = blockIdx.x; orb < norbit; orb += gridDim.x) {
+    int A, B, C;
+    decode_tile_orbit(orb, nt, A, B, C);
+    const int TP[6][3] = {{A, B, C}, {A, C, B}, {B, A, C}, {B, C, A}, {C, A, B}, {C, B, A}};
+    int slot[6];
+    int nslot = 0;
+    int slot_tile[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
-      off[p] = (long long)P[p][0] * v2 + (long long)P[p][1] * v + P[p][2];
-      r[p] = Rt[off[p]];
+      slot[p] = -1;
+      for (int q = 0; q < p; ++q)
+        if (TP[q][0] == TP[p][0] && TP[q][1] == TP[p][1] && TP[q][2] == TP[p][2]) { slot[p] = slot[q]; break; }
+      if (slot[p] < 0) { slot[p] = nslot; slot_tile[nslot] = p; ++nslot; }
     }
-    // placement reached by swapping the first two / the last two positions
-    const int sw12[6] = {2, 4, 0, 5, 1, 3};
-    const int sw23[6] = {1, 0, 3, 2, 5, 4};
-    double s[6];
-    if (ij && jk) {
-#pragma unroll
-      for (int p = 0; p < 6; ++p) s[p] = 0.0;
-    } else if (ij) {
-#pragma unroll
-      for (int p = 0; p < 6; ++p) s[p] = 0.5 * (r[p] + r[sw12[p]]);
-    } else if (jk) {
-#pragma unroll
-      for (int p = 0; p < 6; ++p) s[p] = 0.5 * (r[p] + r[sw23[p]]);
-    } else {
-#pragma unroll
-      for (int p = 0; p < 6; ++p) s[p] = r[p];
-    }
-    const double mean = (s[0] + s[1] + s[2] + s[3] + s[4] + s[5]) * (1.0 / 6.0);
-    // distinct placements: p is a duplicate if an earlier placement has the same offset
-    double part = 0.0;
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-      bool dup = false;
-#pragma unroll
-      for (int q = 0; q < p; ++q) dup = dup || (off[q] == off[p]);
-      if (dup) continue;
-      const double x = s[p] - mean;
-      part += x * x;
-      if (pa.keep_r) Rt[off[p]] = x;
-      if (pa.do_update) {
-        const double den = eocc - eps[o + P[p][0]] - eps[o + P[p][1]] - eps[o + P[p][2]];
-        Tt[off[p]] += x / den;
+    // stage the distinct R tiles (rows of PT contiguous elements)
+    for (int sl = 0; sl < nslot; ++sl) {
+      const int* tp = TP[slot_tile[sl]];
+      for (int e = threadIdx.x; e < PT3; e += blockDim.x) {
+        const int x = tp[0] * PT + e / (PT * PT), y = tp[1] * PT + (e / PT) % PT, z = tp[2] * PT + e % PT;
+        if (x < v && y < v && z < v) L[sl * PT3 + e] = Rt[x * v2 + (long long)y * v + z];
       }
     }
-    nrm += part;
+    __syncthreads();
+    // element orbits with a representative in tile (A,B,C)
+    for (int e = threadIdx.x; e < PT3; e += blockDim.x) {
+      const int a = A * PT + e / (PT * PT), b = B * PT + (e / PT) % PT, c = C * PT + e % PT;
+      if (a >= v || b >= v || c >= v) continue;
+      if ((A == B && a > b) || (B == C && b > c)) continue;
+      const int P[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
+      int li[6];
+      double r[6];
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const int* tp = TP[p];
+        li[p] = slot[p] * PT3 + (P[p][0] - tp[0] * PT) * PT * PT + (P[p][1] - tp[1] * PT) * PT + (P[p][2] - tp[2] * PT);
+        r[p] = L[li[p]];
+      }
+      double sv[6];
+      if (ij && jk) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sv[p] = 0.0;
+      } else if (ij) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sv[p] = 0.5 * (r[p] + r[sw12[p]]);
+      } else if (jk) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sv[p] = 0.5 * (r[p] + r[sw23[p]]);
+      } else {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sv[p] = r[p];
+      }
+      const double mean = (sv[0] + sv[1] + sv[2] + sv[3] + sv[4] + sv[5]) * (1.0 / 6.0);
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        bool dup = false;
+#pragma unroll
+        for (int q = 0; q < p; ++q) dup = dup || (li[q] == li[p]);
+        if (dup) continue;
+        const double x = sv[p] - mean;
+        nrm += x * x;
+        L[li[p]] = x;
+      }
+    }
+    __syncthreads();
+    // write R, update T (rows of PT contiguous elements)
+    for (int sl = 0; sl < nslot; ++sl) {
+      const int* tp = TP[slot_tile[sl]];
+      for (int e = threadIdx.x; e < PT3; e += blockDim.x) {
+        const int x = tp[0] * PT + e / (PT * PT), y = tp[1] * PT + (e / PT) % PT, z = tp[2] * PT + e % PT;
+        if (x >= v || y >= v || z >= v) continue;
+        const long long off = x * v2 + (long long)y * v + z;
+        const double val = L[sl * PT3 + e];
+        if (pa.keep_r) Rt[off] = val;
+        if (pa.do_update) Tt[off] += val / (eocc - eps[o + x] - eps[o + y] - eps[o + z]);
+      }
+    }
+    __syncthreads();
   }
   red[threadIdx.x] = nrm * (double)ijk.w;
   __syncthreads();
@@ -450,11 +509,12 @@ hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTa
 
 hipError_t post_update(double* R, double* T, const int4* tri, const double* eps, double* partial, int* npartial,
                        const PostArgs& a, hipStream_t s) {
-  const long long v3 = (long long)a.v * a.v * a.v;
-  const unsigned gx = blocks_for(v3, TPB * 8, 64);
   if (a.ntri > 65535) return hipErrorInvalidValue;
+  const int nt = (a.v + PT - 1) / PT;
+  const int norbit = nt * (nt + 1) * (nt + 2) / 6;
+  const unsigned gx = (unsigned)std::min(norbit, 64);
   dim3 grid(gx, (unsigned)a.ntri);
-  hipLaunchKernelGGL(post_update_kernel, grid, dim3(TPB), 0, s, R, T, tri, eps, partial, a);
+  hipLaunchKernelGGL(post_update_kernel, grid, dim3(TPB), 0, s, R, T, tri, eps, partial, a, nt, norbit);
   *npartial = (int)(gx * a.ntri);
   return hipGetLastError();
 }
