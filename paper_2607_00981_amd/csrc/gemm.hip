@@ -743,11 +743,21 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
   int variant = g.variant;
   if (variant == 0) {
-    // 128 x 256 tiles (8 waves of 64 x 64) once there are enough of them to
-    // fill the chip twice; 128 x 128 below that; 64 x 64 for small outputs
-    const long long t256 = (long long)((g.M + 127) / 128) * ((g.N + 255) / 256) * g.batch;
-    const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-    variant = t256 >= 512 ? 1 : (t128 >= 256 ? 4 : 3);
+    // score each tile shape by the fraction of its MFMA work that lands inside
+    // the matrix (skinny M or N wastes most of a large tile), by how well its
+    // tile count fills the chip (two workgroups on each of 256 CUs), and by
+    // the measured relative speed of the shape on full tiles
+    struct Cand { int var, bm, bn; double speed; };
+    const Cand cands[4] = {{1, 128, 256, 1.00}, {2, 256, 128, 1.00}, {4, 128, 128, 0.96}, {3, 64, 64, 0.86}};
+    double best = -1.0;
+    for (const Cand& c : cands) {
+      const long long tm = (g.M + c.bm - 1) / c.bm, tn = (g.N + c.bn - 1) / c.bn;
+      const double used = ((double)g.M / (double)(tm * c.bm)) * ((double)g.N / (double)(tn * c.bn));
+      const double tiles = (double)(tm * tn * g.batch);
+      const double fill = tiles >= 512.0 ? 1.0 : tiles / 512.0;
+      const double score = used * fill * c.speed;
+      if (score > best) { best = score; variant = c.var; }
+    }
   }
   switch (variant) {
     case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
