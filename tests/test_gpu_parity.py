@@ -4,7 +4,7 @@ Inputs come from cct_inputs (seeded); expected values from oracle/ only.
 Tolerances: FP64 residuals agree to 1e-11 relative to the largest residual
 element (roundoff of a few-thousand-term sums is ~1e-14 relative); energies
 after 20 iterations to 1e-10 Eh.  Mixed modes (ladder and ring contractions
-on FP32 or split-BF16 operands, FP32 accumulation inside a K tile of 32):
+on FP32 or split-BF16 operands, FP32 accumulation over 128 products):
 operand rounding is 2^-24 (FP32) or about 2^-17 (hi+lo BF16) relative, so
 R3 is held to 2e-6 (FP32) and 5e-5 (BF16X3) of its largest element, and the
 energy after 20 DIIS iterations to 1e-6 Eh of the FP64 oracle.
