@@ -1063,7 +1063,8 @@ hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
 //   FP32 accumulation over LP_FLUSH K tiles and an FP64 flush after them.
 //   Split-BF16 operands: hi and lo planes, 16-byte loads of 8 bf16 per plane,
 //   K tile of 32 (one bf16 MFMA step), three products per tile, FP32
-//   accumulation flushed into FP64 after every LP_FLUSH K tiles.
+//   accumulation over the whole K (the kernel keeps an FP64 flush as an
+//   option, unused by the library).
 // ===========================================================================
 namespace cct {
 namespace {
@@ -1211,7 +1212,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC, bool VEC>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
   constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LK = KB + 8;
   constexpr int SA = BM * (KB / 8) / NTH, SB = BN * (KB / 8) / NTH;  // 16-byte segments per plane per thread
@@ -1246,13 +1247,17 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
   }
   const int wave = tid / 64, lane = tid & 63;
   const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
-  double out[TM][TN][4];
+  // ACC64: FP32 accumulators flushed into FP64 every LP_FLUSH K tiles;
+  // otherwise FP32 accumulation over the whole K (no FP64 registers)
+  double out[ACC64 ? TM : 1][ACC64 ? TN : 1][4];
+  if constexpr (ACC64) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+        for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  }
   u32x4 rah[SA], ral[SA], rbh[SB], rbl[SB];
   bool oa[SA], ob[SB];
   const int nk = (g.K + KB - 1) / KB;
@@ -1326,7 +1331,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) load((kt + 1) * KB);
-    if (kt % LP_FLUSH == 0) {
+    if (kt == 0 || (ACC64 && kt % LP_FLUSH == 0)) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -1351,13 +1356,15 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
       }
     }
-    if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
+    if constexpr (ACC64) {
+      if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+          for (int j = 0; j < TN; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+            for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+      }
     }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
@@ -1375,13 +1382,13 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
         const int n = tn * BN + wn0 + j * 16 + (lane & 15);
         if (n >= g.N) continue;
         double* p = g.C + mo + map2(g.cn, n);
-        const double x = g.alpha * out[i][j][r];
+        const double x = g.alpha * (ACC64 ? out[ACC64 ? i : 0][ACC64 ? j : 0][r] : (double)acc[i][j][r]);
         *p = (g.beta == 0.0) ? x : x + g.beta * *p;
       }
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC, bool VEC>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64 = true>
 hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   const long long nb = (long long)tiles_m * tiles_n;
@@ -1391,7 +1398,7 @@ hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (prec == Prec::F32)
     hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, WM, WN, OCC, VEC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC, VEC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
+    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC, VEC, ACC64>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
                        tiles_n);
   return hipGetLastError();
 }
@@ -1412,18 +1419,36 @@ hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const bool vec = !(g.K % w || g.lda % w || g.ldb % w || g.a_batch % w || g.b_batch % w ||
                      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15) ||
                      (prec == Prec::BF16X3 && (g.a_plane % w || g.b_plane % w)));
-  if (!vec) return launch_lp<64, 64, 2, 2, 2, false>(g, prec, s);
+  // FP32 operands: FP32 accumulation over LP_FLUSH K tiles, then FP64.
+  // Split-BF16 operands: FP32 accumulation over the whole K (the three
+  // products of the split already carry ~2^-17 relative rounding).
+  if (prec == Prec::F32) {
+    if (!vec) return launch_lp<64, 64, 2, 2, 2, false, true>(g, prec, s);
+    int variant = g.variant;
+    if (variant == 0) {
+      // 128 x 128 tiles of 8 waves (64 x 32 each, two waves per SIMD) once
+      // there are enough of them; 64 x 64 below that
+      const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+      variant = t128 >= 256 ? 2 : 3;
+    }
+    switch (variant) {
+      case 1: return launch_lp<128, 128, 2, 2, 1, true, true>(g, prec, s);
+      case 2: return launch_lp<128, 128, 2, 4, 2, true, true>(g, prec, s);
+      default: return launch_lp<64, 64, 2, 2, 2, true, true>(g, prec, s);
+    }
+  }
+  if (!vec) return launch_lp<64, 64, 2, 2, 2, false, false>(g, prec, s);
   int variant = g.variant;
   if (variant == 0) {
-    // 128 x 128 tiles of 8 waves (64 x 32 each, two waves per SIMD) once
-    // there are enough of them; 64 x 64 below that
+    // 256 x 128 tiles of 8 waves (64 x 64 each) once there are enough of them
+    const long long t256 = (long long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch;
     const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-    variant = t128 >= 256 ? 2 : 3;
+    variant = t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3);
   }
   switch (variant) {
-    case 1: return launch_lp<128, 128, 2, 2, 1, true>(g, prec, s);
-    case 2: return launch_lp<128, 128, 2, 4, 2, true>(g, prec, s);
-    default: return launch_lp<64, 64, 2, 2, 2, true>(g, prec, s);
+    case 1: return launch_lp<256, 128, 4, 2, 1, true, false>(g, prec, s);
+    case 2: return launch_lp<128, 128, 2, 4, 2, true, false>(g, prec, s);
+    default: return launch_lp<64, 64, 2, 2, 2, true, false>(g, prec, s);
   }
 }
 
