@@ -91,13 +91,14 @@ def cpu_baseline(o, v, naux, seed):
 
 
 NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64,64,2,2,2>", 4: "<128,128,2,2,2>"}
-LP_TILES = {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"}
+LP_TILES = {"fp32": {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"},
+            "bf16x3": {0: "size-based", 1: "<256,128,4,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"}}
 
 
 def kernel_name(prec, variant):
     if prec == "fp64":
         return "gemm_nt_f64_kernel" + NT_TILES.get(variant, str(variant))
-    return f"gemm_lp_{prec.replace('fp32', 'f32')}_kernel" + LP_TILES.get(variant, str(variant))
+    return f"gemm_lp_{prec.replace('fp32', 'f32')}_kernel" + LP_TILES[prec].get(variant, str(variant))
 
 
 def run_mode(binding, s, o, v, naux, prec, steps, warmup, tune_ms=0.0):
