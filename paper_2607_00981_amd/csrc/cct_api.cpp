@@ -882,7 +882,7 @@ int r3_pp(cct_ctx* ctx) {
       g.C = ctx->r3; g.cm = cm[term]; g.cn = cn[term];
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = nt * v3; g.b_len = v2 * v2; g.c_len = nt * v3;
-      HIPCK(gemm(g, ctx->prec, ctx->s));
+      HIPCK(gemm(g, Prec::F64, ctx->s));
     }
     return CCT_OK;
   }
@@ -1065,7 +1065,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
-      HIPCK(gemm(g, ctx->prec, ctx->s));
+      HIPCK(gemm(g, Prec::F64, ctx->s));
     }
     HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);

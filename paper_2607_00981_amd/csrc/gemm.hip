@@ -310,185 +310,6 @@ __global__ void splitk_reduce_kernel(const double* __restrict__ part, int splits
   }
 }
 
-// ---------------------------------------------------------------------------
-// FP32 kernel (operands rounded to FP32, FP64 flush per K tile)
-// ---------------------------------------------------------------------------
-template <int BM, int BN>
-__global__ __launch_bounds__(NT, 1) void gemm_f32_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  using T = Tiles<BM, BN>;
-  __shared__ float As[2][BK * T::LA];
-  __shared__ float Bs[2][BK * T::LB];
-  __shared__ long long rowA[BM], colB[BN];
-  int tm, tn;
-  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
-  const int b = blockIdx.z;
-  const double* A = (const double*)g.A;
-  const double* B = (const double*)g.B;
-  Loader<BM, BN> L;
-  init_loader<BM, BN>(g, tm, tn, (long long)b * g.a_batch, (long long)b * g.b_batch, rowA, colB, L);
-  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
-  double out[T::TM][T::TN][4];
-#pragma unroll
-  for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
-  double ra[T::EA], rb[T::EB];
-  const int nk = (g.K + BK - 1) / BK;
-  load_tile<BM, BN>(g, A, B, L, 0, ra, rb);
-  store_tile<BM, BN, float>(L, ra, rb, As[0], Bs[0]);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load_tile<BM, BN>(g, A, B, L, (kt + 1) * BK, ra, rb);
-    const float* as = As[cur];
-    const float* bs = Bs[cur];
-    f4 acc[T::TM][T::TN];
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < T::TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kr = ks * 4 + lane / 16;
-      float af[T::TM], bf[T::TN];
-#pragma unroll
-      for (int i = 0; i < T::TM; ++i) af[i] = as[kr * T::LA + wm0 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < T::TN; ++j) bf[j] = bs[kr * T::LB + wn0 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < T::TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
-    if (kt + 1 < nk) store_tile<BM, BN, float>(L, ra, rb, As[cur ^ 1], Bs[cur ^ 1]);
-    __syncthreads();
-  }
-  store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, false);
-}
-
-// ---------------------------------------------------------------------------
-// split-BF16 kernel: x = hi + lo, A*B ~ Ahi*Bhi + Ahi*Blo + Alo*Bhi
-// K tile of 32 (one bf16 MFMA k-step); LDS holds hi and lo planes k-major in
-// groups of 8 consecutive k per lane.
-// ---------------------------------------------------------------------------
-constexpr int BK16 = 32;
-
-template <int BM, int BN>
-struct TilesB {
-  static constexpr int TM = BM / 32, TN = BN / 32;
-  static constexpr int EA = BM * BK16 / NT, EB = BN * BK16 / NT;
-  // LDS layout: [row][k] with k contiguous (row stride padded) so that a lane
-  // reads its 8 consecutive k values as one 16-byte vector.
-  static constexpr int LK = BK16 + 8;
-};
-
-__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
-  const float xf = (float)x;
-  hi = (__bf16)xf;
-  lo = (__bf16)(float)(x - (double)(float)hi);
-}
-
-template <int BM, int BN>
-__global__ __launch_bounds__(NT, 1) void gemm_bf16x3_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  using T = TilesB<BM, BN>;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM * T::LK];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[BM * T::LK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN * T::LK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN * T::LK];
-  int tm, tn;
-  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
-  const int b = blockIdx.z;
-  const double* A = (const double*)g.A;
-  const double* B = (const double*)g.B;
-  const long long a_off = (long long)b * g.a_batch, b_off = (long long)b * g.b_batch;
-  const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
-  const int m_base = tm * BM, n_base = tn * BN;
-  // load mappings (single-buffered; this path trades peak speed for simplicity)
-  const bool a_kfast = (g.ak.s_lo == 1);
-  const bool b_nfast = (g.bn.s_lo == 1);
-  double out[T::TM][T::TN][4];
-#pragma unroll
-  for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-    for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
-  const int nk = (g.K + BK16 - 1) / BK16;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int k0 = kt * BK16;
-    // stage A
-#pragma unroll
-    for (int e = 0; e < T::EA; ++e) {
-      int mm, kk;
-      if (a_kfast) { kk = tid % BK16; mm = tid / BK16 + e * (NT / BK16); }
-      else { mm = tid % BM; kk = tid / BM + e * (NT / BM); }
-      const int m = m_base + mm, k = k0 + kk;
-      const double x = (m < g.M && k < g.K) ? A[a_off + map2(g.am, m) + map2(g.ak, k)] : 0.0;
-      __bf16 h, l;
-      split_bf16(x, h, l);
-      Ah[mm * T::LK + kk] = h;
-      Al[mm * T::LK + kk] = l;
-    }
-#pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      int nn, kk;
-      if (b_nfast) { nn = tid % BN; kk = tid / BN + e * (NT / BN); }
-      else { kk = tid % BK16; nn = tid / BK16 + e * (NT / BK16); }
-      const int n = n_base + nn, k = k0 + kk;
-      const double x = (n < g.N && k < g.K) ? B[b_off + map2(g.bk, k) + map2(g.bn, n)] : 0.0;
-      __bf16 h, l;
-      split_bf16(x, h, l);
-      Bh[nn * T::LK + kk] = h;
-      Bl[nn * T::LK + kk] = l;
-    }
-    __syncthreads();
-    f4 acc[T::TM][T::TN];
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < T::TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    const int kq = 8 * (lane / 16);
-    bf8 ah[T::TM], al[T::TM];
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i) {
-      const int row = wm0 + i * 16 + (lane & 15);
-      ah[i] = *(const bf8*)&Ah[row * T::LK + kq];
-      al[i] = *(const bf8*)&Al[row * T::LK + kq];
-    }
-#pragma unroll
-    for (int j = 0; j < T::TN; ++j) {
-      const int col = wn0 + j * 16 + (lane & 15);
-      const bf8 bh = *(const bf8*)&Bh[col * T::LK + kq];
-      const bf8 bl = *(const bf8*)&Bl[col * T::LK + kq];
-#pragma unroll
-      for (int i = 0; i < T::TM; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-      for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
-    __syncthreads();
-  }
-  store_c<BM, BN>(g, tm, tn, (long long)b * g.c_batch, out, wm0, wn0, false);
-}
-
 template <int BM, int BN>
 hipError_t launch(const GemmArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
@@ -532,16 +353,13 @@ hipError_t launch(const GemmArgs& g, Prec prec, hipStream_t s) {
     }
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n, 0, (double*)nullptr);
   }
-  else if (prec == Prec::F32)
-    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
-  else
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<BM, BN>), grid, dim3(NT), 0, s, g, tiles_m, tiles_n);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s) {
+  if (prec != Prec::F64) return hipErrorInvalidValue;  // low precision: gemm_nt_lp on converted operands
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + idx_max(g.am, g.M) + idx_max(g.ak, g.K) >= g.a_len) return hipErrorInvalidValue;
@@ -765,294 +583,6 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
     case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);
     default: return launch_nt<128, 128, 2, 2, 2>(g, s);
   }
-}
-
-}  // namespace cct
-
-// ===========================================================================
-// Mixed-precision K-contiguous kernels.  Operands are read as FP64 and
-// rounded when they are written to LDS.
-//   FP32:   v_mfma_f32_16x16x4_f32, FP32 accumulation within a K tile,
-//           flushed into FP64 registers after every K tile.
-//   BF16X3: x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each product
-//           is hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16),
-//           FP32 accumulation within a K tile of 32, flushed into FP64.
-// ===========================================================================
-namespace cct {
-namespace {
-
-template <int BM, int BN>
-__global__ __launch_bounds__(256, 1) void gemm_nt_f32_kernel(NtArgs g, int tiles_m, int tiles_n) {
-  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, LA = BM + 4, LB = BN + 4;
-  constexpr int SA = BM * (BK / 2) / NTH, SB = BN * (BK / 2) / NTH;
-  __shared__ float As[2][BK * LA];
-  __shared__ float Bs[2][BK * LB];
-  int tm, tn;
-  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
-  const int tid = threadIdx.x, b = blockIdx.z;
-  const double* A = g.A + (long long)b * g.a_batch;
-  const double* B = g.B + (long long)b * g.b_batch;
-  const double* pa[SA];
-  const double* pb[SB];
-  int ka[SA], kb[SB];
-  bool va[SA], vb[SB];
-#pragma unroll
-  for (int i = 0; i < SA; ++i) {
-    const int seg = tid + i * NTH, row = seg / (BK / 2);
-    ka[i] = 2 * (seg % (BK / 2));
-    const int m = tm * BM + row;
-    va[i] = m < g.M;
-    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
-  }
-#pragma unroll
-  for (int i = 0; i < SB; ++i) {
-    const int seg = tid + i * NTH, row = seg / (BK / 2);
-    kb[i] = 2 * (seg % (BK / 2));
-    const int n = tn * BN + row;
-    vb[i] = n < g.N;
-    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
-  }
-  const int wave = tid / 64, lane = tid & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
-  double out[TM][TN][4];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
-  dbl2 ra[SA], rb[SB];
-  bool oa[SA], ob[SB];
-  const int nk = (g.K + BK - 1) / BK;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const dbl2*)(pa[i] + (oa[i] ? k0 : 0)); }
-#pragma unroll
-    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0)); }
-  };
-  auto store = [&](float* as, float* bs) {
-#pragma unroll
-    for (int i = 0; i < SA; ++i) {
-      const int row = (tid + i * NTH) / (BK / 2);
-      as[ka[i] * LA + row] = oa[i] ? (float)ra[i].x : 0.f;
-      as[(ka[i] + 1) * LA + row] = oa[i] ? (float)ra[i].y : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < SB; ++i) {
-      const int row = (tid + i * NTH) / (BK / 2);
-      bs[kb[i] * LB + row] = ob[i] ? (float)rb[i].x : 0.f;
-      bs[(kb[i] + 1) * LB + row] = ob[i] ? (float)rb[i].y : 0.f;
-    }
-  };
-  load(0);
-  store(As[0], Bs[0]);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
-    const float* as = As[cur];
-    const float* bs = Bs[cur];
-    f4 acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kr = ks * 4 + lane / 16;
-      float af[TM], bf[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = as[kr * LA + wm0 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[j] = bs[kr * LB + wn0 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
-    if (kt + 1 < nk) store(As[cur ^ 1], Bs[cur ^ 1]);
-    __syncthreads();
-  }
-  const long long coff = (long long)b * g.c_batch;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
-      if (m >= g.M) continue;
-      const long long mo = coff + map2(g.cm, m);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
-        if (n >= g.N) continue;
-        double* p = g.C + mo + map2(g.cn, n);
-        const double x = g.alpha * out[i][j][r];
-        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
-      }
-    }
-}
-
-template <int BM, int BN>
-__global__ __launch_bounds__(256, 1) void gemm_nt_bf16x3_kernel(NtArgs g, int tiles_m, int tiles_n) {
-  constexpr int NTH = 256, TM = BM / 32, TN = BN / 32, KB = 32, LK = KB + 8;
-  constexpr int SA = BM * (KB / 2) / NTH, SB = BN * (KB / 2) / NTH;
-  // [buffer][plane hi/lo][row][k], k contiguous so a lane reads 8 consecutive k as 16 bytes
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM * LK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN * LK];
-  int tm, tn;
-  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
-  const int tid = threadIdx.x, b = blockIdx.z;
-  const double* A = g.A + (long long)b * g.a_batch;
-  const double* B = g.B + (long long)b * g.b_batch;
-  const double* pa[SA];
-  const double* pb[SB];
-  int ka[SA], kb[SB], rowa[SA], rowb[SB];
-  bool va[SA], vb[SB];
-#pragma unroll
-  for (int i = 0; i < SA; ++i) {
-    const int seg = tid + i * NTH;
-    rowa[i] = seg / (KB / 2);
-    ka[i] = 2 * (seg % (KB / 2));
-    const int m = tm * BM + rowa[i];
-    va[i] = m < g.M;
-    pa[i] = A + (long long)(va[i] ? m : 0) * g.lda + ka[i];
-  }
-#pragma unroll
-  for (int i = 0; i < SB; ++i) {
-    const int seg = tid + i * NTH;
-    rowb[i] = seg / (KB / 2);
-    kb[i] = 2 * (seg % (KB / 2));
-    const int n = tn * BN + rowb[i];
-    vb[i] = n < g.N;
-    pb[i] = B + (long long)(vb[i] ? n : 0) * g.ldb + kb[i];
-  }
-  const int wave = tid / 64, lane = tid & 63;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
-  double out[TM][TN][4];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
-  dbl2 ra[SA], rb[SB];
-  bool oa[SA], ob[SB];
-  const int nk = (g.K + KB - 1) / KB;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < SA; ++i) { oa[i] = va[i] && (k0 + ka[i] < g.K); ra[i] = *(const dbl2*)(pa[i] + (oa[i] ? k0 : 0)); }
-#pragma unroll
-    for (int i = 0; i < SB; ++i) { ob[i] = vb[i] && (k0 + kb[i] < g.K); rb[i] = *(const dbl2*)(pb[i] + (ob[i] ? k0 : 0)); }
-  };
-  auto put = [&](__bf16* hi, __bf16* lo, int off, double x0, double x1) {
-    __bf16 h0, l0, h1, l1;
-    split_bf16(x0, h0, l0);
-    split_bf16(x1, h1, l1);
-    hi[off] = h0; hi[off + 1] = h1;
-    lo[off] = l0; lo[off + 1] = l1;
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < SA; ++i)
-      put(As[buf][0], As[buf][1], rowa[i] * LK + ka[i], oa[i] ? ra[i].x : 0.0, oa[i] ? ra[i].y : 0.0);
-#pragma unroll
-    for (int i = 0; i < SB; ++i)
-      put(Bs[buf][0], Bs[buf][1], rowb[i] * LK + kb[i], ob[i] ? rb[i].x : 0.0, ob[i] ? rb[i].y : 0.0);
-  };
-  load(0);
-  store(0);
-  __syncthreads();
-  const int kq = 8 * (lane / 16);
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * KB);
-    f4 acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    bf8 ah[TM], al[TM];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int row = wm0 + i * 16 + (lane & 15);
-      ah[i] = *(const bf8*)&As[cur][0][row * LK + kq];
-      al[i] = *(const bf8*)&As[cur][1][row * LK + kq];
-    }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = wn0 + j * 16 + (lane & 15);
-      const bf8 bh = *(const bf8*)&Bs[cur][0][col * LK + kq];
-      const bf8 bl = *(const bf8*)&Bs[cur][1][col * LK + kq];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
-    if (kt + 1 < nk) store(cur ^ 1);
-    __syncthreads();
-  }
-  const long long coff = (long long)b * g.c_batch;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
-      if (m >= g.M) continue;
-      const long long mo = coff + map2(g.cm, m);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
-        if (n >= g.N) continue;
-        double* p = g.C + mo + map2(g.cn, n);
-        const double x = g.alpha * out[i][j][r];
-        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
-      }
-    }
-}
-
-template <int BM, int BN>
-hipError_t launch_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
-  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
-  const long long nb = (long long)tiles_m * tiles_n;
-  const long long grid_x = ((nb + 7) / 8) * 8;
-  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
-  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
-  if (prec == Prec::F32)
-    hipLaunchKernelGGL((gemm_nt_f32_kernel<BM, BN>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
-  else
-    hipLaunchKernelGGL((gemm_nt_bf16x3_kernel<BM, BN>), grid, dim3(256), 0, s, g, tiles_m, tiles_n);
-  return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (prec == Prec::F64) return gemm_nt(g, prec, s);
-  if (g.K <= 0 || (g.K & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_batch & 1) || (g.b_batch & 1) ||
-      ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15))
-    return hipErrorInvalidValue;
-  const long long nb = g.batch - 1;
-  if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
-  if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
-  if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
-  const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-  if (t128 >= 256) return launch_nt_mixed<128, 128>(g, prec, s);
-  return launch_nt_mixed<64, 64>(g, prec, s);
 }
 
 }  // namespace cct

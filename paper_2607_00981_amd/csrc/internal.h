@@ -51,6 +51,8 @@ static inline long long idx_max(const Idx2& d, long long n) {
 
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
+// Strided FP64 product (prec must be Prec::F64; the low-precision modes run
+// on converted K-contiguous operands through gemm_nt_lp).
 hipError_t gemm(const GemmArgs& g, Prec prec, hipStream_t s);
 
 // C[b](m,n) = alpha * sum_k A[b][m*lda + k] * B[b][n*ldb + k] + beta * C[b](m,n):
@@ -68,9 +70,6 @@ struct NtArgs {
   int b_kn;                       // 1: B is stored [K][N] (row stride ldb, N contiguous) instead of [N][K]
 };
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s);
-// The same product in FP32 or split-BF16 (FP64 operands rounded in LDS, FP64
-// output); Prec::F64 forwards to gemm_nt.
-hipError_t gemm_nt_mixed(const NtArgs& g, Prec prec, hipStream_t s);
 
 // Y = alpha * X + beta * Y over an index space of up to 6 dimensions.
 struct PermArgs {

@@ -255,7 +255,7 @@ int slab_pp(cct_slab* sl) {
         g.C = sl->r3 + coff; g.cm = cm[term]; g.cn = cn[term];
         g.alpha = 1.0; g.beta = 1.0;
         g.a_len = nb * v3; g.b_len = prow * v2; g.c_len = nb * v3 - coff;
-        SHIP(gemm(g, sl->prec, sl->s));
+        SHIP(gemm(g, Prec::F64, sl->s));
       }
     }
     if (sl->timers) {
