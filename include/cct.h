@@ -133,8 +133,12 @@ int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters
 /* Algorithmic multiply-add counts of the last residual per R3 term group
  * (indices as the CCT_TERM_* bit positions, 9 entries) and device time in ms
  * per phase (entries: 0 setup/dressing+CCSD, 1 feedback, 2 PP, 3 rings,
- * 4 HH+F2, 5 drivers, 6 F1, 7 post+update, 8 DIIS+energy).  cap = length of
- * both arrays provided; writes min(cap, 9). */
+ * 4 HH+F2, 5 drivers, 6 F1, 7 post+update, 8 DIIS+energy).  Entry 9: the
+ * multiply-adds the ladder GEMMs executed (half the PP count in the
+ * symmetric/antisymmetric form) and their device time alone (timers on);
+ * entry 10: the number of ladder GEMM launches (ms: 0).  The per-term counts
+ * are the direct-traversal ones whichever ladder form ran.  cap = length of
+ * both arrays provided; writes min(cap, 11). */
 int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap);
 
 /* Tile autotuner: times every tile variant of the particle-particle ladder

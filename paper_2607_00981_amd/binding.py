@@ -213,10 +213,17 @@ class Engine:
         return var[0], var[1]
 
     def counters(self):
-        macs = np.zeros(9)
-        ms = np.zeros(9)
-        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 9))
-        return dict(zip(TERMS.keys(), macs)), dict(zip(PHASES, ms))
+        """(macs per R3 term group, ms per phase); the ladder GEMMs alone
+        appear as macs['ladder_gemm'] / ms['ladder_gemm'] (executed
+        multiply-adds, device time) and macs['ladder_launches']."""
+        macs = np.zeros(11)
+        ms = np.zeros(11)
+        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 11))
+        m = dict(zip(TERMS.keys(), macs[:9]))
+        t = dict(zip(PHASES, ms[:9]))
+        m["ladder_gemm"], t["ladder_gemm"] = float(macs[9]), float(ms[9])
+        m["ladder_launches"] = float(macs[10])
+        return m, t
 
 
 class _SystemView(Engine):

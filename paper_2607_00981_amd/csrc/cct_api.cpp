@@ -88,6 +88,9 @@ struct cct_ctx {
   BlockRef* tbl = nullptr;
   int4* tri = nullptr;
   int* pair_rows = nullptr;  // p*o + q for the ordered pairs p <= q (hole ladder rows)
+  long long* vpair_src = nullptr;  // (y*v + z)*v^2 for the virtual pairs y <= z (ladder W rows)
+  int2* vpair_yz = nullptr;        // (y, z) of the virtual pairs y <= z
+  bool ladder_split = true;        // symmetric / antisymmetric split of the ladder
   double* red = nullptr;  // reduction scratch
   long long red_n = 0;
   double* scal = nullptr;  // device scalars
@@ -107,6 +110,11 @@ struct cct_ctx {
   double ms[PH_N] = {0};
   hipEvent_t ev[PH_N + 1] = {};
   bool events = false;
+  // device time of the ladder GEMM launches alone (event pairs around each
+  // group of launches, created on first use), their multiply-adds and count
+  std::vector<hipEvent_t> lad_ev;
+  int lad_nev = 0;
+  double lad_macs = 0.0, lad_launches = 0.0, lad_ms = 0.0;
 };
 
 namespace {
@@ -398,6 +406,20 @@ int build_plans(cct_ctx* ctx) {
     RCK(dalloc_t(ctx, &ctx->pair_rows, (long long)rows.size()));
     HIPCK(hipMemcpy(ctx->pair_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice));
   }
+  // ---- ladder split: the virtual pairs y <= z in the order p(y,z)
+  {
+    std::vector<long long> src;
+    std::vector<int2> yz;
+    for (int y = 0; y < v; ++y)
+      for (int z = y; z < v; ++z) {
+        src.push_back(((long long)y * v + z) * v2);
+        yz.push_back(int2{y, z});
+      }
+    RCK(dalloc_t(ctx, &ctx->vpair_src, (long long)src.size()));
+    RCK(dalloc_t(ctx, &ctx->vpair_yz, (long long)yz.size()));
+    HIPCK(hipMemcpy(ctx->vpair_src, src.data(), sizeof(long long) * src.size(), hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(ctx->vpair_yz, yz.data(), sizeof(int2) * yz.size(), hipMemcpyHostToDevice));
+  }
   // ---- drivers
   {
     Job& J = ctx->d1;  // slots q; Z[slot(q)][(x,y)][(p,r,z)]
@@ -500,6 +522,25 @@ void set_ident(UnpackArgs& a, const int occ[3]) {
 // ---------------------------------------------------------------------------
 void mark(cct_ctx* ctx, int ph) {
   if (ctx->events) (void)hipEventRecord(ctx->ev[ph], ctx->s);
+}
+
+// Bracket a group of ladder GEMM launches (macs: their multiply-adds,
+// n: launches).  Timing stops quietly past 256 groups per residual.
+void lad_begin(cct_ctx* ctx) {
+  if (!ctx->events || ctx->lad_nev >= 512) return;
+  while ((int)ctx->lad_ev.size() < ctx->lad_nev + 2) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->lad_ev.push_back(e);
+  }
+  (void)hipEventRecord(ctx->lad_ev[ctx->lad_nev], ctx->s);
+}
+void lad_end(cct_ctx* ctx, double macs, int n) {
+  ctx->lad_macs += macs;
+  ctx->lad_launches += n;
+  if (!ctx->events || ctx->lad_nev >= 512 || (int)ctx->lad_ev.size() < ctx->lad_nev + 2) return;
+  (void)hipEventRecord(ctx->lad_ev[ctx->lad_nev + 1], ctx->s);
+  ctx->lad_nev += 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -848,10 +889,112 @@ int r3_pp_lp(cct_ctx* ctx, const Idx2 cm[3], const Idx2 cn[3]) {
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = nb * v3; g.b_len = v4; g.c_len = (nt - t0) * v3;
       g.variant = ctx->tune_ladder;
+      lad_begin(ctx);
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
+      lad_end(ctx, (double)nb * v * v2 * v2, 1);
     }
   }
   ws.reset(mk);
+  return CCT_OK;
+}
+
+// Ladder with each relabelled term split into symmetric and antisymmetric
+// parts (the further factor-of-two reduction the paper points to in its
+// section on contractions without unpacking, after Scuseria et al.): with
+// W^{yz}_{de} = W^{zy}_{ed},
+//   C^{yz} + C^{zy} = sum_{d<=e} (A^{de} + A^{ed}) (W^{yz}_{de} + W^{yz}_{ed}) [d=e: A 2x, W 1x]
+//   C^{yz} - C^{zy} = sum_{d<e}  (A^{de} - A^{ed}) (W^{yz}_{de} - W^{yz}_{ed})
+// for the output pairs y <= z only, so each term is two GEMMs of half the
+// size in K and in N: half the multiply-adds of the direct traversal.  The
+// split operands are written in the working precision, K padded with zeros to
+// the vector width; products are FP64; a combine kernel rebuilds C^{yz} and
+// C^{zy} and adds them into R3 through the term's relabelling.
+long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+int r3_pp_split(cct_ctx* ctx) {
+  const int v = ctx->v;
+  const long long v2 = (long long)v * v, v3 = ctx->v3, nt = ctx->ntri;
+  const long long P = (long long)v * (v + 1) / 2, Q = (long long)v * (v - 1) / 2;
+  const bool f64 = ctx->prec == Prec::F64;
+  const int w = f64 ? 2 : (ctx->prec == Prec::F32 ? 4 : 8);
+  const long long pp = round_up(P, w), pq = round_up(std::max<long long>(Q, 1), w);
+  const int fmt = f64 ? OUT_F64 : lp_fmt(ctx->prec);
+  const long long esz = f64 ? 8 : 4;  // bytes per stored operand element (hi+lo BF16: 2 x 2)
+  Arena& ws = ctx->ws;
+  const size_t mk0 = ws.mark();
+  auto alloc_b = [&](long long bytes) { return (void*)ws.alloc((size_t)((bytes + 7) / 8)); };
+  void* Wp = alloc_b(P * pp * esz);
+  void* Wm = alloc_b(P * pq * esz);
+  if (!Wp || !Wm) { ctx->err = "workspace exhausted (ladder split W)"; return CCT_ENOMEM; }
+  // W+ / W- rows y <= z from W[(y,z)][(d,e)]; W+ keeps W^{yz}_{dd} once
+  HIPCK(pair_split(ctx->Wvvvv, idx1(0), ctx->vpair_src, P, v, v, OutSpec{Wp, fmt, P * pp}, pp,
+                   OutSpec{Wm, fmt, P * pq}, pq, 0.5, ctx->s));
+  // chunk of packed blocks: A+/A- (esz), C+/C- (FP64), FP64 relabelled copy for term 0
+  const long long per_block = v * (pp + pq) * esz + 2 * v * P * 8 + v3 * 8;
+  long long chunk = (long long)(ws.available() / (size_t)per_block) - 1;
+  if (chunk < 1) { ctx->err = "workspace exhausted (ladder split)"; return CCT_ENOMEM; }
+  if (chunk > nt) chunk = nt;
+  void* Ap = alloc_b(chunk * v * pp * esz);
+  void* Am = alloc_b(chunk * v * pq * esz);
+  double* Cp = ws.alloc((size_t)(chunk * v * P));
+  double* Cm = ws.alloc((size_t)(chunk * v * P));
+  double* Tc = ws.alloc((size_t)(chunk * v3));
+  if (!Ap || !Am || !Cp || !Cm || !Tc) { ctx->err = "workspace exhausted (ladder split)"; return CCT_ENOMEM; }
+  auto gemm_pair = [&](int M, int N, long long K, const void* A, long long lda, long long a_len, long long a_plane,
+                       const void* B, long long ldb, long long b_len, long long b_plane, double* C, long long c_len,
+                       Idx2 cm) -> int {
+    if (f64) {
+      NtArgs g{};
+      g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
+      g.A = (const double*)A; g.lda = lda; g.B = (const double*)B; g.ldb = ldb;
+      g.C = C; g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = a_len; g.b_len = b_len; g.c_len = c_len; g.variant = ctx->tune_ladder;
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+    } else {
+      NtLpArgs g{};
+      g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
+      g.A = A; g.lda = lda; g.a_plane = a_plane; g.B = B; g.ldb = ldb; g.b_plane = b_plane;
+      g.C = C; g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = a_len; g.b_len = b_len; g.c_len = c_len; g.variant = ctx->tune_ladder;
+      HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
+    }
+    return CCT_OK;
+  };
+  for (long long t0 = 0; t0 < nt; t0 += chunk) {
+    const long long nb = std::min(chunk, nt - t0), rows = nb * v;
+    const double* src = ctx->t3 + t0 * v3;
+    double* Rc = ctx->r3 + t0 * v3;
+    const OutSpec ap{Ap, fmt, rows * pp}, am{Am, fmt, rows * pq};
+    for (int term = 2; term >= 0; --term) {
+      // A^{de} rows (t,x): term 2 T[t][x][d][e]; term 1 T[t][d][x][e]; term 0 T[t][d][e][x] via a copy
+      if (term == 2) HIPCK(pair_split(src, idx2(v, v3, v2), nullptr, rows, v, v, ap, pp, am, pq, 1.0, ctx->s));
+      else if (term == 1) HIPCK(pair_split(src, idx2(v, v3, v), nullptr, rows, v2, v, ap, pp, am, pq, 1.0, ctx->s));
+      else {
+        HIPCK(transpose_batched(src, OutSpec{Tc, OUT_F64, 0}, nb, (int)v2, v, ctx->s));  // [t][x][(d,e)]
+        HIPCK(pair_split(Tc, idx2(v, v3, v2), nullptr, rows, v, v, ap, pp, am, pq, 1.0, ctx->s));
+      }
+      lad_begin(ctx);
+      if (term > 0) {
+        // C+-[(t,x)][p] = A+-[(t,x)][k] W+-[p][k]
+        RCK(gemm_pair((int)rows, (int)P, pp, Ap, pp, rows * pp, rows * pp, Wp, pp, P * pp, P * pp, Cp, rows * P,
+                      idx1(P)));
+        RCK(gemm_pair((int)rows, (int)P, pq, Am, pq, rows * pq, rows * pq, Wm, pq, P * pq, P * pq, Cm, rows * P,
+                      idx1(P)));
+        lad_end(ctx, (double)rows * P * (P + Q), 2);
+        if (term == 2) HIPCK(pair_combine_rows(Cp, Cm, P, P, rows, v, Rc, idx2(v, v3, v2), v, 1, ctx->s));
+        else HIPCK(pair_combine_rows(Cp, Cm, P, P, rows, v, Rc, idx2(v, v3, v), v2, 1, ctx->s));
+      } else {
+        // transposed products C+-T[p][(t,x)] so that the output runs along x
+        RCK(gemm_pair((int)P, (int)rows, pp, Wp, pp, P * pp, P * pp, Ap, pp, rows * pp, rows * pp, Cp, rows * P,
+                      idx1(rows)));
+        RCK(gemm_pair((int)P, (int)rows, pq, Wm, pq, P * pq, P * pq, Am, pq, rows * pq, rows * pq, Cm, rows * P,
+                      idx1(rows)));
+        lad_end(ctx, (double)rows * P * (P + Q), 2);
+        HIPCK(pair_combine_cols(Cp, Cm, rows, ctx->vpair_yz, v, Rc, idx2(v, v3, 1), v2, v, ctx->s));
+      }
+    }
+  }
+  ws.reset(mk0);
   return CCT_OK;
 }
 
@@ -869,6 +1012,7 @@ int r3_pp(cct_ctx* ctx) {
   // output maps of the three terms: C[(t,x)][(y,z)] -> R[t][..]
   const Idx2 cm[3] = {idx2(v, v3, 1), idx2(v, v3, v), idx2(v, v3, v2)};
   const Idx2 cn[3] = {idx1(v), idx2(v, v2, 1), idx1(1)};
+  if (ctx->ladder_split && v >= 2) return r3_pp_split(ctx);
   if (ctx->prec != Prec::F64) return r3_pp_lp(ctx, cm, cn);
   if (v2 & 1) {
     // generic strided kernel reading T3 in place
@@ -896,7 +1040,9 @@ int r3_pp(cct_ctx* ctx) {
     g.alpha = 1.0; g.beta = 1.0;
     g.a_len = nt * v3; g.b_len = v2 * v2; g.c_len = nt * v3;
     g.variant = ctx->tune_ladder;
+    lad_begin(ctx);
     HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+    lad_end(ctx, (double)M * v2 * v2, 1);
   }
   // terms 2 and 1 from relabelled copies, in chunks of blocks that fit the workspace
   Arena& ws = ctx->ws;
@@ -921,7 +1067,9 @@ int r3_pp(cct_ctx* ctx) {
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = nb * v3; g.b_len = v2 * v2; g.c_len = (nt - t0) * v3;
       g.variant = ctx->tune_ladder;
+      lad_begin(ctx);
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
+      lad_end(ctx, (double)nb * v * v2 * v2, 1);
     }
   }
   ws.reset(mk);
@@ -1219,6 +1367,8 @@ int enqueue_residual(cct_ctx* ctx, unsigned mask, bool update_t3) {
   }
   hipStream_t s = ctx->s;
   ctx->ws.reset(0);  // the arena holds only per-evaluation scratch; drop what a failed call left
+  ctx->lad_nev = 0;
+  ctx->lad_macs = ctx->lad_launches = ctx->lad_ms = 0.0;
   mark(ctx, 0);
   RCK(dress(ctx));
   RCK(ccsd_part(ctx));
@@ -1270,6 +1420,10 @@ int finish_residual(cct_ctx* ctx, double norms[3]) {
     for (int i = 0; i < PH_DIIS; ++i) {
       float msv = 0.f;
       if (hipEventElapsedTime(&msv, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) ctx->ms[i] = msv;
+    }
+    for (int i = 0; i + 1 < ctx->lad_nev; i += 2) {
+      float msv = 0.f;
+      if (hipEventElapsedTime(&msv, ctx->lad_ev[i], ctx->lad_ev[i + 1]) == hipSuccess) ctx->lad_ms += msv;
     }
   }
   ctx->have_res = true;
@@ -1466,6 +1620,9 @@ int update(cct_ctx* ctx, double* e, double norms[3]) {
 // (o, v, precision, class).
 const char* prec_name(Prec p) { return p == Prec::F64 ? "fp64" : (p == Prec::F32 ? "fp32" : "bf16x3"); }
 
+// the two ladder forms have different GEMM shapes and are tuned apart
+const char* ladder_class(const cct_ctx* ctx) { return ctx->ladder_split && ctx->v >= 2 ? "ladder_split" : "ladder"; }
+
 std::string tune_key(const cct_ctx* ctx, const char* cls) {
   return "o" + std::to_string(ctx->o) + "_v" + std::to_string(ctx->v) + "_" + prec_name(ctx->prec) + "_" + cls;
 }
@@ -1511,7 +1668,7 @@ void write_tune_cache(const std::map<std::string, int>& m) {
 
 void apply_tune_cache(cct_ctx* ctx) {
   const auto m = read_tune_cache();
-  auto it = m.find(tune_key(ctx, "ladder"));
+  auto it = m.find(tune_key(ctx, ladder_class(ctx)));
   if (it != m.end()) ctx->tune_ladder = it->second;
   it = m.find(tune_key(ctx, "rings"));
   if (it != m.end()) ctx->tune_rings = it->second;
@@ -1552,36 +1709,43 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     }
     return best;
   };
-  // ---- ladder: one relabelled term on the first Mt rows of the stored blocks
-  const bool lad_lp = !f64, lad_nt = f64 && !(v2 & 1);
-  if (lad_lp || lad_nt) {
-    const long long M = ctx->ntri * v;
-    const long long Mt = std::min(M, std::max<long long>(1024, (long long)(2e9 / 8.0 / (double)v2)));
+  // ---- ladder: one relabelled term on the first Mt rows of the stored blocks,
+  // in the shape of the form in use (split: N = pairs y <= z, K = pairs d <= e
+  // padded to the vector width; direct: N = K = v^2)
+  const bool split = ctx->ladder_split && v >= 2;
+  const long long vp = (long long)v * (v + 1) / 2;
+  const long long lN = split ? vp : v2, lK = split ? round_up(vp, f64 ? 2 : (ctx->prec == Prec::F32 ? 4 : 8)) : v2;
+  const bool lad_lp = !f64, lad_nt = f64 && (split || !(v2 & 1));
+  if ((lad_lp || lad_nt) && lN * lK <= v4) {
+    const long long M = std::min(ctx->ntri * v, ctx->ntri * ctx->v3 / lK);
+    const long long Mt = std::min(M, std::max<long long>(1024, (long long)(2e9 / 8.0 / (double)lN)));
     const size_t mk = ws.mark();
-    double* C = ws.alloc((size_t)(Mt * v2));
+    double* C = ws.alloc((size_t)(Mt * lN));
     if (!C) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
+    // operands: T3 and W read as Mt x lK and lN x lK matrices (values only
+    // matter for timing; both fit inside the stored arrays)
     if (lad_nt) {
       ctx->tune_ladder = pick({1, 2, 3, 4}, [&](int var) {
         NtArgs g{};
-        g.M = (int)Mt; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
-        g.A = ctx->t3; g.lda = v2; g.B = ctx->Wvvvv; g.ldb = v2;
-        g.C = C; g.cm = idx1(v2); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
-        g.a_len = ctx->ntri * ctx->v3; g.b_len = v4; g.c_len = Mt * v2; g.variant = var;
+        g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
+        g.A = ctx->t3; g.lda = lK; g.B = ctx->Wvvvv; g.ldb = lK;
+        g.C = C; g.cm = idx1(lN); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+        g.a_len = ctx->ntri * ctx->v3; g.b_len = v4; g.c_len = Mt * lN; g.variant = var;
         return gemm_nt(g, Prec::F64, ctx->s);
       });
     } else {
-      void* Al = alloc_lp(ws, Mt * v2);
-      void* Bl = alloc_lp(ws, v4);
+      void* Al = alloc_lp(ws, Mt * lK);
+      void* Bl = alloc_lp(ws, lN * lK);
       if (!Al || !Bl) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
       const int fmt = lp_fmt(ctx->prec);
-      HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * v2}, Mt * v2, ctx->s));
-      HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, v4}, v4, ctx->s));
+      HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * lK}, Mt * lK, ctx->s));
+      HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, lN * lK}, lN * lK, ctx->s));
       ctx->tune_ladder = pick({1, 2, 3}, [&](int var) {
         NtLpArgs g{};
-        g.M = (int)Mt; g.N = (int)v2; g.K = (int)v2; g.batch = 1;
-        g.A = Al; g.lda = v2; g.a_plane = Mt * v2; g.B = Bl; g.ldb = v2; g.b_plane = v4;
-        g.C = C; g.cm = idx1(v2); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
-        g.a_len = Mt * v2; g.b_len = v4; g.c_len = Mt * v2; g.variant = var;
+        g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
+        g.A = Al; g.lda = lK; g.a_plane = Mt * lK; g.B = Bl; g.ldb = lK; g.b_plane = lN * lK;
+        g.C = C; g.cm = idx1(lN); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+        g.a_len = Mt * lK; g.b_len = lN * lK; g.c_len = Mt * lN; g.variant = var;
         return gemm_nt_lp(g, ctx->prec, ctx->s);
       });
     }
@@ -1625,7 +1789,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
   }
   HIPCK(hipStreamSynchronize(ctx->s));
   auto m = read_tune_cache();
-  m[tune_key(ctx, "ladder")] = ctx->tune_ladder;
+  m[tune_key(ctx, ladder_class(ctx))] = ctx->tune_ladder;
   m[tune_key(ctx, "rings")] = ctx->tune_rings;
   write_tune_cache(m);
   if (spent) *spent = used;
@@ -1662,6 +1826,7 @@ void cct_destroy(cct_ctx* ctx) {
   if (ctx->wsbuf) (void)hipFree(ctx->wsbuf);
   for (int i = 0; i <= PH_N; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (hipEvent_t e : ctx->lad_ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1693,6 +1858,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (json_find(js, "diis", val)) ctx->diis_on = (val != "false" && val != "0" && val != "off");
     if (json_find(js, "workspace_gb", val)) ctx->ws_gb = std::atof(val.c_str());
     if (json_find(js, "timers", val)) ctx->events = (val == "true" || val == "1");
+    if (json_find(js, "ladder_split", val)) ctx->ladder_split = (val == "true" || val == "1");
     if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb < 0) {
       delete ctx;
       return CCT_EINVAL;
@@ -1713,8 +1879,14 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   fixed += (long long)(2 * M + 1) * dlen;
   // workspace: enough for every job in one batch (two unpacked/contracted
   // slabs per slot, o^2 slots for the rings), capped by the option
-  const long long ws_min = 6 * (long long)o * v3 + 2 * o2v3 + (1 << 22);
-  const long long need_ws = 6 * (long long)o * v3 + 2 * o2v3 * o + (1 << 22);
+  // the split ladder needs W+- (about v^4/2) and, per packed block, its split
+  // operands, pair products and one relabelled copy (about 3 v^3)
+  const long long vp = (long long)v * (v + 1) / 2, ntri_l = (long long)o * (o + 1) * (o + 2) / 6;
+  const long long lad_w = vp * (2 * vp + 16), lad_blk = (long long)v * (2 * vp + 16) + 2 * (long long)v * vp + v3;
+  const long long ws_min =
+      std::max(6 * (long long)o * v3 + 2 * o2v3, lad_w + 2 * lad_blk) + (1 << 22);
+  const long long need_ws =
+      std::max(6 * (long long)o * v3 + 2 * o2v3 * o, lad_w + ntri_l * lad_blk) + (1 << 22);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     ctx->err = "hipMemGetInfo failed (no HIP device?)";
@@ -1929,6 +2101,14 @@ int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, in
     if (macs_by_term) macs_by_term[i] = ctx->macs[i];
     if (ms_by_phase) ms_by_phase[i] = ctx->ms[i];
   }
+  if (cap > 9) {
+    if (macs_by_term) macs_by_term[9] = ctx->lad_macs;
+    if (ms_by_phase) ms_by_phase[9] = ctx->lad_ms;
+  }
+  if (cap > 10) {
+    if (macs_by_term) macs_by_term[10] = ctx->lad_launches;
+    if (ms_by_phase) ms_by_phase[10] = 0.0;
+  }
   return CCT_OK;
 }
 
@@ -2038,7 +2218,7 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
     std::string js(opts_json), val;
     if (json_find(js, "streams", val)) nstreams = std::atoi(val.c_str());
     if (json_find(js, "graph", val)) use_graph = (val == "true" || val == "1");
-    for (const char* key : {"diis_space", "diis_start", "diis", "workspace_gb"})
+    for (const char* key : {"diis_space", "diis_start", "diis", "workspace_gb", "ladder_split"})
       if (json_find(js, key, val)) sys_opts += std::string(", \"") + key + "\": " + val;
     if (json_find(js, "diis_t3", val)) sys_opts += ", \"diis_t3\": \"" + val + "\"";
   }

@@ -177,6 +177,24 @@ hipError_t fill(double* y, double val, long long n, hipStream_t s);
 // R1[i][a] += 1/2 sum_{j in [f0, f0+S), k, b, c} vvT[j][k][c][b] (2 U[(k,i,c)][j-f0][a][b] - U[(k,i,a)][j-f0][c][b])
 // with U[(k,i,x)][j'][p][q] the single-check spin-summed slab t~_{j k i}^{q x p} (one block per (i,a)).
 hipError_t feedback_r1(const double* U, const double* vvT, double* r1, int o, int v, int S, int f0, hipStream_t s);
+// Symmetric / antisymmetric pair split of one v x v matrix per row r (element
+// (d,e) at in + off(r) + d*sd + e, off(r) = src[r] if src else map2(rmap, r)):
+//   plus [r*pitch_p + p(d,e)] = M[d][e] + M[e][d] (d < e), diag_scale*2*M[d][d] (d = e)
+//   minus[r*pitch_m + q(d,e)] = M[d][e] - M[e][d] (d < e)
+// with p(d,e) = d v - d(d-1)/2 + e - d and q(d,e) = d(v-1) - d(d-1)/2 + e - d - 1;
+// columns beyond v(v+1)/2 (plus) and v(v-1)/2 (minus) up to the pitch are zeroed.
+hipError_t pair_split(const double* in, Idx2 rmap, const long long* src, long long rows, long long sd, int v,
+                      OutSpec plus, long long pitch_p, OutSpec minus, long long pitch_m, double diag_scale,
+                      hipStream_t s);
+// R[cmap(r) + y*sy + z*sz] += C^{yz} from the pair products of row r (both
+// indexed by the output pair p(min(y,z), max(y,z))):
+// C^{yz} = (C+[p(y,z)] + C-[p(y,z)])/2 (y < z), (C+[p(z,y)] - C-[p(z,y)])/2 (y > z), C+[p(y,y)]/2.
+hipError_t pair_combine_rows(const double* Cp, const double* Cm, long long pitch_p, long long pitch_m, long long rows,
+                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s);
+// The same from transposed products C+T[p][c], C-T[p][c] over ncol columns c, pairs given by yz[p]:
+// R[ccol(c) + y*sy + z*sz] += C^{yz}.
+hipError_t pair_combine_cols(const double* CpT, const double* CmT, long long ncol, const int2* yz, int v, double* R,
+                             Idx2 ccol, long long sy, long long sz, hipStream_t s);
 // out[r * ld_out + c] = in[rows[r] * ld_in + c] for r < nrows, c < ncols (rows: device array).
 hipError_t gather_rows(const double* in, long long ld_in, const int* rows, int nrows, long long ncols, double* out,
                        long long ld_out, hipStream_t s);

@@ -7,6 +7,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace cct {
 namespace {
@@ -589,6 +590,160 @@ hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r
                        hipStream_t s) {
   const long long n = (long long)o * v + (long long)o * o * v * v;
   hipLaunchKernelGGL(jacobi_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, t1, r1, t2, r2, eps, o, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric / antisymmetric pair split of the ladder (see ladder_pair_split)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int PS = 32;  // tile edge of the pair kernels
+
+__device__ __forceinline__ long long imap(const Idx2& d, long long i) {
+  if (d.inner == 0) return i * d.s_lo;
+  const long long hi = i / d.inner;
+  return hi * d.s_hi + (i - hi * d.inner) * d.s_lo;
+}
+
+__device__ __forceinline__ long long pidx(int d, int e, int v) {  // d <= e
+  return (long long)d * v - (long long)d * (d - 1) / 2 + (e - d);
+}
+__device__ __forceinline__ long long qidx(int d, int e, int v) {  // d < e
+  return (long long)d * (v - 1) - (long long)d * (d - 1) / 2 + (e - d - 1);
+}
+__device__ __forceinline__ void tile_pair(int idx, int nt, int& Dt, int& Et) {  // Dt <= Et
+  Dt = 0;
+  while (idx >= nt - Dt) {
+    idx -= nt - Dt;
+    ++Dt;
+  }
+  Et = Dt + idx;
+}
+
+__global__ __launch_bounds__(256) void pair_split_kernel(const double* __restrict__ in, Idx2 rmap,
+                                                         const long long* __restrict__ src, long long sd, int v,
+                                                         OutSpec plus, long long pitch_p, OutSpec minus,
+                                                         long long pitch_m, double diag_scale, int nt) {
+  __shared__ double T1[PS][PS + 1], T2[PS][PS + 1];
+  const long long r = blockIdx.x;
+  const double* M = in + (src ? src[r] : imap(rmap, r));
+  int Dt, Et;
+  tile_pair(blockIdx.y, nt, Dt, Et);
+  for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
+    const int i = e / PS, j = e % PS;
+    const int d1 = Dt * PS + i, e1 = Et * PS + j;
+    if (d1 < v && e1 < v) T1[i][j] = M[d1 * sd + e1];
+    const int d2 = Et * PS + i, e2 = Dt * PS + j;
+    if (d2 < v && e2 < v) T2[i][j] = M[d2 * sd + e2];
+  }
+  __syncthreads();
+  const long long P = (long long)v * (v + 1) / 2, Q = (long long)v * (v - 1) / 2;
+  for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
+    const int i = e / PS, j = e % PS;
+    const int d = Dt * PS + i, f = Et * PS + j;
+    if (d >= v || f >= v || d > f) continue;
+    const double a = T1[i][j], b = T2[j][i];  // M[d][f], M[f][d]
+    put_out(plus, r * pitch_p + pidx(d, f, v), d == f ? diag_scale * (a + b) : a + b);
+    if (d < f) put_out(minus, r * pitch_m + qidx(d, f, v), a - b);
+  }
+  // zero the padding columns of this row once
+  if (blockIdx.y == 0) {
+    for (long long c = P + threadIdx.x; c < pitch_p; c += blockDim.x) put_out(plus, r * pitch_p + c, 0.0);
+    for (long long c = Q + threadIdx.x; c < pitch_m; c += blockDim.x) put_out(minus, r * pitch_m + c, 0.0);
+  }
+}
+
+// Rows form: C+[r][p], C-[r][q] -> R[cmap(r) + y*sy + z*sz] += C^{yz}
+__global__ __launch_bounds__(256) void pair_combine_rows_kernel(const double* __restrict__ Cp,
+                                                                const double* __restrict__ Cm, long long pitch_p,
+                                                                long long pitch_m, int v, double* __restrict__ R,
+                                                                Idx2 cmap, long long sy, long long sz, int nt) {
+  __shared__ double U[PS][PS + 1];
+  const long long r = blockIdx.x;
+  double* Rr = R + imap(cmap, r);
+  const double* cp = Cp + r * pitch_p;
+  const double* cq = Cm + r * pitch_m;
+  int Yt, Zt;
+  tile_pair(blockIdx.y, nt, Yt, Zt);
+  for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
+    const int i = e / PS, j = e % PS;
+    const int y = Yt * PS + i, z = Zt * PS + j;
+    if (y >= v || z >= v || y > z) continue;
+    const double p = cp[pidx(y, z, v)];
+    if (y == z) {
+      Rr[y * sy + z * sz] += 0.5 * p;
+    } else {
+      const double m = cq[pidx(y, z, v)];
+      Rr[y * sy + z * sz] += 0.5 * (p + m);
+      U[j][i] = 0.5 * (p - m);  // C^{zy}
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
+    const int i = e / PS, j = e % PS;  // row z = Zt*PS + i, column y = Yt*PS + j
+    const int z = Zt * PS + i, y = Yt * PS + j;
+    if (y >= v || z >= v || y >= z) continue;
+    Rr[z * sy + y * sz] += U[i][j];
+  }
+}
+
+// Columns form: C+T[p][c], C-T[q][c] (c = column, contiguous) ->
+// R[ccol(c) + y*sy + z*sz] and R[ccol(c) + z*sy + y*sz]
+__global__ __launch_bounds__(256) void pair_combine_cols_kernel(const double* __restrict__ CpT,
+                                                                const double* __restrict__ CmT, long long ncol,
+                                                                const int2* __restrict__ yz, int v,
+                                                                double* __restrict__ R, Idx2 ccol, long long sy,
+                                                                long long sz) {
+  const long long p = blockIdx.x;
+  const int2 t = yz[p];
+  const int y = t.x, z = t.y;
+  for (long long c = (long long)blockIdx.y * blockDim.x + threadIdx.x; c < ncol; c += (long long)gridDim.y * blockDim.x) {
+    const double cp = CpT[p * ncol + c];
+    double* base = R + imap(ccol, c);
+    if (y == z) {
+      base[y * sy + z * sz] += 0.5 * cp;
+    } else {
+      const double cm = CmT[p * ncol + c];
+      base[y * sy + z * sz] += 0.5 * (cp + cm);
+      base[z * sy + y * sz] += 0.5 * (cp - cm);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t pair_split(const double* in, Idx2 rmap, const long long* src, long long rows, long long sd, int v,
+                      OutSpec plus, long long pitch_p, OutSpec minus, long long pitch_m, double diag_scale,
+                      hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int nt = (v + PS - 1) / PS;
+  const int npair = nt * (nt + 1) / 2;
+  if (rows > INT_MAX || npair > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pair_split_kernel, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, in, rmap, src, sd, v,
+                     plus, pitch_p, minus, pitch_m, diag_scale, nt);
+  return hipGetLastError();
+}
+
+hipError_t pair_combine_rows(const double* Cp, const double* Cm, long long pitch_p, long long pitch_m, long long rows,
+                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int nt = (v + PS - 1) / PS;
+  const int npair = nt * (nt + 1) / 2;
+  if (rows > INT_MAX || npair > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pair_combine_rows_kernel, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, Cp, Cm, pitch_p,
+                     pitch_m, v, R, cmap, sy, sz, nt);
+  return hipGetLastError();
+}
+
+hipError_t pair_combine_cols(const double* CpT, const double* CmT, long long ncol, const int2* yz, int v, double* R,
+                             Idx2 ccol, long long sy, long long sz, hipStream_t s) {
+  const long long P = (long long)v * (v + 1) / 2;
+  if (ncol <= 0) return hipSuccess;
+  if (P > INT_MAX) return hipErrorInvalidValue;
+  const unsigned gy = (unsigned)std::min<long long>((ncol + TPB - 1) / TPB, 64);
+  hipLaunchKernelGGL(pair_combine_cols_kernel, dim3((unsigned)P, gy), dim3(TPB), 0, s, CpT, CmT, ncol, yz, v, R, ccol,
+                     sy, sz);
   return hipGetLastError();
 }
 

@@ -220,9 +220,62 @@ def test_autotune_keeps_results_and_writes_cache(prec, tmp_path, monkeypatch):
         assert np.abs(x - y).max() <= 1e-12 * max(1.0, np.abs(x).max())
     import json
     js = json.loads(cache.read_text())
-    assert js[f"o{o}_v{v}_{prec}_ladder"] == lad and js[f"o{o}_v{v}_{prec}_rings"] == rng
+    assert js[f"o{o}_v{v}_{prec}_ladder_split"] == lad and js[f"o{o}_v{v}_{prec}_rings"] == rng
     with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
         eng.set_amplitudes(t1, t2, t3p)
         c = eng.residual()
     for x, y in zip(b[:3], c[:3]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("shape", [(3, 7, 31), (3, 8, 32)], ids=["odd_v", "even_v"])
+def test_direct_ladder_matches_oracle(shape):
+    """The direct-traversal ladder (symmetric/antisymmetric split switched
+    off) against the oracle's PP term."""
+    o, v, seed = shape
+    say(f"[direct ladder] o={o} v={v} seed={seed}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    _, _, e3 = _oracle_residual(f, B, o, t1, t2, t3p, terms=("PP",))
+    with _engine(o, v, B.shape[0], f, B, opts={"ladder_split": False}) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        _, _, g3, _ = eng.residual(["PP"])
+    ok, err, scale = _close(g3, e3)
+    assert ok, f"direct ladder: max err {err:.3e} (scale {scale:.3e})"
+
+
+# (o, v, workspace cap in GB): v = 2 (one pair tile, padding of K), v = 33
+# (ragged second pair tile), v = 70 (three tiles); the last case caps the
+# workspace so that the 56 packed blocks are split over two chunks.
+SPLIT_CASES = [(2, 2, 0.0), (3, 33, 0.0), (2, 70, 0.0), (6, 60, 0.001)]
+
+
+@pytest.mark.parametrize("o,v,ws", SPLIT_CASES, ids=["v2", "v33", "v70", "v60_chunks"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_ladder_split_matches_direct(prec, o, v, ws):
+    """The symmetric/antisymmetric ladder against the direct traversal in
+    FP64 (PP term alone, same inputs): FP64 agrees to summation order, the
+    mixed modes to their operand rounding.  The executed multiply-adds are
+    v(v+1)/2 v^2 per row and term against v^4 for the direct form."""
+    seed = 40 + v
+    say(f"[ladder split] prec={prec} o={o} v={v} ws={ws}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    opts = {"timers": True}
+    if ws:
+        opts["workspace_gb"] = ws
+    with _engine(o, v, B.shape[0], f, B, opts=dict(opts, ladder_split=False)) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        _, _, ref, _ = eng.residual(["PP"])
+    with _engine(o, v, B.shape[0], f, B, precision=prec, opts=opts) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        _, _, got, _ = eng.residual(["PP"])
+        macs, _ = eng.counters()
+    rel = 1e-12 if prec == "fp64" else MIXED_TOL[prec]
+    ok, err, scale = _close(got, ref, rel)
+    say(f"  max err {err:.3e} scale {scale:.3e}")
+    assert ok, f"split ladder {prec}: max err {err:.3e} (scale {scale:.3e})"
+    assert np.abs(ref).max() > 1e-6
+    ntri = o * (o + 1) * (o + 2) // 6
+    assert macs["ladder_gemm"] == 3 * ntri * v * (v * (v + 1) // 2) * v * v
+    assert macs["PP"] == 3 * ntri * v ** 5
