@@ -1740,7 +1740,8 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
       const int fmt = lp_fmt(ctx->prec);
       HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * lK}, Mt * lK, ctx->s));
       HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, lN * lK}, lN * lK, ctx->s));
-      ctx->tune_ladder = pick({1, 2, 3}, [&](int var) {
+      ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3},
+                              [&](int var) {
         NtLpArgs g{};
         g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
         g.A = Al; g.lda = lK; g.a_plane = Mt * lK; g.B = Bl; g.ldb = lK; g.b_plane = lN * lK;
@@ -1767,7 +1768,9 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     } else {
       HIPCK(fill((double*)U, 0.01, S * ov3, ctx->s));
     }
-    ctx->tune_rings = pick(ring_lp ? std::vector<int>{1, 2, 3} : std::vector<int>{1, 2, 3, 4}, [&](int var) {
+    const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{1, 2, 3, 4}
+                                        : (ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3});
+    ctx->tune_rings = pick(ring_cands, [&](int var) {
       if (ring_lp) {
         NtLpArgs g{};
         g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = S;

@@ -867,24 +867,27 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    bf8 ah[TM], al[TM];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int row = wm0 + i * 16 + (lane & 15);
-      ah[i] = *(const bf8*)&As[cur][0][row * LK + kq];
-      al[i] = *(const bf8*)&As[cur][1][row * LK + kq];
-    }
+    // all B fragments of the wave, then one A fragment at a time: each
+    // accumulator takes its three products (lo*hi, hi*lo, hi*hi, in that
+    // order) TN launches apart
+    bf8 bh[TN], bl[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int col = wn0 + j * 16 + (lane & 15);
-      const bf8 bh = *(const bf8*)&Bs[cur][0][col * LK + kq];
-      const bf8 bl = *(const bf8*)&Bs[cur][1][col * LK + kq];
+      bh[j] = *(const bf8*)&Bs[cur][0][col * LK + kq];
+      bl[j] = *(const bf8*)&Bs[cur][1][col * LK + kq];
+    }
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-      }
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm0 + i * 16 + (lane & 15);
+      const bf8 ah = *(const bf8*)&As[cur][0][row * LK + kq];
+      const bf8 al = *(const bf8*)&As[cur][1][row * LK + kq];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
     }
     if constexpr (ACC64) {
       if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
@@ -970,12 +973,15 @@ hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (!vec) return launch_lp<64, 64, 2, 2, 2, false, false>(g, prec, s);
   int variant = g.variant;
   if (variant == 0) {
-    // 256 x 128 tiles of 8 waves (64 x 64 each) once there are enough of them
+    // 256 x 256 tiles of 8 waves (128 x 64 each; the two LDS buffers take
+    // the whole 160 KB) once there are enough of them, then 256 x 128, ...
+    const long long t2x2 = (long long)((g.M + 255) / 256) * ((g.N + 255) / 256) * g.batch;
     const long long t256 = (long long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch;
     const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-    variant = t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3);
+    variant = t2x2 >= 256 ? 4 : (t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3));
   }
   switch (variant) {
+    case 4: return launch_lp<256, 256, 2, 4, 1, true, false>(g, prec, s);
     case 1: return launch_lp<256, 128, 4, 2, 1, true, false>(g, prec, s);
     case 2: return launch_lp<128, 128, 2, 4, 2, true, false>(g, prec, s);
     default: return launch_lp<64, 64, 2, 2, 2, true, false>(g, prec, s);

@@ -279,3 +279,31 @@ def test_ladder_split_matches_direct(prec, o, v, ws):
     ntri = o * (o + 1) * (o + 2) // 6
     assert macs["ladder_gemm"] == 3 * ntri * v * (v * (v + 1) // 2) * v * v
     assert macs["PP"] == 3 * ntri * v ** 5
+
+
+TILE_VARIANTS = {"fp64": (1, 2, 3, 4), "fp32": (1, 2, 3), "bf16x3": (1, 2, 3, 4)}
+
+
+@pytest.mark.parametrize("prec,var", [(p, x) for p, vs in TILE_VARIANTS.items() for x in vs])
+def test_every_tile_variant_matches_oracle(prec, var, tmp_path, monkeypatch):
+    """Each GEMM tile variant, forced for the ladder and the rings through the
+    tuning cache, on a shape whose GEMMs all end in ragged tiles (v = 30:
+    465 pairs, o v = 90, 10 packed blocks)."""
+    import json
+
+    o, v, seed = 3, 30, 23
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({f"o{o}_v{v}_{prec}_ladder_split": var, f"o{o}_v{v}_{prec}_rings": var}))
+    monkeypatch.setenv("CCT_TUNE_CACHE", str(cache))
+    say(f"[tile variant] prec={prec} variant={var}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
+    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, _ = eng.residual()
+    rel = 1e-11 if prec == "fp64" else MIXED_TOL[prec]
+    for name, a, b, r in (("R1", g1, e1, 1e-11), ("R2", g2, e2, 1e-11), ("R3", g3, e3, rel)):
+        ok, err, scale = _close(a, b, r)
+        say(f"  {name}: max err {err:.3e} scale {scale:.3e}")
+        assert ok, f"{prec} variant {var} {name}: max err {err:.3e} (scale {scale:.3e})"
