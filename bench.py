@@ -92,7 +92,8 @@ def cpu_baseline(o, v, naux, seed):
     }
 
 
-NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64,64,2,2,2>", 4: "<128,128,2,2,2>"}
+NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64,64,2,2,2>", 4: "<128,128,2,2,2>",
+            5: "<256,32,4,1,2>", 6: "<32,256,1,4,2>"}
 LP_TILES = {"fp32": {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"},
             "bf16x3": {0: "size-based", 1: "<256,128,4,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>",
                        4: "<256,256,2,4,1>"}}

@@ -807,24 +807,18 @@ int feedback(cct_ctx* ctx) {
     double* UA = ws.alloc((size_t)slab);
     double* UB = ws.alloc((size_t)slab);
     if (!UA || !UB) { ctx->err = "workspace exhausted (feedback)"; return CCT_ENOMEM; }
-    const int occ[3] = {0, 2, 3};  // t~_{f, free0, free1}
+    const int occ[3] = {0, 2, 3};  // t~_{f, free0, free1}, gathered once, written in two layouts
     {
       UnpackArgs ua{};
       ua.o = o; ua.v = v; ua.nslots = S; ua.nfree = 2;
       set_s1(ua, occ);
-      const long long row = (long long)S * v2;  // one (i,j,a) row
+      const long long row = (long long)S * v2;  // UA: one (i,j,a) row
       ua.s_slot = v2; ua.s_free[0] = (long long)o * v * row; ua.s_free[1] = v * row;
       ua.s_x = 1; ua.s_y = row; ua.s_z = v; ua.fast = 2;  // (x,y,z) = (q,a,p)
-      HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, UA, ua, s));
-    }
-    {
-      UnpackArgs ua{};
-      ua.o = o; ua.v = v; ua.nslots = S; ua.nfree = 2;
-      set_s1(ua, occ);
-      const long long row = (long long)S * ov;  // one (i,a,b) row
-      ua.s_slot = ov; ua.s_free[0] = v2 * row; ua.s_free[1] = v;
-      ua.s_x = 1; ua.s_y = v * row; ua.s_z = row; ua.fast = 2;  // (x,y,z) = (c,a,b)
-      HIPCK(unpack_t3(ctx->t3, ctx->tbl, b.d_slots, UB, ua, s));
+      const long long rowb = (long long)S * ov;  // UB: one (i,a,b) row
+      ua.s2_slot = ov; ua.s2_free[0] = v2 * rowb; ua.s2_free[1] = v;
+      ua.s2_x = 1; ua.s2_y = v * rowb; ua.s2_z = rowb; ua.fast2 = 2;  // (x,y,z) = (c,a,b)
+      HIPCK(unpack_t3_dual(ctx->t3, ctx->tbl, b.d_slots, OutSpec{UA, OUT_F64, 0}, OutSpec{UB, OUT_F64, 0}, ua, s));
     }
     const long long KA = (long long)S * v2, KB = (long long)S * ov;
     // X2[(i,j,a)][b] += UA[(i,j,a)][K] VbT[b][f0.. K]
@@ -1103,18 +1097,19 @@ int r3_f1(cct_ctx* ctx) {
       h.a_len = nt3 - off; h.b_len = v2; h.c_len = nt3 - off;
       HIPCK(gemm_nt(h, Prec::F64, ctx->s));
     }
-    // axis 1 (strided in the block): generic kernel, batched over blocks
+    // axis 1: C[b][(a,c)] += F[b][d] T[a][d][c], the block read as [K][N]
+    // rows d (stride v) whose columns (a,c) sit at a v^2 + c
     for (int start = 0; start < nt; start += 65535) {
       const int nb = std::min(65535, nt - start);
       const long long off = (long long)start * v3;
-      GemmArgs g{};
-      g.M = v; g.K = v; g.N = (int)v2; g.batch = nb;
-      g.A = ctx->Fvv; g.am = idx1(v); g.ak = idx1(1); g.a_batch = 0;
-      g.B = ctx->t3 + off; g.bk = idx1(v); g.bn = idx2(v, v2, 1); g.b_batch = v3;
+      NtArgs g{};
+      g.M = v; g.N = (int)v2; g.K = v; g.batch = nb;
+      g.A = ctx->Fvv; g.lda = v; g.a_batch = 0;
+      g.B = ctx->t3 + off; g.ldb = v; g.b_batch = v3; g.b_kn = 1; g.b_map = 1; g.bnm = idx2(v, v2, 1);
       g.C = ctx->r3 + off; g.cm = idx1(v); g.cn = idx2(v, v2, 1); g.c_batch = v3;
       g.alpha = 1.0; g.beta = 1.0;
       g.a_len = v2; g.b_len = nt3 - off; g.c_len = nt3 - off;
-      HIPCK(gemm(g, Prec::F64, ctx->s));
+      HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     }
     return CCT_OK;
   }

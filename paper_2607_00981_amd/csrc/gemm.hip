@@ -427,7 +427,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_nt_f64_kernel(NtArgs g
       kb[i] = seg / (BN / 2);
       const int n = tn * BN + 2 * (seg % (BN / 2));
       vb[i] = n < g.N;
-      pb[i] = B + (long long)kb[i] * g.ldb + (vb[i] ? n : 0);
+      pb[i] = B + (long long)kb[i] * g.ldb + (vb[i] ? (g.b_map ? map2(g.bnm, n) : (long long)n) : 0);
     } else {
       const int row = seg / (BK / 2);
       kb[i] = 2 * (seg % (BK / 2));
@@ -552,11 +552,14 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
   if (g.K <= 0 || (g.K & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_batch & 1) || (g.b_batch & 1) ||
       ((uintptr_t)g.A & 15) || ((uintptr_t)g.B & 15) || (g.b_kn && (g.N & 1)))
     return hipErrorInvalidValue;
+  if (g.b_map && (!g.b_kn || g.bnm.s_lo != 1 || (g.bnm.inner != 0 && (g.bnm.inner & 1)) || (g.bnm.s_hi & 1)))
+    return hipErrorInvalidValue;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && !g.b_kn && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len)
     return hipErrorInvalidValue;
-  if (g.b_len > 0 && g.b_kn && nb * g.b_batch + (long long)(g.K - 1) * g.ldb + g.N > g.b_len)
+  if (g.b_len > 0 && g.b_kn && nb * g.b_batch + (long long)(g.K - 1) * g.ldb + (g.b_map ? idx_max(g.bnm, g.N) + 1 : g.N) >
+                                   g.b_len)
     return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
   int variant = g.variant;
@@ -566,7 +569,8 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
     // tile count fills the chip (two workgroups on each of 256 CUs), and by
     // the measured relative speed of the shape on full tiles
     struct Cand { int var, bm, bn; double speed; };
-    const Cand cands[4] = {{1, 128, 256, 1.00}, {2, 256, 128, 1.00}, {4, 128, 128, 0.96}, {3, 64, 64, 0.86}};
+    const Cand cands[6] = {{1, 128, 256, 1.00}, {2, 256, 128, 1.00}, {4, 128, 128, 0.96},
+                           {3, 64, 64, 0.86},   {5, 256, 32, 0.80},  {6, 32, 256, 0.80}};
     double best = -1.0;
     for (const Cand& c : cands) {
       const long long tm = (g.M + c.bm - 1) / c.bm, tn = (g.N + c.bn - 1) / c.bn;
@@ -581,6 +585,8 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
     case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
     case 2: return launch_nt<256, 128, 4, 2, 2>(g, s);
     case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);
+    case 5: return launch_nt<256, 32, 4, 1, 2>(g, s);  // N of a few tens: 64 x 32 per wave
+    case 6: return launch_nt<32, 256, 1, 4, 2>(g, s);  // M of a few tens: 32 x 64 per wave
     default: return launch_nt<128, 128, 2, 2, 2>(g, s);
   }
 }

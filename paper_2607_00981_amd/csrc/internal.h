@@ -68,6 +68,8 @@ struct NtArgs {
   long long a_len, b_len, c_len;  // bounds for the host check (0 = unchecked)
   int variant;                    // tile variant (0 = default)
   int b_kn;                       // 1: B is stored [K][N] (row stride ldb, N contiguous) instead of [N][K]
+  int b_map;                      // with b_kn: column n of a B row sits at map2(bnm, n) (pairs n, n+1
+  Idx2 bnm;                       // adjacent: bnm.inner even, bnm.s_lo == 1) instead of at n
 };
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s);
 
@@ -112,12 +114,20 @@ struct UnpackArgs {
   int nterms;
   UnpackTerm terms[6];
   long long s_free[2], s_x, s_y, s_z, s_slot;
+  // optional second copy of the same unpacked values in another layout
+  // (unpack_t3_dual): its strides and unit-stride axis
+  int fast2;
+  long long s2_free[2], s2_x, s2_y, s2_z, s2_slot;
 };
 // slots: device array of int2 (fixed occupied indices) per slot.
 hipError_t unpack_t3(const double* T, const BlockRef* tbl, const int2* slots, double* out,
                      const UnpackArgs& a, hipStream_t s);
 hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots, OutSpec out, const UnpackArgs& a,
                          hipStream_t s);
+// The same values written twice: to out with the s_* strides and to out2
+// with the s2_* strides (one gather pass for two layouts).
+hipError_t unpack_t3_dual(const double* T, const BlockRef* tbl, const int2* slots, OutSpec out, OutSpec out2,
+                          const UnpackArgs& a, hipStream_t s);
 
 // out[b][j][i] = in[b][i][j] for a batch of R x C matrices (row-major).
 hipError_t transpose_batched(const double* in, OutSpec out, long long batch, int R, int C, hipStream_t s);

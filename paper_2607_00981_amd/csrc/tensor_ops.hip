@@ -66,10 +66,11 @@ constexpr int UT = 16;
 constexpr int UP_Z = UT + 1;            // pitch of y rows in the LDS tile
 constexpr int UP_X = UT * UP_Z + 1;     // pitch of x planes
 
+template <bool DUAL>
 __global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restrict__ T,
                                                            const BlockRef* __restrict__ tbl,
                                                            const int2* __restrict__ slots, OutSpec out,
-                                                           UnpackArgs a, int nt) {
+                                                           OutSpec out2, UnpackArgs a, int nt) {
   __shared__ double L[UT * UP_X];
   const int o = a.o, v = a.v;
   const int nfc = (a.nfree == 2) ? o * o : o;
@@ -123,17 +124,35 @@ __global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restr
     __syncthreads();
   }
   // write the tile along the output's unit-stride axis (fast: 0 = z, 1 = y, 2 = x)
-  const int w = a.fast == 0 ? 2 : (a.fast == 1 ? 1 : 0);
-  const int wa = (w + 1) % 3, wb = (w + 2) % 3;
-  const long long so[3] = {a.s_x, a.s_y, a.s_z};
-  for (int e = threadIdx.x; e < UT * UT * UT; e += blockDim.x) {
-    int c[3];
-    c[w] = e % UT;
-    c[wa] = (e / UT) % UT;
-    c[wb] = e / (UT * UT);
-    const int x = base[0] + c[0], y = base[1] + c[1], z = base[2] + c[2];
-    if (x >= v || y >= v || z >= v) continue;
-    put_out(out, obase + x * so[0] + y * so[1] + z * so[2], L[c[0] * UP_X + c[1] * UP_Z + c[2]]);
+  {
+    const int w = a.fast == 0 ? 2 : (a.fast == 1 ? 1 : 0);
+    const int wa = (w + 1) % 3, wb = (w + 2) % 3;
+    const long long so[3] = {a.s_x, a.s_y, a.s_z};
+    for (int e = threadIdx.x; e < UT * UT * UT; e += blockDim.x) {
+      int c[3];
+      c[w] = e % UT;
+      c[wa] = (e / UT) % UT;
+      c[wb] = e / (UT * UT);
+      const int x = base[0] + c[0], y = base[1] + c[1], z = base[2] + c[2];
+      if (x >= v || y >= v || z >= v) continue;
+      put_out(out, obase + x * so[0] + y * so[1] + z * so[2], L[c[0] * UP_X + c[1] * UP_Z + c[2]]);
+    }
+  }
+  if constexpr (DUAL) {
+    const long long obase2 =
+        (long long)slot * a.s2_slot + (long long)f0 * a.s2_free[0] + (long long)f1 * a.s2_free[1];
+    const int w = a.fast2 == 0 ? 2 : (a.fast2 == 1 ? 1 : 0);
+    const int wa = (w + 1) % 3, wb = (w + 2) % 3;
+    const long long so[3] = {a.s2_x, a.s2_y, a.s2_z};
+    for (int e = threadIdx.x; e < UT * UT * UT; e += blockDim.x) {
+      int c[3];
+      c[w] = e % UT;
+      c[wa] = (e / UT) % UT;
+      c[wb] = e / (UT * UT);
+      const int x = base[0] + c[0], y = base[1] + c[1], z = base[2] + c[2];
+      if (x >= v || y >= v || z >= v) continue;
+      put_out(out2, obase2 + x * so[0] + y * so[1] + z * so[2], L[c[0] * UP_X + c[1] * UP_Z + c[2]]);
+    }
   }
 }
 
@@ -489,7 +508,20 @@ hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots
   if (a.nterms < 1 || a.nterms > 6) return hipErrorInvalidValue;
   const int nt = (a.v + UT - 1) / UT;
   dim3 grid((unsigned)(nt * nt * nt), (unsigned)ny);
-  hipLaunchKernelGGL(unpack_tiled_kernel, grid, dim3(TPB), 0, s, T, tbl, slots, out, a, nt);
+  hipLaunchKernelGGL(unpack_tiled_kernel<false>, grid, dim3(TPB), 0, s, T, tbl, slots, out, out, a, nt);
+  return hipGetLastError();
+}
+
+hipError_t unpack_t3_dual(const double* T, const BlockRef* tbl, const int2* slots, OutSpec out, OutSpec out2,
+                          const UnpackArgs& a, hipStream_t s) {
+  const long long v3 = (long long)a.v * a.v * a.v;
+  const long long ny = (long long)a.nslots * (a.nfree == 2 ? (long long)a.o * a.o : a.o);
+  if (ny <= 0 || v3 <= 0) return hipSuccess;
+  if (ny > 65535) return hipErrorInvalidValue;
+  if (a.nterms < 1 || a.nterms > 6) return hipErrorInvalidValue;
+  const int nt = (a.v + UT - 1) / UT;
+  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ny);
+  hipLaunchKernelGGL(unpack_tiled_kernel<true>, grid, dim3(TPB), 0, s, T, tbl, slots, out, out2, a, nt);
   return hipGetLastError();
 }
 
