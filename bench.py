@@ -272,7 +272,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed iterations first (one makes T3 non-zero, so every term contracts real data)")
     ap.add_argument("--precision", default="fp64", choices=list(PEAK),
                     help="mode whose rate is the reported value")
     ap.add_argument("--compare", default="fp32,bf16x3",
@@ -349,7 +350,9 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tf = json.load(open(TRAFFIC_FILE))
-            if tf.get("precision") == args.precision and tf.get("workload") == args.workload:
+            if (tf.get("precision") == args.precision and tf.get("workload") == args.workload and
+                    tf.get("form") == "split" and tf.get("kernel") == kernel_name(args.precision,
+                                                                                   main_run["tile_variants"]["ladder"])):
                 traffic = tf.get("bytes_per_launch")
         except Exception:
             traffic = None

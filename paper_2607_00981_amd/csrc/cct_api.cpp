@@ -1700,7 +1700,9 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
       const float t = time_launch(ctx->s, [&] { return run(c); });
       if (t < 0.f) continue;
       used += 2.0 * t;
-      if (best == 0 || t < tbest) { best = c; tbest = t; }
+      // a later candidate has to be clearly faster (2 %) to replace the
+      // earlier one, so that near-ties keep the first-listed shape
+      if (best == 0 || t < 0.98f * tbest) { best = c; tbest = t; }
     }
     return best;
   };
