@@ -79,17 +79,30 @@ enum {
 
 typedef struct cct_ctx cct_ctx;
 
+/* Device memory through the caller's allocator (for instance a framework's
+ * caching allocator).  alloc returns a device pointer of at least `bytes`
+ * bytes, aligned to 256 bytes, or NULL on failure; free releases it.  Both
+ * receive the `user` pointer given at creation.  Pass both NULL to let the
+ * library use hipMalloc / hipFree; passing exactly one is CCT_EINVAL.  The
+ * library frees everything it obtained this way in the matching destroy
+ * call, after synchronising its stream(s). */
+typedef void* (*cct_alloc_fn)(size_t bytes, void* user);
+typedef void (*cct_free_fn)(void* ptr, void* user);
+
 /* Create a context for o occupied / v virtual orbitals and naux fitting
  * functions.  opts_json may be NULL or a JSON object with integer/string
  * fields: "diis_space" (default 8), "diis_start" (default 2), "diis_t3"
  * ("full" | "none", default "full"), "diis" (true/false, default true),
  * "workspace_gb" (cap on the scratch buffer; default: enough for every
  * unpacked slab in one batch, limited by free device memory), "timers"
- * (true: per-phase device times for cct_get_counters).  hip_stream: a
- * hipStream_t or NULL.  The memory plan is checked
- * against free device memory here; CCT_ENOMEM if it does not fit. */
-int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json,
-               void* hip_stream, cct_ctx** out);
+ * (true: per-phase device times for cct_get_counters), "ladder_split"
+ * (true by default: the symmetric/antisymmetric ladder; false: the direct
+ * form).  alloc/free_fn/alloc_user: the caller's device allocator (see
+ * cct_alloc_fn), or both NULL.  hip_stream: a hipStream_t or NULL.  The
+ * memory plan is checked against free device memory here; CCT_ENOMEM if it
+ * does not fit (or if the caller's allocator returns NULL). */
+int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json, cct_alloc_fn alloc,
+               cct_free_fn free_fn, void* alloc_user, void* hip_stream, cct_ctx** out);
 /* Free the context and all device memory it owns.  NULL is ignored. */
 void cct_destroy(cct_ctx* ctx);
 
@@ -173,10 +186,15 @@ typedef struct cct_batch cct_batch;
  * stream; the graph forks and joins them),
  * "graph" (true by default; false enqueues every iteration eagerly, the same
  * kernels in the same order), and the per-system keys of cct_create
- * ("diis", "diis_space", "diis_start", "diis_t3", "workspace_gb").
+ * ("diis", "diis_space", "diis_start", "diis_t3", "workspace_gb",
+ * "ladder_split").  alloc/free_fn/alloc_user: as for cct_create, used by
+ * every system.  hip_stream (may be NULL): the caller's stream becomes the
+ * first of the batch's streams, on which the graph is launched and joined
+ * (not destroyed by the library); the others are created by the library.
  * Errors: CCT_EINVAL (sizes, options), CCT_ENOMEM, CCT_EDEVICE. */
 int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux, cct_precision prec,
-                     const char* opts_json, cct_batch** out);
+                     const char* opts_json, cct_alloc_fn alloc, cct_free_fn free_fn, void* alloc_user,
+                     void* hip_stream, cct_batch** out);
 /* Upload system s's bare Fock f[n][n] and factors B[naux][n][n] (host) and
  * start it from the MP2 guess.  Does not invalidate a recorded graph (the
  * device buffers keep their addresses). */
@@ -214,9 +232,10 @@ typedef struct cct_slab cct_slab;
 
 /* first + count <= nocc(nocc+1)(nocc+2)/6, count <= 65535.  opts_json:
  * "panel" (rows a per W panel, 1..nvir), "timers" (true: per-phase times
- * in cct_slab_get_counters).  Errors: CCT_EINVAL, CCT_ENOMEM. */
+ * in cct_slab_get_counters).  alloc/free_fn/alloc_user: as for cct_create.
+ * Errors: CCT_EINVAL, CCT_ENOMEM. */
 int cct_slab_create(int nocc, int nvir, int naux, int first, int count, cct_precision prec, const char* opts_json,
-                    void* hip_stream, cct_slab** out);
+                    cct_alloc_fn alloc, cct_free_fn free_fn, void* alloc_user, void* hip_stream, cct_slab** out);
 /* Replicated inputs (host arrays, copied in): Bt = T1-dressed factors
  * B~[naux][n][n] (Appendix A, "T1-dressed formalism"), t2 [o][o][v][v]
  * (t_ij^ab = t_ji^ba), Fvv [a][d] = F^a_d, Wt [j][a][b][d] = W^{ab}_{dj},

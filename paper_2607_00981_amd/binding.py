@@ -30,6 +30,24 @@ class CCTError(RuntimeError):
         self.code = code
 
 
+# The caller-allocator callbacks of the C ABI (device pointer alloc(bytes, user); free(ptr, user)).
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def _allocator_args(allocator):
+    """(alloc, free, user) for the create calls: None -> library default
+    (hipMalloc); otherwise a pair of Python callables alloc(bytes) -> int
+    device address and free(address), wrapped as C callbacks (the wrappers
+    are returned too, to be kept alive as long as the handle)."""
+    if allocator is None:
+        return None, None, None, ()
+    alloc_py, free_py = allocator
+    a = ALLOC_FN(lambda nbytes, user: alloc_py(int(nbytes)) or None)
+    f = FREE_FN(lambda ptr, user: free_py(int(ptr)))
+    return C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None, (a, f)
+
+
 def load(path: str | None = None):
     """Load libcct.so (raises if it has not been built)."""
     global _lib
@@ -42,7 +60,7 @@ def load(path: str | None = None):
     dp = C.POINTER(C.c_double)
     vp = C.c_void_p
     sig = {
-        "cct_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp, C.POINTER(vp)]),
+        "cct_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp, vp, vp, vp, C.POINTER(vp)]),
         "cct_destroy": (None, [vp]),
         "cct_set_fock": (C.c_int, [vp, dp]),
         "cct_set_eri_df": (C.c_int, [vp, dp]),
@@ -61,14 +79,14 @@ def load(path: str | None = None):
         "cct_strerror": (C.c_char_p, [C.c_int]),
         "cct_last_error": (C.c_char_p, [vp]),
         "cct_batch_create": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                       C.c_int, C.c_char_p, C.POINTER(vp)]),
+                                       C.c_int, C.c_char_p, vp, vp, vp, vp, C.POINTER(vp)]),
         "cct_batch_set_system": (C.c_int, [vp, C.c_int, dp, dp]),
         "cct_batch_iterate": (C.c_int, [vp, C.c_int, dp, dp]),
         "cct_batch_system": (vp, [vp, C.c_int]),
         "cct_batch_last_error": (C.c_char_p, [vp]),
         "cct_batch_destroy": (None, [vp]),
-        "cct_slab_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp,
-                                      C.POINTER(vp)]),
+        "cct_slab_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_char_p, vp, vp, vp,
+                                      vp, C.POINTER(vp)]),
         "cct_slab_set_intermediates": (C.c_int, [vp, dp, dp, dp, dp, dp]),
         "cct_slab_set_t3": (C.c_int, [vp, dp]),
         "cct_slab_residual": (C.c_int, [vp, C.c_uint, dp, dp]),
@@ -109,7 +127,7 @@ def ntri(o):
 class Engine:
     """One CCSDT context on the current HIP device."""
 
-    def __init__(self, nocc, nvir, naux, precision="fp64", opts=None, stream=None):
+    def __init__(self, nocc, nvir, naux, precision="fp64", opts=None, stream=None, allocator=None):
         import json
 
         self.lib = load()
@@ -118,7 +136,8 @@ class Engine:
         self.ntri = ntri(nocc)
         js = json.dumps(opts).encode() if opts else None
         h = C.c_void_p()
-        rc = self.lib.cct_create(nocc, nvir, naux, PRECISIONS[precision], js, stream, C.byref(h))
+        a, f, u, self._keep = _allocator_args(allocator)
+        rc = self.lib.cct_create(nocc, nvir, naux, PRECISIONS[precision], js, a, f, u, stream, C.byref(h))
         if rc != CCT_OK:
             raise CCTError(rc, self.lib.cct_strerror(rc).decode())
         self.h = h
@@ -243,7 +262,7 @@ class _SystemView(Engine):
 class Batch:
     """Independent systems iterated together (one graph launch per iteration)."""
 
-    def __init__(self, sizes, precision="fp64", opts=None):
+    def __init__(self, sizes, precision="fp64", opts=None, stream=None, allocator=None):
         import json
 
         self.lib = load()
@@ -252,7 +271,9 @@ class Batch:
         arr = lambda k: (C.c_int * n)(*[s[k] for s in self.sizes])  # noqa: E731
         js = json.dumps(opts).encode() if opts else None
         h = C.c_void_p()
-        rc = self.lib.cct_batch_create(n, arr(0), arr(1), arr(2), PRECISIONS[precision], js, C.byref(h))
+        a, f, u, self._keep = _allocator_args(allocator)
+        rc = self.lib.cct_batch_create(n, arr(0), arr(1), arr(2), PRECISIONS[precision], js, a, f, u, stream,
+                                       C.byref(h))
         if rc != CCT_OK:
             raise CCTError(rc, self.lib.cct_strerror(rc).decode())
         self.h = h
@@ -309,7 +330,7 @@ SLAB_PHASES = ("views", "w_rebuild", "ladder", "f_vv", "drivers", "post")
 class Slab:
     """The block-local R3 terms for packed triples [first, first + count)."""
 
-    def __init__(self, nocc, nvir, naux, first, count, precision="fp64", opts=None, stream=None):
+    def __init__(self, nocc, nvir, naux, first, count, precision="fp64", opts=None, stream=None, allocator=None):
         import json
 
         self.lib = load()
@@ -317,7 +338,9 @@ class Slab:
         self.n = nocc + nvir
         js = json.dumps(opts).encode() if opts else None
         h = C.c_void_p()
-        rc = self.lib.cct_slab_create(nocc, nvir, naux, first, count, PRECISIONS[precision], js, stream, C.byref(h))
+        a, f, u, self._keep = _allocator_args(allocator)
+        rc = self.lib.cct_slab_create(nocc, nvir, naux, first, count, PRECISIONS[precision], js, a, f, u, stream,
+                                      C.byref(h))
         if rc != CCT_OK:
             raise CCTError(rc, self.lib.cct_strerror(rc).decode())
         self.h = h

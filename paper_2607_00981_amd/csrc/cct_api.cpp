@@ -58,6 +58,9 @@ const char* kErr[] = {"ok", "invalid argument", "out of device memory", "device 
 }  // namespace
 
 struct cct_ctx {
+  cct_alloc_fn alloc_fn = nullptr;  // the caller's device allocator (both null: hipMalloc / hipFree)
+  cct_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   int o = 0, v = 0, n = 0, naux = 0;
   long long ntri = 0, v3 = 0;
   Prec prec = Prec::F64;
@@ -146,13 +149,37 @@ namespace {
 
 long long tri_count(int o) { return (long long)o * (o + 1) * (o + 2) / 6; }
 
+// Device memory from the caller's allocator when one was given, else hipMalloc.
+int dev_alloc(cct_ctx* ctx, void** p, size_t bytes) {
+  void* q = nullptr;
+  bytes = std::max<size_t>(bytes, 8);
+  if (ctx->alloc_fn) {
+    q = ctx->alloc_fn(bytes, ctx->alloc_user);
+    if (!q || ((uintptr_t)q & 255)) {
+      if (q) ctx->free_fn(q, ctx->alloc_user);
+      ctx->err = "caller allocator: " + std::string(q ? "pointer not 256-byte aligned" : "NULL") + " for " +
+                 std::to_string(bytes) + " bytes";
+      return CCT_ENOMEM;
+    }
+  } else {
+    const hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+      ctx->err = std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e);
+      return CCT_ENOMEM;
+    }
+  }
+  *p = q;
+  return CCT_OK;
+}
+void dev_free(cct_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->free_fn) ctx->free_fn(p, ctx->alloc_user);
+  else (void)hipFree(p);
+}
+
 int dalloc(cct_ctx* ctx, double** p, long long n) {
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(n, 1) * sizeof(double));
-  if (e != hipSuccess) {
-    ctx->err = std::string("hipMalloc of ") + std::to_string(n * 8) + " bytes: " + hipGetErrorString(e);
-    return CCT_ENOMEM;
-  }
+  RCK(dev_alloc(ctx, &q, (size_t)std::max<long long>(n, 1) * sizeof(double)));
   ctx->owned.push_back(q);
   *p = (double*)q;
   return CCT_OK;
@@ -161,11 +188,7 @@ int dalloc(cct_ctx* ctx, double** p, long long n) {
 template <typename T>
 int dalloc_t(cct_ctx* ctx, T** p, long long n) {
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(n, 1) * sizeof(T));
-  if (e != hipSuccess) {
-    ctx->err = std::string("hipMalloc: ") + hipGetErrorString(e);
-    return CCT_ENOMEM;
-  }
+  RCK(dev_alloc(ctx, &q, (size_t)std::max<long long>(n, 1) * sizeof(T)));
   ctx->owned.push_back(q);
   *p = (T*)q;
   return CCT_OK;
@@ -1822,21 +1845,26 @@ int64_t cct_packed_index(int nocc, int i, int j, int k) {
 
 void cct_destroy(cct_ctx* ctx) {
   if (!ctx) return;
-  for (void* p : ctx->owned) (void)hipFree(p);
-  if (ctx->wsbuf) (void)hipFree(ctx->wsbuf);
+  (void)hipStreamSynchronize(ctx->s);  // nothing in flight may touch what is freed below
+  for (void* p : ctx->owned) dev_free(ctx, p);
+  dev_free(ctx, ctx->wsbuf);
   for (int i = 0; i <= PH_N; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   for (hipEvent_t e : ctx->lad_ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
-int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json, void* hip_stream,
-               cct_ctx** out) {
+int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opts_json, cct_alloc_fn alloc,
+               cct_free_fn free_fn, void* alloc_user, void* hip_stream, cct_ctx** out) {
   if (!out) return CCT_EINVAL;
   *out = nullptr;
   if (nocc < 1 || nvir < 1 || naux < 1 || nocc > 200 || nvir > 1200 || (int)prec < 0 || (int)prec > 2)
     return CCT_EINVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return CCT_EINVAL;
   cct_ctx* ctx = new cct_ctx();
+  ctx->alloc_fn = alloc;
+  ctx->free_fn = free_fn;
+  ctx->alloc_user = alloc_user;
   ctx->o = nocc;
   ctx->v = nvir;
   ctx->n = nocc + nvir;
@@ -1936,8 +1964,8 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
 #undef AL
   if (rc == CCT_OK) {
     void* w = nullptr;
-    if (hipMalloc(&w, (size_t)ws_doubles * 8) != hipSuccess) rc = CCT_ENOMEM;
-    else {
+    rc = dev_alloc(ctx, &w, (size_t)ws_doubles * 8);
+    if (rc == CCT_OK) {
       ctx->wsbuf = (char*)w;
       ctx->ws.init(ctx->wsbuf, (size_t)ws_doubles * 8);
     }
@@ -2126,7 +2154,8 @@ int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, in
 // ===========================================================================
 struct cct_batch {
   std::vector<cct_ctx*> sys;
-  std::vector<hipStream_t> streams;
+  std::vector<hipStream_t> streams;  // streams[0] may be the caller's (owned_first false)
+  bool owned_first = true;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
@@ -2201,16 +2230,18 @@ void cct_batch_destroy(cct_batch* b) {
   for (hipEvent_t e : b->join)
     if (e) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
-  for (hipStream_t s : b->streams)
-    if (s) (void)hipStreamDestroy(s);
+  for (size_t i = 0; i < b->streams.size(); ++i)
+    if (b->streams[i] && (i > 0 || b->owned_first)) (void)hipStreamDestroy(b->streams[i]);
   delete b;
 }
 
 int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux, cct_precision prec,
-                     const char* opts_json, cct_batch** out) {
+                     const char* opts_json, cct_alloc_fn alloc, cct_free_fn free_fn, void* alloc_user,
+                     void* hip_stream, cct_batch** out) {
   if (!out) return CCT_EINVAL;
   *out = nullptr;
   if (nsys < 1 || nsys > 4096 || !nocc || !nvir || !naux) return CCT_EINVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return CCT_EINVAL;
   int nstreams = 4;
   bool use_graph = true;
   std::string sys_opts = "{\"timers\": false";
@@ -2229,7 +2260,12 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
   int rc = CCT_OK;
   for (int i = 0; i < nstreams && rc == CCT_OK; ++i) {
     hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) rc = CCT_EDEVICE;
+    if (i == 0 && hip_stream) {
+      s = (hipStream_t)hip_stream;
+      b->owned_first = false;
+    } else if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      rc = CCT_EDEVICE;
+    }
     b->streams.push_back(s);
     hipEvent_t e = nullptr;
     if (rc == CCT_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = CCT_EDEVICE;
@@ -2257,7 +2293,8 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
   }
   for (int i = 0; i < nsys && rc == CCT_OK; ++i) {
     cct_ctx* c = nullptr;
-    rc = cct_create(nocc[i], nvir[i], naux[i], prec, sys_opts.c_str(), b->streams[stream_of[i]], &c);
+    rc = cct_create(nocc[i], nvir[i], naux[i], prec, sys_opts.c_str(), alloc, free_fn, alloc_user,
+                    b->streams[stream_of[i]], &c);
     if (rc == CCT_OK) b->sys.push_back(c);
   }
   if (rc != CCT_OK) {

@@ -25,6 +25,9 @@
 using namespace cct;
 
 struct cct_slab {
+  cct_alloc_fn alloc_fn = nullptr;  // the caller's device allocator (both null: hipMalloc / hipFree)
+  cct_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   int o = 0, v = 0, n = 0, naux = 0, first = 0, count = 0, ntri_all = 0;
   Prec prec = Prec::F64;
   hipStream_t s = nullptr;
@@ -73,12 +76,35 @@ namespace {
     if (r_ != CCT_OK) return r_;   \
   } while (0)
 
-int salloc(cct_slab* sl, void** p, size_t bytes) {
+// Device memory from the caller's allocator when one was given, else hipMalloc.
+int sdev_alloc(cct_slab* sl, void** p, size_t bytes) {
   void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(bytes, 8)) != hipSuccess) {
+  bytes = std::max<size_t>(bytes, 8);
+  if (sl->alloc_fn) {
+    q = sl->alloc_fn(bytes, sl->alloc_user);
+    if (!q || ((uintptr_t)q & 255)) {
+      if (q) sl->free_fn(q, sl->alloc_user);
+      sl->err = "caller allocator: " + std::string(q ? "pointer not 256-byte aligned" : "NULL") + " for " +
+                std::to_string(bytes) + " bytes";
+      return CCT_ENOMEM;
+    }
+  } else if (hipMalloc(&q, bytes) != hipSuccess) {
     sl->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
     return CCT_ENOMEM;
   }
+  *p = q;
+  return CCT_OK;
+}
+void sdev_free(cct_slab* sl, void* p) {
+  if (!p) return;
+  if (sl->free_fn) sl->free_fn(p, sl->alloc_user);
+  else (void)hipFree(p);
+}
+
+int salloc(cct_slab* sl, void** p, size_t bytes) {
+  void* q = nullptr;
+  const int rc = sdev_alloc(sl, &q, bytes);
+  if (rc != CCT_OK) return rc;
   sl->owned.push_back(q);
   *p = q;
   return CCT_OK;
@@ -366,21 +392,25 @@ extern "C" {
 void cct_slab_destroy(cct_slab* sl) {
   if (!sl) return;
   if (sl->s) (void)hipStreamSynchronize(sl->s);
-  for (void* p : sl->owned) (void)hipFree(p);
+  for (void* p : sl->owned) sdev_free(sl, p);
   for (hipEvent_t e : sl->ev)
     if (e) (void)hipEventDestroy(e);
   delete sl;
 }
 
 int cct_slab_create(int nocc, int nvir, int naux, int first, int count, cct_precision prec, const char* opts_json,
-                    void* hip_stream, cct_slab** out) {
+                    cct_alloc_fn alloc, cct_free_fn free_fn, void* alloc_user, void* hip_stream, cct_slab** out) {
   if (!out) return CCT_EINVAL;
   *out = nullptr;
   if (nocc < 1 || nvir < 1 || naux < 1 || nocc > 200 || nvir > 1200 || (int)prec < 0 || (int)prec > 2)
     return CCT_EINVAL;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return CCT_EINVAL;
   const long long ntri = (long long)nocc * (nocc + 1) * (nocc + 2) / 6;
   if (first < 0 || count < 1 || first + (long long)count > ntri || count > 65535) return CCT_EINVAL;
   cct_slab* sl = new cct_slab();
+  sl->alloc_fn = alloc;
+  sl->free_fn = free_fn;
+  sl->alloc_user = alloc_user;
   sl->o = nocc; sl->v = nvir; sl->n = nocc + nvir; sl->naux = naux;
   sl->first = first; sl->count = count; sl->ntri_all = (int)ntri;
   sl->prec = (Prec)prec;
@@ -469,7 +499,7 @@ int cct_slab_set_intermediates(cct_slab* sl, const double* Bt, const double* t2,
     for (int l = 0; l < o; ++l)
       for (int d = 0; d < v; ++d) bov[((size_t)P * o + l) * v + d] = Bt[(size_t)P * n2 + (size_t)l * n + (o + d)];
   double* dbov = nullptr;
-  if (hipMalloc(&dbov, bov.size() * 8) != hipSuccess) { sl->err = "hipMalloc (factors)"; return CCT_ENOMEM; }
+  RCK_(sdev_alloc(sl, (void**)&dbov, bov.size() * 8));
   hipError_t e = hipMemcpy(dbov, bov.data(), bov.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     // C[(d,e)][(l,m)] = sum_P bov[P][l][d] bov[P][m][e]: batch over d, M = e... written as
@@ -485,7 +515,7 @@ int cct_slab_set_intermediates(cct_slab* sl, const double* Bt, const double* t2,
     e = gemm(g, Prec::F64, sl->s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(sl->s);
-  (void)hipFree(dbov);
+  sdev_free(sl, dbov);
   if (e != hipSuccess) {
     sl->err = std::string("v~^{lm}_{de} build: ") + hipGetErrorString(e);
     return CCT_EDEVICE;

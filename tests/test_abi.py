@@ -55,8 +55,25 @@ def test_create_rejects_bad_arguments():
     import ctypes as C
     lib = binding.load()
     h = C.c_void_p()
-    assert lib.cct_create(0, 10, 10, 0, None, None, C.byref(h)) == binding.CCT_EINVAL
-    assert lib.cct_create(2, 10, 10, 7, None, None, C.byref(h)) == binding.CCT_EINVAL
-    assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "bogus"}', None, C.byref(h)) == binding.CCT_EINVAL
-    assert lib.cct_create(2, 10, 10, 0, None, None, None) == binding.CCT_EINVAL
+    assert lib.cct_create(0, 10, 10, 0, None, None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 7, None, None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "bogus"}', None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, None, None, None, None, None, None) == binding.CCT_EINVAL
     lib.cct_destroy(None)
+
+
+def test_create_rejects_half_an_allocator():
+    """The caller's allocator comes as a pair: alloc without free (or free
+    without alloc) is refused before any device call, for every create."""
+    import ctypes as C
+    lib = binding.load()
+    h = C.c_void_p()
+    a_cb = binding.ALLOC_FN(lambda n, u: None)
+    f_cb = binding.FREE_FN(lambda p, u: None)
+    a, f = C.cast(a_cb, C.c_void_p), C.cast(f_cb, C.c_void_p)
+    assert lib.cct_create(2, 10, 10, 0, None, a, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, None, None, f, None, None, C.byref(h)) == binding.CCT_EINVAL
+    sizes = (C.c_int * 1)(2)
+    assert lib.cct_batch_create(1, sizes, sizes, sizes, 0, None, a, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_slab_create(2, 10, 10, 0, 1, 0, None, None, f, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert not h.value

@@ -32,16 +32,16 @@ def test_state_and_argument_errors_single():
         assert lib.cct_solve(eng.h, 0, 1e-8, None, None) == binding.CCT_EINVAL
     lib = binding.load()
     h = binding.C.c_void_p()
-    assert lib.cct_create(0, 5, 10, 0, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
-    assert lib.cct_create(2, 5, 10, 7, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
-    assert lib.cct_create(2, 5, 10, 0, b'{"diis_t3": "sometimes"}', None, binding.C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(0, 5, 10, 0, None, None, None, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 5, 10, 7, None, None, None, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 5, 10, 0, b'{"diis_t3": "sometimes"}', None, None, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
 
 
 def test_slab_and_batch_errors():
     lib = binding.load()
     h = binding.C.c_void_p()
     # slab range beyond the packed triples of o = 3 (10 triples)
-    assert lib.cct_slab_create(3, 8, 20, 8, 4, 0, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_slab_create(3, 8, 20, 8, 4, 0, None, None, None, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
     with binding.Slab(3, 8, 20, 0, 4) as sl:
         with pytest.raises(binding.CCTError) as e:
             sl.residual()
