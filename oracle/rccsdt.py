@@ -374,9 +374,15 @@ def unpack_vec(vec, o, v, triples=True):
     return t1, t2, t3
 
 
-def iterate(f, V, t1, t2, t3, o, triples=True, diis=None):
+def iterate(f, V, t1, t2, t3, o, triples=True, diis=None, diis_t3="full"):
     """One iteration: residuals, R3 post-processing, norms, Jacobi update
     t <- t + r / eps, optional DIIS, energy of the new amplitudes.
+
+    diis_t3 selects the part of T3 in the DIIS vectors (Sec. "Distributed
+    DIIS"): "full", "none" (T1/T2 only; T3 keeps its Jacobi step), or an int
+    nv: only the components whose three virtual indices lie in the
+    low-energy subspace (the first nv virtuals) enter the overlaps and are
+    extrapolated; the rest of T3 keeps its Jacobi step.
 
     Returns (t1, t2, t3, energy, (|R1|^2, |R2|^2, |R3|^2))."""
     r1, r2, r3 = residuals(f, V, t1, t2, t3, o, triples=triples)
@@ -389,14 +395,27 @@ def iterate(f, V, t1, t2, t3, o, triples=True, diis=None):
     n3 = t3 + r3 / d3 if triples else None
     if diis is not None:
         v = t1.shape[1]
-        new = pack_vec(n1, n2, n3)
-        old = pack_vec(t1, t2, t3 if triples else None)
-        n1, n2, n3 = unpack_vec(diis.update(new, new - old), o, v, triples)
+        if not triples or diis_t3 == "none":
+            sub = 0
+        elif diis_t3 == "full":
+            sub = v
+        else:
+            sub = int(diis_t3)
+        part = (lambda x: x[:, :, :, :sub, :sub, :sub]) if sub else (lambda x: None)
+        new = pack_vec(n1, n2, part(n3) if triples else None)
+        old = pack_vec(t1, t2, part(t3) if triples else None)
+        out = diis.update(new, new - old)
+        n_12 = o * v + o * o * v * v
+        n1 = out[:o * v].reshape(o, v).copy()
+        n2 = out[o * v:n_12].reshape(o, o, v, v).copy()
+        if sub:
+            n3 = n3.copy()
+            n3[:, :, :, :sub, :sub, :sub] = out[n_12:].reshape(o, o, o, sub, sub, sub)
     e = energy(f, V, n1, n2, o)
     return n1, n2, n3, e, norms
 
 
-def solve(f, V, o, triples=True, max_iter=200, tol=1e-10, diis=True, t_init=None, verbose=False):
+def solve(f, V, o, triples=True, max_iter=200, tol=1e-10, diis=True, t_init=None, verbose=False, diis_t3="full"):
     """Iterate from the MP2 guess until sqrt(sum of squared norms) < tol.
     Returns (energy, t1, t2, t3, iterations, converged)."""
     if t_init is None:
@@ -408,7 +427,7 @@ def solve(f, V, o, triples=True, max_iter=200, tol=1e-10, diis=True, t_init=None
     d = DIIS() if diis else None
     e = energy(f, V, t1, t2, o)
     for it in range(1, max_iter + 1):
-        t1, t2, t3, e, nrm = iterate(f, V, t1, t2, t3, o, triples=triples, diis=d)
+        t1, t2, t3, e, nrm = iterate(f, V, t1, t2, t3, o, triples=triples, diis=d, diis_t3=diis_t3)
         rn = np.sqrt(sum(nrm))
         if verbose:
             print(it, e, rn)

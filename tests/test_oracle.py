@@ -357,3 +357,61 @@ def test_hashed_t3_symmetry_and_determinism():
         if j == k:
             assert np.array_equal(blk, blk.transpose(0, 2, 1))
     assert abs(a.std() - 0.01 / np.sqrt(3)) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# DIIS on a T3 subspace (Sec. "Distributed DIIS")
+# ---------------------------------------------------------------------------
+
+def _diis_run(f, V, o, mode, niter):
+    t1, t2, t3 = R.mp2_guess(f, V, o)
+    d = R.DIIS()
+    out = []
+    for _ in range(niter):
+        j1, j2, j3 = t1, t2, t3
+        t1, t2, t3, e, _ = R.iterate(f, V, t1, t2, t3, o, diis=d, diis_t3=mode)
+        out.append((j1, j2, j3, t1, t2, t3, e))
+    return out
+
+
+def test_subspace_diis_over_all_virtuals_is_full_diis():
+    """A subspace holding every virtual is the plain T3 DIIS, bit for bit."""
+    o, v = 2, 4
+    f, V = _tiny(o, v, 41)
+    a = _diis_run(f, V, o, "full", 6)
+    b = _diis_run(f, V, o, v, 6)
+    for x, y in zip(a, b):
+        assert x[6] == y[6]
+        assert np.array_equal(x[5], y[5])
+
+
+@pytest.mark.parametrize("mode", [2, "none"])
+def test_t3_outside_the_diis_part_keeps_its_jacobi_step(mode):
+    """Components of T3 that are not in the DIIS vectors equal the plain
+    Jacobi update t + r/eps; the extrapolated ones (and T1, T2) do not."""
+    o, v = 2, 4
+    f, V = _tiny(o, v, 42)
+    d1, d2, d3 = R.denominators(f, o)
+    sub = 0 if mode == "none" else mode
+    for j1, j2, j3, t1, t2, t3, _ in _diis_run(f, V, o, mode, 5)[2:]:
+        r1, r2, r3 = R.residuals(f, V, j1, j2, j3, o)
+        jac = j3 + R.postprocess_r3(r3) / d3
+        outside = np.ones(t3.shape, bool)
+        outside[:, :, :, :sub, :sub, :sub] = False
+        assert np.array_equal(t3[outside], jac[outside])
+        if sub:
+            assert not np.allclose(t3[~outside], jac[~outside], rtol=0, atol=1e-14)
+        assert not np.allclose(t1, j1 + r1 / d1, rtol=0, atol=1e-14)
+
+
+def test_subspace_diis_converges_to_the_same_energy():
+    """The accelerator does not move the fixed point: DIIS on a T3 subspace
+    and on the whole T3 converge to the same RCCSDT energy."""
+    o, v = 2, 4
+    s = ci.make_system(o, v, 2 * (o + v), 43, sigma=0.1)  # a system plain Jacobi steps converge on
+    f, V = s["f"], R.eri_phys_from_B(s["B"])
+    ef, *_, itf, cf = R.solve(f, V, o, tol=1e-11, max_iter=300)
+    es, *_, its, cs = R.solve(f, V, o, tol=1e-11, max_iter=300, diis_t3=2)
+    en, *_, itn, cn = R.solve(f, V, o, tol=1e-11, max_iter=300, diis_t3="none")
+    assert cf and cs and cn
+    assert abs(ef - es) < 1e-12 and abs(ef - en) < 1e-12
