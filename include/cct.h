@@ -92,7 +92,11 @@ typedef void (*cct_free_fn)(void* ptr, void* user);
 /* Create a context for o occupied / v virtual orbitals and naux fitting
  * functions.  opts_json may be NULL or a JSON object with integer/string
  * fields: "diis_space" (default 8), "diis_start" (default 2), "diis_t3"
- * ("full" | "none", default "full"), "diis" (true/false, default true),
+ * ("full" | "none" | "subspace:<nv>", default "full"; Sec. "Distributed
+ * DIIS": with "subspace:<nv>" only the T3 components whose three virtual
+ * indices are among the first nv enter the DIIS overlaps and are
+ * extrapolated, the rest of T3 keeps its Jacobi step; "none" leaves T3 out),
+ * "diis" (true/false, default true),
  * "workspace_gb" (cap on the scratch buffer; default: enough for every
  * unpacked slab in one batch, limited by free device memory), "timers"
  * (true: per-phase device times for cct_get_counters), "ladder_split"

@@ -67,6 +67,7 @@ struct cct_ctx {
   hipStream_t s = nullptr;
   int diis_space = 8, diis_start = 2;
   bool diis_on = true, diis_t3 = true;
+  int diis_sv = 0;  // T3 in DIIS: the sub-cube a, b, c < diis_sv of every block (0: all of T3)
   double ws_gb = 0.0;  // 0: size the workspace from free device memory
   int tune_ladder = 0, tune_rings = 0;  // GEMM tile variants chosen by cct_autotune (0 = size-based default)
   std::string err;
@@ -1475,16 +1476,27 @@ int energy_dev(cct_ctx* ctx, double* e) {
 }
 
 // --- DIIS ---------------------------------------------------------------
+// T3 elements per packed block that take part in DIIS (Sec. "Distributed
+// DIIS": all of T3, none of it, or only the low-energy virtual subspace)
+long long diis_block(const cct_ctx* ctx) {
+  if (!ctx->diis_t3) return 0;
+  const long long s = ctx->diis_sv > 0 ? ctx->diis_sv : ctx->v;
+  return s * s * s;
+}
+
 long long diis_len(cct_ctx* ctx) {
   const long long n12 = (long long)ctx->o * ctx->v + (long long)ctx->o * ctx->o * ctx->v * ctx->v;
-  return n12 + (ctx->diis_t3 ? ctx->ntri * ctx->v3 : 0);
+  return n12 + ctx->ntri * diis_block(ctx);
 }
 
 int copy_amps_to(cct_ctx* ctx, double* dst) {
   const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
   HIPCK(axpby(1.0, ctx->t1, 0.0, dst, n1, ctx->s));
   HIPCK(axpby(1.0, ctx->t2, 0.0, dst + n1, n2, ctx->s));
-  if (ctx->diis_t3) HIPCK(axpby(1.0, ctx->t3, 0.0, dst + n1 + n2, ctx->ntri * ctx->v3, ctx->s));
+  if (ctx->diis_t3 && ctx->diis_sv > 0)
+    HIPCK(t3_subcube(ctx->t3, dst + n1 + n2, ctx->ntri, ctx->v, ctx->diis_sv, true, ctx->s));
+  else if (ctx->diis_t3)
+    HIPCK(axpby(1.0, ctx->t3, 0.0, dst + n1 + n2, ctx->ntri * ctx->v3, ctx->s));
   return CCT_OK;
 }
 
@@ -1492,8 +1504,9 @@ int diis_dot(cct_ctx* ctx, const double* x, const double* y, double* out_dev) {
   const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
   HIPCK(dot(x, y, n1 + n2, out_dev, ctx->red, ctx->s));
   if (ctx->diis_t3) {
-    HIPCK(weighted_dot_t3(x + n1 + n2, y + n1 + n2, ctx->tri, (int)ctx->ntri, ctx->v3, ctx->v3, out_dev + 1,
-                          ctx->red, ctx->s));
+    const long long bs = diis_block(ctx);
+    HIPCK(weighted_dot_t3(x + n1 + n2, y + n1 + n2, ctx->tri, (int)ctx->ntri, bs, bs, out_dev + 1, ctx->red,
+                          ctx->s));
   } else {
     HIPCK(fill(out_dev + 1, 0.0, 1, ctx->s));
   }
@@ -1581,16 +1594,22 @@ int diis_step(cct_ctx* ctx) {
       order.erase(order.begin());
       continue;
     }
-    // T = sum_m c_m vec_m
+    // T = sum_m c_m vec_m.  With a T3 subspace the extrapolated sub-cubes are
+    // summed in the (no longer needed) pre-step copy and written back; T3
+    // outside the subspace keeps its Jacobi step.
     double* t1 = ctx->t1;
     double* t2 = ctx->t2;
+    const bool sub = ctx->diis_t3 && ctx->diis_sv > 0;
+    double* t3_acc = sub ? ctx->diis_old + n1 + n2 : ctx->t3;
+    const long long n3 = ctx->ntri * diis_block(ctx);
     for (int a = 0; a < m; ++a) {
       const double* vp = ctx->dvec[order[a]];
       const double b = a == 0 ? 0.0 : 1.0;
       HIPCK(axpby(x[a], vp, b, t1, n1, ctx->s));
       HIPCK(axpby(x[a], vp + n1, b, t2, n2, ctx->s));
-      if (ctx->diis_t3) HIPCK(axpby(x[a], vp + n1 + n2, b, ctx->t3, ctx->ntri * ctx->v3, ctx->s));
+      if (ctx->diis_t3) HIPCK(axpby(x[a], vp + n1 + n2, b, t3_acc, n3, ctx->s));
     }
+    if (sub) HIPCK(t3_subcube(ctx->t3, t3_acc, ctx->ntri, ctx->v, ctx->diis_sv, false, ctx->s));
     return CCT_OK;
   }
 }
@@ -1881,6 +1900,13 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (json_find(js, "diis_t3", val)) {
       if (val == "none") ctx->diis_t3 = false;
       else if (val == "full") ctx->diis_t3 = true;
+      else if (val.rfind("subspace:", 0) == 0 && val.size() > 9 &&
+               val.find_first_not_of("0123456789", 9) == std::string::npos && val.size() < 15 &&
+               std::atoi(val.c_str() + 9) >= 1 && std::atoi(val.c_str() + 9) <= nvir) {
+        ctx->diis_t3 = true;
+        ctx->diis_sv = std::atoi(val.c_str() + 9);
+        if (ctx->diis_sv == nvir) ctx->diis_sv = 0;  // the whole block: plain T3 DIIS
+      }
       else { delete ctx; return CCT_EINVAL; }
     }
     if (json_find(js, "diis", val)) ctx->diis_on = (val != "false" && val != "0" && val != "off");
@@ -1903,7 +1929,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   fixed += v * v + o * o + 2LL * o * o * o * o + 4 * o2v2 + 2 * (long long)v * v * v * o + (long long)v * o * o * o;
   fixed += (long long)v * v * v * v + o2v2 + ov;
   const int M = ctx->diis_on ? ctx->diis_space : 0;
-  const long long dlen = ov + o2v2 + (ctx->diis_t3 ? t3n : 0);
+  const long long dlen = ov + o2v2 + ctx->ntri * diis_block(ctx);
   fixed += (long long)(2 * M + 1) * dlen;
   // workspace: enough for every job in one batch (two unpacked/contracted
   // slabs per slot, o^2 slots for the rings), capped by the option

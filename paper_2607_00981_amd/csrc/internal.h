@@ -181,6 +181,9 @@ hipError_t reduce_sum(const double* x, long long n, double* out, double* scratch
 hipError_t dot(const double* x, const double* y, long long n, double* out, double* scratch, hipStream_t s);
 hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, int ntri, long long bs, long long v3,
                            double* out, double* scratch, hipStream_t s);
+// Low-energy virtual sub-cube of every packed block (a, b, c < sv):
+// gather: sub[t][a][b][c] = T[t][a][b][c]; otherwise the reverse copy.
+hipError_t t3_subcube(double* T, double* sub, long long ntri, int v, int sv, bool gather, hipStream_t s);
 // y = a*x + b*y (elementwise, n elements)
 hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s);
 hipError_t fill(double* y, double val, long long n, hipStream_t s);

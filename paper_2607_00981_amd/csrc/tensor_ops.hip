@@ -573,6 +573,31 @@ hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, in
   return hipGetLastError();
 }
 
+namespace {
+__global__ void t3_subcube_kernel(double* __restrict__ T, double* __restrict__ sub, int v, int sv, long long total,
+                                  bool gather) {
+  const long long s3 = (long long)sv * sv * sv, v2 = (long long)v * v, v3 = v2 * v;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long t = i / s3;
+    const long long r = i - t * s3;
+    const int a = (int)(r / ((long long)sv * sv)), b = (int)((r / sv) % sv), c = (int)(r % sv);
+    const long long off = t * v3 + a * v2 + (long long)b * v + c;
+    if (gather) sub[i] = T[off];
+    else T[off] = sub[i];
+  }
+}
+}  // namespace
+
+hipError_t t3_subcube(double* T, double* sub, long long ntri, int v, int sv, bool gather, hipStream_t s) {
+  const long long total = ntri * (long long)sv * sv * sv;
+  if (total <= 0) return hipSuccess;
+  if (sv > v) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(t3_subcube_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, T, sub, v, sv, total,
+                     gather);
+  return hipGetLastError();
+}
+
 hipError_t axpby(double a, const double* x, double b, double* y, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n, TPB * 4)), dim3(TPB), 0, s, a, x, b, y, n);
