@@ -96,7 +96,8 @@ typedef void (*cct_free_fn)(void* ptr, void* user);
  * DIIS": with "subspace:<nv>" only the T3 components whose three virtual
  * indices are among the first nv enter the DIIS overlaps and are
  * extrapolated, the rest of T3 keeps its Jacobi step; "none" leaves T3 out),
- * "diis" (true/false, default true),
+ * "diis" (true/false, default true), "tol" (> 0: default threshold of
+ * cct_solve, 1e-8),
  * "workspace_gb" (cap on the scratch buffer; default: enough for every
  * unpacked slab in one batch, limited by free device memory), "timers"
  * (true: per-phase device times for cct_get_counters), "ladder_split"
@@ -143,8 +144,9 @@ int cct_copy_r3(cct_ctx* ctx, int64_t first, int64_t count, double* out);
 int cct_update(cct_ctx* ctx, double* e_corr, double norms[3]);
 /* Correlation energy of the current amplitudes with the bare integrals. */
 int cct_energy(cct_ctx* ctx, double* e_corr);
-/* Iterate until sqrt(|R1|^2 + |R2|^2 + |R3|^2) < tol or max_iter.  Returns
- * CCT_ENOTCONV (with the last energy and count filled in) if not converged. */
+/* Iterate until sqrt(|R1|^2 + |R2|^2 + |R3|^2) < tol or max_iter; tol <= 0
+ * takes the context's option "tol" (default 1e-8).  Returns CCT_ENOTCONV
+ * (with the last energy and count filled in) if not converged. */
 int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters);
 
 /* Algorithmic multiply-add counts of the last residual per R3 term group

@@ -218,10 +218,12 @@ class Engine:
         self._check(self.lib.cct_energy(self.h, C.byref(e)))
         return e.value
 
-    def solve(self, max_iter=100, tol=1e-8):
+    def solve(self, max_iter=100, tol=None):
+        """Iterate to sqrt(sum |R|^2) < tol (None: the context's "tol" option);
+        returns (energy, iterations, converged)."""
         e = C.c_double()
         it = C.c_int()
-        rc = self._check(self.lib.cct_solve(self.h, max_iter, tol, C.byref(e), C.byref(it)),
+        rc = self._check(self.lib.cct_solve(self.h, max_iter, 0.0 if tol is None else tol, C.byref(e), C.byref(it)),
                          ok=(CCT_OK, CCT_ENOTCONV))
         return e.value, it.value, rc == CCT_OK
 

@@ -68,6 +68,7 @@ struct cct_ctx {
   int diis_space = 8, diis_start = 2;
   bool diis_on = true, diis_t3 = true;
   int diis_sv = 0;  // T3 in DIIS: the sub-cube a, b, c < diis_sv of every block (0: all of T3)
+  double tol = 1e-8;  // default convergence threshold of cct_solve
   double ws_gb = 0.0;  // 0: size the workspace from free device memory
   int tune_ladder = 0, tune_rings = 0;  // GEMM tile variants chosen by cct_autotune (0 = size-based default)
   std::string err;
@@ -1913,6 +1914,10 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (json_find(js, "workspace_gb", val)) ctx->ws_gb = std::atof(val.c_str());
     if (json_find(js, "timers", val)) ctx->events = (val == "true" || val == "1");
     if (json_find(js, "ladder_split", val)) ctx->ladder_split = (val == "true" || val == "1");
+    if (json_find(js, "tol", val)) {
+      ctx->tol = std::atof(val.c_str());
+      if (!(ctx->tol > 0)) { delete ctx; return CCT_EINVAL; }
+    }
     if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb < 0) {
       delete ctx;
       return CCT_EINVAL;
@@ -2127,7 +2132,8 @@ int cct_energy(cct_ctx* ctx, double* e_corr) {
 }
 
 int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters) {
-  if (!ctx || max_iter < 1 || !(tol > 0)) return CCT_EINVAL;
+  if (!ctx || max_iter < 1 || std::isnan(tol)) return CCT_EINVAL;
+  if (!(tol > 0)) tol = ctx->tol;  // the context's default (option "tol")
   double e = 0.0, nr[3] = {0, 0, 0};
   for (int it = 1; it <= max_iter; ++it) {
     RCK(update(ctx, &e, nr));
@@ -2275,7 +2281,7 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
     std::string js(opts_json), val;
     if (json_find(js, "streams", val)) nstreams = std::atoi(val.c_str());
     if (json_find(js, "graph", val)) use_graph = (val == "true" || val == "1");
-    for (const char* key : {"diis_space", "diis_start", "diis", "workspace_gb", "ladder_split"})
+    for (const char* key : {"diis_space", "diis_start", "diis", "workspace_gb", "ladder_split", "tol"})
       if (json_find(js, key, val)) sys_opts += std::string(", \"") + key + "\": " + val;
     if (json_find(js, "diis_t3", val)) sys_opts += ", \"diis_t3\": \"" + val + "\"";
   }

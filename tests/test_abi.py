@@ -59,6 +59,11 @@ def test_create_rejects_bad_arguments():
     assert lib.cct_create(2, 10, 10, 7, None, None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
     assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "bogus"}', None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
     assert lib.cct_create(2, 10, 10, 0, None, None, None, None, None, None) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, b'{"tol": -1}', None, None, None, None, C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "subspace:11"}', None, None, None, None,
+                          C.byref(h)) == binding.CCT_EINVAL
+    assert lib.cct_create(2, 10, 10, 0, b'{"diis_t3": "subspace:0"}', None, None, None, None,
+                          C.byref(h)) == binding.CCT_EINVAL
     lib.cct_destroy(None)
 
 

@@ -339,3 +339,22 @@ def test_twenty_iterations_partial_t3_diis(mode):
     assert np.max(np.abs(np.array(got[mode]) - np.array(ref))) < 1e-10
     assert np.abs(g3 - R.pack_t3(t3)).max() < 1e-9
     assert np.max(np.abs(np.array(got[mode]) - np.array(got["full"]))) > 1e-12
+
+
+def test_solve_takes_the_tol_option():
+    """cct_solve with tol <= 0 stops at the context's "tol" option; a tighter
+    explicit threshold needs more iterations and lands on the oracle's
+    converged energy."""
+    o, v, seed = 2, 8, 61
+    s = ci.make_system(o, v, 2 * (o + v), seed, sigma=0.1)
+    f, B = s["f"], s["B"]
+    say("[solve tol]")
+    with _engine(o, v, B.shape[0], f, B, opts={"tol": 1e-5}) as eng:
+        eng.init_mp2()
+        e1, it1, ok1 = eng.solve(200)
+    with _engine(o, v, B.shape[0], f, B) as eng:
+        eng.init_mp2()
+        e2, it2, ok2 = eng.solve(200, tol=1e-11)
+    assert ok1 and ok2 and it2 > it1
+    eref, *_, conv = R.solve(f, R.eri_phys_from_B(B), o, tol=1e-11, max_iter=200)
+    assert conv and abs(e2 - eref) < 1e-10
