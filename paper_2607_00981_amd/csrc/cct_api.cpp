@@ -382,7 +382,7 @@ int build_plans(cct_ctx* ctx) {
   for (int kind = 0; kind < 3; ++kind) {
     Job& J = ctx->ring[kind];
     J.nslot_total = (int)J.slots.size();
-    J.per_batch = slots_per_batch(budget, 2 * ov3, J.nslot_total);
+    J.per_batch = slots_per_batch(budget, 2 * ov3 + 8 * v2, J.nslot_total);  // U rows padded by <= 8
     const double cf = ring_coef[kind];
     RCK(build_job(ctx, J, ov3, [&](int t) {
       std::vector<Contrib> cs;
@@ -1167,31 +1167,33 @@ int r3_f1(cct_ctx* ctx) {
 // belongs to with the right virtual permutation and coefficient.
 int r3_rings(cct_ctx* ctx, int kind) {
   const int o = ctx->o, v = ctx->v;
-  const long long v2 = (long long)v * v, v3 = ctx->v3, ov3 = o * v3;
+  const long long v2 = (long long)v * v;
   const long long ov = (long long)o * v;
   Arena& ws = ctx->ws;
-  const bool f64 = ctx->prec == Prec::F64;
-  const bool nt = f64 && !(ov & 1);
-  const bool lp = !f64;
+  const bool lp = ctx->prec != Prec::F64;
+  // K = (l,d) padded with zeros to the vector width of the working precision,
+  // so that every shape runs on the K-contiguous kernels
+  const long long kp = round_up(ov, lp ? (ctx->prec == Prec::F32 ? 4 : 8) : 2);
+  const int fmt = lp ? lp_fmt(ctx->prec) : OUT_F64;
   // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
   const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
   const size_t mk0 = ws.mark();
-  void* Al = nullptr;
-  if (lp) {
-    Al = alloc_lp(ws, ov * ov);
-    if (!Al) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
-    HIPCK(convert(Aw, OutSpec{Al, lp_fmt(ctx->prec), ov * ov}, ov * ov, ctx->s));
-  }
+  void* Ap = lp ? alloc_lp(ws, ov * kp) : (void*)ws.alloc((size_t)(ov * kp));
+  if (!Ap) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
+  HIPCK(copy_pad_rows(Aw, ov, ov, OutSpec{Ap, fmt, ov * kp}, kp, ctx->s));
   for (const Batch& b : ctx->ring[kind].batches) {
     const size_t mk = ws.mark();
-    void* U = lp ? alloc_lp(ws, b.nslots * ov3) : (void*)ws.alloc((size_t)(b.nslots * ov3));
-    double* Z = ws.alloc((size_t)(b.nslots * ov3));
+    const long long ulen = b.nslots * v2 * kp;
+    void* U = lp ? alloc_lp(ws, ulen) : (void*)ws.alloc((size_t)ulen);
+    double* Z = ws.alloc((size_t)(b.nslots * ov * v2));
     if (!U || !Z) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
+    const OutSpec uo{U, fmt, ulen};
+    if (kp != ov) HIPCK(zero_cols(uo, b.nslots * v2, kp, ov, ctx->s));
     UnpackArgs ua{};
     ua.o = o; ua.v = v; ua.nslots = b.nslots; ua.nfree = 1;
-    // U[s][(y,z)][(l,d)]: (x, y, z) of the unpack are (d, y, z); d runs fastest
-    ua.s_slot = ov3; ua.s_free[0] = v; ua.s_free[1] = 0;
-    ua.s_x = 1; ua.s_y = ov * v; ua.s_z = ov; ua.fast = 2;
+    // U[s][(y,z)][(l,d)] (rows of kp): (x, y, z) of the unpack are (d, y, z); d runs fastest
+    ua.s_slot = v2 * kp; ua.s_free[0] = v; ua.s_free[1] = 0;
+    ua.s_x = 1; ua.s_y = kp * v; ua.s_z = kp; ua.fast = 2;
     if (kind == 0) {
       const int occ[3] = {2, 0, 1};  // S1 t~_{l q r}^{d y z}
       set_s1(ua, occ);
@@ -1203,39 +1205,30 @@ int r3_rings(cct_ctx* ctx, int kind) {
       const int occ[3] = {0, 2, 1};  // t_{q l r}^{d x z}
       set_ident(ua, occ);
     }
-    const OutSpec uo{U, lp ? lp_fmt(ctx->prec) : OUT_F64, b.nslots * ov3};
     HIPCK(unpack_t3_fmt(ctx->t3, ctx->tbl, b.d_slots, uo, ua, ctx->s));
+    // Z[s][(p,x)][(y,z)] = sum_(l,d) A[(p,x)][(l,d)] U[s][(y,z)][(l,d)]
     if (lp) {
       NtLpArgs g{};
-      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
-      g.A = Al; g.lda = ov; g.a_batch = 0; g.a_plane = ov * ov;
-      g.B = U; g.ldb = ov; g.b_batch = ov3; g.b_plane = b.nslots * ov3;
-      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = b.nslots;
+      g.A = Ap; g.lda = kp; g.a_batch = 0; g.a_plane = ov * kp;
+      g.B = U; g.ldb = kp; g.b_batch = v2 * kp; g.b_plane = ulen;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      g.a_len = ov * kp; g.b_len = ulen; g.c_len = b.nslots * ov * v2;
       g.variant = ctx->tune_rings;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
-    } else if (nt) {
+    } else {
       NtArgs g{};
-      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
-      g.A = Aw; g.lda = ov; g.a_batch = 0;
-      g.B = (const double*)U; g.ldb = ov; g.b_batch = ov3;
-      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = b.nslots;
+      g.A = (const double*)Ap; g.lda = kp; g.a_batch = 0;
+      g.B = (const double*)U; g.ldb = kp; g.b_batch = v2 * kp;
+      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
+      g.a_len = ov * kp; g.b_len = ulen; g.c_len = b.nslots * ov * v2;
       g.variant = ctx->tune_rings;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
-    } else {
-      GemmArgs g{};
-      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = b.nslots;
-      g.A = Aw; g.am = idx1(ov); g.ak = idx1(1); g.a_batch = 0;
-      g.B = (const double*)U; g.bk = idx1(1); g.bn = idx1(ov); g.b_batch = ov3;
-      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3;
-      g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * ov; g.b_len = b.nslots * ov3; g.c_len = b.nslots * ov3;
-      HIPCK(gemm(g, Prec::F64, ctx->s));
     }
-    HIPCK(fold_r3(ctx->r3, v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    HIPCK(fold_r3(ctx->r3, ctx->v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }
   ws.reset(mk0);
@@ -1792,40 +1785,41 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     }
     ws.reset(mk);
   }
-  // ---- rings: one batch of occupied pairs with the planned batch size (at most 8)
-  const bool ring_lp = !f64, ring_nt = f64 && !(ov & 1);
-  if ((ring_lp || ring_nt) && !ctx->ring[0].batches.empty()) {
+  // ---- rings: one batch of occupied pairs with the planned batch size (at
+  // most 8), in the padded shape the ring contraction uses
+  if (!ctx->ring[0].batches.empty()) {
+    const bool ring_lp = !f64;
+    const long long kp = round_up(ov, ring_lp ? (ctx->prec == Prec::F32 ? 4 : 8) : 2);
+    const int fmt = ring_lp ? lp_fmt(ctx->prec) : OUT_F64;
     const int S = std::min(8, ctx->ring[0].per_batch);
+    const long long ulen = S * v2 * kp;
     const size_t mk = ws.mark();
     double* Z = ws.alloc((size_t)(S * ov3));
-    void* U = ring_lp ? alloc_lp(ws, S * ov3) : (void*)ws.alloc((size_t)(S * ov3));
-    void* Al = ring_lp ? alloc_lp(ws, ov * ov) : nullptr;
-    if (!Z || !U || (ring_lp && !Al)) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
-    if (ring_lp) {
-      const int fmt = lp_fmt(ctx->prec);
-      HIPCK(convert(ctx->t3, OutSpec{U, fmt, S * ov3}, std::min<long long>(S * ov3, ctx->ntri * ctx->v3), ctx->s));
-      HIPCK(convert(ctx->Wb1, OutSpec{Al, fmt, ov * ov}, ov * ov, ctx->s));
-    } else {
-      HIPCK(fill((double*)U, 0.01, S * ov3, ctx->s));
-    }
+    void* U = ring_lp ? alloc_lp(ws, ulen) : (void*)ws.alloc((size_t)ulen);
+    void* Al = ring_lp ? alloc_lp(ws, ov * kp) : (void*)ws.alloc((size_t)(ov * kp));
+    if (!Z || !U || !Al) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
+    // operand values only matter for timing: T3 data (in bounds of both), the ring matrix padded
+    if (ring_lp) HIPCK(convert(ctx->t3, OutSpec{U, fmt, ulen}, std::min<long long>(ulen, ctx->ntri * ctx->v3), ctx->s));
+    else HIPCK(fill((double*)U, 0.01, ulen, ctx->s));
+    HIPCK(copy_pad_rows(ctx->Wb1, ov, ov, OutSpec{Al, fmt, ov * kp}, kp, ctx->s));
     const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{1, 2, 3, 4}
                                         : (ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3});
     ctx->tune_rings = pick(ring_cands, [&](int var) {
       if (ring_lp) {
         NtLpArgs g{};
-        g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = S;
-        g.A = Al; g.lda = ov; g.a_batch = 0; g.a_plane = ov * ov;
-        g.B = U; g.ldb = ov; g.b_batch = ov3; g.b_plane = S * ov3;
+        g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = S;
+        g.A = Al; g.lda = kp; g.a_batch = 0; g.a_plane = ov * kp;
+        g.B = U; g.ldb = kp; g.b_batch = v2 * kp; g.b_plane = ulen;
         g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3; g.alpha = 1.0; g.beta = 0.0;
-        g.a_len = ov * ov; g.b_len = S * ov3; g.c_len = S * ov3; g.variant = var;
+        g.a_len = ov * kp; g.b_len = ulen; g.c_len = S * ov3; g.variant = var;
         return gemm_nt_lp(g, ctx->prec, ctx->s);
       }
       NtArgs g{};
-      g.M = (int)ov; g.N = (int)v2; g.K = (int)ov; g.batch = S;
-      g.A = ctx->Wb1; g.lda = ov; g.a_batch = 0;
-      g.B = (const double*)U; g.ldb = ov; g.b_batch = ov3;
+      g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = S;
+      g.A = (const double*)Al; g.lda = kp; g.a_batch = 0;
+      g.B = (const double*)U; g.ldb = kp; g.b_batch = v2 * kp;
       g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3; g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * ov; g.b_len = S * ov3; g.c_len = S * ov3; g.variant = var;
+      g.a_len = ov * kp; g.b_len = ulen; g.c_len = S * ov3; g.variant = var;
       return gemm_nt(g, Prec::F64, ctx->s);
     });
     ws.reset(mk);

@@ -181,6 +181,12 @@ hipError_t reduce_sum(const double* x, long long n, double* out, double* scratch
 hipError_t dot(const double* x, const double* y, long long n, double* out, double* scratch, hipStream_t s);
 hipError_t weighted_dot_t3(const double* x, const double* y, const int4* tri, int ntri, long long bs, long long v3,
                            double* out, double* scratch, hipStream_t s);
+// out[r][c] = in[r*cols + c] for c < cols, 0 for cols <= c < ld_out, in the
+// output's format (rows padded with zeros to a vector-load multiple).
+hipError_t copy_pad_rows(const double* in, long long rows, long long cols, OutSpec out, long long ld_out,
+                         hipStream_t s);
+// out[r*ld + c] = 0 for c0 <= c < ld, every row r < rows (the padding columns).
+hipError_t zero_cols(OutSpec out, long long rows, long long ld, long long c0, hipStream_t s);
 // Low-energy virtual sub-cube of every packed block (a, b, c < sv):
 // gather: sub[t][a][b][c] = T[t][a][b][c]; otherwise the reverse copy.
 hipError_t t3_subcube(double* T, double* sub, long long ntri, int v, int sv, bool gather, hipStream_t s);

@@ -589,6 +589,42 @@ __global__ void t3_subcube_kernel(double* __restrict__ T, double* __restrict__ s
 }
 }  // namespace
 
+namespace {
+__global__ void copy_pad_rows_kernel(const double* __restrict__ in, long long rows, long long cols, OutSpec out,
+                                     long long ld, long long total) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / ld, c = i - r * ld;
+    put_out(out, i, c < cols ? in[r * cols + c] : 0.0);
+  }
+}
+__global__ void zero_cols_kernel(OutSpec out, long long ld, long long c0, long long total) {
+  const long long w = ld - c0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / w;
+    put_out(out, r * ld + c0 + (i - r * w), 0.0);
+  }
+}
+}  // namespace
+
+hipError_t copy_pad_rows(const double* in, long long rows, long long cols, OutSpec out, long long ld_out,
+                         hipStream_t s) {
+  const long long total = rows * ld_out;
+  if (total <= 0) return hipSuccess;
+  if (ld_out < cols) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_pad_rows_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, in, rows, cols, out,
+                     ld_out, total);
+  return hipGetLastError();
+}
+
+hipError_t zero_cols(OutSpec out, long long rows, long long ld, long long c0, hipStream_t s) {
+  const long long total = rows * (ld - c0);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_cols_kernel, dim3(blocks_for(total, TPB * 4)), dim3(TPB), 0, s, out, ld, c0, total);
+  return hipGetLastError();
+}
+
 hipError_t t3_subcube(double* T, double* sub, long long ntri, int v, int sv, bool gather, hipStream_t s) {
   const long long total = ntri * (long long)sv * sv * sv;
   if (total <= 0) return hipSuccess;
