@@ -382,7 +382,10 @@ int build_plans(cct_ctx* ctx) {
   for (int kind = 0; kind < 3; ++kind) {
     Job& J = ctx->ring[kind];
     J.nslot_total = (int)J.slots.size();
-    J.per_batch = slots_per_batch(budget, 2 * ov3 + 8 * v2, J.nslot_total);  // U rows padded by <= 8
+    // per slot: the unpacked operand U (rows padded by <= 8) and the products Z,
+    // each in its working format (FP64; FP32 U and FP64 Z; split-BF16 U and FP32 Z)
+    const long long ring_slot = ctx->prec == Prec::F64 ? 2 * ov3 : (ctx->prec == Prec::F32 ? ov3 + ov3 / 2 : ov3);
+    J.per_batch = slots_per_batch(budget, ring_slot + 8 * v2, J.nslot_total);
     const double cf = ring_coef[kind];
     RCK(build_job(ctx, J, ov3, [&](int t) {
       std::vector<Contrib> cs;
@@ -1185,7 +1188,11 @@ int r3_rings(cct_ctx* ctx, int kind) {
     const size_t mk = ws.mark();
     const long long ulen = b.nslots * v2 * kp;
     void* U = lp ? alloc_lp(ws, ulen) : (void*)ws.alloc((size_t)ulen);
-    double* Z = ws.alloc((size_t)(b.nslots * ov * v2));
+    // contracted blocks: FP32 in the split-BF16 mode (its accumulation is
+    // FP32, so nothing is lost), FP64 otherwise
+    const bool z32 = ctx->prec == Prec::BF16X3;
+    const long long zlen = b.nslots * ov * v2;
+    void* Z = z32 ? alloc_lp(ws, zlen) : (void*)ws.alloc((size_t)zlen);
     if (!U || !Z) { ctx->err = "workspace exhausted (rings)"; return CCT_ENOMEM; }
     const OutSpec uo{U, fmt, ulen};
     if (kp != ov) HIPCK(zero_cols(uo, b.nslots * v2, kp, ov, ctx->s));
@@ -1212,9 +1219,11 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = b.nslots;
       g.A = Ap; g.lda = kp; g.a_batch = 0; g.a_plane = ov * kp;
       g.B = U; g.ldb = kp; g.b_batch = v2 * kp; g.b_plane = ulen;
-      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
+      if (z32) g.C32 = (float*)Z;
+      else g.C = (double*)Z;
+      g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * kp; g.b_len = ulen; g.c_len = b.nslots * ov * v2;
+      g.a_len = ov * kp; g.b_len = ulen; g.c_len = zlen;
       g.variant = ctx->tune_rings;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     } else {
@@ -1222,13 +1231,14 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.M = (int)ov; g.N = (int)v2; g.K = (int)kp; g.batch = b.nslots;
       g.A = (const double*)Ap; g.lda = kp; g.a_batch = 0;
       g.B = (const double*)U; g.ldb = kp; g.b_batch = v2 * kp;
-      g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
+      g.C = (double*)Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov * v2;
       g.alpha = 1.0; g.beta = 0.0;
-      g.a_len = ov * kp; g.b_len = ulen; g.c_len = b.nslots * ov * v2;
+      g.a_len = ov * kp; g.b_len = ulen; g.c_len = zlen;
       g.variant = ctx->tune_rings;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     }
-    HIPCK(fold_r3(ctx->r3, ctx->v3, v, Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    if (z32) HIPCK(fold_r3(ctx->r3, ctx->v3, v, (const float*)Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
+    else HIPCK(fold_r3(ctx->r3, ctx->v3, v, (const double*)Z, b.d_tasks, b.ntasks, b.d_contribs, ctx->s));
     ws.reset(mk);
   }
   ws.reset(mk0);

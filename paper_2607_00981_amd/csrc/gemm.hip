@@ -920,8 +920,12 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
       for (int j = 0; j < TN; ++j) {
         const int n = tn * BN + wn0 + j * 16 + (lane & 15);
         if (n >= g.N) continue;
-        double* p = g.C + mo + map2(g.cn, n);
         const double x = g.alpha * (ACC64 ? out[ACC64 ? i : 0][ACC64 ? j : 0][r] : (double)acc[i][j][r]);
+        if (!ACC64 && g.C32) {
+          g.C32[mo + map2(g.cn, n)] = (float)x;
+          continue;
+        }
+        double* p = g.C + mo + map2(g.cn, n);
         *p = (g.beta == 0.0) ? x : x + g.beta * *p;
       }
     }
@@ -948,6 +952,8 @@ hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (prec == Prec::F64 || g.K <= 0) return hipErrorInvalidValue;
   if (prec == Prec::BF16X3 && (g.a_plane <= 0 || g.b_plane <= 0)) return hipErrorInvalidValue;
+  // FP32 output only where it is exact: FP32 accumulation (split BF16), no read of C
+  if (g.C32 && (prec != Prec::BF16X3 || g.beta != 0.0 || g.alpha != 1.0)) return hipErrorInvalidValue;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;

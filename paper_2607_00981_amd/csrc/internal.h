@@ -147,6 +147,7 @@ struct NtLpArgs {
   double alpha, beta;
   long long a_len, b_len, c_len;
   int variant;  // tile variant (0 = size-based default)
+  float* C32;   // split BF16 only: FP32 output here instead of C (exact: the accumulation is FP32; beta 0)
 };
 hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s);
 
@@ -160,6 +161,9 @@ struct FoldTask {
   int t, nc, c0, pad;
 };
 hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTask* tasks, int ntasks,
+                   const FoldContrib* contribs, hipStream_t s);
+// The same with FP32 contracted blocks (accumulated into FP64 R3).
+hipError_t fold_r3(double* R, long long bs, int v, const float* Z, const FoldTask* tasks, int ntasks,
                    const FoldContrib* contribs, hipStream_t s);
 
 // R3 post-processing, norms and Jacobi update on packed blocks.

@@ -163,8 +163,9 @@ __global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restr
 // LDS, each contribution is added with the threads running along the axis
 // that is unit-stride in Z for that contribution (coalesced reads for any
 // virtual permutation), and the tile is written back along c.
+template <typename ZT>
 __global__ __launch_bounds__(256) void fold_tiled_kernel(double* __restrict__ R, long long bs, int v,
-                                                         const double* __restrict__ Z,
+                                                         const ZT* __restrict__ Z,
                                                          const FoldTask* __restrict__ tasks,
                                                          const FoldContrib* __restrict__ contribs, int nt) {
   __shared__ double L[UT * UP_X];
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void fold_tiled_kernel(double* __restrict__ R,
       const int a = base[0] + cc[0], b = base[1] + cc[1], c = base[2] + cc[2];
       const bool ok = a < v && b < v && c < v;
       lds[it] = ok ? cc[0] * UP_X + cc[1] * UP_Z + cc[2] : -1;
-      vals[it] = ok ? Z[fc.base + a * st[0] + b * st[1] + c * st[2]] : 0.0;
+      vals[it] = ok ? (double)Z[fc.base + a * st[0] + b * st[1] + c * st[2]] : 0.0;
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it)
@@ -536,7 +537,17 @@ hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTa
   if (ntasks > 65535) return hipErrorInvalidValue;
   const int nt = (v + UT - 1) / UT;
   dim3 grid((unsigned)(nt * nt * nt), (unsigned)ntasks);
-  hipLaunchKernelGGL(fold_tiled_kernel, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
+  hipLaunchKernelGGL(fold_tiled_kernel<double>, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
+  return hipGetLastError();
+}
+
+hipError_t fold_r3(double* R, long long bs, int v, const float* Z, const FoldTask* tasks, int ntasks,
+                   const FoldContrib* contribs, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (ntasks > 65535) return hipErrorInvalidValue;
+  const int nt = (v + UT - 1) / UT;
+  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ntasks);
+  hipLaunchKernelGGL(fold_tiled_kernel<float>, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
   return hipGetLastError();
 }
 

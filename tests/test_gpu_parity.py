@@ -358,3 +358,23 @@ def test_solve_takes_the_tol_option():
     assert ok1 and ok2 and it2 > it1
     eref, *_, conv = R.solve(f, R.eri_phys_from_B(B), o, tol=1e-11, max_iter=200)
     assert conv and abs(e2 - eref) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("o,v", [(1, 1), (2, 1), (1, 2), (3, 2), (2, 3)])
+def test_degenerate_shapes_match_oracle(prec, o, v):
+    """Smallest shapes: a single virtual (no virtual pairs off the diagonal,
+    the ladder falls back to the direct form), a single occupied (one packed
+    block, i=j=k), two virtuals (one pair tile, K padded far beyond v(v+1)/2)."""
+    seed = 70 + 10 * o + v
+    say(f"[degenerate] prec={prec} o={o} v={v}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
+    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, _ = eng.residual()
+    rel = 1e-11 if prec == "fp64" else MIXED_TOL[prec]
+    for name, a, b, r in (("R1", g1, e1, 1e-11), ("R2", g2, e2, 1e-11), ("R3", g3, e3, rel)):
+        ok, err, scale = _close(a, b, r)
+        assert ok, f"{prec} o={o} v={v} {name}: max err {err:.3e} (scale {scale:.3e})"
