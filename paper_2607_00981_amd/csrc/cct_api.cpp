@@ -9,9 +9,11 @@
 //   4. T3 feedback into R1, R2, W^{ab}_{dj}, W^{al}_{ij} from unpacked,
 //      spin-summed T3 slabs.
 //   5. R3 on packed i<=j<=k blocks: particle-particle ladder by direct
-//      traversal (three relabelled GEMMs over all stored blocks), Fock terms,
-//      hole ladder (+F_oo), the three ring types and the two T2*W drivers by
-//      tile unpacking -> GEMM -> output-stationary fold.
+//      traversal (each of the three relabelled terms split into symmetric
+//      and antisymmetric halves over the virtual pairs, two GEMMs over all
+//      stored blocks), Fock terms, hole ladder (+F_oo), the three ring types
+//      and the two T2*W drivers by tile unpacking -> GEMM -> output-stationary
+//      fold.
 //   6. R3 post-processing fused with the norm and the Jacobi update.
 #include "../../include/cct.h"
 

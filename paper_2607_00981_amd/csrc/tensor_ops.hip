@@ -698,7 +698,8 @@ hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric / antisymmetric pair split of the ladder (see ladder_pair_split)
+// Symmetric / antisymmetric pair split of the ladder operands and the
+// rebuild of both output orders (the split ladder of r3_pp_split)
 // ---------------------------------------------------------------------------
 namespace {
 
