@@ -45,6 +45,10 @@ struct cct_slab {
   double* t3 = nullptr;    // [count][v^3]
   double* r3 = nullptr;    // [count][v^3]
   void* views = nullptr;   // relabelled copies of the slab's T3 (see slab_pp)
+  void* BvvL = nullptr;    // mixed modes: BvvT, t2T, VoT in the working precision with
+  void* t2L = nullptr;     // their K (naux, o^2) padded with zeros to the vector width
+  void* VoL = nullptr;     // (ka, ko elements per row), the operands of the panel rebuild
+  long long ka = 0, ko = 0;
   double* Wp = nullptr;    // FP64 panel [panel][v][v][v]
   void* Wl = nullptr;      // low-precision panel
   double* eps0 = nullptr;  // zeros (no Jacobi step here)
@@ -181,6 +185,31 @@ int build_views(cct_slab* sl) {
 int build_panel(cct_slab* sl, int a0, int na) {
   const int o = sl->o, v = sl->v, naux = sl->naux;
   const long long v2 = (long long)v * v, v3 = sl->v3, o2 = (long long)o * o;
+  if (lp_ok(sl)) {
+    // mixed modes: the panel is an operand of the low-precision ladder, so it
+    // is rebuilt from operands in the same precision (FP64 output, converted
+    // with the panel afterwards)
+    const size_t esz = sl->prec == Prec::F32 ? 4 : 2;  // bytes per element of one operand plane
+    const long long ka = sl->ka, ko = sl->ko;
+    NtLpArgs g{};
+    g.M = v; g.N = (int)v2; g.K = (int)ka; g.batch = na;
+    g.A = (const char*)sl->BvvL + (size_t)((long long)a0 * v * ka) * esz; g.lda = ka; g.a_batch = (long long)v * ka;
+    g.a_plane = v2 * ka;
+    g.B = sl->BvvL; g.ldb = ka; g.b_batch = 0; g.b_plane = v2 * ka;
+    g.C = sl->Wp; g.cm = idx1(v); g.cn = idx2(v, v2, 1); g.c_batch = v3;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.a_len = (v2 - (long long)a0 * v) * ka; g.b_len = v2 * ka; g.c_len = (long long)na * v3;
+    SHIP(gemm_nt_lp(g, sl->prec, sl->s));
+    NtLpArgs h{};
+    h.M = (int)((long long)na * v); h.N = (int)v2; h.K = (int)ko; h.batch = 1;
+    h.A = (const char*)sl->t2L + (size_t)((long long)a0 * v * ko) * esz; h.lda = ko; h.a_plane = v2 * ko;
+    h.B = sl->VoL; h.ldb = ko; h.b_plane = v2 * ko;
+    h.C = sl->Wp; h.cm = idx1(v2); h.cn = idx1(1);
+    h.alpha = 1.0; h.beta = 1.0;
+    h.a_len = (v2 - (long long)a0 * v) * ko; h.b_len = v2 * ko; h.c_len = (long long)na * v3;
+    SHIP(gemm_nt_lp(h, sl->prec, sl->s));
+    return CCT_OK;
+  }
   // sum_P B~_{ad} B~_{be}: per a, C[d][(b,e)] = sum_P BvvT[a][d][P] BvvT[(b,e)][P]
   if (naux % 2 == 0) {
     NtArgs g{};
@@ -450,6 +479,14 @@ int cct_slab_create(int nocc, int nvir, int naux, int first, int count, cct_prec
   if (rc == CCT_OK) rc = sallocd(sl, &sl->r3, nb * v3);
   if (rc == CCT_OK) rc = salloc(sl, &sl->views, view_bytes);
   if (rc == CCT_OK) rc = sallocd(sl, &sl->Wp, (long long)sl->panel * v3);
+  if (lp) {
+    const int w = sl->prec == Prec::F32 ? 4 : 8;
+    sl->ka = ((long long)naux + w - 1) / w * w;
+    sl->ko = (o2 + w - 1) / w * w;
+    if (rc == CCT_OK) rc = salloc(sl, &sl->BvvL, (size_t)(v2 * sl->ka) * 4);
+    if (rc == CCT_OK) rc = salloc(sl, &sl->t2L, (size_t)(v2 * sl->ko) * 4);
+    if (rc == CCT_OK) rc = salloc(sl, &sl->VoL, (size_t)(v2 * sl->ko) * 4);
+  }
   if (rc == CCT_OK && lp) rc = salloc(sl, &sl->Wl, (size_t)sl->panel * v3 * 4);
   if (rc == CCT_OK) rc = sallocd(sl, &sl->eps0, n);
   if (rc == CCT_OK) rc = sallocd(sl, &sl->tri, nb);
@@ -519,6 +556,13 @@ int cct_slab_set_intermediates(cct_slab* sl, const double* Bt, const double* t2,
   if (e != hipSuccess) {
     sl->err = std::string("v~^{lm}_{de} build: ") + hipGetErrorString(e);
     return CCT_EDEVICE;
+  }
+  if (lp_ok(sl)) {
+    const int fmt = sl->prec == Prec::F32 ? OUT_F32 : OUT_BF16X2;
+    SHIP(copy_pad_rows(sl->BvvT, v2, naux, OutSpec{sl->BvvL, fmt, v2 * sl->ka}, sl->ka, sl->s));
+    SHIP(copy_pad_rows(sl->t2T, v2, o2, OutSpec{sl->t2L, fmt, v2 * sl->ko}, sl->ko, sl->s));
+    SHIP(copy_pad_rows(sl->VoT, v2, o2, OutSpec{sl->VoL, fmt, v2 * sl->ko}, sl->ko, sl->s));
+    SHIP(hipStreamSynchronize(sl->s));
   }
   sl->have_ims = true;
   return CCT_OK;
