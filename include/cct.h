@@ -53,14 +53,17 @@ enum {
 };
 
 /* Precision of the particle-particle ladder and ring contractions (the
- * dominant O(o^3 v^5) and O(o^4 v^4) terms).  Everything else (T1 dressing,
+ * dominant O(o^3 v^5) and O(o^4 v^4) terms; in a slab also the rebuild of the
+ * ladder's W panels).  Everything else (T1 dressing,
  * RCCSD parts, feedback, drivers, Fock and hole-ladder terms, post-processing,
  * update, DIIS, energy) is FP64 in every mode. */
 typedef enum {
   CCT_FP64 = 0,   /* FP64 MFMA */
-  CCT_FP32 = 1,   /* FP32 operands, FP32 MFMA accumulation, FP64 flush per K block */
-  CCT_BF16X3 = 2  /* split BF16 (hi + lo) operands, three BF16 MFMA products,
-                     FP32 accumulation, FP64 flush per K block */
+  CCT_FP32 = 1,   /* FP32 operands, FP32 MFMA accumulation over 128 products,
+                     FP64 across those */
+  CCT_BF16X3 = 2  /* split BF16 (hi + lo) operands, three BF16 MFMA products
+                     (lo*lo dropped), FP32 accumulation over the whole
+                     contraction, FP64 output */
 } cct_precision;
 
 /* Residual term groups of Eq. resi-rccsdt (bit mask for cct_residual). */
