@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
                                    "design only, sharded by packed triples)"}))
         sys.exit(2)
     if args.calibrate_copy:
