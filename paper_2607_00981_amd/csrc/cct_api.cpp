@@ -953,32 +953,37 @@ int r3_pp_split(cct_ctx* ctx) {
   // W+ / W- rows y <= z from W[(y,z)][(d,e)]; W+ keeps W^{yz}_{dd} once
   HIPCK(pair_split(ctx->Wvvvv, idx1(0), ctx->vpair_src, P, v, v, OutSpec{Wp, fmt, P * pp}, pp,
                    OutSpec{Wm, fmt, P * pq}, pq, 0.5, ctx->s));
-  // chunk of packed blocks: A+/A- (esz), C+/C- (FP64), FP64 relabelled copy for term 0
-  const long long per_block = v * (pp + pq) * esz + 2 * v * P * 8 + v3 * 8;
+  // products: FP32 in the split-BF16 mode (exact for its FP32 accumulation), else FP64
+  const bool z32 = ctx->prec == Prec::BF16X3;
+  const long long csz = z32 ? 4 : 8;
+  // chunk of packed blocks: A+/A- (esz), C+/C- (csz), FP64 relabelled copy for term 0
+  const long long per_block = v * (pp + pq) * esz + 2 * v * P * csz + v3 * 8;
   long long chunk = (long long)(ws.available() / (size_t)per_block) - 1;
   if (chunk < 1) { ctx->err = "workspace exhausted (ladder split)"; return CCT_ENOMEM; }
   if (chunk > nt) chunk = nt;
   void* Ap = alloc_b(chunk * v * pp * esz);
   void* Am = alloc_b(chunk * v * pq * esz);
-  double* Cp = ws.alloc((size_t)(chunk * v * P));
-  double* Cm = ws.alloc((size_t)(chunk * v * P));
+  void* Cp = alloc_b(chunk * v * P * csz);
+  void* Cm = alloc_b(chunk * v * P * csz);
   double* Tc = ws.alloc((size_t)(chunk * v3));
   if (!Ap || !Am || !Cp || !Cm || !Tc) { ctx->err = "workspace exhausted (ladder split)"; return CCT_ENOMEM; }
   auto gemm_pair = [&](int M, int N, long long K, const void* A, long long lda, long long a_len, long long a_plane,
-                       const void* B, long long ldb, long long b_len, long long b_plane, double* C, long long c_len,
+                       const void* B, long long ldb, long long b_len, long long b_plane, void* C, long long c_len,
                        Idx2 cm) -> int {
     if (f64) {
       NtArgs g{};
       g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
       g.A = (const double*)A; g.lda = lda; g.B = (const double*)B; g.ldb = ldb;
-      g.C = C; g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+      g.C = (double*)C; g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
       g.a_len = a_len; g.b_len = b_len; g.c_len = c_len; g.variant = ctx->tune_ladder;
       HIPCK(gemm_nt(g, Prec::F64, ctx->s));
     } else {
       NtLpArgs g{};
       g.M = M; g.N = N; g.K = (int)K; g.batch = 1;
       g.A = A; g.lda = lda; g.a_plane = a_plane; g.B = B; g.ldb = ldb; g.b_plane = b_plane;
-      g.C = C; g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
+      if (z32) g.C32 = (float*)C;
+      else g.C = (double*)C;
+      g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
       g.a_len = a_len; g.b_len = b_len; g.c_len = c_len; g.variant = ctx->tune_ladder;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     }
@@ -1005,8 +1010,10 @@ int r3_pp_split(cct_ctx* ctx) {
         RCK(gemm_pair((int)rows, (int)P, pq, Am, pq, rows * pq, rows * pq, Wm, pq, P * pq, P * pq, Cm, rows * P,
                       idx1(P)));
         lad_end(ctx, (double)rows * P * (P + Q), 2);
-        if (term == 2) HIPCK(pair_combine_rows(Cp, Cm, P, P, rows, v, Rc, idx2(v, v3, v2), v, 1, ctx->s));
-        else HIPCK(pair_combine_rows(Cp, Cm, P, P, rows, v, Rc, idx2(v, v3, v), v2, 1, ctx->s));
+        const Idx2 cmap = term == 2 ? idx2(v, v3, v2) : idx2(v, v3, v);
+        const long long sy = term == 2 ? v : v2;
+        if (z32) HIPCK(pair_combine_rows((const float*)Cp, (const float*)Cm, P, P, rows, v, Rc, cmap, sy, 1, ctx->s));
+        else HIPCK(pair_combine_rows((const double*)Cp, (const double*)Cm, P, P, rows, v, Rc, cmap, sy, 1, ctx->s));
       } else {
         // transposed products C+-T[p][(t,x)] so that the output runs along x
         RCK(gemm_pair((int)P, (int)rows, pp, Wp, pp, P * pp, P * pp, Ap, pp, rows * pp, rows * pp, Cp, rows * P,
@@ -1014,7 +1021,12 @@ int r3_pp_split(cct_ctx* ctx) {
         RCK(gemm_pair((int)P, (int)rows, pq, Wm, pq, P * pq, P * pq, Am, pq, rows * pq, rows * pq, Cm, rows * P,
                       idx1(rows)));
         lad_end(ctx, (double)rows * P * (P + Q), 2);
-        HIPCK(pair_combine_cols(Cp, Cm, rows, ctx->vpair_yz, v, Rc, idx2(v, v3, 1), v2, v, ctx->s));
+        if (z32)
+          HIPCK(pair_combine_cols((const float*)Cp, (const float*)Cm, rows, ctx->vpair_yz, v, Rc, idx2(v, v3, 1), v2, v,
+                                  ctx->s));
+        else
+          HIPCK(pair_combine_cols((const double*)Cp, (const double*)Cm, rows, ctx->vpair_yz, v, Rc, idx2(v, v3, 1), v2,
+                                  v, ctx->s));
       }
     }
   }

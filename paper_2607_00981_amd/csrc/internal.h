@@ -214,9 +214,13 @@ hipError_t pair_split(const double* in, Idx2 rmap, const long long* src, long lo
 // C^{yz} = (C+[p(y,z)] + C-[p(y,z)])/2 (y < z), (C+[p(z,y)] - C-[p(z,y)])/2 (y > z), C+[p(y,y)]/2.
 hipError_t pair_combine_rows(const double* Cp, const double* Cm, long long pitch_p, long long pitch_m, long long rows,
                              int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s);
+hipError_t pair_combine_rows(const float* Cp, const float* Cm, long long pitch_p, long long pitch_m, long long rows,
+                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s);
 // The same from transposed products C+T[p][c], C-T[p][c] over ncol columns c, pairs given by yz[p]:
-// R[ccol(c) + y*sy + z*sz] += C^{yz}.
+// R[ccol(c) + y*sy + z*sz] += C^{yz}.  (FP32 products: split-BF16 GEMM outputs.)
 hipError_t pair_combine_cols(const double* CpT, const double* CmT, long long ncol, const int2* yz, int v, double* R,
+                             Idx2 ccol, long long sy, long long sz, hipStream_t s);
+hipError_t pair_combine_cols(const float* CpT, const float* CmT, long long ncol, const int2* yz, int v, double* R,
                              Idx2 ccol, long long sy, long long sz, hipStream_t s);
 // out[r * ld_out + c] = in[rows[r] * ld_in + c] for r < nrows, c < ncols (rows: device array).
 hipError_t gather_rows(const double* in, long long ld_in, const int* rows, int nrows, long long ncols, double* out,

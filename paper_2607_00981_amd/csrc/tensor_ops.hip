@@ -760,26 +760,27 @@ __global__ __launch_bounds__(256) void pair_split_kernel(const double* __restric
 }
 
 // Rows form: C+[r][p], C-[r][q] -> R[cmap(r) + y*sy + z*sz] += C^{yz}
-__global__ __launch_bounds__(256) void pair_combine_rows_kernel(const double* __restrict__ Cp,
-                                                                const double* __restrict__ Cm, long long pitch_p,
+template <typename CT>
+__global__ __launch_bounds__(256) void pair_combine_rows_kernel(const CT* __restrict__ Cp,
+                                                                const CT* __restrict__ Cm, long long pitch_p,
                                                                 long long pitch_m, int v, double* __restrict__ R,
                                                                 Idx2 cmap, long long sy, long long sz, int nt) {
   __shared__ double U[PS][PS + 1];
   const long long r = blockIdx.x;
   double* Rr = R + imap(cmap, r);
-  const double* cp = Cp + r * pitch_p;
-  const double* cq = Cm + r * pitch_m;
+  const CT* cp = Cp + r * pitch_p;
+  const CT* cq = Cm + r * pitch_m;
   int Yt, Zt;
   tile_pair(blockIdx.y, nt, Yt, Zt);
   for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
     const int i = e / PS, j = e % PS;
     const int y = Yt * PS + i, z = Zt * PS + j;
     if (y >= v || z >= v || y > z) continue;
-    const double p = cp[pidx(y, z, v)];
+    const double p = (double)cp[pidx(y, z, v)];
     if (y == z) {
       Rr[y * sy + z * sz] += 0.5 * p;
     } else {
-      const double m = cq[pidx(y, z, v)];
+      const double m = (double)cq[pidx(y, z, v)];
       Rr[y * sy + z * sz] += 0.5 * (p + m);
       U[j][i] = 0.5 * (p - m);  // C^{zy}
     }
@@ -795,8 +796,9 @@ __global__ __launch_bounds__(256) void pair_combine_rows_kernel(const double* __
 
 // Columns form: C+T[p][c], C-T[q][c] (c = column, contiguous) ->
 // R[ccol(c) + y*sy + z*sz] and R[ccol(c) + z*sy + y*sz]
-__global__ __launch_bounds__(256) void pair_combine_cols_kernel(const double* __restrict__ CpT,
-                                                                const double* __restrict__ CmT, long long ncol,
+template <typename CT>
+__global__ __launch_bounds__(256) void pair_combine_cols_kernel(const CT* __restrict__ CpT,
+                                                                const CT* __restrict__ CmT, long long ncol,
                                                                 const int2* __restrict__ yz, int v,
                                                                 double* __restrict__ R, Idx2 ccol, long long sy,
                                                                 long long sz) {
@@ -804,12 +806,12 @@ __global__ __launch_bounds__(256) void pair_combine_cols_kernel(const double* __
   const int2 t = yz[p];
   const int y = t.x, z = t.y;
   for (long long c = (long long)blockIdx.y * blockDim.x + threadIdx.x; c < ncol; c += (long long)gridDim.y * blockDim.x) {
-    const double cp = CpT[p * ncol + c];
+    const double cp = (double)CpT[p * ncol + c];
     double* base = R + imap(ccol, c);
     if (y == z) {
       base[y * sy + z * sz] += 0.5 * cp;
     } else {
-      const double cm = CmT[p * ncol + c];
+      const double cm = (double)CmT[p * ncol + c];
       base[y * sy + z * sz] += 0.5 * (cp + cm);
       base[z * sy + y * sz] += 0.5 * (cp - cm);
     }
@@ -830,26 +832,45 @@ hipError_t pair_split(const double* in, Idx2 rmap, const long long* src, long lo
   return hipGetLastError();
 }
 
-hipError_t pair_combine_rows(const double* Cp, const double* Cm, long long pitch_p, long long pitch_m, long long rows,
-                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
+template <typename CT>
+hipError_t combine_rows_t(const CT* Cp, const CT* Cm, long long pitch_p, long long pitch_m, long long rows, int v,
+                          double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   const int nt = (v + PS - 1) / PS;
   const int npair = nt * (nt + 1) / 2;
   if (rows > INT_MAX || npair > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pair_combine_rows_kernel, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, Cp, Cm, pitch_p,
-                     pitch_m, v, R, cmap, sy, sz, nt);
+  hipLaunchKernelGGL(pair_combine_rows_kernel<CT>, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, Cp, Cm,
+                     pitch_p, pitch_m, v, R, cmap, sy, sz, nt);
   return hipGetLastError();
 }
 
-hipError_t pair_combine_cols(const double* CpT, const double* CmT, long long ncol, const int2* yz, int v, double* R,
-                             Idx2 ccol, long long sy, long long sz, hipStream_t s) {
+template <typename CT>
+hipError_t combine_cols_t(const CT* CpT, const CT* CmT, long long ncol, const int2* yz, int v, double* R, Idx2 ccol,
+                          long long sy, long long sz, hipStream_t s) {
   const long long P = (long long)v * (v + 1) / 2;
   if (ncol <= 0) return hipSuccess;
   if (P > INT_MAX) return hipErrorInvalidValue;
   const unsigned gy = (unsigned)std::min<long long>((ncol + TPB - 1) / TPB, 64);
-  hipLaunchKernelGGL(pair_combine_cols_kernel, dim3((unsigned)P, gy), dim3(TPB), 0, s, CpT, CmT, ncol, yz, v, R, ccol,
-                     sy, sz);
+  hipLaunchKernelGGL(pair_combine_cols_kernel<CT>, dim3((unsigned)P, gy), dim3(TPB), 0, s, CpT, CmT, ncol, yz, v, R,
+                     ccol, sy, sz);
   return hipGetLastError();
+}
+
+hipError_t pair_combine_rows(const double* Cp, const double* Cm, long long pitch_p, long long pitch_m, long long rows,
+                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
+  return combine_rows_t(Cp, Cm, pitch_p, pitch_m, rows, v, R, cmap, sy, sz, s);
+}
+hipError_t pair_combine_rows(const float* Cp, const float* Cm, long long pitch_p, long long pitch_m, long long rows,
+                             int v, double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
+  return combine_rows_t(Cp, Cm, pitch_p, pitch_m, rows, v, R, cmap, sy, sz, s);
+}
+hipError_t pair_combine_cols(const double* CpT, const double* CmT, long long ncol, const int2* yz, int v, double* R,
+                             Idx2 ccol, long long sy, long long sz, hipStream_t s) {
+  return combine_cols_t(CpT, CmT, ncol, yz, v, R, ccol, sy, sz, s);
+}
+hipError_t pair_combine_cols(const float* CpT, const float* CmT, long long ncol, const int2* yz, int v, double* R,
+                             Idx2 ccol, long long sy, long long sz, hipStream_t s) {
+  return combine_cols_t(CpT, CmT, ncol, yz, v, R, ccol, sy, sz, s);
 }
 
 // ---------------------------------------------------------------------------
