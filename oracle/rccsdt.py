@@ -156,20 +156,28 @@ def ccsdt_intermediates(ft, Vt, t2, t3, o, ims):
 R3_TERMS = ("D1", "D2", "F1", "F2", "RA", "RB", "RC", "HH", "PP")
 
 
-def r3_terms(t2, t3, ims, ims3):
-    """The nine terms inside P_{(ia)(jb)(kc)} of Eq. resi-rccsdt, each as a
+_R3_TERM_EXPR = {
+    "D1": lambda t2, t3, ims, ims3: _es("abdj,ikdc->ijkabc", ims3["Wvvvo"], t2),
+    "D2": lambda t2, t3, ims, ims3: -_es("alij,lkbc->ijkabc", ims3["Wvooo"], t2),
+    "F1": lambda t2, t3, ims, ims3: 0.5 * _es("ad,ijkdbc->ijkabc", ims["Fvv"], t3),
+    "F2": lambda t2, t3, ims, ims3: -0.5 * _es("li,ljkabc->ijkabc", ims["Foo"], t3),
+    "RA": lambda t2, t3, ims, ims3: 0.25 * _es("ladi,ljkdbc->ijkabc", ims3["Wbar_ovvo"], chk3_1(t3)),
+    "RB": lambda t2, t3, ims, ims3: -0.5 * _es("laid,jlkdbc->ijkabc", ims3["Wbar_ovov"], t3),
+    "RC": lambda t2, t3, ims, ims3: -_es("lbid,jlkdac->ijkabc", ims3["Wbar_ovov"], t3),
+    "HH": lambda t2, t3, ims, ims3: 0.5 * _es("lmij,lmkabc->ijkabc", ims["Woooo"], t3),
+    "PP": lambda t2, t3, ims, ims3: 0.5 * _es("abde,ijkdec->ijkabc", ims3["Wvvvv"], t3),
+}
+
+
+def r3_term(name, t2, t3, ims, ims3):
+    """One of the nine terms inside P_{(ia)(jb)(kc)} of Eq. resi-rccsdt, as a
     full (o,o,o,v,v,v) tensor before the permutation operator."""
-    out = {}
-    out["D1"] = _es("abdj,ikdc->ijkabc", ims3["Wvvvo"], t2)
-    out["D2"] = -_es("alij,lkbc->ijkabc", ims3["Wvooo"], t2)
-    out["F1"] = 0.5 * _es("ad,ijkdbc->ijkabc", ims["Fvv"], t3)
-    out["F2"] = -0.5 * _es("li,ljkabc->ijkabc", ims["Foo"], t3)
-    out["RA"] = 0.25 * _es("ladi,ljkdbc->ijkabc", ims3["Wbar_ovvo"], chk3_1(t3))
-    out["RB"] = -0.5 * _es("laid,jlkdbc->ijkabc", ims3["Wbar_ovov"], t3)
-    out["RC"] = -_es("lbid,jlkdac->ijkabc", ims3["Wbar_ovov"], t3)
-    out["HH"] = 0.5 * _es("lmij,lmkabc->ijkabc", ims["Woooo"], t3)
-    out["PP"] = 0.5 * _es("abde,ijkdec->ijkabc", ims3["Wvvvv"], t3)
-    return out
+    return _R3_TERM_EXPR[name](t2, t3, ims, ims3)
+
+
+def r3_terms(t2, t3, ims, ims3):
+    """All nine terms (see r3_term), in the order D1 D2 F1 F2 RA RB RC HH PP."""
+    return {name: r3_term(name, t2, t3, ims, ims3) for name in _R3_TERM_EXPR}
 
 
 def residuals(f, V, t1, t2, t3, o, triples=True, terms=None, return_parts=False):
@@ -213,11 +221,16 @@ def residuals(f, V, t1, t2, t3, o, triples=True, terms=None, return_parts=False)
         X2 += _es("bkcd,kijdac->ijab", Vt[Vs, O, Vs, Vs], s1)
         X2 -= _es("kljc,likcab->ijab", Vt[O, O, O, Vs], s1)
         ims3 = ccsdt_intermediates(ft, Vt, t2, t3, o, ims)
-        parts = r3_terms(t2, t3, ims, ims3)
         use = R3_TERMS if terms is None else terms
         X3 = np.zeros((o, o, o, v, v, v))
-        for name in use:
-            X3 += parts[name]
+        if return_parts:
+            parts = r3_terms(t2, t3, ims, ims3)
+            for name in use:
+                X3 += parts[name]
+        else:
+            # one term at a time (same sum, same order; only one term tensor alive)
+            for name in use:
+                X3 += r3_term(name, t2, t3, ims, ims3)
         r3 = perm_sym3(X3)
     r2 = X2 + X2.transpose(1, 0, 3, 2)
     if return_parts:
