@@ -207,8 +207,9 @@ __device__ __forceinline__ void store_c(const GemmArgs& g, int tm, int tn, long 
 // ---------------------------------------------------------------------------
 // FP64 kernel
 // ---------------------------------------------------------------------------
-// kchunk > 0: this workgroup covers K range [blockIdx.y * kchunk, + kchunk) and
-// writes its raw partial sums to part[((b * splits + y) * M + m) * N + n].
+// kchunk > 0: this workgroup covers K range [blockIdx.y * kchunk, + kchunk)
+// (absolute K indices through the operands' index maps, so a range may start
+// anywhere) and writes its raw partial sums to part[((b * splits + y) * M + m) * N + n].
 template <int BM, int BN>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m, int tiles_n, int kchunk,
                                                          double* __restrict__ part) {
@@ -220,12 +221,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
   if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
   const int b = blockIdx.z;
   constexpr bool can_split = (BM == 64);  // the split path exists for the small-tile kernel only
+  int kb = 0;  // first K index of this workgroup; g.K becomes the end of its range
   if (can_split && kchunk > 0) {
-    // K sub-range of this split: shift A and B by its start, shorten K
-    const int k_begin = blockIdx.y * kchunk;
-    g.K = min(g.K, k_begin + kchunk) - k_begin;
-    g.A = (const double*)g.A + map2(g.ak, k_begin);
-    g.B = (const double*)g.B + map2(g.bk, k_begin);
+    kb = blockIdx.y * kchunk;
+    g.K = min(g.K, kb + kchunk);
   }
   const double* A = (const double*)g.A;
   const double* B = (const double*)g.B;
@@ -241,13 +240,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(GemmArgs g, int tiles_m
     for (int j = 0; j < T::TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   double ra[T::EA], rb[T::EB];
-  const int nk = (g.K + BK - 1) / BK;
-  load_tile<BM, BN>(g, A, B, L, 0, ra, rb);
+  const int nk = (g.K - kb + BK - 1) / BK;
+  load_tile<BM, BN>(g, A, B, L, kb, ra, rb);
   store_tile<BM, BN, double>(L, ra, rb, As[0], Bs[0]);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) load_tile<BM, BN>(g, A, B, L, (kt + 1) * BK, ra, rb);
+    if (kt + 1 < nk) load_tile<BM, BN>(g, A, B, L, kb + (kt + 1) * BK, ra, rb);
     const double* as = As[cur];
     const double* bs = Bs[cur];
 #pragma unroll
@@ -327,11 +326,8 @@ hipError_t launch(const GemmArgs& g, Prec prec, hipStream_t s) {
       splits = (int)std::min<long long>(splits, g.split_cap / std::max<long long>(mn, 1));
       splits = std::min(splits, 64);
     }
-    // a split starts at a multiple of BK and of both operands' inner K extents,
-    // so that each operand's K map shifts by a constant
-    long long unit = BK;
-    for (int inner : {g.ak.inner, g.bk.inner})
-      if (inner > 0) unit = std::lcm(unit, (long long)inner);
+    // each split covers whole K tiles
+    const long long unit = BK;
     if (splits >= 2 && unit < g.K) {
       const long long per = (g.K + splits - 1) / splits;
       const int kchunk = (int)(((per + unit - 1) / unit) * unit);
