@@ -1,0 +1,124 @@
+"""Perturbative quadruples correction E_(Q) of spin-restricted CCSDT(Q), FP64,
+on full spin-free tensors (test oracle only).
+
+Follows the paper's Appendix "(Q) energy correction" (Eq. ener-pt-q with the
+residual Eq. resi-pt-q): from converged (or any) T2 and T3 and the bare
+integrals,
+
+  X_ijkl^abcd = 1/2 sum_e v^{ab}_{ej} t_ikl^ecd - 1/2 sum_m v^{am}_{ij} t_mkl^bcd
+  V_ijkl^abcd = 1/4 v^{ab}_{ij} t_kl^cd
+  Wbar_ejk^abc = P_(jb)(kc) [ 1/2 sum_f v^{ab}_{ef} t_jk^fc ]
+  Wbar_ijk^abm = P_(ia)(jb) [ sum_e v^{ma}_{ei} t_jk^be + sum_e v^{ma}_{ke} t_ji^be
+                              - 1/2 sum_n v^{mn}_{ki} t_nj^ab ]
+  Y_ijkl^abcd = 1/2 sum_e Wbar_ejk^abc t_il^ed - 1/2 sum_m Wbar_ijk^abm t_ml^cd
+  r = P_(ia)(jb)(kc)(ld) (X + Y),   z = P_(ia)(jb)(kc)(ld) (X + V)
+  t4 = r / eps_ijkl^abcd   (eps = sum eps_occ - sum eps_vir, eps_p = f_pp)
+  E_(Q) = 1/24 sum_ijklabcd z_ijkl^abcd tchk_ijkl^abcd
+
+with P the unnormalised sum over simultaneous permutations of the listed
+columns and the fully spin-summed quadruples amplitude (Eq. quadruples-spin-sum
+and the (Q) appendix)
+
+  u1 = (2 - P_a^b - P_a^c - P_a^d) t4
+  u2 = (2 - P_b^c - P_b^d) u1
+  tchk = 2 (2 - P_c^d) u2
+
+where P_x^y exchanges two virtual labels with the occupied labels fixed.
+Canonical orbitals are assumed (the denominators use the diagonal of f only,
+as the paper's non-iterative amplitudes do).  T1 does not enter.
+
+Array conventions as in oracle.rccsdt: V[p,q,r,s] = v^{pq}_{rs} (bare),
+t2[i,j,a,b], t3[i,j,k,a,b,c], full tensors t4[i,j,k,l,a,b,c,d] (o^4 v^4
+elements: small systems only).
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+PERMS4 = list(itertools.permutations(range(4)))
+
+
+def _es(spec, *ops):
+    return np.einsum(spec, *ops, optimize=True)
+
+
+def perm_sym4(X: np.ndarray) -> np.ndarray:
+    """P_(ia)(jb)(kc)(ld) X: sum over the 24 simultaneous permutations of the
+    four (occupied, virtual) columns of X[i,j,k,l,a,b,c,d]."""
+    out = np.zeros_like(X)
+    for p in PERMS4:
+        out += X.transpose(*p, *(4 + q for q in p))
+    return out
+
+
+def wbar_vvvo(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """Wbar_ejk^abc as W[e,j,k,a,b,c] (Eq. q_w_vvv_voo)."""
+    Vs = slice(o, None)
+    vvvv = V[Vs, Vs, Vs, Vs]                       # v^{ab}_{ef} = vvvv[a,b,e,f]
+    half = 0.5 * _es("abef,jkfc->ejkabc", vvvv, t2)
+    return half + half.transpose(0, 2, 1, 3, 5, 4)  # + (j,b) <-> (k,c)
+
+
+def wbar_vooo(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """Wbar_ijk^abm as W[i,j,k,a,b,m] (Eq. q_w_vvo_ooo)."""
+    O, Vs = slice(0, o), slice(o, None)
+    g = (_es("maei,jkbe->ijkabm", V[O, Vs, Vs, O], t2)
+         + _es("make,jibe->ijkabm", V[O, Vs, O, Vs], t2)
+         - 0.5 * _es("mnki,njab->ijkabm", V[O, O, O, O], t2))
+    return g + g.transpose(1, 0, 2, 4, 3, 5)        # + (i,a) <-> (j,b)
+
+
+def x_term(V: np.ndarray, t3: np.ndarray, o: int) -> np.ndarray:
+    """X_ijkl^abcd (Eq. q_t3_terms) as X[i,j,k,l,a,b,c,d]."""
+    O, Vs = slice(0, o), slice(o, None)
+    return (0.5 * _es("abej,iklecd->ijklabcd", V[Vs, Vs, Vs, O], t3)
+            - 0.5 * _es("amij,mklbcd->ijklabcd", V[Vs, O, O, O], t3))
+
+
+def y_term(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """Y_ijkl^abcd as Y[i,j,k,l,a,b,c,d]."""
+    return (0.5 * _es("ejkabc,iled->ijklabcd", wbar_vvvo(V, t2, o), t2)
+            - 0.5 * _es("ijkabm,mlcd->ijklabcd", wbar_vooo(V, t2, o), t2))
+
+
+def v_term(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """V_ijkl^abcd = 1/4 v^{ab}_{ij} t_kl^cd."""
+    O, Vs = slice(0, o), slice(o, None)
+    return 0.25 * _es("abij,klcd->ijklabcd", V[Vs, Vs, O, O], t2)
+
+
+def denominators4(f: np.ndarray, o: int) -> np.ndarray:
+    e = np.diag(f)
+    eo, ev = e[:o], e[o:]
+    occ = eo[:, None, None, None] + eo[None, :, None, None] + eo[None, None, :, None] + eo[None, None, None, :]
+    vir = ev[:, None, None, None] + ev[None, :, None, None] + ev[None, None, :, None] + ev[None, None, None, :]
+    return occ[:, :, :, :, None, None, None, None] - vir[None, None, None, None]
+
+
+def quadruples(f, V, t2, t3, o):
+    """(t4, z): the non-iterative quadruples amplitudes and the energy weights."""
+    X = x_term(V, t3, o)
+    t4 = perm_sym4(X + y_term(V, t2, o)) / denominators4(f, o)
+    z = perm_sym4(X + v_term(V, t2, o))
+    return t4, z
+
+
+def spin_sum4(t4: np.ndarray) -> np.ndarray:
+    """Fully spin-summed quadruples amplitude from the spin-free one (virtual
+    label exchanges at fixed occupied labels, applied in the order listed)."""
+    def swap(x, p, q):
+        ax = list(range(8))
+        ax[4 + p], ax[4 + q] = ax[4 + q], ax[4 + p]
+        return x.transpose(ax)
+    u1 = 2.0 * t4 - swap(t4, 0, 1) - swap(t4, 0, 2) - swap(t4, 0, 3)
+    u2 = 2.0 * u1 - swap(u1, 1, 2) - swap(u1, 1, 3)
+    return 2.0 * (2.0 * u2 - swap(u2, 2, 3))
+
+
+def energy_q(f, V, t2, t3, o) -> float:
+    """E_(Q) = 1/24 sum z tchk."""
+    t4, z = quadruples(f, V, t2, t3, o)
+    return float(_es("ijklabcd,ijklabcd->", z, spin_sum4(t4)) / 24.0)

@@ -272,6 +272,48 @@ class SpinOrbitalSystem:
             out += ((-1.0) ** (k + 1) / k) * term
         return np.array([sg * out[pos] for (pos, sg) in self._ref_pos])
 
+    def q_correction(self, tso, eps):
+        """Perturbative quadruples energy from spin-orbital T2, T3 (entries of
+        ``tso`` on the excitations passed to ``prepare``, which must include
+        rank 4; other ranks are ignored) and spatial orbital energies ``eps``:
+
+          E = sum_Q <Q|H_N (T2 + T3)|0> <Q|H_N T3 + 1/2 (H_N T2^2)_C|0> / D_Q
+
+        over the unique quadruply excited determinants Q, with
+        H_N = H - <0|H|0> and D_Q = sum eps_occ - sum eps_vir.  The connected
+        part of H_N T2^2 / 2 on quadruples is the whole term minus
+        (H_N T2)_C T2, where (H_N T2)_C is the doubles projection of H_N T2|0>
+        read back as an excitation operator (its only non-vanishing rank on
+        quadruples; excitation operators commute).  Canonical reference: the
+        Fock matrix of |Phi_0> is diagonal, so H_N has no pure one-body
+        excitation part."""
+        rank = np.array([len(I) for I, _ in self.excs])
+        tso = np.asarray(tso, dtype=float)
+        T2 = self.t_matrix(np.where(rank == 2, tso, 0.0))
+        T3 = self.t_matrix(np.where(rank == 3, tso, 0.0))
+        e_ref = self.hf_energy()
+        phi = np.zeros(len(self.space))
+        phi[self.ref_index] = 1.0
+
+        def hn(x):
+            return self.apply_h(x) - e_ref * x
+
+        def proj(x):
+            return np.array([sg * x[pos] for (pos, sg) in self._ref_pos])
+
+        a2 = T2 @ phi
+        a3 = T3 @ phi
+        x2 = np.where(rank == 2, proj(hn(a2)), 0.0)
+        left = proj(hn(a2 + a3))
+        right = proj(hn(a3) + 0.5 * hn(T2 @ a2) - self.t_matrix(x2) @ a2)
+        e = 0.0
+        for mu, (I, A) in enumerate(self.excs):
+            if len(I) != 4:
+                continue
+            d = sum(eps[P // 2] for P in I) - sum(eps[P // 2] for P in A)
+            e += left[mu] * right[mu] / d
+        return float(e)
+
     def fci_vector(self):
         dim = len(self.space)
         H = np.empty((dim, dim))
