@@ -268,6 +268,39 @@ def run_slab(binding, modes, panel):
     return out
 
 
+def q_macs(o, v):
+    """Algorithmic multiply-adds of one E_(Q) evaluation in the occupied-tuple
+    traversal: per ordered occupied tuple without three equal indices, the two
+    contractions of v^5 (X from T3, Y from Wbar_ejk^abc), the two of o v^4 and
+    the V outer product (v^4); plus the Wbar_ejk^abc build (2 o^2 v^5)."""
+    nord = o ** 4 - o - 4 * o * (o - 1)
+    return nord * (2 * v ** 5 + 2 * o * v ** 4 + v ** 4) + 2 * o * o * v ** 5
+
+
+def run_q(binding, name, reps=2):
+    """E_(Q) on a named workload after two FP64 iterations from the MP2 guess
+    (T3 non-zero): wall time of cct_energy_q (setup of the intermediates and
+    the task loop), algorithmic FLOP rate against the FP64 MFMA peak."""
+    s = ci.make_named(name)
+    o, v, naux = s["o"], s["v"], s["naux"]
+    with binding.Engine(o, v, naux) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        for _ in range(2):
+            eng.update()
+        times, e = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            e = eng.energy_q()
+            times.append(time.perf_counter() - t0)
+            log(f"[bench] (Q) {name}: E_(Q) = {e:.12f} in {times[-1]:.2f} s")
+    wall = min(times)
+    flop = 2.0 * q_macs(o, v)
+    return {"workload": name, "e_q": e, "s": wall, "algorithmic_flop": flop, "tflops": flop / wall / 1e12,
+            "peak": PEAK["fp64"], "frac": flop / wall / 1e12 / PEAK["fp64"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +325,8 @@ def main():
     ap.add_argument("--slab", action="store_true",
                     help="only the block-local terms of a 64-triple slab at o=50 v=400 (FP32 and split-BF16)")
     ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
+    ap.add_argument("--q-workload", default="", metavar="NAME",
+                    help="also time the (Q) correction on this workload (e.g. o10v90-scaled); off by default")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
@@ -405,6 +440,8 @@ def main():
     if not args.no_accuracy:
         out["accuracy"] = run_accuracy(binding, [args.precision] + [m for m in args.compare.split(",")
                                                                     if m and m != args.precision])
+    if args.q_workload:
+        out["q"] = run_q(binding, args.q_workload)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)

@@ -152,6 +152,25 @@ int cct_energy(cct_ctx* ctx, double* e_corr);
  * (with the last energy and count filled in) if not converged. */
 int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters);
 
+/* Perturbative quadruples correction E_(Q) of CCSDT(Q) (the paper's (Q)
+ * appendix, Eq. ener-pt-q with the residual Eq. resi-pt-q and the Wbar
+ * intermediates Eqs. q_w_vvv_voo, q_w_vvo_ooo) from the context's current T2
+ * and T3 (normally converged) and the BARE integrals; T1 does not enter, and
+ * the denominators use the orbital energies f_pp (canonical orbitals).  FP64
+ * whatever the context's precision.  Occupied-tuple traversal: one task per
+ * i <= j <= k <= l in lexicographic order (cct_q_task_count(nocc) tasks;
+ * tasks with three equal indices contribute exactly 0).  e_tasks (may be
+ * NULL; else cap >= cct_q_task_count entries, host memory) receives each
+ * task's contribution; *e_q their fixed-order sum.  Needs, beyond the
+ * context, about 8 * (n^4 + o^2 v^4 + o^3 v^3 + 6 v^4 + 2 o^4 v^2) bytes of
+ * device memory for the duration of the call (n = o + v): CCT_ENOMEM if that
+ * is not free; CCT_EINVAL for nocc > 40; CCT_ESTATE before cct_set_fock /
+ * cct_set_eri_df.  Synchronous (returns after the stream has drained). */
+int cct_energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap);
+/* Number of (Q) tasks, i <= j <= k <= l < nocc: nocc(nocc+1)(nocc+2)(nocc+3)/24
+ * (-1 for nocc < 0). */
+int64_t cct_q_task_count(int nocc);
+
 /* Algorithmic multiply-add counts of the last residual per R3 term group
  * (indices as the CCT_TERM_* bit positions, 9 entries) and device time in ms
  * per phase (entries: 0 setup/dressing+CCSD, 1 feedback, 2 PP, 3 rings,

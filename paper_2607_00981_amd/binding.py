@@ -71,6 +71,8 @@ def load(path: str | None = None):
         "cct_copy_r3": (C.c_int, [vp, C.c_int64, C.c_int64, dp]),
         "cct_update": (C.c_int, [vp, dp, dp]),
         "cct_energy": (C.c_int, [vp, dp]),
+        "cct_energy_q": (C.c_int, [vp, dp, dp, C.c_int64]),
+        "cct_q_task_count": (C.c_int64, [C.c_int]),
         "cct_solve": (C.c_int, [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int)]),
         "cct_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
         "cct_autotune": (C.c_int, [vp, C.c_double, C.POINTER(C.c_int)]),
@@ -122,6 +124,10 @@ def packed_index(o, i, j, k):
 
 def ntri(o):
     return o * (o + 1) * (o + 2) // 6
+
+
+def q_task_count(o):
+    return load().cct_q_task_count(o)
 
 
 class Engine:
@@ -217,6 +223,16 @@ class Engine:
         e = C.c_double()
         self._check(self.lib.cct_energy(self.h, C.byref(e)))
         return e.value
+
+    def energy_q(self, tasks=False):
+        """Perturbative quadruples correction E_(Q) from the current T2, T3 and
+        the bare integrals; with tasks=True also the per-task contributions
+        (i <= j <= k <= l < nocc, lexicographic)."""
+        e = C.c_double()
+        nt = q_task_count(self.o)
+        et = np.zeros(max(nt, 1)) if tasks else None
+        self._check(self.lib.cct_energy_q(self.h, C.byref(e), _ptr(et), nt if tasks else 0))
+        return (e.value, et[:nt]) if tasks else e.value
 
     def solve(self, max_iter=100, tol=None):
         """Iterate to sqrt(sum |R|^2) < tol (None: the context's "tol" option);

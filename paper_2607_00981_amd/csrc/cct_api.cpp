@@ -1493,6 +1493,274 @@ int energy_dev(cct_ctx* ctx, double* e) {
   return finite_or_err(ctx, *e);
 }
 
+// --- perturbative quadruples correction ----------------------------------
+// E_(Q) of the (Q) appendix (Eq. ener-pt-q with Eq. resi-pt-q), by the
+// occupied-tuple traversal of the "IJK-based algorithm" section: one task per
+// i <= j <= k <= l (no three equal: those blocks of the spin-summed quadruples
+// vanish).  With G = X + Y and A = X + V, the task accumulates
+//   R[w]    = sum over the 24 column permutations s of G_{o.s}[w.s]
+//   Abar[w] = sum over the distinct orderings q = o.s of A_q[w.s]
+// and contributes <Abar, S(R) / eps_o>, S the full spin summation; since S
+// commutes with column permutations and z = P(X + V), this equals the
+// task's share of 1/24 sum z tchk.  The blocks X_q, Y_q of an ordered tuple q
+// cost two dense contractions of 2 v^5 (X from T3, Y from the resident
+// Wbar_ejk^abc) plus two of 2 o v^4; all orderings of a task stay resident
+// and one permuted-combine pass writes R and Abar.
+DT Vview(cct_ctx* c, double* base, const char* blk) {
+  DT t = Vv(c, blk);
+  t.p = base + (t.p - c->V);
+  return t;
+}
+
+struct QMem {
+  cct_ctx* c;
+  std::vector<void*> ps;
+  explicit QMem(cct_ctx* cc) : c(cc) {}
+  ~QMem() {
+    if (!ps.empty()) (void)hipStreamSynchronize(c->s);
+    for (void* p : ps) dev_free(c, p);
+  }
+  template <typename T>
+  int get(T** p, long long n) {
+    void* q = nullptr;
+    RCK(dev_alloc(c, &q, (size_t)std::max<long long>(n, 1) * sizeof(T)));
+    ps.push_back(q);
+    *p = (T*)q;
+    return CCT_OK;
+  }
+};
+
+long long q_task_count(int o) { return (long long)o * (o + 1) * (o + 2) * (o + 3) / 24; }
+
+int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
+  const int o = ctx->o, v = ctx->v, n = ctx->n;
+  const long long naux = ctx->naux, n2 = (long long)n * n, n4 = n2 * n2;
+  const long long v2 = (long long)v * v, v3 = v2 * v, v4 = v3 * v, o2 = (long long)o * o;
+  const long long ntask = q_task_count(o);
+  if (e_tasks && cap < ntask) {
+    ctx->err = "energy_q: task array holds " + std::to_string(cap) + " entries, " + std::to_string(ntask) + " needed";
+    return CCT_EINVAL;
+  }
+  if ((long long)o * o * o > 65535) { ctx->err = "energy_q: nocc above 40"; return CCT_EINVAL; }
+  if (v3 > INT_MAX || o2 * o * v3 > LLONG_MAX / 8) { ctx->err = "energy_q: nvir too large"; return CCT_EINVAL; }
+  hipStream_t s = ctx->s;
+  const long long arena_n = std::max(v4, o2 * o2 * v2) + (8LL << 20);
+  const long long need = n4 + v4 + (long long)o * v3 + o2 * o * v + o2 * v2 + o2 * v4 + 2 * o2 * o2 * v2 +
+                         o2 * o * v3 + 50 * v4 + ntask + 1 + arena_n;
+  if (!ctx->alloc_fn) {
+    size_t fr = 0, tot = 0;
+    HIPCK(hipMemGetInfo(&fr, &tot));
+    if ((double)need * 8.0 + 256e6 > (double)fr) {
+      ctx->err = "energy_q: needs " + std::to_string(need * 8.0 / 1e9) + " GB of device memory, " +
+                 std::to_string(fr / 1e9) + " GB free";
+      return CCT_ENOMEM;
+    }
+  }
+  QMem mem(ctx);
+  double *Vb, *VVVV, *VVVO, *VOOO, *VVOO, *Wv, *g, *Wo, *T3u, *Xb, *Gb, *Rb, *Ab, *et, *ar;
+  int2* slots;
+  RCK(mem.get(&Vb, n4));
+  RCK(mem.get(&VVVV, v4));
+  RCK(mem.get(&VVVO, (long long)o * v3));
+  RCK(mem.get(&VOOO, o2 * o * v));
+  RCK(mem.get(&VVOO, o2 * v2));
+  RCK(mem.get(&Wv, o2 * v4));
+  RCK(mem.get(&g, o2 * o2 * v2));
+  RCK(mem.get(&Wo, o2 * o2 * v2));
+  RCK(mem.get(&T3u, o2 * o * v3));
+  RCK(mem.get(&Xb, 24 * v4));  // X of each distinct ordering of a task
+  RCK(mem.get(&Gb, 24 * v4));  // Y of each distinct ordering
+  RCK(mem.get(&Rb, v4));
+  RCK(mem.get(&Ab, v4));
+  RCK(mem.get(&et, ntask + 1));
+  RCK(mem.get(&ar, arena_n));
+  RCK(mem.get(&slots, o2));
+  Arena qa;
+  qa.init((char*)ar, (size_t)arena_n * 8);
+  const Prec F = Prec::F64;
+
+  // bare integrals v^{pq}_{rs} = (pr|qs), stored like the dressed ones
+  {
+    GemmArgs ga{};
+    ga.M = (int)n2; ga.N = (int)n2; ga.K = (int)naux; ga.batch = 1;
+    ga.A = ctx->B; ga.am = idx1(1); ga.ak = idx1(n2);
+    ga.B = ctx->B; ga.bk = idx1(n2); ga.bn = idx1(1);
+    ga.C = Vb; ga.cm = idx1(n2); ga.cn = idx1(1);
+    ga.alpha = 1.0; ga.beta = 0.0;
+    ga.a_len = naux * n2; ga.b_len = naux * n2; ga.c_len = n4;
+    HIPCK(gemm(ga, F, s));
+  }
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvvv"), "abef", 0.0, dense(VVVV, {v, v, v, v}), "abef"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvvo"), "abej", 0.0, dense(VVVO, {o, v, v, v}), "jabe"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vooo"), "amij", 0.0, dense(VOOO, {o, o, v, o}), "ijam"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvoo"), "abij", 0.0, dense(VVOO, {o, o, v, v}), "ijab"));
+  // Wbar_eqr^abc (Eq. q_w_vvv_voo) as Wv[q][r][a][b][c][e], one (q, r) at a time
+  for (int q = 0; q < o; ++q)
+    for (int r = 0; r < o; ++r) {
+      const DT w = dense(Wv + ((long long)q * o + r) * v4, {v, v, v, v});
+      STCK(contract(qa, s, F, 0.5, dense(VVVV, {v, v, v, v}), "abef", dense(ctx->t2 + ((long long)q * o + r) * v2, {v, v}),
+                    "fc", 0.0, w, "abce"));
+      STCK(contract(qa, s, F, 0.5, dense(VVVV, {v, v, v, v}), "acef", dense(ctx->t2 + ((long long)r * o + q) * v2, {v, v}),
+                    "fb", 1.0, w, "abce"));
+    }
+  // Wbar_ijk^abm (Eq. q_w_vvo_ooo) as Wo[i][j][k][a][b][m]
+  {
+    const DT t2 = dense(ctx->t2, {o, o, v, v});
+    const DT gd = dense(g, {o, o, o, v, v, o}), wd = dense(Wo, {o, o, o, v, v, o});
+    STCK(contract(qa, s, F, 1.0, Vview(ctx, Vb, "ovvo"), "maei", t2, "jkbe", 0.0, gd, "ijkabm"));
+    STCK(contract(qa, s, F, 1.0, Vview(ctx, Vb, "ovov"), "make", t2, "jibe", 1.0, gd, "ijkabm"));
+    STCK(contract(qa, s, F, -0.5, Vview(ctx, Vb, "oooo"), "mnki", t2, "njab", 1.0, gd, "ijkabm"));
+    STCK(accumulate(s, 1.0, gd, "ijkabm", 0.0, wd, "ijkabm"));
+    STCK(accumulate(s, 1.0, gd, "jikbam", 1.0, wd, "ijkabm"));
+  }
+  // T3u[r][s][m] = t_{m r s}^{xyz} (full v^3 blocks) for every ordered (r, s)
+  {
+    std::vector<int2> sl((size_t)o2);
+    for (int r = 0; r < o; ++r)
+      for (int t = 0; t < o; ++t) sl[(size_t)r * o + t] = make_int2(r, t);
+    HIPCK(hipMemcpyAsync(slots, sl.data(), sizeof(int2) * sl.size(), hipMemcpyHostToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    UnpackArgs ua{};
+    ua.o = o; ua.v = v; ua.nslots = (int)o2; ua.nfree = 1;
+    ua.s_slot = (long long)o * v3; ua.s_free[0] = v3; ua.s_free[1] = 0;
+    ua.s_x = v2; ua.s_y = v; ua.s_z = 1; ua.fast = 0;
+    const int occ[3] = {2, 0, 1};
+    set_ident(ua, occ);
+    HIPCK(unpack_t3(ctx->t3, ctx->tbl, slots, T3u, ua, s));
+  }
+  HIPCK(fill(et, 0.0, ntask + 1, s));
+
+  std::vector<double> eps((size_t)n);
+  HIPCK(hipMemcpyAsync(eps.data(), ctx->eps, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  const bool nt_ok = (v % 2) == 0;  // K-contiguous MFMA kernel: even K and 16-byte aligned rows
+  auto gemm_x1_y1 = [&](const double* A, long long lda, const double* Bm, long long ldb, double* C, long long M,
+                        long long N, double alpha) -> int {
+    // C[M][N] = alpha * sum_e A[m][e] B[e][n], K = v
+    if (nt_ok) {
+      NtArgs na{};
+      na.M = (int)M; na.N = (int)N; na.K = v; na.batch = 1;
+      na.A = A; na.lda = lda; na.B = Bm; na.ldb = ldb; na.b_kn = 1;
+      na.C = C; na.cm = idx1(N); na.cn = idx1(1);
+      na.alpha = alpha; na.beta = 0.0;
+      na.a_len = M * lda; na.b_len = (long long)v * ldb; na.c_len = M * N;
+      HIPCK(gemm_nt(na, F, s));
+    } else {
+      GemmArgs ga{};
+      ga.M = (int)M; ga.N = (int)N; ga.K = v; ga.batch = 1;
+      ga.A = A; ga.am = idx1(lda); ga.ak = idx1(1);
+      ga.B = Bm; ga.bk = idx1(ldb); ga.bn = idx1(1);
+      ga.C = C; ga.cm = idx1(N); ga.cn = idx1(1);
+      ga.alpha = alpha; ga.beta = 0.0;
+      ga.a_len = M * lda; ga.b_len = (long long)v * ldb; ga.c_len = M * N;
+      HIPCK(gemm(ga, F, s));
+    }
+    return CCT_OK;
+  };
+  auto gemm_k_o = [&](const double* A, const double* Bm, long long bk, double* C, long long M, long long N) -> int {
+    // C[M][N] += -1/2 sum_m A[m][k] B[k][n], K = o, A rows of o, B rows at stride bk
+    GemmArgs ga{};
+    ga.M = (int)M; ga.N = (int)N; ga.K = o; ga.batch = 1;
+    ga.A = A; ga.am = idx1(o); ga.ak = idx1(1);
+    ga.B = Bm; ga.bk = idx1(bk); ga.bn = idx1(1);
+    ga.C = C; ga.cm = idx1(N); ga.cn = idx1(1);
+    ga.alpha = -0.5; ga.beta = 1.0;
+    ga.a_len = M * o; ga.b_len = (long long)(o - 1) * bk + N; ga.c_len = M * N;
+    HIPCK(gemm(ga, F, s));
+    return CCT_OK;
+  };
+  static const int P24[24][4] = {{0, 1, 2, 3}, {0, 1, 3, 2}, {0, 2, 1, 3}, {0, 2, 3, 1}, {0, 3, 1, 2}, {0, 3, 2, 1},
+                                 {1, 0, 2, 3}, {1, 0, 3, 2}, {1, 2, 0, 3}, {1, 2, 3, 0}, {1, 3, 0, 2}, {1, 3, 2, 0},
+                                 {2, 0, 1, 3}, {2, 0, 3, 1}, {2, 1, 0, 3}, {2, 1, 3, 0}, {2, 3, 0, 1}, {2, 3, 1, 0},
+                                 {3, 0, 1, 2}, {3, 0, 2, 1}, {3, 1, 0, 2}, {3, 1, 2, 0}, {3, 2, 0, 1}, {3, 2, 1, 0}};
+  auto term = [](const double* in, const int* pm, double coef) {
+    QPermTerm t{};
+    t.in = in;
+    t.dst = 1;
+    for (int k = 0; k < 4; ++k) t.perm[k] = pm[k];
+    t.coef = coef;
+    return t;
+  };
+  static const int ID[4] = {0, 1, 2, 3};
+  long long task = -1;
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k)
+        for (int l = k; l < o; ++l) {
+          ++task;
+          if ((i == j && j == k) || (j == k && k == l)) continue;
+          const int oc[4] = {i, j, k, l};
+          // distinct orderings q = o.s with the permutations that reach them
+          std::vector<std::array<int, 4>> qs;
+          std::vector<std::vector<int>> sig;
+          for (int p = 0; p < 24; ++p) {
+            const std::array<int, 4> q = {oc[P24[p][0]], oc[P24[p][1]], oc[P24[p][2]], oc[P24[p][3]]};
+            size_t x = 0;
+            while (x < qs.size() && qs[x] != q) ++x;
+            if (x == qs.size()) {
+              qs.push_back(q);
+              sig.emplace_back();
+            }
+            sig[x].push_back(p);
+          }
+          QCombineArgs cr{};
+          cr.v = v; cr.beta = 0.0;
+          for (size_t x = 0; x < qs.size(); ++x) {
+            const long long q0 = qs[x][0], q1 = qs[x][1], q2 = qs[x][2], q3 = qs[x][3];
+            double* X = Xb + (long long)x * v4;
+            double* G = Gb + (long long)x * v4;
+            // X = 1/2 sum_e v^{ab}_{e q1} t_{q0 q2 q3}^{ecd} - 1/2 sum_m v^{am}_{q0 q1} t_{m q2 q3}^{bcd}
+            const double* t3r = T3u + (q2 * o + q3) * o * v3;
+            RCK(gemm_x1_y1(VVVO + q1 * v3, v, t3r + q0 * v3, v2, X, v2, v2, 0.5));
+            RCK(gemm_k_o(VOOO + (q0 * o + q1) * v * o, t3r, v3, X, v, v3));
+            // Y = 1/2 sum_e Wbar_{e q1 q2}^{abc} t_{q0 q3}^{ed} - 1/2 sum_m Wbar_{q0 q1 q2}^{abm} t_{m q3}^{cd}
+            RCK(gemm_x1_y1(Wv + (q1 * o + q2) * v4, v, ctx->t2 + (q0 * o + q3) * v2, v, G, v3, v, 0.5));
+            RCK(gemm_k_o(Wo + ((q0 * o + q1) * o + q2) * v2 * o, ctx->t2 + q3 * v2, o * v2, G, v2, v2));
+            // R gets X + Y under every permutation reaching q; Abar gets
+            // X + 1/4 v^{ab}_{q0 q1} t_{q2 q3}^{cd} under the first of them
+            for (size_t k = 0; k < sig[x].size(); ++k) {
+              QPermTerm tx = term(X, P24[sig[x][k]], 1.0);
+              if (k == 0) {
+                tx.dst = 3;
+                tx.va = VVOO + (q0 * o + q1) * v2;
+                tx.vb = ctx->t2 + (q2 * o + q3) * v2;
+                tx.vcoef = 0.25;
+              }
+              cr.t[cr.nterms++] = tx;
+              cr.t[cr.nterms++] = term(G, P24[sig[x][k]], 1.0);
+            }
+          }
+          // one pass writes R and Abar (24 permutations: 48 terms, QMAXT)
+          HIPCK(perm_combine(Rb, Ab, cr, s));
+          // S(R) / eps_o: S = 2 (2 - P_cd) (2 - P_bc - P_bd) (2 - P_ab - P_ac - P_ad)
+          static const int Sab[4] = {1, 0, 2, 3}, Sac[4] = {2, 1, 0, 3}, Sad[4] = {3, 1, 2, 0};
+          static const int Sbc[4] = {0, 2, 1, 3}, Sbd[4] = {0, 3, 2, 1}, Scd[4] = {0, 1, 3, 2};
+          QCombineArgs c1{};
+          c1.v = v; c1.nterms = 4; c1.beta = 0.0;
+          c1.t[0] = term(Rb, ID, 2.0); c1.t[1] = term(Rb, Sab, -1.0);
+          c1.t[2] = term(Rb, Sac, -1.0); c1.t[3] = term(Rb, Sad, -1.0);
+          HIPCK(perm_combine(Xb, nullptr, c1, s));
+          QCombineArgs c2{};
+          c2.v = v; c2.nterms = 3; c2.beta = 0.0;
+          c2.t[0] = term(Xb, ID, 2.0); c2.t[1] = term(Xb, Sbc, -1.0); c2.t[2] = term(Xb, Sbd, -1.0);
+          HIPCK(perm_combine(Gb, nullptr, c2, s));
+          QCombineArgs c3{};
+          c3.v = v; c3.nterms = 2; c3.beta = 0.0;
+          c3.t[0] = term(Gb, ID, 4.0); c3.t[1] = term(Gb, Scd, -2.0);
+          c3.eps_v = ctx->eps + o;
+          c3.eps_occ = eps[i] + eps[j] + eps[k] + eps[l];
+          HIPCK(perm_combine(Rb, nullptr, c3, s));
+          HIPCK(dot(Ab, Rb, v4, et + task, ctx->red, s));
+        }
+  HIPCK(reduce_sum(et, ntask, et + ntask, ctx->red, s));
+  std::vector<double> h((size_t)ntask + 1);
+  HIPCK(hipMemcpyAsync(h.data(), et, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (e_tasks) std::copy(h.begin(), h.begin() + ntask, e_tasks);
+  *e_q = h[(size_t)ntask];
+  return finite_or_err(ctx, *e_q);
+}
+
 // --- DIIS ---------------------------------------------------------------
 // T3 elements per packed block that take part in DIIS (Sec. "Distributed
 // DIIS": all of T3, none of it, or only the low-energy virtual subspace)
@@ -2148,6 +2416,14 @@ int cct_energy(cct_ctx* ctx, double* e_corr) {
   if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
   return energy_dev(ctx, e_corr);
 }
+
+int cct_energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap) {
+  if (!ctx || !e_q || (e_tasks && cap < 0)) return CCT_EINVAL;
+  if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
+  return energy_q(ctx, e_q, e_tasks, (long long)cap);
+}
+
+int64_t cct_q_task_count(int nocc) { return nocc < 0 ? -1 : (int64_t)q_task_count(nocc); }
 
 int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters) {
   if (!ctx || max_iter < 1 || std::isnan(tol)) return CCT_EINVAL;

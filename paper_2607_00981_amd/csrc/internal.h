@@ -236,4 +236,30 @@ hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r
 // W_diag: add c * F[a][d] on the (b == e) diagonal and c * F[b][e] on (a == d) for a [x][y][x][y] tensor.
 hipError_t add_pair_diag(double* W, const double* F, long long ldF, int nx, double c, hipStream_t s);
 
+// Permuted combination of v^4 virtual blocks (perturbative quadruples):
+//   out[w]  = beta * out[w]  + f(w) * sum_{t: dst_t & 1} coef_t * x_t(w)
+//   out2[w] = beta * out2[w] +        sum_{t: dst_t & 2} coef_t * (x_t(w) + vcoef_t * va_t[y0 v + y1] * vb_t[y2 v + y3])
+// with y = (w_{perm_t[0]}, .., w_{perm_t[3]}) and x_t(w) = in_t[y0][y1][y2][y3]
+// (row-major, w in [0, v)^4); f(w) = 1 / (eps_occ - sum_k eps_v[w_k]) when
+// eps_v is set, else 1.  out2 may be null (then no term may have dst & 2);
+// no input may be an output.
+constexpr int QMAXT = 48;
+struct QPermTerm {
+  const double* in;
+  int perm[4];
+  double coef;
+  int dst;            // 1: out, 2: out2, 3: both
+  const double* va;   // optional rank-one addend of the out2 contribution (nullptr: none)
+  const double* vb;
+  double vcoef;
+};
+struct QCombineArgs {
+  int v, nterms;
+  QPermTerm t[QMAXT];
+  double beta;
+  const double* eps_v;  // device, v virtual orbital energies (nullptr: no division)
+  double eps_occ;       // sum of the four occupied orbital energies
+};
+hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStream_t s);
+
 }  // namespace cct

@@ -82,3 +82,10 @@ def test_create_rejects_half_an_allocator():
     assert lib.cct_batch_create(1, sizes, sizes, sizes, 0, None, a, None, None, None, C.byref(h)) == binding.CCT_EINVAL
     assert lib.cct_slab_create(2, 10, 10, 0, 1, 0, None, None, f, None, None, C.byref(h)) == binding.CCT_EINVAL
     assert not h.value
+
+
+def test_q_task_count_formula():
+    for o in range(0, 12):
+        n = sum(1 for i in range(o) for j in range(i, o) for k in range(j, o) for l in range(k, o))
+        assert binding.q_task_count(o) == n
+    assert binding.q_task_count(-1) == -1

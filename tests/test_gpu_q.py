@@ -1,0 +1,130 @@
+"""GPU: the perturbative quadruples correction (cct_energy_q) against the
+(Q) oracle.
+
+The total E_(Q) and every task's contribution (occupied tuple i <= j <= k <= l)
+are compared with the oracle on the same amplitudes: random physical T2/T3 on
+shapes that cover an odd virtual count (the strided GEMM path), repeated
+occupied indices and several 8^4 tiles with a ragged tail, and the o=4 v=20
+workload after three GPU iterations.  The oracle's per-task split is its own
+full tensors summed over each task's distinct orderings: sum_q A_q . tchk_q
+with A = X + V (the pinned identity E_(Q) = sum (X + V) . tchk).
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import cct_inputs as ci
+from oracle import rccsdt as R, rccsdt_q as Q
+from paper_2607_00981_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _oracle(f, V, t2, t3, o):
+    t4, z = Q.quadruples(f, V, t2, t3, o)
+    U = Q.spin_sum4(t4)
+    e = float(np.einsum("ijklabcd,ijklabcd->", z, U) / 24.0)
+    A = Q.x_term(V, t3, o) + Q.v_term(V, t2, o)
+    tasks = []
+    for i in range(o):
+        for j in range(i, o):
+            for k in range(j, o):
+                for l in range(k, o):
+                    qs = set(itertools.permutations((i, j, k, l)))
+                    tasks.append(sum(float(np.sum(A[q] * U[q])) for q in qs))
+    return e, np.array(tasks)
+
+
+def _random_case(o, v, seed):
+    s = ci.make_system(o, v, 2 * (o + v), seed, sigma=0.1)
+    _, t2, t3 = ci.random_amplitudes(o, v, seed + 1, 0.02, 0.05, 0.05)
+    t3 = R.orthogonalize_r3(R.purify_r3(t3))
+    return s, t2, t3
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 4, 1), (3, 5, 2), (3, 10, 3), (4, 9, 4), (2, 17, 5)])
+def test_energy_q_matches_oracle(o, v, seed):
+    say(f"[energy_q] o={o} v={v} seed={seed}")
+    s, t2, t3 = _random_case(o, v, seed)
+    f, B = s["f"], s["B"]
+    V = R.eri_phys_from_B(B)
+    e_ref, tasks_ref = _oracle(f, V, t2, t3, o)
+    with binding.Engine(o, v, B.shape[0]) as eng:
+        eng.set_fock(f)
+        eng.set_eri_df(B)
+        eng.set_amplitudes(np.zeros((o, v)), t2, R.pack_t3(t3))
+        e, tasks = eng.energy_q(tasks=True)
+    say(f"  gpu {e:.15e} oracle {e_ref:.15e} diff {e - e_ref:.2e}")
+    assert abs(e_ref) > 1e-6
+    assert abs(e - e_ref) <= 1e-13 + 1e-11 * abs(e_ref)
+    assert np.abs(tasks - tasks_ref).max() <= 1e-13 + 1e-11 * np.abs(tasks_ref).max()
+    # tasks with three equal occupied indices contribute exactly nothing
+    n = 0
+    for i in range(o):
+        for j in range(i, o):
+            for k in range(j, o):
+                for l in range(k, o):
+                    if (i == j == k) or (j == k == l):
+                        assert tasks[n] == 0.0
+                    n += 1
+
+
+def test_energy_q_two_electrons_is_zero_and_precision_independent():
+    say("[energy_q] o=1 and mixed-precision context")
+    s, t2, t3 = _random_case(1, 6, 9)
+    with binding.Engine(1, 6, s["B"].shape[0]) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.set_amplitudes(np.zeros((1, 6)), t2, R.pack_t3(t3))
+        assert eng.energy_q() == 0.0
+    o, v = 3, 8
+    s, t2, t3 = _random_case(o, v, 11)
+    out = []
+    for prec in ("fp64", "bf16x3"):
+        with binding.Engine(o, v, s["B"].shape[0], precision=prec) as eng:
+            eng.set_fock(s["f"])
+            eng.set_eri_df(s["B"])
+            eng.set_amplitudes(np.zeros((o, v)), t2, R.pack_t3(t3))
+            out.append(eng.energy_q())
+    assert out[0] == out[1]
+
+
+def test_energy_q_after_iterations_o4v20():
+    s = ci.make_named("o4v20")
+    o, v, naux = s["o"], s["v"], s["naux"]
+    say(f"[energy_q] o4v20 after 3 iterations")
+    with binding.Engine(o, v, naux) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        for _ in range(3):
+            eng.update()
+        _, t2, t3p = eng.get_amplitudes()
+        e = eng.energy_q()
+    V = R.eri_phys_from_B(s["B"])
+    e_ref = Q.energy_q(s["f"], V, t2, R.unpack_t3(t3p, o), o)
+    say(f"  gpu {e:.15e} oracle {e_ref:.15e} diff {e - e_ref:.2e}")
+    assert abs(e_ref) > 1e-6
+    assert abs(e - e_ref) <= 1e-13 + 1e-11 * abs(e_ref)
+
+
+def test_energy_q_argument_errors():
+    s, t2, t3 = _random_case(2, 4, 1)
+    import ctypes as C
+    with binding.Engine(2, 4, s["B"].shape[0]) as eng:
+        e = C.c_double()
+        tasks = np.zeros(2)
+        # before the integrals are set
+        assert eng.lib.cct_energy_q(eng.h, C.byref(e), None, 0) == binding.CCT_ESTATE
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        assert eng.lib.cct_energy_q(eng.h, None, None, 0) == binding.CCT_EINVAL
+        # task array shorter than the 5 tasks of o = 2
+        assert eng.lib.cct_energy_q(eng.h, C.byref(e), tasks.ctypes.data_as(C.POINTER(C.c_double)), 2) == \
+            binding.CCT_EINVAL
