@@ -74,3 +74,26 @@ def test_converged_o10v90_scaled_mixed_vs_fp64():
         e, n = hist[-1]
         say(f"  {prec}: E={e:.12f} |R|={n:.2e} after {len(hist)} iterations, dE={e - e_ref:.3e}")
         assert abs(e - e_ref) <= 1e-6
+
+
+def test_o10v90_first_iterations_match_oracle_golden():
+    """The o=10 v=90 workload (variance-scaled integrals): energies and
+    squared residual norms of the first three iterations from the MP2 guess
+    against the oracle's values stored by
+    tests/golden/make_o10v90_scaled_iterations.py (DIIS on T1/T2 only)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "o10v90_scaled_iterations.txt")
+    rows = [list(map(float, ln.split())) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    s = ci.make_named("o10v90-scaled")
+    o, v, naux = s["o"], s["v"], s["naux"]
+    print(f"[o10v90 golden] {len(rows)} iterations", flush=True)
+    with binding.Engine(o, v, naux, opts={"diis_t3": "none"}) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        for it, e_ref, r1, r2, r3 in rows:
+            e, nr = eng.update()
+            print(f"  it {int(it)}: gpu {e:.14f} oracle {e_ref:.14f} diff {e - e_ref:.2e}", flush=True)
+            assert abs(e - e_ref) < 1e-10
+            for a, b in zip(nr, (r1, r2, r3)):
+                assert abs(a - b) <= 1e-10 * max(1.0, b)
