@@ -1659,6 +1659,10 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   };
   auto gemm_k_o = [&](const double* A, const double* Bm, long long bk, double* C, long long M, long long N) -> int {
     // C[M][N] += -1/2 sum_m A[m][k] B[k][n], K = o, A rows of o, B rows at stride bk
+    if (nt_ok && o <= 16) {  // a streaming read-modify-write of C (even v: aligned pairs)
+      HIPCK(rank_k_update(C, N, A, o, Bm, bk, (int)M, N, o, -0.5, s));
+      return CCT_OK;
+    }
     GemmArgs ga{};
     ga.M = (int)M; ga.N = (int)N; ga.K = o; ga.batch = 1;
     ga.A = A; ga.am = idx1(o); ga.ak = idx1(1);

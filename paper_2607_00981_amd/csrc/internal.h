@@ -261,5 +261,10 @@ struct QCombineArgs {
   double eps_occ;       // sum of the four occupied orbital energies
 };
 hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStream_t s);
+// C[m][n] += alpha * sum_{k<K} A[m*lda + k] * B[k*ldb + n], m < M, n < N, C
+// row stride ldc: streaming update for K <= 16.  Requires N, ldc, ldb even
+// and 16-byte aligned C and B (hipErrorInvalidValue otherwise).
+hipError_t rank_k_update(double* C, long long ldc, const double* A, long long lda, const double* B, long long ldb,
+                         int M, long long N, int K, double alpha, hipStream_t s);
 
 }  // namespace cct

@@ -30,6 +30,23 @@ __global__ __launch_bounds__(QTPB) void perm_combine_kernel(double* __restrict__
 #pragma unroll
   for (int e = 0; e < QPER; ++e) acc[e] = acc2[e] = 0.0;
 
+  // the global loads of term t+1 are issued into registers before term t is
+  // computed from LDS, so their latency overlaps that work
+  double pre[QPER];
+  auto load_term = [&](int t) {
+    const QPermTerm& T = a.t[t];
+    int sorg[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sorg[k] = org[T.perm[k]];
+#pragma unroll
+    for (int e = 0; e < QPER; ++e) {
+      const int lin = threadIdx.x + e * QTPB;
+      const int m3 = lin & 7, m2 = (lin >> 3) & 7, m1 = (lin >> 6) & 7, m0 = lin >> 9;
+      const int y0 = sorg[0] + m0, y1 = sorg[1] + m1, y2 = sorg[2] + m2, y3 = sorg[3] + m3;
+      pre[e] = (y0 < v && y1 < v && y2 < v && y3 < v) ? T.in[y0 * v3 + y1 * v2 + y2 * v1 + y3] : 0.0;
+    }
+  };
+  load_term(0);
   for (int t = 0; t < a.nterms; ++t) {
     const QPermTerm& T = a.t[t];
     // source tile: in-index y_k = w_{perm[k]} runs over org[perm[k]] + [0, QT)
@@ -41,12 +58,10 @@ __global__ __launch_bounds__(QTPB) void perm_combine_kernel(double* __restrict__
     for (int e = 0; e < QPER; ++e) {
       const int lin = threadIdx.x + e * QTPB;
       const int m3 = lin & 7, m2 = (lin >> 3) & 7, m1 = (lin >> 6) & 7, m0 = lin >> 9;
-      const int y0 = sorg[0] + m0, y1 = sorg[1] + m1, y2 = sorg[2] + m2, y3 = sorg[3] + m3;
-      double val = 0.0;
-      if (y0 < v && y1 < v && y2 < v && y3 < v) val = T.in[y0 * v3 + y1 * v2 + y2 * v1 + y3];
-      L[m0 * QS0 + m1 * QS1 + m2 * QS2 + m3] = val;
+      L[m0 * QS0 + m1 * QS1 + m2 * QS2 + m3] = pre[e];
     }
     __syncthreads();
+    if (t + 1 < a.nterms) load_term(t + 1);
 #pragma unroll
     for (int e = 0; e < QPER; ++e) {
       const int lin = threadIdx.x + e * QTPB;
@@ -78,6 +93,49 @@ __global__ __launch_bounds__(QTPB) void perm_combine_kernel(double* __restrict__
   }
 }
 
+// C[m][n] += alpha * sum_k A[m*lda + k] * B[k*ldb + n] for a short K: a
+// streaming read-modify-write of C.  Each thread owns two adjacent columns
+// (16-byte loads and stores, consecutive threads on consecutive pairs) and
+// keeps their K values of B in registers; the block walks RM rows, reading
+// each row of A once (the same for every thread).
+constexpr int RK_MAX = 16;
+constexpr int RM = 16;
+
+__global__ __launch_bounds__(256) void rank_k_update_kernel(double* __restrict__ C, long long ldc,
+                                                            const double* __restrict__ A, long long lda,
+                                                            const double* __restrict__ B, long long ldb, int M,
+                                                            long long N, int K, double alpha) {
+  const long long n = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  const int m0 = blockIdx.y * RM;
+  __shared__ double As[RM * RK_MAX];
+  for (int i = threadIdx.x; i < RM * K; i += blockDim.x) {
+    const int r = i / K, k = i - r * K;
+    As[r * RK_MAX + k] = (m0 + r < M) ? A[(long long)(m0 + r) * lda + k] : 0.0;
+  }
+  __syncthreads();
+  if (n >= N) return;
+  double2 b[RK_MAX];
+#pragma unroll
+  for (int k = 0; k < RK_MAX; ++k)
+    if (k < K) b[k] = *reinterpret_cast<const double2*>(B + (long long)k * ldb + n);
+  const int mend = min(RM, M - m0);
+  for (int r = 0; r < mend; ++r) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < RK_MAX; ++k)
+      if (k < K) {
+        const double a = As[r * RK_MAX + k];
+        acc.x += a * b[k].x;
+        acc.y += a * b[k].y;
+      }
+    double2* c = reinterpret_cast<double2*>(C + (long long)(m0 + r) * ldc + n);
+    double2 cv = *c;
+    cv.x += alpha * acc.x;
+    cv.y += alpha * acc.y;
+    *c = cv;
+  }
+}
+
 }  // namespace
 
 hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStream_t s) {
@@ -99,6 +157,19 @@ hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStr
   const long long ntiles = (long long)nt * nt * nt * nt;
   if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(perm_combine_kernel, dim3((unsigned)ntiles), dim3(QTPB), 0, s, out, out2, a, nt);
+  return hipGetLastError();
+}
+
+hipError_t rank_k_update(double* C, long long ldc, const double* A, long long lda, const double* B, long long ldb,
+                         int M, long long N, int K, double alpha, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  if (K > RK_MAX || (N & 1) || (ldc & 1) || (ldb & 1) || ((uintptr_t)C & 15) || ((uintptr_t)B & 15))
+    return hipErrorInvalidValue;
+  const long long nx = (N / 2 + 255) / 256;
+  const long long ny = (M + RM - 1) / RM;
+  if (nx > 0x7fffffffLL || ny > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rank_k_update_kernel, dim3((unsigned)nx, (unsigned)ny), dim3(256), 0, s, C, ldc, A, lda, B, ldb,
+                     M, N, K, alpha);
   return hipGetLastError();
 }
 
