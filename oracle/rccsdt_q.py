@@ -122,3 +122,93 @@ def energy_q(f, V, t2, t3, o) -> float:
     """E_(Q) = 1/24 sum z tchk."""
     t4, z = quadruples(f, V, t2, t3, o)
     return float(_es("ijklabcd,ijklabcd->", z, spin_sum4(t4)) / 24.0)
+
+
+# ---------------------------------------------------------------------------
+# One occupied tuple at a time (sizes where the o^4 v^4 tensors do not fit)
+# ---------------------------------------------------------------------------
+
+def _blocks_for(V, t2, t3, o, q):
+    """X, Y and V blocks [a][b][c][d] of the ordered occupied tuple q, from
+    the same expressions as x_term, y_term and v_term with the occupied
+    indices fixed (t3 full [i][j][k][a][b][c])."""
+    q0, q1, q2, q3 = q
+    O, Vs = slice(0, o), slice(o, None)
+    X = (0.5 * np.tensordot(V[Vs, Vs, Vs, q1], t3[q0, q2, q3], axes=([2], [0]))
+         - 0.5 * np.tensordot(V[Vs, O, q0, q1], t3[:, q2, q3], axes=([1], [0])))
+    vvvv = V[Vs, Vs, Vs, Vs]
+    # Wbar_{e q1 q2}^{abc} = 1/2 sum_f v^{ab}_{ef} t_{q1 q2}^{fc} + 1/2 sum_f v^{ac}_{ef} t_{q2 q1}^{fb}, as [e][a][b][c]
+    w1 = 0.5 * np.tensordot(vvvv, t2[q1, q2], axes=([3], [0]))            # [a][b][e][c]
+    w2 = 0.5 * np.tensordot(vvvv, t2[q2, q1], axes=([3], [0]))            # [a][c][e][b]
+    Wv = w1.transpose(2, 0, 1, 3) + w2.transpose(2, 0, 3, 1)
+    Y = 0.5 * np.tensordot(Wv, t2[q0, q3], axes=([0], [0]))               # [a][b][c][d]
+
+    def g(i, j, k):  # the bracket of Wbar_ijk^abm as [a][b][m]
+        return (np.einsum("mae,be->abm", V[O, Vs, Vs, i], t2[j, k])
+                + np.einsum("mae,be->abm", V[O, Vs, k, Vs], t2[j, i])
+                - 0.5 * np.einsum("mn,nab->abm", V[O, O, k, i], t2[:, j]))
+
+    Wo = g(q0, q1, q2) + g(q1, q0, q2).transpose(1, 0, 2)
+    Y -= 0.5 * np.tensordot(Wo, t2[:, q3], axes=([2], [0]))
+    Vb = 0.25 * np.multiply.outer(V[Vs, Vs, q0, q1], t2[q2, q3])
+    return X, Y, Vb
+
+
+def spin_sum_block(u):
+    """spin_sum4 on one [a][b][c][d] block (the occupied labels fixed)."""
+    def swap(x, p, q):
+        ax = [0, 1, 2, 3]
+        ax[p], ax[q] = ax[q], ax[p]
+        return x.transpose(ax)
+    u1 = 2.0 * u - swap(u, 0, 1) - swap(u, 0, 2) - swap(u, 0, 3)
+    u2 = 2.0 * u1 - swap(u1, 1, 2) - swap(u1, 1, 3)
+    return 2.0 * (2.0 * u2 - swap(u2, 2, 3))
+
+
+def task_energy(f, V, t2, t3, o, task):
+    """Contribution of the occupied tuple task = (i, j, k, l), i <= j <= k <= l,
+    to E_(Q): sum over its distinct orderings q of sum_abcd (X + V)_q tchk_q,
+    with tchk_q the fully spin-summed t4 block at q.  t4 at the tuple itself
+    is the 24-permutation sum of (X + Y) blocks at the permuted tuples over
+    the denominator; at another ordering q = the tuple permuted by p, tchk_q
+    is tchk at the tuple with its virtual axes permuted the same way (the
+    column symmetry of the spin-summed amplitudes)."""
+    o_ = tuple(task)
+    e = np.diag(f)
+    eps_o = sum(e[x] for x in o_)
+    ev = e[o:]
+    den = eps_o - (ev[:, None, None, None] + ev[None, :, None, None] + ev[None, None, :, None]
+                   + ev[None, None, None, :])
+    cache = {}
+
+    def blocks(q):
+        if q not in cache:
+            cache[q] = _blocks_for(V, t2, t3, o, q)
+        return cache[q]
+
+    r = 0.0
+    for p in PERMS4:
+        # full-tensor convention of perm_sym4: out[o][w] += G[o'][w'] with o'_{p[k]} = o_k
+        qq = [0] * 4
+        for k in range(4):
+            qq[p[k]] = o_[k]
+        X, Y, _ = blocks(tuple(qq))
+        r = r + (X + Y).transpose(p)
+    U = spin_sum_block(r / den)
+    total = 0.0
+    seen = set()
+    for p in PERMS4:
+        qq = [0] * 4
+        for k in range(4):
+            qq[p[k]] = o_[k]
+        q = tuple(qq)
+        if q in seen:
+            continue
+        seen.add(q)
+        X, _, Vb = blocks(q)
+        # tchk_q[w'] with w'_{p[k]} = w_k equals U[w]: U transposed by the inverse of p
+        inv = [0] * 4
+        for k in range(4):
+            inv[p[k]] = k
+        total += float(np.sum((X + Vb) * U.transpose(inv)))
+    return total

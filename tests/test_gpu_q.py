@@ -128,3 +128,39 @@ def test_energy_q_argument_errors():
         # task array shorter than the 5 tasks of o = 2
         assert eng.lib.cct_energy_q(eng.h, C.byref(e), tasks.ctypes.data_as(C.POINTER(C.c_double)), 2) == \
             binding.CCT_EINVAL
+
+
+@pytest.mark.timeout(900)
+def test_energy_q_o10v90_sampled_tasks():
+    """At the measured workload (o=10 v=90, the configuration bench.py's (Q)
+    leg times): the per-task contributions of two sampled occupied tuples,
+    one with two repeated pairs (6 orderings) and one with one (12), against
+    the one-tuple oracle on the same amplitudes; the tasks sum to E_(Q)."""
+    s = ci.make_named("o10v90-scaled")
+    o, v, naux = s["o"], s["v"], s["naux"]
+    say("[energy_q] o10v90-scaled after 2 iterations, sampled tasks")
+    with binding.Engine(o, v, naux) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        for _ in range(2):
+            eng.update()
+        _, t2, t3p = eng.get_amplitudes()
+        e, tasks = eng.energy_q(tasks=True)
+    assert abs(e - float(np.sum(tasks))) <= 1e-12 * max(1.0, abs(e))
+    V = R.eri_phys_from_B(s["B"])
+    t3 = R.unpack_t3(t3p, o)
+    del t3p
+    index = {}
+    for i in range(o):
+        for j in range(i, o):
+            for k in range(j, o):
+                for l in range(k, o):
+                    index[(i, j, k, l)] = len(index)
+    scale = np.abs(tasks).max()
+    for task in [(0, 0, 1, 1), (0, 1, 1, 2)]:
+        ref = Q.task_energy(s["f"], V, t2, t3, o, task)
+        got = tasks[index[task]]
+        say(f"  task {task}: gpu {got:.15e} oracle {ref:.15e} diff {got - ref:.2e}")
+        assert abs(ref) > 1e-8
+        assert abs(got - ref) <= 1e-10 * scale

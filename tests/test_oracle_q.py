@@ -136,3 +136,26 @@ def test_spin_summed_quadruples_symmetry_and_vanishing_triples():
     A = Q.x_term(V, t3, o) + Q.v_term(V, t2, o)
     e_paper = np.einsum("ijklabcd,ijklabcd->", z, U) / 24.0
     assert abs(np.einsum("ijklabcd,ijklabcd->", A, U) - e_paper) < 1e-15
+
+
+@pytest.mark.parametrize("o,v,seed", [(3, 5, 2), (4, 6, 4)])
+def test_task_energy_matches_full_tensor_split(o, v, seed):
+    """The one-tuple-at-a-time oracle (for sizes where o^4 v^4 does not fit)
+    equals the full-tensor sum over each task's distinct orderings of
+    (X + V) . tchk, and the tasks add up to E_(Q)."""
+    import itertools
+    f, V = _system(o, v, seed, sigma=0.1)
+    t2, t3 = _amps(o, v, seed + 1)
+    t4, _ = Q.quadruples(f, V, t2, t3, o)
+    U = Q.spin_sum4(t4)
+    A = Q.x_term(V, t3, o) + Q.v_term(V, t2, o)
+    total = 0.0
+    for i in range(o):
+        for j in range(i, o):
+            for k in range(j, o):
+                for l in range(k, o):
+                    ref = sum(float(np.sum(A[q] * U[q])) for q in set(itertools.permutations((i, j, k, l))))
+                    got = Q.task_energy(f, V, t2, t3, o, (i, j, k, l))
+                    assert abs(got - ref) < 1e-15
+                    total += got
+    assert abs(total - Q.energy_q(f, V, t2, t3, o)) < 1e-14
