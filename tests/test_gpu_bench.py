@@ -45,6 +45,17 @@ def test_bench_prints_one_complete_json_line():
     assert set(d["batched"]["modes"]) == {"fp64", "bf16x3"}
 
 
+def test_bench_q_leg():
+    p = _bench("--workload", "o4v20", "--steps", "1", "--warmup", "0", "--compare", "", "--batched-iters", "0",
+               "--no-accuracy", "--no-cpu-baseline", "--autotune-ms", "0", "--q-workload", "o4v20")
+    assert p.returncode == 0, p.stderr[-2000:]
+    lines = [ln for ln in p.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1, p.stdout
+    q = json.loads(lines[0])["q"]
+    assert q["workload"] == "o4v20" and q["s"] > 0 and q["algorithmic_flop"] > 0
+    assert q["e_q"] != 0.0 and abs(q["frac"] - q["tflops"] / q["peak"]) < 1e-12
+
+
 def test_bench_refuses_more_than_one_gpu():
     p = _bench("--gpus", "2", timeout=60)
     assert p.returncode != 0
