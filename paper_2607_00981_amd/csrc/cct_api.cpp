@@ -1575,6 +1575,8 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   RCK(mem.get(&et, ntask + 1));
   RCK(mem.get(&ar, arena_n));
   RCK(mem.get(&slots, o2));
+  double* Bc;
+  RCK(mem.get(&Bc, 24 * v2));  // t2 blocks of the orderings sharing one Y1 product
   Arena qa;
   qa.init((char*)ar, (size_t)arena_n * 8);
   const Prec F = Prec::F64;
@@ -1707,18 +1709,72 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
             }
             sig[x].push_back(p);
           }
+          // slots in (q1, q2) order: orderings that share Wbar_{e q1 q2}^{abc}
+          // sit in adjacent slots and take one Y1 product between them
+          {
+            std::vector<size_t> ord(qs.size());
+            for (size_t x = 0; x < ord.size(); ++x) ord[x] = x;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t a1, size_t b1) {
+              return std::make_pair(qs[a1][1], qs[a1][2]) < std::make_pair(qs[b1][1], qs[b1][2]);
+            });
+            std::vector<std::array<int, 4>> qs2;
+            std::vector<std::vector<int>> sig2;
+            for (size_t x : ord) {
+              qs2.push_back(qs[x]);
+              sig2.push_back(sig[x]);
+            }
+            qs.swap(qs2);
+            sig.swap(sig2);
+          }
           QCombineArgs cr{};
           cr.v = v; cr.beta = 0.0;
           for (size_t x = 0; x < qs.size(); ++x) {
             const long long q0 = qs[x][0], q1 = qs[x][1], q2 = qs[x][2], q3 = qs[x][3];
             double* X = Xb + (long long)x * v4;
             double* G = Gb + (long long)x * v4;
+            // Y1 = 1/2 sum_e Wbar_{e q1 q2}^{abc} t_{q0 q3}^{ed} for this ordering and
+            // the following ones with the same (q1, q2): their t2 blocks side by side
+            // as the [e][(member, d)] operand, outputs to their adjacent slots
+            if (x == 0 || qs[x - 1][1] != q1 || qs[x - 1][2] != q2) {
+              size_t k = 1;
+              while (x + k < qs.size() && qs[x + k][1] == q1 && qs[x + k][2] == q2) ++k;
+              const double* Bm = ctx->t2 + (q0 * o + q3) * v2;
+              long long ldb = v;
+              if (k > 1) {
+                for (size_t j = 0; j < k; ++j)
+                  HIPCK(hipMemcpy2DAsync(Bc + (long long)j * v, sizeof(double) * k * v,
+                                         ctx->t2 + ((long long)qs[x + j][0] * o + qs[x + j][3]) * v2,
+                                         sizeof(double) * v, sizeof(double) * v, v, hipMemcpyDeviceToDevice, s));
+                Bm = Bc;
+                ldb = (long long)k * v;
+              }
+              const long long N = (long long)k * v;
+              const Idx2 cn = idx2(v, v4, 1);
+              const long long c_len = (24 - (long long)x) * v4;
+              if (nt_ok) {
+                NtArgs na{};
+                na.M = (int)v3; na.N = (int)N; na.K = v; na.batch = 1;
+                na.A = Wv + (q1 * o + q2) * v4; na.lda = v; na.B = Bm; na.ldb = ldb; na.b_kn = 1;
+                na.C = G; na.cm = idx1(v); na.cn = cn;
+                na.alpha = 0.5; na.beta = 0.0;
+                na.a_len = v4; na.b_len = (long long)v * ldb; na.c_len = c_len;
+                HIPCK(gemm_nt(na, F, s));
+              } else {
+                GemmArgs ga{};
+                ga.M = (int)v3; ga.N = (int)N; ga.K = v; ga.batch = 1;
+                ga.A = Wv + (q1 * o + q2) * v4; ga.am = idx1(v); ga.ak = idx1(1);
+                ga.B = Bm; ga.bk = idx1(ldb); ga.bn = idx1(1);
+                ga.C = G; ga.cm = idx1(v); ga.cn = cn;
+                ga.alpha = 0.5; ga.beta = 0.0;
+                ga.a_len = v4; ga.b_len = (long long)v * ldb; ga.c_len = c_len;
+                HIPCK(gemm(ga, F, s));
+              }
+            }
             // X = 1/2 sum_e v^{ab}_{e q1} t_{q0 q2 q3}^{ecd} - 1/2 sum_m v^{am}_{q0 q1} t_{m q2 q3}^{bcd}
             const double* t3r = T3u + (q2 * o + q3) * o * v3;
             RCK(gemm_x1_y1(VVVO + q1 * v3, v, t3r + q0 * v3, v2, X, v2, v2, 0.5));
             RCK(gemm_k_o(VOOO + (q0 * o + q1) * v * o, t3r, v3, X, v, v3));
-            // Y = 1/2 sum_e Wbar_{e q1 q2}^{abc} t_{q0 q3}^{ed} - 1/2 sum_m Wbar_{q0 q1 q2}^{abm} t_{m q3}^{cd}
-            RCK(gemm_x1_y1(Wv + (q1 * o + q2) * v4, v, ctx->t2 + (q0 * o + q3) * v2, v, G, v3, v, 0.5));
+            // Y2 = -1/2 sum_m Wbar_{q0 q1 q2}^{abm} t_{m q3}^{cd}
             RCK(gemm_k_o(Wo + ((q0 * o + q1) * o + q2) * v2 * o, ctx->t2 + q3 * v2, o * v2, G, v2, v2));
             // R gets X + Y under every permutation reaching q; Abar gets
             // X + 1/4 v^{ab}_{q0 q1} t_{q2 q3}^{cd} under the first of them
