@@ -152,3 +152,28 @@ def test_failing_allocator_gives_enomem_and_leaks_nothing():
             binding.Engine(3, 12, 30, allocator=alloc.pair())
         assert ei.value.code == binding.CCT_ENOMEM
         assert not alloc.live and not alloc.errors
+
+
+def test_energy_q_scratch_through_caller_allocator():
+    """cct_energy_q takes its scratch (bare integrals, Wbar, unpacked T3, the
+    task blocks) from the caller's allocator and returns every block before it
+    returns; the energy equals the library-allocated one bit for bit."""
+    o, v, seed = 3, 10, 41
+    say(f"[allocator] energy_q o={o} v={v}")
+    f, B, t1, t2, t3p = _system(o, v, seed)
+    alloc = CountingAllocator()
+    out = []
+    for allocator in (None, alloc.pair()):
+        with binding.Engine(o, v, B.shape[0], allocator=allocator) as eng:
+            eng.set_fock(f)
+            eng.set_eri_df(B)
+            eng.set_amplitudes(t1, t2, t3p)
+            before = dict(alloc.live)
+            calls = alloc.calls
+            out.append(eng.energy_q(tasks=True))
+            if allocator is not None:
+                assert alloc.calls > calls, "no scratch came from the caller's allocator"
+                assert alloc.live == before, "energy_q left scratch blocks allocated"
+    assert not alloc.live and not alloc.errors
+    (ea, ta), (eb, tb) = out
+    assert ea == eb and np.array_equal(ta, tb)
