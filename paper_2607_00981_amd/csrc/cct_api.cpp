@@ -1545,8 +1545,12 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   if (v3 > INT_MAX || o2 * o * v3 > LLONG_MAX / 8) { ctx->err = "energy_q: nvir too large"; return CCT_EINVAL; }
   hipStream_t s = ctx->s;
   const long long arena_n = std::max(v4, o2 * o2 * v2) + (8LL << 20);
+  // even v with o <= 16: the K=o updates write tile-major copies of the task
+  // blocks (XT, GT), which the permuted combine reads as contiguous tiles
+  const bool tl = (v % 2) == 0 && o <= 16;
+  const long long T4 = tiled_len(v);
   const long long need = n4 + v4 + (long long)o * v3 + o2 * o * v + o2 * v2 + o2 * v4 + 2 * o2 * o2 * v2 +
-                         o2 * o * v3 + 50 * v4 + ntask + 1 + arena_n;
+                         o2 * o * v3 + 50 * v4 + (tl ? 48 * T4 : 0) + ntask + 1 + arena_n;
   if (!ctx->alloc_fn) {
     size_t fr = 0, tot = 0;
     HIPCK(hipMemGetInfo(&fr, &tot));
@@ -1568,7 +1572,7 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   RCK(mem.get(&g, o2 * o2 * v2));
   RCK(mem.get(&Wo, o2 * o2 * v2));
   RCK(mem.get(&T3u, o2 * o * v3));
-  RCK(mem.get(&Xb, 24 * v4));  // X of each distinct ordering of a task
+  RCK(mem.get(&Xb, (tl ? 1 : 24) * v4));  // X of each distinct ordering of a task (tiled path: one scratch block)
   RCK(mem.get(&Gb, 24 * v4));  // Y of each distinct ordering
   RCK(mem.get(&Rb, v4));
   RCK(mem.get(&Ab, v4));
@@ -1577,6 +1581,11 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   RCK(mem.get(&slots, o2));
   double* Bc;
   RCK(mem.get(&Bc, 24 * v2));  // t2 blocks of the orderings sharing one Y1 product
+  double *XT = nullptr, *GT = nullptr;
+  if (tl) {
+    RCK(mem.get(&XT, 24 * T4));
+    RCK(mem.get(&GT, 24 * T4));
+  }
   Arena qa;
   qa.init((char*)ar, (size_t)arena_n * 8);
   const Prec F = Prec::F64;
@@ -1727,7 +1736,7 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
             sig.swap(sig2);
           }
           QCombineArgs cr{};
-          cr.v = v; cr.beta = 0.0;
+          cr.v = v; cr.beta = 0.0; cr.tiled = tl ? 1 : 0;
           for (size_t x = 0; x < qs.size(); ++x) {
             const long long q0 = qs[x][0], q1 = qs[x][1], q2 = qs[x][2], q3 = qs[x][3];
             double* X = Xb + (long long)x * v4;
@@ -1772,10 +1781,20 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
             }
             // X = 1/2 sum_e v^{ab}_{e q1} t_{q0 q2 q3}^{ecd} - 1/2 sum_m v^{am}_{q0 q1} t_{m q2 q3}^{bcd}
             const double* t3r = T3u + (q2 * o + q3) * o * v3;
+            if (tl) X = Xb;  // one plain-layout scratch block; the sum goes to XT[x]
             RCK(gemm_x1_y1(VVVO + q1 * v3, v, t3r + q0 * v3, v2, X, v2, v2, 0.5));
-            RCK(gemm_k_o(VOOO + (q0 * o + q1) * v * o, t3r, v3, X, v, v3));
+            const double* VO = VOOO + (q0 * o + q1) * v * o;
             // Y2 = -1/2 sum_m Wbar_{q0 q1 q2}^{abm} t_{m q3}^{cd}
-            RCK(gemm_k_o(Wo + ((q0 * o + q1) * o + q2) * v2 * o, ctx->t2 + q3 * v2, o * v2, G, v2, v2));
+            const double* WO = Wo + ((q0 * o + q1) * o + q2) * v2 * o;
+            if (tl) {
+              HIPCK(rank_k_update_tiled(X, XT + (long long)x * T4, v, 1, VO, o, t3r, v3, o, -0.5, s));
+              HIPCK(rank_k_update_tiled(G, GT + (long long)x * T4, v, 2, WO, o, ctx->t2 + q3 * v2, o * v2, o, -0.5, s));
+              X = XT + (long long)x * T4;
+              G = GT + (long long)x * T4;
+            } else {
+              RCK(gemm_k_o(VO, t3r, v3, X, v, v3));
+              RCK(gemm_k_o(WO, ctx->t2 + q3 * v2, o * v2, G, v2, v2));
+            }
             // R gets X + Y under every permutation reaching q; Abar gets
             // X + 1/4 v^{ab}_{q0 q1} t_{q2 q3}^{cd} under the first of them
             for (size_t k = 0; k < sig[x].size(); ++k) {

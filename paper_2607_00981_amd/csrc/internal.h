@@ -259,6 +259,7 @@ struct QCombineArgs {
   double beta;
   const double* eps_v;  // device, v virtual orbital energies (nullptr: no division)
   double eps_occ;       // sum of the four occupied orbital energies
+  int tiled;            // 1: every input is tile-major (see rank_k_update_tiled)
 };
 hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStream_t s);
 // C[m][n] += alpha * sum_{k<K} A[m*lda + k] * B[k*ldb + n], m < M, n < N, C
@@ -266,5 +267,17 @@ hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStr
 // and 16-byte aligned C and B (hipErrorInvalidValue otherwise).
 hipError_t rank_k_update(double* C, long long ldc, const double* A, long long lda, const double* B, long long ldb,
                          int M, long long N, int K, double alpha, hipStream_t s);
+// The same update of a v^4 block C (row-major [a][b][c][d]; rows m cover the
+// first rsplit of the four axes, columns n the rest) written to D in the
+// tile-major layout instead of back to C: 8^4 tiles of 4096 consecutive
+// doubles, tiles in row-major order over ceil(v/8)^4, elements inside a tile
+// row-major; padding positions are not written.  Requires v even.
+hipError_t rank_k_update_tiled(const double* C, double* D, int v, int rsplit, const double* A, long long lda,
+                               const double* B, long long ldb, int K, double alpha, hipStream_t s);
+// Elements of a tile-major v^4 block (padded to whole tiles).
+static inline long long tiled_len(int v) {
+  const long long nt = (v + 7) / 8;
+  return nt * nt * nt * nt * 4096;
+}
 
 }  // namespace cct

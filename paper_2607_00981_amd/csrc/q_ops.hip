@@ -15,6 +15,7 @@ constexpr int QS0 = QT * QS1 + 1;
 constexpr int QTPB = 256;
 constexpr int QPER = QT * QT * QT * QT / QTPB;  // output elements per thread
 
+template <bool TILED>
 __global__ __launch_bounds__(QTPB) void perm_combine_kernel(double* __restrict__ out, double* __restrict__ out2,
                                                             QCombineArgs a, int nt) {
   __shared__ double L[QT * QS0];
@@ -38,6 +39,16 @@ __global__ __launch_bounds__(QTPB) void perm_combine_kernel(double* __restrict__
     int sorg[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) sorg[k] = org[T.perm[k]];
+    if (TILED) {
+      // the source tile is one contiguous run of 4096 doubles; its padding
+      // positions only reach outputs outside [0, v)^4, which are not stored
+      const long long ti = (((long long)(sorg[0] >> 3) * nt + (sorg[1] >> 3)) * nt + (sorg[2] >> 3)) * nt +
+                           (sorg[3] >> 3);
+      const double* src = T.in + ti * 4096;
+#pragma unroll
+      for (int e = 0; e < QPER; ++e) pre[e] = src[threadIdx.x + e * QTPB];
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < QPER; ++e) {
       const int lin = threadIdx.x + e * QTPB;
@@ -136,6 +147,49 @@ __global__ __launch_bounds__(256) void rank_k_update_kernel(double* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void rank_k_update_tiled_kernel(const double* __restrict__ C, double* __restrict__ D,
+                                                                  int v, int rsplit, long long M, long long N,
+                                                                  const double* __restrict__ A, long long lda,
+                                                                  const double* __restrict__ B, long long ldb, int K,
+                                                                  double alpha, int nt) {
+  const long long n = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x);
+  const long long m0 = (long long)blockIdx.y * RM;
+  __shared__ double As[RM * RK_MAX];
+  for (int i = threadIdx.x; i < RM * K; i += blockDim.x) {
+    const int r = i / K, k = i - r * K;
+    As[r * RK_MAX + k] = (m0 + r < M) ? A[(m0 + r) * lda + k] : 0.0;
+  }
+  __syncthreads();
+  if (n >= N) return;
+  double2 b[RK_MAX];
+#pragma unroll
+  for (int k = 0; k < RK_MAX; ++k)
+    if (k < K) b[k] = *reinterpret_cast<const double2*>(B + (long long)k * ldb + n);
+  // axes of column n: (c, d) when rows cover (a, b); (b, c, d) when rows cover a
+  const int d = (int)(n % v);
+  const int c = (int)((n / v) % v);
+  const int bcol = rsplit == 1 ? (int)(n / ((long long)v * v)) : 0;
+  const long long mend = min((long long)RM, M - m0);
+  for (long long r = 0; r < mend; ++r) {
+    const long long m = m0 + r;
+    const int a = rsplit == 1 ? (int)m : (int)(m / v);
+    const int bb = rsplit == 1 ? bcol : (int)(m % v);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < RK_MAX; ++k)
+      if (k < K) {
+        const double x = As[r * RK_MAX + k];
+        acc.x += x * b[k].x;
+        acc.y += x * b[k].y;
+      }
+    double2 cv = *reinterpret_cast<const double2*>(C + m * N + n);
+    cv.x += alpha * acc.x;
+    cv.y += alpha * acc.y;
+    const long long ti = (((long long)(a >> 3) * nt + (bb >> 3)) * nt + (c >> 3)) * nt + (d >> 3);
+    *reinterpret_cast<double2*>(D + ti * 4096 + (((a & 7) * 8 + (bb & 7)) * 8 + (c & 7)) * 8 + (d & 7)) = cv;
+  }
+}
+
 }  // namespace
 
 hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStream_t s) {
@@ -156,7 +210,10 @@ hipError_t perm_combine(double* out, double* out2, const QCombineArgs& a, hipStr
   const int nt = (a.v + QT - 1) / QT;
   const long long ntiles = (long long)nt * nt * nt * nt;
   if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(perm_combine_kernel, dim3((unsigned)ntiles), dim3(QTPB), 0, s, out, out2, a, nt);
+  if (a.tiled)
+    hipLaunchKernelGGL(perm_combine_kernel<true>, dim3((unsigned)ntiles), dim3(QTPB), 0, s, out, out2, a, nt);
+  else
+    hipLaunchKernelGGL(perm_combine_kernel<false>, dim3((unsigned)ntiles), dim3(QTPB), 0, s, out, out2, a, nt);
   return hipGetLastError();
 }
 
@@ -170,6 +227,24 @@ hipError_t rank_k_update(double* C, long long ldc, const double* A, long long ld
   if (nx > 0x7fffffffLL || ny > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rank_k_update_kernel, dim3((unsigned)nx, (unsigned)ny), dim3(256), 0, s, C, ldc, A, lda, B, ldb,
                      M, N, K, alpha);
+  return hipGetLastError();
+}
+
+hipError_t rank_k_update_tiled(const double* C, double* D, int v, int rsplit, const double* A, long long lda,
+                               const double* B, long long ldb, int K, double alpha, hipStream_t s) {
+  if (v <= 0 || K <= 0) return hipSuccess;
+  if ((v & 1) || K > RK_MAX || (rsplit != 1 && rsplit != 2) || (ldb & 1) || ((uintptr_t)C & 15) ||
+      ((uintptr_t)B & 15) || ((uintptr_t)D & 15))
+    return hipErrorInvalidValue;
+  const long long v2 = (long long)v * v;
+  const long long M = rsplit == 1 ? v : v2;
+  const long long N = rsplit == 1 ? v2 * v : v2;
+  const long long nx = (N / 2 + 255) / 256;
+  const long long ny = (M + RM - 1) / RM;
+  if (nx > 0x7fffffffLL || ny > 65535) return hipErrorInvalidValue;
+  const int nt = (v + 7) / 8;
+  hipLaunchKernelGGL(rank_k_update_tiled_kernel, dim3((unsigned)nx, (unsigned)ny), dim3(256), 0, s, C, D, v, rsplit, M,
+                     N, A, lda, B, ldb, K, alpha, nt);
   return hipGetLastError();
 }
 
