@@ -325,8 +325,8 @@ def main():
     ap.add_argument("--slab", action="store_true",
                     help="only the block-local terms of a 64-triple slab at o=50 v=400 (FP32 and split-BF16)")
     ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
-    ap.add_argument("--q-workload", default="", metavar="NAME",
-                    help="also time the (Q) correction on this workload (e.g. o10v90-scaled); off by default")
+    ap.add_argument("--q-workload", default="o10v90-scaled", metavar="NAME",
+                    help="also time the (Q) correction on this workload ('none' skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
@@ -440,7 +440,8 @@ def main():
     if not args.no_accuracy:
         out["accuracy"] = run_accuracy(binding, [args.precision] + [m for m in args.compare.split(",")
                                                                     if m and m != args.precision])
-    if args.q_workload:
+    if args.q_workload and args.q_workload != "none":
+        log(f"[bench] (Q) correction on {args.q_workload} ...")
         out["q"] = run_q(binding, args.q_workload)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")

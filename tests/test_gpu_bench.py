@@ -25,7 +25,7 @@ def _bench(*args, timeout=240):
 
 def test_bench_prints_one_complete_json_line():
     p = _bench("--workload", "o4v20", "--steps", "2", "--warmup", "1", "--compare", "bf16x3", "--batched-iters", "2",
-               "--no-accuracy", "--autotune-ms", "100")
+               "--no-accuracy", "--autotune-ms", "100", "--q-workload", "none")
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [ln for ln in p.stdout.splitlines() if ln.strip()]
     assert len(lines) == 1, p.stdout
