@@ -277,7 +277,29 @@ def q_macs(o, v):
     return nord * (2 * v ** 5 + 2 * o * v ** 4 + v ** 4) + 2 * o * o * v ** 5
 
 
-def run_q(binding, name, reps=2):
+def q_cpu_baseline(s, t2, t3p, task=(0, 0, 1, 1)):
+    """Time the one-tuple (Q) oracle on one task of the same workload and
+    amplitudes (a bounded sample); rate with the GPU path's algorithmic count
+    for the task's orderings."""
+    from oracle import rccsdt as R, rccsdt_q as Q  # test infrastructure, CPU only
+    import itertools
+
+    o, v = s["o"], s["v"]
+    V = R.eri_phys_from_B(s["B"])
+    t3 = R.unpack_t3(t3p, o)
+    t0 = time.time()
+    e = Q.task_energy(s["f"], V, t2, t3, o, task)
+    dt = time.time() - t0
+    nq = len(set(itertools.permutations(task)))
+    flop = 2.0 * nq * (2 * v ** 5 + 2 * o * v ** 4 + v ** 4)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": flop / dt / 1e12, "unit": "TFLOP/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": (f"task {task} ({nq} orderings) of E_(Q) at o={o} v={v}: {dt:.1f} s, energy {e:.6e}; rate uses "
+                       f"the GPU path's count for these orderings (the oracle also rebuilds Wbar per ordering)")}
+
+
+def run_q(binding, name, reps=2, cpu=True):
     """E_(Q) on a named workload after two FP64 iterations from the MP2 guess
     (T3 non-zero): wall time of cct_energy_q (setup of the intermediates and
     the task loop), algorithmic FLOP rate against the FP64 MFMA peak."""
@@ -289,6 +311,7 @@ def run_q(binding, name, reps=2):
         eng.init_mp2()
         for _ in range(2):
             eng.update()
+        amps = eng.get_amplitudes() if cpu else None
         times, e = [], None
         for _ in range(reps):
             t0 = time.perf_counter()
@@ -297,8 +320,13 @@ def run_q(binding, name, reps=2):
             log(f"[bench] (Q) {name}: E_(Q) = {e:.12f} in {times[-1]:.2f} s")
     wall = min(times)
     flop = 2.0 * q_macs(o, v)
-    return {"workload": name, "e_q": e, "s": wall, "algorithmic_flop": flop, "tflops": flop / wall / 1e12,
-            "peak": PEAK["fp64"], "frac": flop / wall / 1e12 / PEAK["fp64"]}
+    out = {"workload": name, "e_q": e, "s": wall, "algorithmic_flop": flop, "tflops": flop / wall / 1e12,
+           "peak": PEAK["fp64"], "frac": flop / wall / 1e12 / PEAK["fp64"]}
+    if cpu:
+        log("[bench] (Q) cpu baseline (oracle, one task) ...")
+        out["cpu_baseline"] = q_cpu_baseline(s, amps[1], amps[2])
+        log(f"[bench] (Q) cpu baseline: {out['cpu_baseline']}")
+    return out
 
 
 def main():
@@ -442,7 +470,7 @@ def main():
                                                                     if m and m != args.precision])
     if args.q_workload and args.q_workload != "none":
         log(f"[bench] (Q) correction on {args.q_workload} ...")
-        out["q"] = run_q(binding, args.q_workload)
+        out["q"] = run_q(binding, args.q_workload, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)
