@@ -89,3 +89,13 @@ def test_q_task_count_formula():
         n = sum(1 for i in range(o) for j in range(i, o) for k in range(j, o) for l in range(k, o))
         assert binding.q_task_count(o) == n
     assert binding.q_task_count(-1) == -1
+
+
+def test_q_task_count_reproduces_the_papers_printed_counts():
+    import math
+    rows = [list(map(int, ln.split())) for ln in open(os.path.join(ROOT, "tests", "golden", "q_task_counts.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for v, blk, n, tasks in rows:
+        assert math.ceil(v / blk) == n
+        assert binding.q_task_count(n) == tasks
