@@ -162,10 +162,15 @@ int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters
  * tasks with three equal indices contribute exactly 0).  e_tasks (may be
  * NULL; else cap >= cct_q_task_count entries, host memory) receives each
  * task's contribution; *e_q their fixed-order sum.  Needs, beyond the
- * context, about 8 * (n^4 + o^2 v^4 + o^3 v^3 + 6 v^4 + 2 o^4 v^2) bytes of
- * device memory for the duration of the call (n = o + v): CCT_ENOMEM if that
- * is not free; CCT_EINVAL for nocc > 40; CCT_ESTATE before cct_set_fock /
- * cct_set_eri_df.  Synchronous (returns after the stream has drained). */
+ * context and for the duration of the call (n = o + v), about
+ * 8 * (n^4 + o^2 v^4 + o^3 v^3 + 2 o^4 v^2 + 28 v^4 + 48 * 4096 ceil(v/8)^4)
+ * bytes of device memory for even v and nocc <= 16 (the task blocks are also
+ * kept tile-major), else 8 * (n^4 + o^2 v^4 + o^3 v^3 + 2 o^4 v^2 + 52 v^4)
+ * (about 110 GB at o=10, v=90): CCT_ENOMEM if that is not free (checked
+ * before allocating when the library allocates; a caller's allocator is
+ * asked block by block); CCT_EINVAL for nocc > 40; CCT_ESTATE before
+ * cct_set_fock / cct_set_eri_df.  Synchronous (returns after the stream has
+ * drained). */
 int cct_energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap);
 /* Number of (Q) tasks, i <= j <= k <= l < nocc: nocc(nocc+1)(nocc+2)(nocc+3)/24
  * (-1 for nocc < 0). */
