@@ -6,26 +6,52 @@ feedback, the whole triples residual R3 on packed i<=j<=k blocks,
 post-processing, Jacobi update, DIIS on T1/T2, energy) on one MI355X, with all
 inputs resident in device memory.  Prints one JSON line.
 
+Workload: o=20 v=180 naux=400 seed 3 with the density-fitting entries drawn at
+standard deviation 0.05 sqrt(48/400) (the variance-scaled variant of the named
+recipe: the same shapes and the same work per iteration, but a coupled-cluster
+iteration that stays bounded from the MP2 guess; with 0.05 the energy grows
+without bound after the first step).  Each mode starts from the MP2 guess.
+
+Wall budget.  The run is capped by --budget-s (wall seconds from the start of
+the process).  The main mode always runs one untimed iteration (T3 non-zero
+from then on) and at least one timed one; the number of timed steps is the
+requested one or as many as fit the main mode's share of the budget, and the
+further requested warm-up iterations run (before the timed steps) only if the
+budget has room for them beyond those.
+"steps" and "warmup" report what ran; "steps_requested" and
+"warmup_requested" what was asked.  The comparison modes, the batch and the
+optional legs run within what is left and are skipped (and named in
+"skipped") when their estimate does not fit.
+
   value        R3 FLOP one iteration executes (2 x the compact multiply-add
                count, the ladder at its symmetric/antisymmetric count) / wall
                time of the step, TFLOP/s; value_direct_count uses the direct
                ladder count instead
-  ms_per_step  seconds per CCSDT iteration x 1000
+  ms_per_step  seconds per CCSDT iteration x 1000 (mean over timed steps)
   roofline     the particle-particle ladder GEMMs (the dominant kernel):
                executed FLOP per launch / average launch time from HIP
                events on the library's stream, against the mode's matrix peak
-  cpu_baseline the FP64 oracle on one sampled output block of the same
-               workload, rate in the same unit
+  cpu_baseline the FP64 oracle on sampled output blocks of the ladder at the
+               same sizes, rate on the same FLOP basis as value
+  modes        per precision mode: seconds per iteration, speedup over the
+               main mode, max |R3(mode) - R3(main)| / max |R3(main)| on
+               sampled packed blocks of the residual evaluated on the state
+               after one iteration (identical in every mode: T3 = 0 at the
+               MP2 guess, so the mixed contractions first act in iteration
+               2), and E(mode) - E(main) after the third iteration
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
 
+_now = time.perf_counter  # the clock of every budget decision and timed step
+T_START = _now()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -35,22 +61,86 @@ import cct_inputs as ci  # noqa: E402
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+# seconds per iteration relative to FP64 (measured at o=20 v=180), for
+# budgeting the comparison modes before they run
+REL_COST = {"fp64": 1.0, "fp32": 0.75, "bf16x3": 0.4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pp_ladder_gemm_o20v180_traffic.json")
+# packed triples whose R3 blocks are compared between modes (distinct,
+# repeated first pair, repeated last pair, first and last blocks)
+SAMPLE_TRIPLES = ((0, 0, 1), (0, 1, 2), (0, 1, 1), (3, 7, 11), (5, 9, 9), (17, 18, 19), (18, 18, 19))
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(o, v, naux, seed):
-    """Time the oracle on packed output blocks of the PP ladder (the dominant
-    term) at the same sizes, about 10 s of work; report the algorithmic rate."""
-    from oracle import blocks  # test infrastructure, CPU only
-    from oracle import counts
+def elapsed():
+    return _now() - T_START
 
-    s = ci.make_system(o, v, naux, seed)
-    B = s["B"]
-    # MP2 amplitudes of this workload (the state the timed step starts from)
+
+# ---------------------------------------------------------------------------
+# budget logic (host only)
+# ---------------------------------------------------------------------------
+def plan_steps(requested: int, per_step_s: float, available_s: float) -> int:
+    """Timed steps that fit available_s at per_step_s each: at least one (the
+    metric needs a measurement), at most the requested count."""
+    if requested <= 0:
+        return 0
+    if per_step_s <= 0:
+        return requested
+    return max(1, min(requested, int(math.floor(available_s / per_step_s))))
+
+
+def plan_extra_warmup(requested_extra: int, per_step_s: float, available_s: float) -> int:
+    """Further untimed iterations (beyond the first) that fit what the timed
+    steps leave; none when the budget is spent."""
+    if requested_extra <= 0 or per_step_s <= 0:
+        return max(0, requested_extra) if per_step_s <= 0 else 0
+    return max(0, min(requested_extra, int(math.floor(available_s / per_step_s))))
+
+
+def compare_reserve(modes, t_iter_main: float, setup_s: float, iters: int = 3, rel=None) -> float:
+    """Estimated seconds for the comparison modes: setup plus `iters`
+    iterations each, scaled from the main mode's iteration time."""
+    rel = rel or REL_COST
+    return sum(setup_s + iters * rel.get(m, 1.0) * t_iter_main for m in modes)
+
+
+def sample_offsets(o: int, v: int):
+    """(triple, first element, count) of the sampled packed R3 blocks that exist at this o."""
+    out = []
+    for ijk in SAMPLE_TRIPLES:
+        if max(ijk) < o:
+            t = ci.packed_triples(o).index(tuple(ijk))
+            out.append((tuple(ijk), t * v ** 3, v ** 3))
+    seen, uniq = set(), []
+    for rec in out:
+        if rec[1] not in seen:
+            seen.add(rec[1])
+            uniq.append(rec)
+    return uniq
+
+
+def ladder_split_macs_per_block(v: int) -> float:
+    """Multiply-adds of the symmetric/antisymmetric ladder per packed block:
+    three terms, each v free virtuals x v(v+1)/2 output pairs x (v(v+1)/2 +
+    v(v-1)/2) = v^2 summed pairs."""
+    p = v * (v + 1) / 2.0
+    return 3.0 * v * p * v * v
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on sampled blocks
+# ---------------------------------------------------------------------------
+def cpu_baseline(s, budget_s=10.0, max_blocks=12):
+    """Time the oracle on packed output blocks of the PP ladder (the dominant
+    term) at the same sizes, about budget_s of work; report the rate on the
+    main value's basis (the split ladder's executed count) and on the direct
+    count."""
+    from oracle import blocks  # test infrastructure, CPU only
+
+    o, v, B = s["o"], s["v"], s["B"]
+    # MP2 amplitudes of this workload (the state the iteration starts from)
     Bov = B[:, :o, o:]
     vovov = np.einsum("Pia,Pjb->ijab", Bov, Bov, optimize=True)
     e = np.diag(s["f"])
@@ -59,39 +149,40 @@ def cpu_baseline(o, v, naux, seed):
     t1 = np.zeros((o, v))
     tri = ci.packed_triples(o)
     idx = len(tri) // 2
-    blk = ci.hashed_t3_block(v, 77, idx, tri[idx])
     Bt = blocks.dressed_factors(B, t1)
     t0 = time.time()
     W = blocks.w_vvvv(Bt, t2, o)
     t_w = time.time() - t0
-    # time whole blocks (oracle work only, not their generation) until at
-    # least 10 s have been spent, at most 12 blocks
-    t_b = 0.0
-    nblk = 0
-    while t_b < 10.0 and nblk < 12:
+    t_b, nblk = 0.0, 0
+    while t_b < budget_s and nblk < max_blocks:
         n = (idx + nblk) % len(tri)
-        blk_n = blk if nblk == 0 else ci.hashed_t3_block(v, 77, n, tri[n])
+        blk_n = ci.hashed_t3_block(v, 77, n, tri[n])
         tb = time.time()
         r = blocks.postprocess_block(blocks.pp_block(W, blk_n, tri[n]), tri[n])
         t_b += time.time() - tb
         nblk += 1
         assert np.isfinite(r).all()
-    # algorithmic FLOP of this sample in the metric's definition: the compact
-    # particle-particle ladder work of one packed block (3 v^5 multiply-adds)
-    flops = nblk * 2.0 * counts.r3_macs(o, v)["pp"] / counts.ntri(o)
+    del W
+    flops_split = nblk * 2.0 * ladder_split_macs_per_block(v)
+    flops_direct = nblk * 2.0 * 3.0 * v ** 5
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {
-        "value": flops / t_b / 1e12,
+        "value": flops_split / t_b / 1e12,
         "unit": "TFLOP/s",
         "cores": min(cores, threads),
         "kind": "oracle",
+        "value_direct_count": flops_direct / t_b / 1e12,
         "sample": (f"{nblk} packed blocks from (i,j,k)={tri[idx]} on of R3 (particle-particle ladder by its "
-                   f"definition, 6 column permutations, + post-processing) at o={o} v={v}; {t_b:.1f} s; rate uses the "
-                   f"compact per-block ladder work 3 v^5; W^ab_de build ({t_w:.1f} s) excluded"),
+                   f"definition, 6 column permutations, + post-processing) at o={o} v={v}; {t_b:.1f} s of oracle "
+                   f"work; value counts the split ladder's 1.5 v^4 (v+1) multiply-adds per block (the basis of the "
+                   f"GPU value), value_direct_count the direct 3 v^5; W^ab_de build ({t_w:.1f} s) excluded"),
     }
 
 
+# ---------------------------------------------------------------------------
+# one precision mode
+# ---------------------------------------------------------------------------
 NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64,64,2,2,2>", 4: "<128,128,2,2,2>",
             5: "<256,32,4,1,2>", 6: "<32,256,1,4,2>"}
 LP_TILES = {"fp32": {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"},
@@ -105,57 +196,116 @@ def kernel_name(prec, variant):
     return f"gemm_lp_{prec.replace('fp32', 'f32')}_kernel" + LP_TILES[prec].get(variant, str(variant))
 
 
-def run_mode(binding, s, o, v, naux, prec, steps, warmup, tune_ms=0.0):
-    """Warmup + timed iterations from the MP2 guess in one precision mode
-    (tile variants autotuned first when tune_ms > 0, outside the timed steps)."""
+def run_mode(binding, s, prec, steps, warmup, tune_ms, samples, end_of, *, main=True):
+    """One precision mode from the MP2 guess: autotune (outside the timed
+    steps), one untimed iteration, then timed iterations.  end_of(t_it) gives
+    the wall time (seconds from the start of the process) by which the mode
+    should be done, from its iteration time.  Main mode: the requested number
+    of timed steps or as many as fit (at least one), preceded by the remaining
+    requested warm-ups if the budget has room for them too.  Comparison mode:
+    up to `steps` timed iterations while the next one fits.  Every cct_update ends with a
+    synchronisation of the library's stream (energy and norms are read back),
+    so the host clock around each call brackets exactly its device work.
+    After the second iteration overall the sampled R3 blocks (the residual of
+    the state after one iteration) are copied out, outside any timing."""
+    o, v, naux = s["o"], s["v"], s["naux"]
+    t_setup0 = _now()
     eng = binding.Engine(o, v, naux, precision=prec,
                          opts={"timers": True, "diis_t3": "none" if o >= 20 else "full"})
+    energies, norms, step_s = [], [], []
+    r3_samples = None
+    phase_ms = {k: 0.0 for k in binding.PHASES}
+    lad = {"ms": 0.0, "macs": 0.0, "launches": 0.0}
+    macs = None
     try:
         eng.set_fock(s["f"])
         eng.set_eri_df(s["B"])
         eng.init_mp2()
         variants = eng.autotune(tune_ms) if tune_ms > 0 else (0, 0)
-        log(f"[bench] {prec}: tile variants ladder={variants[0]} rings={variants[1]}")
-        # every cct_update ends with a synchronisation of the library's stream
-        # (the energy and norms are read back), so the host clock brackets
-        # exactly the device work of the timed steps.
-        for w in range(warmup):
+        setup_s = _now() - t_setup0
+        log(f"[bench] {prec}: setup {setup_s:.1f} s, tile variants ladder={variants[0]} rings={variants[1]}")
+
+        def iterate(tag):
+            nonlocal r3_samples
+            t0 = _now()
             e, nr = eng.update()
-            log(f"[bench] {prec} warmup {w}: E={e:.10f}")
-        phase_ms = {k: 0.0 for k in binding.PHASES}
-        lad = {"ms": 0.0, "macs": 0.0, "launches": 0.0}
-        t0 = time.perf_counter()
-        for st in range(steps):
-            e, nr = eng.update()
+            dt = _now() - t0
+            energies.append(e)
+            norms.append(float(np.sqrt(nr.sum())))
+            log(f"[bench] {prec} {tag}: E={e:.12f} |R|={norms[-1]:.3e} {dt:.2f} s (t={elapsed():.0f} s)")
+            if len(energies) == 2 and samples:
+                r3_samples = [eng.copy_r3(first, count) for _, first, count in samples]
+            return dt
+
+        def timed_step(k):
+            nonlocal macs
+            step_s.append(iterate(f"step {k}"))
             macs, ms = eng.counters()
-            for k in phase_ms:
-                phase_ms[k] += ms[k]
+            for key in phase_ms:
+                phase_ms[key] += ms[key]
             lad["ms"] += ms["ladder_gemm"]
             lad["macs"] += macs["ladder_gemm"]
             lad["launches"] += macs["ladder_launches"]
-            log(f"[bench] {prec} step {st}: E={e:.10f} |R|={np.sqrt(nr.sum()):.3e}")
-        wall = time.perf_counter() - t0
+
+        warm_done = 0
+        if warmup > 0:
+            # the first iteration (from T3 = 0) runs a few per cent faster than
+            # later ones; the estimate is padded accordingly
+            t_it = 1.05 * iterate("warmup 0")
+            warm_done = 1
+        else:
+            timed_step(0)
+            t_it = step_s[0]
+        end = end_of(t_it)
+        todo = steps - len(step_s)
+        if main:
+            n_steps = plan_steps(todo, t_it, end - elapsed()) if todo > 0 else 0
+            extra = plan_extra_warmup(warmup - warm_done, t_it, end - elapsed() - n_steps * t_it)
+            log(f"[bench] {prec}: ~{t_it:.2f} s per iteration; {n_steps + len(step_s)} timed steps of {steps} "
+                f"and {warm_done + extra} warm-up iterations of {warmup} requested fit the mode's budget "
+                f"(ends at t={end:.0f} s)")
+            for k in range(extra):
+                iterate(f"warmup {warm_done + k}")
+            warm_done += extra
+            for k in range(n_steps):
+                timed_step(len(step_s))
+        else:
+            for k in range(max(todo, 1 if not step_s else 0)):
+                if step_s and elapsed() + t_it > end:
+                    break
+                timed_step(len(step_s))
     finally:
         eng.close()
+    n = len(step_s)
     term_macs = {k: macs[k] for k in binding.TERMS}
     # multiply-adds the step executes: the ladder at what its GEMMs ran (the
     # symmetric/antisymmetric form halves the direct count), the rest as counted
     r3_macs_direct = sum(term_macs.values())
-    r3_macs = r3_macs_direct - term_macs["PP"] + lad["macs"] / steps
-    r3_ms = sum(phase_ms[k] for k in ("pp", "rings", "hh_f2", "drivers", "f1")) / steps
+    r3_macs = r3_macs_direct - term_macs["PP"] + lad["macs"] / n
+    r3_ms = sum(phase_ms[k] for k in ("pp", "rings", "hh_f2", "drivers", "f1")) / n
     return {
-        "ms_per_step": 1000.0 * wall / steps,
-        "energy": e,
-        "macs": term_macs,
-        "r3_macs": r3_macs,
-        "r3_macs_direct": r3_macs_direct,
+        "steps": n, "warmup": warm_done, "setup_s": setup_s, "ms_per_step": 1000.0 * sum(step_s) / n,
+        "step_s": step_s, "energies": energies, "norms": norms, "energy": energies[-1], "macs": term_macs,
+        "r3_macs": r3_macs, "r3_macs_direct": r3_macs_direct,
         "r3_tflops": 2.0 * r3_macs / (r3_ms / 1000.0) / 1e12,
-        "phase_ms": {k: x / steps for k, x in phase_ms.items()},
-        "ladder_gemm": {"ms": lad["ms"] / steps, "macs": lad["macs"] / steps, "launches": lad["launches"] / steps},
-        "tile_variants": {"ladder": variants[0], "rings": variants[1]},
+        "phase_ms": {k: x / n for k, x in phase_ms.items()},
+        "ladder_gemm": {"ms": lad["ms"] / n, "macs": lad["macs"] / n, "launches": lad["launches"] / n},
+        "tile_variants": {"ladder": variants[0], "rings": variants[1]}, "r3_samples": r3_samples,
     }
 
 
+def r3_deviation(ref, got):
+    """max |got - ref| / max |ref| over the sampled blocks."""
+    if ref is None or got is None:
+        return None
+    num = max(float(np.abs(g - r).max()) for r, g in zip(ref, got))
+    den = max(float(np.abs(r).max()) for r in ref)
+    return num / den if den > 0 else None
+
+
+# ---------------------------------------------------------------------------
+# optional legs
+# ---------------------------------------------------------------------------
 def run_batched(binding, niter, modes, tune_ms=0.0, graph=True, streams=4):
     """The 64-system batch (o uniform in 3..8, v in 20..60, seeded): niter
     iterations from the MP2 guess per mode, one graph replay per iteration.
@@ -170,14 +320,14 @@ def run_batched(binding, niter, modes, tune_ms=0.0, graph=True, streams=4):
     for prec in modes:
         with binding.Batch([(o, v, na) for o, v, na, _ in sizes], precision=prec,
                            opts={"graph": graph, "streams": streams}) as b:
-            for k, s in enumerate(systems):
-                b.set_system(k, s["f"], s["B"])
+            for k, sy in enumerate(systems):
+                b.set_system(k, sy["f"], sy["B"])
             if tune_ms > 0:
                 b.autotune(tune_ms)
             b.iterate(1)
-            t0 = time.perf_counter()
+            t0 = _now()
             e, nr = b.iterate(niter - 1)
-            dt = time.perf_counter() - t0
+            dt = _now() - t0
         rec = {"systems_per_s": len(sizes) * (niter - 1) / dt, "s_per_batch_iteration": dt / (niter - 1)}
         if e_ref is None:
             e_ref = e
@@ -195,10 +345,9 @@ def run_batched(binding, niter, modes, tune_ms=0.0, graph=True, streams=4):
 
 
 def run_accuracy(binding, modes, tol=1e-8, max_iter=150):
-    """Converged energy per mode on o=10 v=90 with variance-scaled integrals
-    (the named recipe has no solution reachable from MP2 at this size): FP64
-    runs DIIS to |R| < tol; each other mode runs as many iterations; dE is
-    measured against the FP64 energy."""
+    """Converged energy per mode on o=10 v=90 with variance-scaled integrals:
+    FP64 runs DIIS to |R| < tol; each other mode runs as many iterations; dE
+    is measured against the FP64 energy."""
     s = ci.make_named("o10v90-scaled")
     o, v, naux = s["o"], s["v"], s["naux"]
     out = {"workload": "o=10 v=90 naux=200 seed 2, B entries N(0, 0.05 sqrt(48/naux)), DIIS on T1/T2/T3, "
@@ -209,13 +358,13 @@ def run_accuracy(binding, modes, tol=1e-8, max_iter=150):
             eng.set_fock(s["f"])
             eng.set_eri_df(s["B"])
             eng.init_mp2()
-            t0 = time.perf_counter()
+            t0 = _now()
             for it in range(n_iter):
                 e, nr = eng.update()
                 nrm = float(np.sqrt(nr.sum()))
                 if e_ref is None and nrm < tol:
                     break
-            wall = time.perf_counter() - t0
+            wall = _now() - t0
         rec = {"energy": e, "iterations": it + 1, "residual_norm": nrm, "s": wall}
         if e_ref is None:
             e_ref, n_iter = e, it + 1
@@ -253,9 +402,9 @@ def run_slab(binding, modes, panel):
             sl.set_intermediates(Bt, t2, Fvv, Wt, Wvooo)
             sl.set_t3(t3)
             log(f"[bench] slab {prec}: inputs uploaded in {time.time() - t1_:.1f} s; residual ...")
-            tr = time.perf_counter()
+            tr = _now()
             _, n2 = sl.residual(want_r3=False)
-            wall = time.perf_counter() - tr
+            wall = _now() - tr
             macs, ms = sl.counters()
         step_macs = macs["ladder"] + macs["f_vv"] + macs["driver_vvvo"] + macs["driver_vooo"]
         rec = {"s_per_residual": wall, "tflops": 2.0 * step_macs / wall / 1e12,
@@ -314,9 +463,9 @@ def run_q(binding, name, reps=2, cpu=True):
         amps = eng.get_amplitudes() if cpu else None
         times, e = [], None
         for _ in range(reps):
-            t0 = time.perf_counter()
+            t0 = _now()
             e = eng.energy_q()
-            times.append(time.perf_counter() - t0)
+            times.append(_now() - t0)
             log(f"[bench] (Q) {name}: E_(Q) = {e:.12f} in {times[-1]:.2f} s")
     wall = min(times)
     flop = 2.0 * q_macs(o, v)
@@ -329,23 +478,46 @@ def run_q(binding, name, reps=2, cpu=True):
     return out
 
 
-def main():
+# ---------------------------------------------------------------------------
+def stored_traffic(prec, workload, kernel):
+    """HBM bytes per launch of the ladder GEMM from the committed counter
+    summary, when it was taken on this mode, workload and kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        tf = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if (tf.get("precision") == prec and tf.get("workload") == workload.split("-")[0] and tf.get("form") == "split"
+            and tf.get("kernel") == kernel):
+        return tf.get("bytes_per_launch")
+    return None
+
+
+def main(argv=None, binding=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1,
-                    help="untimed iterations first (one makes T3 non-zero, so every term contracts real data)")
+                    help="untimed iterations (the first one makes T3 non-zero, so every term contracts real data)")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall seconds for the whole run, counted from the start of the process")
     ap.add_argument("--precision", default="fp64", choices=list(PEAK),
                     help="mode whose rate is the reported value")
-    ap.add_argument("--compare", default="fp32,bf16x3",
-                    help="further modes run from the same start for speedup and dE ('' for none)")
-    ap.add_argument("--workload", default="o20v180", choices=list(ci.CONFIGS))
+    ap.add_argument("--compare", default="bf16x3,fp32",
+                    help="further modes run from the same start for speedup, R3 deviation and dE ('' for none)")
+    ap.add_argument("--compare-steps", type=int, default=2,
+                    help="timed iterations per comparison mode (after its untimed first one)")
+    ap.add_argument("--workload", default="o20v180-scaled",
+                    help="named workload (o4v20, o10v90, o20v180; '-scaled' for the variance-scaled integrals)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle work timed for cpu_baseline")
     ap.add_argument("--autotune-ms", type=float, default=3000.0,
                     help="tile autotuning budget per mode before the timed steps (0: size-based defaults)")
     ap.add_argument("--batched-iters", type=int, default=5,
                     help="iterations of the 64-system batch per mode (0 skips it)")
-    ap.add_argument("--no-accuracy", action="store_true", help="skip the converged-energy comparison of the modes")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="also the converged-energy comparison of the modes on o10v90-scaled")
     ap.add_argument("--batched-graph", type=int, default=1, help="1: replay a recorded graph, 0: enqueue eagerly")
     ap.add_argument("--batched-streams", type=int, default=4, help="streams the batch's systems are spread over")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -353,9 +525,9 @@ def main():
     ap.add_argument("--slab", action="store_true",
                     help="only the block-local terms of a 64-triple slab at o=50 v=400 (FP32 and split-BF16)")
     ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
-    ap.add_argument("--q-workload", default="o10v90-scaled", metavar="NAME",
-                    help="also time the (Q) correction on this workload ('none' skips it)")
-    args = ap.parse_args()
+    ap.add_argument("--q-workload", default="none", metavar="NAME",
+                    help="also time the (Q) correction on this workload (e.g. o10v90-scaled)")
+    args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (the multi-GPU path is a "
                                    "design only, sharded by packed triples)"}))
@@ -373,7 +545,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
         return
 
-    from paper_2607_00981_amd import binding
+    if binding is None:
+        from paper_2607_00981_amd import binding
 
     if args.slab:
         modes = [m for m in ("fp32", "bf16x3") if m in [args.precision] + args.compare.split(",")]
@@ -397,83 +570,131 @@ def main():
         }), flush=True)
         return
 
-    o, v, naux, seed = ci.CONFIGS[args.workload]
-    s = ci.make_system(o, v, naux, seed)
-    log(f"[bench] o={o} v={v} naux={naux} seed={seed} precision={args.precision}")
-    main_run = run_mode(binding, s, o, v, naux, args.precision, args.steps, args.warmup, args.autotune_ms)
-    macs, phase_ms, ms_step, e = main_run["macs"], main_run["phase_ms"], main_run["ms_per_step"], main_run["energy"]
+    budget_end = args.budget_s
+    s = ci.make_named(args.workload)
+    o, v, naux, seed = s["o"], s["v"], s["naux"], s["seed"]
+    sigma = ci.scaled_sigma(naux) if args.workload.endswith("-scaled") else 0.05
+    compare = [m for m in args.compare.split(",") if m and m != args.precision]
+    samples = sample_offsets(o, v)
+    log(f"[bench] {args.workload}: o={o} v={v} naux={naux} seed={seed} sigma={sigma:.6g} main={args.precision} "
+        f"compare={compare} budget {args.budget_s:.0f} s")
+
+    # the main mode's share of the budget: what the comparison modes, the
+    # batch and the CPU baseline are estimated to need is kept back; the
+    # estimate scales with the iteration time, known after the first one
+    est_setup = 20.0
+    est_cpu = 0.0 if args.no_cpu_baseline else args.cpu_seconds + 15.0
+    est_batch = 45.0 if args.batched_iters > 1 else 0.0
+
+    def main_end(t_it):
+        return (budget_end - compare_reserve(compare, t_it, est_setup, 1 + max(args.compare_steps, 0))
+                - est_cpu - est_batch - 5.0)
+
+    skipped = []
+    main_run = run_mode(binding, s, args.precision, args.steps, args.warmup, args.autotune_ms, samples, main_end)
+    log(f"[bench] main mode done at t={elapsed():.0f} s")
+    ms_step = main_run["ms_per_step"]
+    t_it_main = ms_step / 1000.0
     value = 2.0 * main_run["r3_macs"] / (ms_step / 1000.0) / 1e12
-    # dominant kernel: the particle-particle ladder GEMMs (executed FLOP and
-    # device time of those launches alone, from HIP events on the library's
-    # stream around each group of launches)
     lad = main_run["ladder_gemm"]
     achieved = 2.0 * lad["macs"] / (lad["ms"] / 1000.0) / 1e12 if lad["ms"] > 0 else None
     peak = PEAK[args.precision]
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    kname = kernel_name(args.precision, main_run["tile_variants"]["ladder"])
+    traffic = stored_traffic(args.precision, args.workload, kname)
+    e_main = main_run["energies"]
+    modes = {args.precision: {"s_per_iteration": t_it_main, "r3_tflops": main_run["r3_tflops"],
+                              "energies": e_main, "residual_norms": main_run["norms"], "speedup": 1.0,
+                              "tile_variants": main_run["tile_variants"], "steps": main_run["steps"]}}
+    for prec in compare:
+        est = compare_reserve([prec], t_it_main, main_run["setup_s"], 1 + max(args.compare_steps, 0))
+        if elapsed() + est > budget_end - est_cpu:
+            skipped.append(f"mode {prec} (estimated {est:.0f} s, {budget_end - elapsed():.0f} s left)")
+            log(f"[bench] skipping {prec}: estimate {est:.0f} s does not fit")
+            continue
         try:
-            tf = json.load(open(TRAFFIC_FILE))
-            if (tf.get("precision") == args.precision and tf.get("workload") == args.workload and
-                    tf.get("form") == "split" and tf.get("kernel") == kernel_name(args.precision,
-                                                                                   main_run["tile_variants"]["ladder"])):
-                traffic = tf.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    modes = {args.precision: {"s_per_iteration": ms_step / 1000.0, "r3_tflops": main_run["r3_tflops"],
-                              "energy": e, "speedup": 1.0, "dE": 0.0, "dE_rel": 0.0,
-                              "tile_variants": main_run["tile_variants"]}}
-    for prec in [m for m in args.compare.split(",") if m and m != args.precision]:
-        r = run_mode(binding, s, o, v, naux, prec, args.steps, args.warmup, args.autotune_ms)
-        modes[prec] = {"s_per_iteration": r["ms_per_step"] / 1000.0, "r3_tflops": r["r3_tflops"],
-                       "energy": r["energy"], "speedup": ms_step / r["ms_per_step"],
-                       "dE": r["energy"] - e, "dE_rel": (r["energy"] - e) / max(abs(e), 1e-300),
-                       "phase_ms": r["phase_ms"], "tile_variants": r["tile_variants"]}
+            r = run_mode(binding, s, prec, args.compare_steps, 1, args.autotune_ms, samples,
+                         lambda _t: budget_end - est_cpu, main=False)
+        except binding.CCTError as exc:
+            modes[prec] = {"error": str(exc)}
+            log(f"[bench] {prec} failed: {exc}")
+            continue
+        rec = {"s_per_iteration": r["ms_per_step"] / 1000.0, "r3_tflops": r["r3_tflops"], "energies": r["energies"],
+               "residual_norms": r["norms"], "speedup": ms_step / r["ms_per_step"], "phase_ms": r["phase_ms"],
+               "tile_variants": r["tile_variants"], "steps": r["steps"],
+               "r3_rel_dev": r3_deviation(main_run["r3_samples"], r["r3_samples"])}
+        n_cmp = min(len(e_main), len(r["energies"]))
+        if n_cmp >= 1:
+            dE = r["energies"][n_cmp - 1] - e_main[n_cmp - 1]
+            rec.update({"dE": dE, "dE_rel": dE / max(abs(e_main[n_cmp - 1]), 1e-300), "dE_after_iterations": n_cmp})
+        modes[prec] = rec
+        log(f"[bench] {prec}: {r['ms_per_step'] / 1000:.2f} s/iteration, R3 deviation {rec['r3_rel_dev']}, "
+            f"dE {rec.get('dE')}")
     out = {
         "metric": "T3-residual TFLOP/s + s/CCSDT iteration, FP64 vs mixed, o=20 v=180, dE vs oracle",
         "value": value,
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": main_run["steps"],
+        "warmup": main_run["warmup"],
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"RCCSDT iteration o={o} v={v} naux={naux} seed={seed}, compact T3 "
-                               f"({o*(o+1)*(o+2)//6} triples x {v}^3), MP2 start, DIIS on T1/T2",
+        "config": {"workload": f"RCCSDT iteration o={o} v={v} naux={naux} seed={seed}, B entries N(0, {sigma:.6g}) "
+                               f"({'variance-scaled' if sigma != 0.05 else 'named'} recipe), compact T3 "
+                               f"({o*(o+1)*(o+2)//6} triples x {v}^3), MP2 start, one untimed iteration, "
+                               f"DIIS on T1/T2",
                    "precision": args.precision},
-        "s_per_iteration": ms_step / 1000.0,
+        "s_per_iteration": t_it_main,
+        "step_s": main_run["step_s"],
         "r3_tflops": main_run["r3_tflops"],
         "value_direct_count": 2.0 * main_run["r3_macs_direct"] / (ms_step / 1000.0) / 1e12,
-        "phase_ms": phase_ms,
+        "phase_ms": main_run["phase_ms"],
         "modes": modes,
-        "modes_note": ("each mode runs warmup+steps iterations from the same MP2 guess (T3 = 0); dE = E(mode) - "
-                       f"E({args.precision}) after the last step, exactly 0 for fewer than 3 iterations since the "
-                       "mixed contractions act on T3, which reaches the energy two iterations later; converged "
-                       "dE per mode: 'accuracy'"),
+        "modes_note": ("every mode starts from the same MP2 guess; after one iteration the state is identical in "
+                       "every mode (T3 = 0 at the guess, so the mixed contractions contribute nothing in it); "
+                       "r3_rel_dev = max|R3(mode) - R3(main)| / max|R3(main)| over the sampled packed blocks "
+                       f"{[t for t, _, _ in samples]} of the residual of that state (iteration 2); dE = E(mode) - "
+                       "E(main) after the same number of iterations (dE_after_iterations; the mixed contractions "
+                       "reach the energy from iteration 3 on)"),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak if achieved else None, "traffic": traffic,
-                     "kernel": kernel_name(args.precision, main_run["tile_variants"]["ladder"]) +
-                               " (particle-particle ladder GEMMs)",
+                     "traffic_source": ("profiles/pp_ladder_gemm_o20v180_fp64_traffic.md (FETCH_SIZE + WRITE_SIZE, "
+                                        "copy-calibrated, stored; not measured by this run)") if traffic else None,
+                     "kernel": kname + " (particle-particle ladder GEMMs)",
                      "launches_per_step": lad["launches"], "ms_per_launch": lad["ms"] / max(lad["launches"], 1),
                      "flop_per_launch": 2.0 * lad["macs"] / max(lad["launches"], 1)},
-        "energy": e,
+        "energy": main_run["energy"],
     }
     if args.batched_iters > 1:
-        out["batched"] = run_batched(binding, args.batched_iters,
-                                     [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision],
-                                     args.autotune_ms, bool(args.batched_graph), args.batched_streams)
-    if not args.no_accuracy:
-        out["accuracy"] = run_accuracy(binding, [args.precision] + [m for m in args.compare.split(",")
-                                                                    if m and m != args.precision])
+        if elapsed() + est_batch > budget_end - est_cpu:
+            skipped.append("batch leg")
+        else:
+            try:
+                out["batched"] = run_batched(binding, args.batched_iters, [args.precision] + compare,
+                                             args.autotune_ms, bool(args.batched_graph), args.batched_streams)
+            except binding.CCTError as exc:
+                out["batched"] = {"error": str(exc)}
+    if args.accuracy:
+        if elapsed() + 90.0 > budget_end - est_cpu:
+            skipped.append("accuracy leg")
+        else:
+            out["accuracy"] = run_accuracy(binding, [args.precision] + compare)
     if args.q_workload and args.q_workload != "none":
-        log(f"[bench] (Q) correction on {args.q_workload} ...")
-        out["q"] = run_q(binding, args.q_workload, cpu=not args.no_cpu_baseline)
+        if elapsed() + 120.0 > budget_end - est_cpu:
+            skipped.append("(Q) leg")
+        else:
+            log(f"[bench] (Q) correction on {args.q_workload} ...")
+            out["q"] = run_q(binding, args.q_workload, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(o, v, naux, seed)
+        out["cpu_baseline"] = cpu_baseline(s, budget_s=args.cpu_seconds)
+    out["skipped"] = skipped
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

@@ -182,9 +182,13 @@ int64_t cct_q_task_count(int nocc);
  * 4 HH+F2, 5 drivers, 6 F1, 7 post+update, 8 DIIS+energy).  Entry 9: the
  * multiply-adds the ladder GEMMs executed (half the PP count in the
  * symmetric/antisymmetric form) and their device time alone (timers on);
- * entry 10: the number of ladder GEMM launches (ms: 0).  The per-term counts
- * are the direct-traversal ones whichever ladder form ran.  cap = length of
- * both arrays provided; writes min(cap, 11). */
+ * entry 10: the number of ladder GEMM launches (ms: 0).  Entries 11-18 (ms:
+ * 0) describe the batch plan the context's workspace allows: the number of
+ * batches of the T3 feedback, of rings A, B and C, of the hole ladder, of
+ * the two T2 drivers (entries 11-17, fixed at cct_create), and the chunks of
+ * packed blocks the last ladder evaluation took (entry 18).  The per-term
+ * counts are the direct-traversal ones whichever ladder form ran.  cap =
+ * length of both arrays provided; writes min(cap, 19). */
 int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, int cap);
 
 /* Tile autotuner: times every tile variant of the particle-particle ladder

@@ -20,6 +20,7 @@ TERMS = {"D1": 1 << 0, "D2": 1 << 1, "F1": 1 << 2, "F2": 1 << 3, "RA": 1 << 4, "
          "RC": 1 << 6, "HH": 1 << 7, "PP": 1 << 8}
 TERM_ALL = 0x1FF
 PHASES = ("ccsd", "feedback", "pp", "rings", "hh_f2", "drivers", "f1", "post", "diis_energy")
+BATCH_PLAN = ("feedback", "ring_a", "ring_b", "ring_c", "hh", "d1", "d2", "ladder_chunks")
 
 _lib = None
 
@@ -253,14 +254,21 @@ class Engine:
         """(macs per R3 term group, ms per phase); the ladder GEMMs alone
         appear as macs['ladder_gemm'] / ms['ladder_gemm'] (executed
         multiply-adds, device time) and macs['ladder_launches']."""
-        macs = np.zeros(11)
-        ms = np.zeros(11)
-        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 11))
+        macs = np.zeros(19)
+        ms = np.zeros(19)
+        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), _ptr(ms), 19))
         m = dict(zip(TERMS.keys(), macs[:9]))
         t = dict(zip(PHASES, ms[:9]))
         m["ladder_gemm"], t["ladder_gemm"] = float(macs[9]), float(ms[9])
         m["ladder_launches"] = float(macs[10])
         return m, t
+
+    def batch_plan(self):
+        """Batches per unpack-and-contract job (fixed by the workspace) and
+        the ladder chunks of the last residual."""
+        macs = np.zeros(19)
+        self._check(self.lib.cct_get_counters(self.h, _ptr(macs), None, 19))
+        return {k: int(x) for k, x in zip(BATCH_PLAN, macs[11:19])}
 
 
 class _SystemView(Engine):

@@ -122,6 +122,7 @@ struct cct_ctx {
   std::vector<hipEvent_t> lad_ev;
   int lad_nev = 0;
   double lad_macs = 0.0, lad_launches = 0.0, lad_ms = 0.0;
+  long long lad_chunks = 0;  // chunks of packed blocks the last ladder took
 };
 
 namespace {
@@ -895,6 +896,7 @@ int r3_pp_lp(cct_ctx* ctx, const Idx2 cm[3], const Idx2 cn[3]) {
   long long chunk = (long long)(ws.available() / 4 / (size_t)v3) - 1;
   if (chunk < 1) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
   if (chunk > nt) chunk = nt;
+  ctx->lad_chunks = (nt + chunk - 1) / chunk;
   void* Tc = alloc_lp(ws, chunk * v3);
   if (!Tc) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
   for (long long t0 = 0; t0 < nt; t0 += chunk) {
@@ -961,6 +963,7 @@ int r3_pp_split(cct_ctx* ctx) {
   long long chunk = (long long)(ws.available() / (size_t)per_block) - 1;
   if (chunk < 1) { ctx->err = "workspace exhausted (ladder split)"; return CCT_ENOMEM; }
   if (chunk > nt) chunk = nt;
+  ctx->lad_chunks = (nt + chunk - 1) / chunk;
   void* Ap = alloc_b(chunk * v * pp * esz);
   void* Am = alloc_b(chunk * v * pq * esz);
   void* Cp = alloc_b(chunk * v * P * csz);
@@ -1086,6 +1089,7 @@ int r3_pp(cct_ctx* ctx) {
   long long chunk = (long long)(ws.available() / sizeof(double) / (size_t)v3) - 1;
   if (chunk < 1) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
   if (chunk > nt) chunk = nt;
+  ctx->lad_chunks = (nt + chunk - 1) / chunk;
   double* Tc = ws.alloc((size_t)(chunk * v3));
   if (!Tc) { ctx->err = "workspace exhausted (ladder copy)"; return CCT_ENOMEM; }
   for (int term = 1; term >= 0; --term) {
@@ -1406,6 +1410,7 @@ int enqueue_residual(cct_ctx* ctx, unsigned mask, bool update_t3) {
   ctx->ws.reset(0);  // the arena holds only per-evaluation scratch; drop what a failed call left
   ctx->lad_nev = 0;
   ctx->lad_macs = ctx->lad_launches = ctx->lad_ms = 0.0;
+  ctx->lad_chunks = 0;
   mark(ctx, 0);
   RCK(dress(ctx));
   RCK(ccsd_part(ctx));
@@ -1898,9 +1903,11 @@ int diis_step(cct_ctx* ctx) {
   HIPCK(axpby(-1.0, ctx->diis_old, 1.0, err, L, ctx->s));
   ctx->diis_next = (slot + 1) % M;
   ctx->diis_n = std::min(ctx->diis_n + 1, M);
-  // new row of the overlap matrix (stored slots are 0..diis_n-1 in ring order)
+  // new row of the overlap matrix against the slots in use: the diis_n
+  // newest of the ring, the new one included (an eviction after a singular
+  // system can leave them anywhere in the ring)
   std::vector<int> slots;
-  for (int k = 0; k < ctx->diis_n; ++k) slots.push_back(k);
+  for (int k = 0; k < ctx->diis_n; ++k) slots.push_back((ctx->diis_next - ctx->diis_n + k + M) % M);
   for (int k : slots) {
     RCK(diis_dot(ctx, err, ctx->derr[k], ctx->scal + 8 + 2 * k));
   }
@@ -1955,8 +1962,11 @@ int diis_step(cct_ctx* ctx) {
       }
     }
     if (singular) {
+      // the oldest vector leaves the history for good (later iterations do
+      // not see it either); with one vector left the Jacobi step stands
       if (m <= 1) return CCT_OK;
       order.erase(order.begin());
+      ctx->diis_n -= 1;
       continue;
     }
     // T = sum_m c_m vec_m.  With a T3 subspace the extrapolated sub-cubes are
@@ -2541,6 +2551,16 @@ int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, in
   if (cap > 10) {
     if (macs_by_term) macs_by_term[10] = ctx->lad_launches;
     if (ms_by_phase) ms_by_phase[10] = 0.0;
+  }
+  // batch plan: how many batches each unpack-and-contract job takes with
+  // this context's workspace, and the ladder's chunks of packed blocks
+  const double plan[8] = {(double)ctx->feed1.batches.size(), (double)ctx->ring[0].batches.size(),
+                          (double)ctx->ring[1].batches.size(), (double)ctx->ring[2].batches.size(),
+                          (double)ctx->hh.batches.size(), (double)ctx->d1.batches.size(),
+                          (double)ctx->d2.batches.size(), (double)ctx->lad_chunks};
+  for (int i = 11; i < std::min(cap, 19); ++i) {
+    if (macs_by_term) macs_by_term[i] = plan[i - 11];
+    if (ms_by_phase) ms_by_phase[i] = 0.0;
   }
   return CCT_OK;
 }

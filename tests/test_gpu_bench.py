@@ -25,7 +25,7 @@ def _bench(*args, timeout=240):
 
 def test_bench_prints_one_complete_json_line():
     p = _bench("--workload", "o4v20", "--steps", "2", "--warmup", "1", "--compare", "bf16x3", "--batched-iters", "2",
-               "--no-accuracy", "--autotune-ms", "100", "--q-workload", "none")
+               "--autotune-ms", "100", "--q-workload", "none")
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [ln for ln in p.stdout.splitlines() if ln.strip()]
     assert len(lines) == 1, p.stdout
@@ -41,13 +41,17 @@ def test_bench_prints_one_complete_json_line():
     assert r["achieved"] > 0 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
-    assert set(d["modes"]) == {"fp64", "bf16x3"}
+    assert set(d["modes"]) == {"fp64", "bf16x3"} and not d["skipped"]
+    m = d["modes"]["bf16x3"]
+    # the mode comparison is taken on the same state (iteration-2 residual)
+    assert 0.0 < m["r3_rel_dev"] < 5e-5 and m["dE_after_iterations"] == 3 and abs(m["dE"]) < 1e-6
+    assert d["modes"]["fp64"]["energies"][0] == m["energies"][0]
     assert set(d["batched"]["modes"]) == {"fp64", "bf16x3"}
 
 
 def test_bench_q_leg():
     p = _bench("--workload", "o4v20", "--steps", "1", "--warmup", "0", "--compare", "", "--batched-iters", "0",
-               "--no-accuracy", "--no-cpu-baseline", "--autotune-ms", "0", "--q-workload", "o4v20")
+               "--no-cpu-baseline", "--autotune-ms", "0", "--q-workload", "o4v20")
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [ln for ln in p.stdout.splitlines() if ln.strip()]
     assert len(lines) == 1, p.stdout

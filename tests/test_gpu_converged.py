@@ -97,3 +97,44 @@ def test_o10v90_first_iterations_match_oracle_golden():
             assert abs(e - e_ref) < 1e-10
             for a, b in zip(nr, (r1, r2, r3)):
                 assert abs(a - b) <= 1e-10 * max(1.0, b)
+
+
+def test_o10v90_residual_elements_match_oracle_golden():
+    """The o=10 v=90 workload (variance-scaled integrals), the residual on the
+    state after one iteration from the MP2 guess, element by element against
+    the oracle: all of R1, 4000 sampled R2 and 10000 sampled R3 elements
+    (blocks with distinct indices, i=j<k, i<j=k, and i=j=k blocks, which must
+    be exactly zero), stored by tests/golden/make_o10v90_scaled_residual.py.
+    Tolerance: 1e-10 of the largest element of each residual."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "o10v90_scaled_residual.txt")
+    rows = {"R1": [], "R2": [], "R3": []}
+    scale = {}
+    for ln in open(path):
+        if ln.startswith("# max_abs"):
+            p = ln.split()
+            scale = {p[2]: float(p[3]), p[4]: float(p[5]), p[6]: float(p[7])}
+        if ln.strip() and not ln.startswith("#"):
+            p = ln.split()
+            rows[p[0]].append(([int(x) for x in p[1:-1]], float(p[-1])))
+    s = ci.make_named("o10v90-scaled")
+    o, v, naux = s["o"], s["v"], s["naux"]
+    print(f"[o10v90 residual golden] {', '.join(f'{k}: {len(x)}' for k, x in rows.items())}", flush=True)
+    with binding.Engine(o, v, naux, opts={"diis_t3": "none"}) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        eng.update()
+        r1, r2, r3p, _ = eng.residual()
+    tri = {t: n for n, t in enumerate(ci.packed_triples(o))}
+    got = {"R1": [r1[i, a] for (i, a), _ in rows["R1"]],
+           "R2": [r2[i, j, a, b] for (i, j, a, b), _ in rows["R2"]],
+           "R3": [r3p[tri[(i, j, k)], a, b, c] for (i, j, k, a, b, c), _ in rows["R3"]]}
+    for name in ("R1", "R2", "R3"):
+        ref = np.array([x for _, x in rows[name]])
+        g = np.array(got[name])
+        err = float(np.abs(g - ref).max())
+        print(f"  {name}: max err {err:.3e} of max |R| {scale[name]:.3e}", flush=True)
+        assert err <= 1e-10 * scale[name]
+    iii = [n for n, ((i, j, k, *_), _) in enumerate(rows["R3"]) if i == j == k]
+    assert iii and all(got["R3"][n] == 0.0 for n in iii)

@@ -55,3 +55,96 @@ def test_slab_and_batch_errors():
         with pytest.raises(binding.CCTError) as e:
             b.iterate(1)
         assert e.value.code == binding.CCT_ESTATE
+
+
+def _ready(o, v, naux, seed, **kw):
+    s = ci.make_system(o, v, naux, seed, sigma=ci.scaled_sigma(naux))
+    eng = binding.Engine(o, v, naux, **kw)
+    eng.set_fock(s["f"])
+    eng.set_eri_df(s["B"])
+    eng.init_mp2()
+    return eng, s
+
+
+def test_non_finite_amplitudes_give_enumeric_and_the_context_recovers():
+    o, v, naux = 3, 10, 26
+    eng, s = _ready(o, v, naux, 11)
+    with eng:
+        t1, t2, t3 = eng.get_amplitudes()
+        t1[1, 2] = np.nan
+        eng.set_amplitudes(t1, t2, t3)
+        with pytest.raises(binding.CCTError) as e:
+            eng.update()
+        assert e.value.code == binding.CCT_ENUMERIC
+        t3 = np.zeros((binding.ntri(o), v, v, v))
+        t3[1, 0, 1, 2] = np.inf
+        eng.set_amplitudes(np.zeros((o, v)), np.zeros((o, o, v, v)), t3)
+        with pytest.raises(binding.CCTError) as e:
+            eng.update()
+        assert e.value.code == binding.CCT_ENUMERIC
+        eng.init_mp2()
+        e1, nr = eng.update()
+        assert np.isfinite(e1) and np.isfinite(nr).all()
+
+
+def test_solve_reports_not_converged_with_the_last_energy():
+    o, v, naux = 3, 10, 26
+    eng, s = _ready(o, v, naux, 12)
+    with eng:
+        lib = binding.load()
+        e = binding.C.c_double()
+        it = binding.C.c_int()
+        rc = lib.cct_solve(eng.h, 3, 1e-14, binding.C.byref(e), binding.C.byref(it))
+        assert rc == binding.CCT_ENOTCONV
+        assert it.value == 3 and np.isfinite(e.value) and e.value != 0.0
+    eng2, _ = _ready(o, v, naux, 12)
+    with eng2:
+        es = [eng2.update()[0] for _ in range(3)]
+    assert es[-1] == e.value
+
+
+def test_restart_from_saved_amplitudes_is_deterministic():
+    """Amplitudes copied out after some iterations and copied into a fresh
+    context (DIIS history cleared in both) continue bit for bit alike."""
+    o, v, naux = 3, 12, 30
+    eng, s = _ready(o, v, naux, 13)
+    with eng:
+        for _ in range(4):
+            eng.update()
+        saved = eng.get_amplitudes()
+        eng.set_amplitudes(*saved)
+        ea = [eng.update()[0] for _ in range(3)]
+        ta = eng.get_amplitudes()
+    fresh = binding.Engine(o, v, naux)
+    with fresh:
+        fresh.set_fock(s["f"])
+        fresh.set_eri_df(s["B"])
+        fresh.set_amplitudes(*saved)
+        eb = [fresh.update()[0] for _ in range(3)]
+        tb = fresh.get_amplitudes()
+    assert ea == eb
+    for x, y in zip(ta, tb):
+        assert np.array_equal(x, y)
+
+
+def test_singular_diis_system_evicts_and_matches_the_oracle():
+    """Vanishing integrals make every error vector zero, so every bordered
+    DIIS system is singular: the oldest vector is dropped (permanently, as in
+    the oracle) and the Jacobi step stands; energies stay exactly zero."""
+    from oracle import rccsdt as R
+
+    o, v, naux = 2, 6, 16
+    s = ci.make_system(o, v, naux, 14)
+    B0 = np.zeros_like(s["B"])
+    with binding.Engine(o, v, naux) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(B0)
+        eng.init_mp2()
+        out = [eng.update() for _ in range(5)]
+    d = R.DIIS()
+    V = R.eri_phys_from_B(B0)
+    t1, t2, t3 = R.mp2_guess(s["f"], V, o)
+    for e, nr in out:
+        t1, t2, t3, eo, no = R.iterate(s["f"], V, t1, t2, t3, o, diis=d)
+        assert e == eo == 0.0 and np.all(nr == 0.0)
+    assert len(d.vecs) == 1

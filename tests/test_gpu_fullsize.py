@@ -115,3 +115,48 @@ def test_slab_o50v400_sampled_elements():
                 assert g == 0.0
             else:
                 assert abs(g - r) <= 1e-4 * scale
+
+
+MIXED_TOL_FULL = {"fp32": 2e-6, "bf16x3": 5e-5}
+
+
+@pytest.mark.timeout(900)
+def test_mixed_modes_o20v180_ladder_and_ring_blocks():
+    """FP32 and split-BF16 at the contraction lengths of the o=20 v=180
+    workload (split ladder K = v(v+1)/2 = 16290 accumulated in FP32, ring
+    K = o v = 3600): the particle-particle ladder and all three ring types
+    (term mask PP|RA|RB|RC) on the same amplitudes in the three modes, the
+    same launch configuration as the benchmark's steps; sampled packed blocks
+    of the mixed modes against GPU FP64 (itself held to the block oracle for
+    the ladder above and to the full oracle at smaller sizes).  Tolerance:
+    2e-6 (FP32) and 5e-5 (split-BF16) of the largest FP64 element of the
+    sampled blocks, as at the smaller parity shapes."""
+    o, v, naux, seed = ci.CONFIGS["o20v180"]
+    s = ci.make_named("o20v180-scaled")
+    t1, t2, _ = ci.random_amplitudes(o, v, 79, 0.01, 0.01, 0.0, triples=False)
+    tri = ci.packed_triples(o)
+    t0 = time.time()
+    say(f"[fullsize mixed] generating packed T3 ({len(tri)} x {v}^3) ...")
+    t3p = ci.hashed_t3_packed(o, v, 80, 0.01, threads=min(16, os.cpu_count() or 1))
+    say(f"[fullsize mixed] T3 ready in {time.time() - t0:.1f} s")
+    sample = [0, tri.index((0, 1, 2)), tri.index((3, 3, 7)), tri.index((2, 9, 9)), tri.index((5, 5, 5)),
+              tri.index((4, 11, 17)), len(tri) - 1]
+    v3 = v ** 3
+    got = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        with binding.Engine(o, v, naux, precision=prec, opts={"diis_t3": "none"}) as eng:
+            eng.set_fock(s["f"])
+            eng.set_eri_df(s["B"])
+            eng.set_amplitudes(t1, t2, t3p)
+            t0 = time.time()
+            eng.residual(["PP", "RA", "RB", "RC"], want_r3=False)
+            say(f"[fullsize mixed] {prec}: residual (PP + rings) {time.time() - t0:.1f} s")
+            got[prec] = {n: eng.copy_r3(n * v3, v3) for n in sample}
+    del t3p
+    scale = max(float(np.abs(b).max()) for b in got["fp64"].values())
+    assert scale > 0.0
+    for prec, tol in MIXED_TOL_FULL.items():
+        err = max(float(np.abs(got[prec][n] - got["fp64"][n]).max()) for n in sample)
+        say(f"[fullsize mixed] {prec}: max |R3 - R3(fp64)| = {err:.3e} = {err / scale:.2e} of max |R3| {scale:.3e}")
+        assert err <= tol * scale
+        assert np.abs(got[prec][tri.index((5, 5, 5))]).max() == 0.0

@@ -378,3 +378,29 @@ def test_degenerate_shapes_match_oracle(prec, o, v):
     for name, a, b, r in (("R1", g1, e1, 1e-11), ("R2", g2, e2, 1e-11), ("R3", g3, e3, rel)):
         ok, err, scale = _close(a, b, r)
         assert ok, f"{prec} o={o} v={v} {name}: max err {err:.3e} (scale {scale:.3e})"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_all_terms_with_every_job_in_several_batches(prec):
+    """The whole residual with the workspace at its minimum (workspace_gb
+    capped far below need), so that the T3 feedback, the three ring types,
+    the hole ladder and both T2 drivers each run in two or more batches of
+    unpacked slabs (slot offsets and per-batch fold plans of the multi-batch
+    path the o=20 v=180 workload takes), against the oracle."""
+    o, v, seed = 6, 24, 61
+    say(f"[multi-batch] prec={prec} o={o} v={v}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
+    with _engine(o, v, B.shape[0], f, B, precision=prec, opts={"workspace_gb": 0.001}) as eng:
+        plan = eng.batch_plan()
+        say(f"  batch plan {plan}")
+        for job in ("feedback", "ring_a", "ring_b", "ring_c", "hh", "d1", "d2"):
+            assert plan[job] >= 2, (job, plan)
+        eng.set_amplitudes(t1, t2, t3p)
+        g1, g2, g3, _ = eng.residual()
+    rel3 = 1e-11 if prec == "fp64" else MIXED_TOL[prec]
+    for name, a, b, rel in (("R1", g1, e1, 1e-11), ("R2", g2, e2, 1e-11), ("R3", g3, e3, rel3)):
+        ok, err, scale = _close(a, b, rel)
+        say(f"  {name}: max err {err:.3e} scale {scale:.3e}")
+        assert ok, f"{name} {prec}: max err {err:.3e} (scale {scale:.3e})"
