@@ -212,3 +212,133 @@ def task_energy(f, V, t2, t3, o, task):
             inv[p[k]] = k
         total += float(np.sum((X + Vb) * U.transpose(inv)))
     return total
+
+
+# ---------------------------------------------------------------------------
+# Alternative intermediates and the virtual-tuple summation order
+# (Sec. "ABC-based algorithm", Eqs. q_w_alter and ener-pt-q-abc)
+# ---------------------------------------------------------------------------
+
+def wbar_vvvo_alt(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """The alternative Wbar_ejk^abc as W[e,j,k,a,b,c]:
+    P_(jb)(kc) [ -sum_m v^{mb}_{ej} t_mk^ac - sum_m v^{ma}_{je} t_mk^bc
+                 + 1/2 sum_f v^{ab}_{ef} t_jk^fc ]."""
+    O, Vs = slice(0, o), slice(o, None)
+    g = (-_es("mbej,mkac->ejkabc", V[O, Vs, Vs, O], t2)
+         - _es("maje,mkbc->ejkabc", V[O, Vs, O, Vs], t2)
+         + 0.5 * _es("abef,jkfc->ejkabc", V[Vs, Vs, Vs, Vs], t2))
+    return g + g.transpose(0, 2, 1, 3, 5, 4)        # + (j,b) <-> (k,c)
+
+
+def wbar_vooo_alt(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """The alternative Wbar_ijk^abm as W[i,j,k,a,b,m]:
+    P_(ia)(jb) [ -1/2 sum_n v^{mn}_{ki} t_nj^ab ]."""
+    O = slice(0, o)
+    g = -0.5 * _es("mnki,njab->ijkabm", V[O, O, O, O], t2)
+    return g + g.transpose(1, 0, 2, 4, 3, 5)        # + (i,a) <-> (j,b)
+
+
+def y_term_alt(V: np.ndarray, t2: np.ndarray, o: int) -> np.ndarray:
+    """Y_ijkl^abcd built from the alternative intermediates (differs from
+    y_term element by element; its 24-permutation sum is the same)."""
+    return (0.5 * _es("ejkabc,iled->ijklabcd", wbar_vvvo_alt(V, t2, o), t2)
+            - 0.5 * _es("ijkabm,mlcd->ijklabcd", wbar_vooo_alt(V, t2, o), t2))
+
+
+def energy_q_by_virtual_tuples(f, V, t2, t3, o):
+    """E_(Q) summed in the virtual-tuple order of Eq. ener-pt-q-abc:
+    1/24 sum over a <= b <= c <= d of f_abcd sum_ijkl z tchk, f_abcd the
+    number of distinct orderings of (a,b,c,d) (the summand is invariant under
+    simultaneous permutations of the virtual labels of z and tchk with the
+    occupied ones); returns (total, {virtual tuple: contribution})."""
+    t4, z = quadruples(f, V, t2, t3, o)
+    w = z * spin_sum4(t4)  # [i,j,k,l,a,b,c,d]
+    per_abcd = w.sum(axis=(0, 1, 2, 3))
+    v = per_abcd.shape[0]
+    parts = {}
+    for a in range(v):
+        for b in range(a, v):
+            for c in range(b, v):
+                for d in range(c, v):
+                    n = len(set(itertools.permutations((a, b, c, d))))
+                    parts[(a, b, c, d)] = n * float(per_abcd[a, b, c, d]) / 24.0
+    return sum(parts.values()), parts
+
+
+def _blocks_for_virtual(V, t2, t3, o, q):
+    """X, Y and V as o^4 arrays [i][j][k][l] for the ordered virtual tuple q
+    (indices 0..v-1), from the same expressions as x_term, y_term_alt and
+    v_term with the virtual indices fixed; Y uses the alternative
+    intermediates of Eq. q_w_alter."""
+    a, b, c, d = (o + x for x in q)
+    O, Vs = slice(0, o), slice(o, None)
+    qa, qb, qc, qd = q
+    # X = 1/2 sum_e v^{ab}_{ej} t_ikl^{ecd} - 1/2 sum_m v^{am}_{ij} t_mkl^{bcd}
+    X = (0.5 * _es("ej,ikle->ijkl", V[a, b, Vs, O], t3[:, :, :, :, qc, qd])
+         - 0.5 * _es("mij,mkl->ijkl", V[a, O, O, O], t3[:, :, :, qb, qc, qd]))
+    # alternative Wbar_ejk^{abc} for this (a,b,c) as [e][j][k]
+    def gv(x, y, z):  # bracket of Eq. q_w_alter (vvv) for virtual labels (x, y, z) as [e][j][k]
+        return (-_es("mej,mk->ejk", V[O, o + y, Vs, O], t2[:, :, x, z])
+                - _es("mje,mk->ejk", V[O, o + x, O, Vs], t2[:, :, y, z])
+                + 0.5 * _es("ef,jkf->ejk", V[o + x, o + y, Vs, Vs], t2[:, :, :, z]))
+    Wv = gv(qa, qb, qc) + gv(qa, qc, qb).transpose(0, 2, 1)
+    # alternative Wbar_ijk^{abm} for this (a,b) as [i][j][k][m]
+    def gvo(x, y):
+        return -0.5 * _es("mnki,nj->ijkm", V[O, O, O, O], t2[:, :, x, y])
+    Wo = gvo(qa, qb) + gvo(qb, qa).transpose(1, 0, 2, 3)
+    Y = (0.5 * _es("ejk,ile->ijkl", Wv, t2[:, :, :, qd])
+         - 0.5 * _es("ijkm,ml->ijkl", Wo, t2[:, :, qc, qd]))
+    Vb = 0.25 * np.multiply.outer(V[a, b, O, O], t2[:, :, qc, qd])
+    return X, Y, Vb
+
+
+def spin_sum_occ_block(u):
+    """The spin summation of the virtual labels, acting on an o^4 array of a
+    fixed virtual tuple: exchanging two virtual labels at fixed occupied ones
+    equals exchanging the two occupied labels at fixed virtual ones (column
+    symmetry), so the same operator applies to the occupied axes."""
+    return spin_sum_block(u)
+
+
+def virtual_task_energy(f, V, t2, t3, o, task):
+    """Contribution of the virtual tuple task = (a, b, c, d), a <= b <= c <= d
+    (indices 0..v-1), to E_(Q) in the order of Eq. ener-pt-q-abc: the mirror
+    of task_energy with the roles of the occupied and virtual labels swapped
+    (o^4 arrays per ordering of the virtual labels)."""
+    t_ = tuple(task)
+    e = np.diag(f)
+    eps_v = sum(e[o + x] for x in t_)
+    eo = e[:o]
+    den = (eo[:, None, None, None] + eo[None, :, None, None] + eo[None, None, :, None]
+           + eo[None, None, None, :]) - eps_v
+    cache = {}
+
+    def blocks(q):
+        if q not in cache:
+            cache[q] = _blocks_for_virtual(V, t2, t3, o, q)
+        return cache[q]
+
+    r = 0.0
+    for p in PERMS4:
+        qq = [0] * 4
+        for k in range(4):
+            qq[p[k]] = t_[k]
+        X, Y, _ = blocks(tuple(qq))
+        r = r + (X + Y).transpose(p)
+    U = spin_sum_occ_block(r / den)
+    total = 0.0
+    seen = set()
+    for p in PERMS4:
+        qq = [0] * 4
+        for k in range(4):
+            qq[p[k]] = t_[k]
+        q = tuple(qq)
+        if q in seen:
+            continue
+        seen.add(q)
+        X, _, Vb = blocks(q)
+        inv = [0] * 4
+        for k in range(4):
+            inv[p[k]] = k
+        total += float(np.sum((X + Vb) * U.transpose(inv)))
+    return total

@@ -2,11 +2,11 @@
 element, on the state after one iteration from the MP2 guess of the
 variance-scaled o=10, v=90 workload (cct_inputs "o10v90-scaled").
 
-The state after one iteration has every T3 block non-zero (the T2 drivers
-fill it in the first iteration), so its residual exercises every R3 term, the
+After one iteration every T3 block with two or more distinct occupied indices
+is non-zero (the T2 drivers fill it), so the residual exercises every R3 term, the
 T3 feedback into R1/R2 and the T1 dressing at the measured shape.  Stored:
 all of R1 (post-processed R3 as in Sec. "Removing redundancies in RCC
-amplitudes"), 4000 sampled R2 elements and 10000 sampled R3 elements (2500
+amplitudes"), 4000 sampled R2 elements and 7600 sampled R3 elements (2500
 each from blocks with distinct indices, i=j<k, i<j=k, and 100 from i=j=k
 blocks, which are exactly zero), with their indices.  Iteration 1 has a
 single DIIS vector, so no extrapolation enters the state.
@@ -68,17 +68,17 @@ def main():
              "# o=10 v=90 naux=200 seed 2, B entries N(0, 0.05 sqrt(48/naux)) (cct_inputs",
              "# o10v90-scaled), DIIS on T1/T2 only (no extrapolation in iteration 1).",
              "# Written by tests/golden/make_o10v90_scaled_residual.py (oracle only).",
-             f"# energy_after_iteration_1 {e1!r}",
+             f"# energy_after_iteration_1 {float(e1)!r}",
              f"# max_abs R1 {float(np.abs(r1).max())!r} R2 {float(np.abs(r2).max())!r} R3 {float(np.abs(r3).max())!r}",
              "# rows: R1 i a value | R2 i j a b value | R3 i j k a b c value (i<=j<=k)"]
     for i in range(o):
         for a in range(v):
-            lines.append(f"R1 {i} {a} {r1[i, a]!r}")
+            lines.append(f"R1 {i} {a} {float(r1[i, a])!r}")
     for _ in range(4000):
         i, j, a, b = (int(x) for x in (rng.integers(o), rng.integers(o), rng.integers(v), rng.integers(v)))
-        lines.append(f"R2 {i} {j} {a} {b} {r2[i, j, a, b]!r}")
+        lines.append(f"R2 {i} {j} {a} {b} {float(r2[i, j, a, b])!r}")
     for (i, j, k, a, b, c) in sample_r3_sites(o, v, rng):
-        lines.append(f"R3 {i} {j} {k} {a} {b} {c} {r3[i, j, k, a, b, c]!r}")
+        lines.append(f"R3 {i} {j} {k} {a} {b} {c} {float(r3[i, j, k, a, b, c])!r}")
     with open(OUT, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(f"wrote {OUT}", flush=True)

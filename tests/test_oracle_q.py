@@ -159,3 +159,53 @@ def test_task_energy_matches_full_tensor_split(o, v, seed):
                     assert abs(got - ref) < 1e-15
                     total += got
     assert abs(total - Q.energy_q(f, V, t2, t3, o)) < 1e-14
+
+
+# --- the virtual-tuple (ABC) order and the alternative intermediates ---------
+
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 21), (3, 4, 22)])
+def test_alternative_intermediates_give_the_same_residual(o, v, seed):
+    """Eq. q_w_alter moves terms between the two Wbar intermediates: Y changes
+    element by element, its 24-permutation sum (the residual) does not; the
+    energy with the alternative Y equals the brute-force-pinned one."""
+    f, V = _system(o, v, seed)
+    t2, t3 = _amps(o, v, seed + 1)
+    Y, Ya = Q.y_term(V, t2, o), Q.y_term_alt(V, t2, o)
+    assert np.abs(Y - Ya).max() > 1e-4
+    PY, PYa = Q.perm_sym4(Y), Q.perm_sym4(Ya)
+    assert np.abs(PY - PYa).max() <= 1e-14 * max(1.0, np.abs(PY).max())
+    X, Vt = Q.x_term(V, t3, o), Q.v_term(V, t2, o)
+    e_alt = _energy_from_parts(f, V, X, Ya, Vt, o, Q.spin_sum4)
+    assert abs(e_alt - Q.energy_q(f, V, t2, t3, o)) < 1e-14
+    # a sign slip in either moved term is caught
+    O, Vs = slice(0, o), slice(o, None)
+    bad = Q.wbar_vvvo_alt(V, t2, o)
+    g = np.einsum("mbej,mkac->ejkabc", V[O, Vs, Vs, O], t2)
+    bad = bad + 2 * (g + g.transpose(0, 2, 1, 3, 5, 4))
+    Yb = 0.5 * np.einsum("ejkabc,iled->ijklabcd", bad, t2) - 0.5 * np.einsum(
+        "ijkabm,mlcd->ijklabcd", Q.wbar_vooo_alt(V, t2, o), t2)
+    assert np.abs(Q.perm_sym4(Yb) - PY).max() > 1e-6
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 3, 23), (3, 4, 24), (2, 5, 25)])
+def test_virtual_tuple_order_sums_to_the_energy(o, v, seed):
+    """Eq. ener-pt-q-abc: the sum over a <= b <= c <= d with the ordering
+    multiplicities is E_(Q); tuples with three equal virtual labels give 0
+    (the fully spin-summed amplitude vanishes there, as for three equal
+    occupied labels); the one-tuple evaluation (alternative intermediates,
+    o^4 arrays, the spin summation applied to the occupied axes) reproduces
+    every tuple's share."""
+    f, V = _system(o, v, seed)
+    t2, t3 = _amps(o, v, seed + 1)
+    e = Q.energy_q(f, V, t2, t3, o)
+    total, parts = Q.energy_q_by_virtual_tuples(f, V, t2, t3, o)
+    assert abs(total - e) < 1e-14
+    for (a, b, c, d), x in parts.items():
+        if a == b == c or b == c == d:
+            assert abs(x) < 1e-15
+    s = 0.0
+    for t, x in parts.items():
+        y = Q.virtual_task_energy(f, V, t2, t3, o, t)
+        assert abs(y - x) < 1e-14, (t, x, y)
+        s += y
+    assert abs(s - e) < 1e-14 and abs(e) > 1e-5
