@@ -340,12 +340,15 @@ def _perm_sign(p):
     return s
 
 
-def spinfree_to_spinorb(excs, o, t1, t2, t3):
+def spinfree_to_spinorb(excs, o, t1, t2, t3, t4=None):
     """Map M: t_{I1..In}^{A1..An} = sum_pi sgn(pi) prod_k delta(s(I_k), s(A_pi(k)))
     tchk_{i1..in}^{a_pi(1)..a_pi(n)}, i.e. antisymmetrisation over virtual labels
     restricted to spin-matched columns (t_{ij kbar}^{ab cbar} = A^{ab} t,
-    t_{ijk}^{abc} = A^{abc} t, t_{i jbar}^{a bbar} = t_ij^ab)."""
+    t_{ijk}^{abc} = A^{abc} t, t_{i jbar}^{a bbar} = t_ij^ab); quadruples (t4)
+    alike when given."""
     amps = {1: t1, 2: t2, 3: t3}
+    if t4 is not None:
+        amps[4] = t4
     out = np.zeros(len(excs))
     for mu, (I, A) in enumerate(excs):
         n = len(I)
