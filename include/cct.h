@@ -298,6 +298,53 @@ int cct_slab_get_counters(cct_slab* sl, double* macs, double* ms, int cap);
 const char* cct_slab_last_error(const cct_slab* sl);
 void cct_slab_destroy(cct_slab* sl);
 
+/* ---- quadruples ladder on compact T4 ----------------------------------------
+ * The particle-particle ladder term of the RCCSDTQ quadruples residual (the
+ * paper's Appendix "RCCSDTQ", Eq. resi-rccsdtq: P_(ia)(jb)(kc)(ld)
+ * [1/4 sum_ef W^{ab}_{ef} t_ijkl^efcd], its O(o^4 v^6) leading term) on T4
+ * stored only for occupied quadruples i <= j <= k <= l, in the compact
+ * six-term form of Sec. "RCCSDTQ contractions": for every stored block
+ * R[.. x at p .. y at q ..] += sum_ef W^{xy}_{ef} T[.. e at p .. f at q ..]
+ * over the six pairs of virtual positions (p, q), every operand from the
+ * same stored block.  Layouts (host, FP64, C-contiguous):
+ *   W    [v][v][v][v]          W[a][b][e][f] = W^{ab}_{ef}; must satisfy
+ *                              W^{ab}_{ef} = W^{ba}_{fe} (as the RCCSDT
+ *                              intermediate does) for the compact form to
+ *                              equal the permutation sum
+ *   t4p  [nq][v][v][v][v]      nq = nocc(nocc+1)(nocc+2)(nocc+3)/24 blocks in
+ *                              lexicographic order of i <= j <= k <= l
+ *                              (cct_quad_packed_index), block (i,j,k,l) holding
+ *                              t_ijkl^abcd for all a,b,c,d
+ * Products in the precision of cct_precision (FP64 MFMA; FP32 or split-BF16
+ * operands with FP64 output), R4 in FP64. */
+typedef struct cct_quad cct_quad;
+
+/* nocc >= 1, nvir >= 1, nq <= 65535, nvir^2 <= 46340.  opts_json: "timers"
+ * (true: device times in cct_quad_get_counters).  alloc/free_fn/alloc_user,
+ * hip_stream: as for cct_create.  Device memory: about 8 (v^4 + 3 nq v^4)
+ * bytes (+ 4 (nq v^4 + v^4) in the mixed modes).  Errors: CCT_EINVAL,
+ * CCT_ENOMEM, CCT_EDEVICE. */
+int cct_quad_create(int nocc, int nvir, cct_precision prec, const char* opts_json, cct_alloc_fn alloc,
+                    cct_free_fn free_fn, void* alloc_user, void* hip_stream, cct_quad** out);
+/* Copy W and/or the packed T4 in (host arrays; either may be NULL, not both). */
+int cct_quad_set(cct_quad* q, const double* W, const double* t4p);
+/* R4 = the compact ladder term for every stored block (raw: no
+ * post-processing).  r4p [nq][v^4] (host) may be NULL; norm2 (may be NULL)
+ * receives sum over blocks of multiplicity x squared elements.  CCT_ESTATE
+ * before both inputs are set; CCT_ENUMERIC on a non-finite norm. */
+int cct_quad_ladder(cct_quad* q, double* r4p, double* norm2);
+/* Copy count elements of R4 from flat element offset first (host). */
+int cct_quad_copy_r4(cct_quad* q, int64_t first, int64_t count, double* out);
+/* macs[0]: multiply-adds of the last evaluation (6 nq v^6); ms (with
+ * "timers"): [0] relabelled copies, [1] GEMMs.  Writes min(cap, 2). */
+int cct_quad_get_counters(cct_quad* q, double* macs, double* ms, int cap);
+/* Number of stored blocks for nocc occupied orbitals (-1 for nocc < 0). */
+int64_t cct_quad_count(int nocc);
+/* Index of the stored block (i,j,k,l), i <= j <= k <= l < nocc; -1 otherwise. */
+int64_t cct_quad_packed_index(int nocc, int i, int j, int k, int l);
+const char* cct_quad_last_error(const cct_quad* q);
+void cct_quad_destroy(cct_quad* q);
+
 #ifdef __cplusplus
 }
 #endif

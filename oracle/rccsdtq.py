@@ -121,6 +121,12 @@ R4_TERMS = ("T3_WBAR", "T3_WVOOO", "F_VV", "F_OO", "RING_A", "RING_B", "RING_C",
             "W_EIJ", "W_IEJ_1", "W_IEJ_2", "W_IJK_AMN", "W_IJK_ABM", "W_EJK")
 
 
+def pp_term(W, t4):
+    """The particle-particle ladder term of Eq. resi-rccsdtq before the
+    permutation operator: 1/4 sum_ef W^{ab}_{ef} t_ijkl^efcd, W[a,b,e,f]."""
+    return 0.25 * _es("abef,ijklefcd->ijklabcd", W, t4)
+
+
 def r4_terms(t2, t3, t4, ims, ims3, ims4):
     """The fifteen terms inside P_{(ia)(jb)(kc)(ld)} of Eq. resi-rccsdtq, in
     the order written there, as [o,o,o,o,v,v,v,v] tensors."""
@@ -135,7 +141,7 @@ def r4_terms(t2, t3, t4, ims, ims3, ims4):
         "RING_B": -0.25 * _es("maie,jmklebcd->ijklabcd", ims3["Wbar_ovov"], t4),
         "RING_C": -0.5 * _es("mbie,jmkleacd->ijklabcd", ims3["Wbar_ovov"], t4),
         "HH": 0.25 * _es("mnij,mnklabcd->ijklabcd", ims["Woooo"], t4),
-        "PP": 0.25 * _es("abef,ijklefcd->ijklabcd", ims3["Wvvvv"], t4),
+        "PP": pp_term(ims3["Wvvvv"], t4),
         "W_EIJ": 0.125 * _es("eijmab,mklecd->ijklabcd", ims4["Weij"], s1_3),
         "W_IEJ_1": -0.5 * _es("iejmab,kmlecd->ijklabcd", ims4["Wiej"], t3),
         "W_IEJ_2": -_es("iejmcb,kmlead->ijklabcd", ims4["Wiej"], t3),
@@ -296,3 +302,29 @@ def solve(f, V, o, max_iter=300, tol=1e-10, diis=True):
         if np.sqrt(sum(nrm)) < tol:
             return e, t1, t2, t3, t4, it, True
     return e, t1, t2, t3, t4, max_iter, False
+
+
+# ---------------------------------------------------------------------------
+# Packed (i <= j <= k <= l) storage
+# ---------------------------------------------------------------------------
+
+def packed_list4(o):
+    """Occupied quadruples i <= j <= k <= l in lexicographic order."""
+    return [q for q in itertools.product(range(o), repeat=4) if q[0] <= q[1] <= q[2] <= q[3]]
+
+
+def pack_t4(t4):
+    return np.stack([t4[q] for q in packed_list4(t4.shape[0])])
+
+
+def unpack_t4(t4p, o):
+    """Full tensor from the stored blocks: block (p,q,r,s) is the stored block
+    of the sorted indices with its virtual axes permuted the same way."""
+    v = t4p.shape[1]
+    full = np.empty((o,) * 4 + (v,) * 4)
+    index = {q: n for n, q in enumerate(packed_list4(o))}
+    for occ in itertools.product(range(o), repeat=4):
+        order = sorted(range(4), key=lambda s: occ[s])
+        blk = t4p[index[tuple(occ[s] for s in order)]]
+        full[occ] = blk.transpose([order.index(s) for s in range(4)])
+    return full

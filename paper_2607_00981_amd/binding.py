@@ -97,6 +97,15 @@ def load(path: str | None = None):
         "cct_slab_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
         "cct_slab_last_error": (C.c_char_p, [vp]),
         "cct_slab_destroy": (None, [vp]),
+        "cct_quad_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_char_p, vp, vp, vp, vp, C.POINTER(vp)]),
+        "cct_quad_set": (C.c_int, [vp, dp, dp]),
+        "cct_quad_ladder": (C.c_int, [vp, dp, dp]),
+        "cct_quad_copy_r4": (C.c_int, [vp, C.c_int64, C.c_int64, dp]),
+        "cct_quad_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
+        "cct_quad_count": (C.c_int64, [C.c_int]),
+        "cct_quad_packed_index": (C.c_int64, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+        "cct_quad_last_error": (C.c_char_p, [vp]),
+        "cct_quad_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -423,3 +432,70 @@ class Slab:
         ms = np.zeros(6)
         self._check(self.lib.cct_slab_get_counters(self.h, _ptr(macs), _ptr(ms), 6))
         return dict(zip(SLAB_MACS, macs)), dict(zip(SLAB_PHASES, ms))
+
+
+def quad_count(o):
+    return load().cct_quad_count(o)
+
+
+class Quad:
+    """The quadruples ladder on compact T4 (blocks i <= j <= k <= l)."""
+
+    def __init__(self, nocc, nvir, precision="fp64", opts=None, stream=None, allocator=None):
+        import json
+
+        self.lib = load()
+        self.o, self.v = nocc, nvir
+        self.nq = quad_count(nocc)
+        js = json.dumps(opts).encode() if opts else None
+        h = C.c_void_p()
+        a, f, u, self._keep = _allocator_args(allocator)
+        rc = self.lib.cct_quad_create(nocc, nvir, PRECISIONS[precision], js, a, f, u, stream, C.byref(h))
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CCT_OK:
+            raise CCTError(rc, self.lib.cct_quad_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cct_quad_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set(self, W=None, t4p=None):
+        v = self.v
+        W = None if W is None else _in(W, (v, v, v, v))
+        t4p = None if t4p is None else _in(t4p, (self.nq, v, v, v, v))
+        self._check(self.lib.cct_quad_set(self.h, _ptr(W), _ptr(t4p)))
+
+    def ladder(self, want_r4=True):
+        v = self.v
+        r4 = np.empty((self.nq, v, v, v, v)) if want_r4 else None
+        n2 = C.c_double()
+        self._check(self.lib.cct_quad_ladder(self.h, _ptr(r4), C.byref(n2)))
+        return r4, n2.value
+
+    def copy_r4(self, first, count):
+        out = np.empty(count)
+        self._check(self.lib.cct_quad_copy_r4(self.h, first, count, _ptr(out)))
+        return out
+
+    def counters(self):
+        macs = np.zeros(2)
+        ms = np.zeros(2)
+        self._check(self.lib.cct_quad_get_counters(self.h, _ptr(macs), _ptr(ms), 2))
+        return {"ladder": float(macs[0])}, {"relabel": float(ms[0]), "gemm": float(ms[1])}

@@ -107,9 +107,11 @@ struct cct_ctx {
   // plans
   Job ring[3], hh, d1, d2, feed1;
   // DIIS
-  std::vector<double*> dvec, derr;
-  int diis_n = 0, diis_next = 0;
-  std::vector<std::vector<double>> Bmat;
+  // history in device memory: M slots of diis_len doubles, overlap matrix,
+  // bookkeeping (see DiisArgs); diis_new: the Jacobi / extrapolated vector
+  double *dvecs = nullptr, *derrs = nullptr, *diis_new = nullptr, *diis_part = nullptr;
+  double *diis_d = nullptr, *diis_B = nullptr, *diis_coef = nullptr;
+  int* diis_st = nullptr;
   double* diis_old = nullptr;
   long long diis_len = 0;
   // counters
@@ -1481,7 +1483,10 @@ int compute(cct_ctx* ctx, unsigned mask, bool update_t3, double norms[3]) {
   return finish_residual(ctx, norms);
 }
 
-int energy_dev(cct_ctx* ctx, double* e) {
+// Energy of the current amplitudes into scal[6] (device; no synchronisation):
+// E = sum (2 v^{ij}_{ab} - v^{ij}_{ba}) (t_ij^ab + t_i^a t_j^b) + 2 sum f_ia t_i^a.
+// out (may be null) also receives the squared norms scal[0..2] and E.
+int enqueue_energy(cct_ctx* ctx, double* out) {
   const int o = ctx->o, v = ctx->v;
   hipStream_t s = ctx->s;
   // tau = t2 + t1 t1
@@ -1491,10 +1496,14 @@ int energy_dev(cct_ctx* ctx, double* e) {
   STCK(contract(ctx->ws, s, Prec::F64, 1.0, t1, "ia", t1, "jb", 1.0, tau, "ijab"));
   HIPCK(dot(ctx->vbare_c, ctx->tau_e, (long long)o * o * v * v, ctx->scal + 4, ctx->red, s));
   HIPCK(dot(ctx->fov, ctx->t1, (long long)o * v, ctx->scal + 5, ctx->red, s));
-  double h[2];
-  HIPCK(hipMemcpyAsync(h, ctx->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCK(hipStreamSynchronize(s));
-  *e = h[0] + 2.0 * h[1];
+  HIPCK(energy_scalars(ctx->scal, out, s));
+  return CCT_OK;
+}
+
+int energy_dev(cct_ctx* ctx, double* e) {
+  RCK(enqueue_energy(ctx, nullptr));
+  HIPCK(hipMemcpyAsync(e, ctx->scal + 6, sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
   return finite_or_err(ctx, *e);
 }
 
@@ -1870,153 +1879,86 @@ int copy_amps_to(cct_ctx* ctx, double* dst) {
   return CCT_OK;
 }
 
-int diis_dot(cct_ctx* ctx, const double* x, const double* y, double* out_dev) {
+// The DIIS part of a vector back into the amplitudes (inverse of copy_amps_to).
+int copy_amps_from(cct_ctx* ctx, const double* src) {
   const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
-  HIPCK(dot(x, y, n1 + n2, out_dev, ctx->red, ctx->s));
-  if (ctx->diis_t3) {
-    const long long bs = diis_block(ctx);
-    HIPCK(weighted_dot_t3(x + n1 + n2, y + n1 + n2, ctx->tri, (int)ctx->ntri, bs, bs, out_dev + 1, ctx->red,
-                          ctx->s));
-  } else {
-    HIPCK(fill(out_dev + 1, 0.0, 1, ctx->s));
-  }
+  HIPCK(axpby(1.0, src, 0.0, ctx->t1, n1, ctx->s));
+  HIPCK(axpby(1.0, src + n1, 0.0, ctx->t2, n2, ctx->s));
+  if (ctx->diis_t3 && ctx->diis_sv > 0)
+    HIPCK(t3_subcube(ctx->t3, const_cast<double*>(src + n1 + n2), ctx->ntri, ctx->v, ctx->diis_sv, false, ctx->s));
+  else if (ctx->diis_t3)
+    HIPCK(axpby(1.0, src + n1 + n2, 0.0, ctx->t3, ctx->ntri * ctx->v3, ctx->s));
   return CCT_OK;
 }
 
-void diis_reset(cct_ctx* ctx) {
-  ctx->diis_n = 0;
-  ctx->diis_next = 0;
-  ctx->Bmat.assign(ctx->diis_space, std::vector<double>(ctx->diis_space, 0.0));
+DiisArgs diis_args(const cct_ctx* ctx) {
+  DiisArgs a{};
+  a.L = ctx->diis_len;
+  a.n12 = (long long)ctx->o * ctx->v + (long long)ctx->o * ctx->o * ctx->v * ctx->v;
+  a.bs = diis_block(ctx);
+  a.tri = ctx->tri;
+  a.ntri = (int)ctx->ntri;
+  a.M = ctx->diis_space;
+  a.start = ctx->diis_start;
+  return a;
 }
 
-// Called after the Jacobi step: T currently holds the Jacobi-updated amplitudes,
-// diis_old the amplitudes before it.
+// Empty DIIS history.  Enqueued on the context's stream (a kernel).
+int diis_reset(cct_ctx* ctx) {
+  if (ctx->diis_st) HIPCK(diis_device_reset(ctx->diis_st, ctx->s));
+  return CCT_OK;
+}
+
+// After the Jacobi step: T holds the Jacobi-updated amplitudes, diis_old the
+// amplitudes before it.  The Jacobi vector is gathered, the device step
+// (overlaps, bordered solve, history update, extrapolation) runs, and the
+// result is written back; no synchronisation.
 int diis_step(cct_ctx* ctx) {
-  const long long L = ctx->diis_len;
-  const long long n1 = (long long)ctx->o * ctx->v, n2 = n1 * n1;
-  const int M = ctx->diis_space;
-  const int slot = ctx->diis_next;
-  double* vec = ctx->dvec[slot];
-  double* err = ctx->derr[slot];
-  RCK(copy_amps_to(ctx, vec));
-  HIPCK(axpby(1.0, vec, 0.0, err, L, ctx->s));
-  HIPCK(axpby(-1.0, ctx->diis_old, 1.0, err, L, ctx->s));
-  ctx->diis_next = (slot + 1) % M;
-  ctx->diis_n = std::min(ctx->diis_n + 1, M);
-  // new row of the overlap matrix against the slots in use: the diis_n
-  // newest of the ring, the new one included (an eviction after a singular
-  // system can leave them anywhere in the ring)
-  std::vector<int> slots;
-  for (int k = 0; k < ctx->diis_n; ++k) slots.push_back((ctx->diis_next - ctx->diis_n + k + M) % M);
-  for (int k : slots) {
-    RCK(diis_dot(ctx, err, ctx->derr[k], ctx->scal + 8 + 2 * k));
-  }
-  std::vector<double> h(2 * M);
-  HIPCK(hipMemcpyAsync(h.data(), ctx->scal + 8, 2 * M * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
-  HIPCK(hipStreamSynchronize(ctx->s));
-  for (int k : slots) {
-    const double b = h[2 * k] + h[2 * k + 1];
-    ctx->Bmat[slot][k] = ctx->Bmat[k][slot] = b;
-  }
-  if (ctx->diis_n < ctx->diis_start) return CCT_OK;
-  // order slots from oldest to newest
-  std::vector<int> order;
-  for (int k = 0; k < ctx->diis_n; ++k) order.push_back((ctx->diis_next - ctx->diis_n + k + M) % M);
-  while (true) {
-    const int m = (int)order.size();
-    std::vector<double> A((size_t)(m + 1) * (m + 1)), rhs(m + 1, 0.0);
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) A[a * (m + 1) + b] = ctx->Bmat[order[a]][order[b]];
-    for (int a = 0; a < m; ++a) { A[a * (m + 1) + m] = -1.0; A[m * (m + 1) + a] = -1.0; }
-    A[m * (m + 1) + m] = 0.0;
-    rhs[m] = -1.0;
-    // LU with partial pivoting
-    bool singular = false;
-    const int N = m + 1;
-    std::vector<int> piv(N);
-    for (int i = 0; i < N; ++i) piv[i] = i;
-    double amax = 0.0;
-    for (double x : A) amax = std::max(amax, std::fabs(x));
-    for (int c = 0; c < N && !singular; ++c) {
-      int pr = c;
-      for (int r = c + 1; r < N; ++r)
-        if (std::fabs(A[r * N + c]) > std::fabs(A[pr * N + c])) pr = r;
-      if (std::fabs(A[pr * N + c]) <= 1e-300 || std::fabs(A[pr * N + c]) < 1e-15 * amax * 1e-10) { singular = true; break; }
-      if (pr != c) {
-        for (int k = 0; k < N; ++k) std::swap(A[pr * N + k], A[c * N + k]);
-        std::swap(rhs[pr], rhs[c]);
-      }
-      for (int r = c + 1; r < N; ++r) {
-        const double f = A[r * N + c] / A[c * N + c];
-        for (int k = c; k < N; ++k) A[r * N + k] -= f * A[c * N + k];
-        rhs[r] -= f * rhs[c];
-      }
-    }
-    std::vector<double> x(N);
-    if (!singular) {
-      for (int r = N - 1; r >= 0; --r) {
-        double acc = rhs[r];
-        for (int k = r + 1; k < N; ++k) acc -= A[r * N + k] * x[k];
-        x[r] = acc / A[r * N + r];
-        if (!std::isfinite(x[r])) singular = true;
-      }
-    }
-    if (singular) {
-      // the oldest vector leaves the history for good (later iterations do
-      // not see it either); with one vector left the Jacobi step stands
-      if (m <= 1) return CCT_OK;
-      order.erase(order.begin());
-      ctx->diis_n -= 1;
-      continue;
-    }
-    // T = sum_m c_m vec_m.  With a T3 subspace the extrapolated sub-cubes are
-    // summed in the (no longer needed) pre-step copy and written back; T3
-    // outside the subspace keeps its Jacobi step.
-    double* t1 = ctx->t1;
-    double* t2 = ctx->t2;
-    const bool sub = ctx->diis_t3 && ctx->diis_sv > 0;
-    double* t3_acc = sub ? ctx->diis_old + n1 + n2 : ctx->t3;
-    const long long n3 = ctx->ntri * diis_block(ctx);
-    for (int a = 0; a < m; ++a) {
-      const double* vp = ctx->dvec[order[a]];
-      const double b = a == 0 ? 0.0 : 1.0;
-      HIPCK(axpby(x[a], vp, b, t1, n1, ctx->s));
-      HIPCK(axpby(x[a], vp + n1, b, t2, n2, ctx->s));
-      if (ctx->diis_t3) HIPCK(axpby(x[a], vp + n1 + n2, b, t3_acc, n3, ctx->s));
-    }
-    if (sub) HIPCK(t3_subcube(ctx->t3, t3_acc, ctx->ntri, ctx->v, ctx->diis_sv, false, ctx->s));
-    return CCT_OK;
-  }
+  RCK(copy_amps_to(ctx, ctx->diis_new));
+  const DiisArgs a = diis_args(ctx);
+  HIPCK(diis_device_step(ctx->diis_new, ctx->diis_old, ctx->dvecs, ctx->derrs, ctx->diis_part, ctx->diis_d,
+                         ctx->diis_B, ctx->diis_st, ctx->diis_coef, a, ctx->s));
+  RCK(copy_amps_from(ctx, ctx->diis_new));
+  return CCT_OK;
 }
 
-// Device part of one iteration: save the amplitudes for DIIS, residual, T3
-// and T1/T2 Jacobi steps.  No host synchronisation (graph-capturable).
-int enqueue_iteration(cct_ctx* ctx) {
-  if (ctx->diis_on && ctx->diis_space > 0) RCK(copy_amps_to(ctx, ctx->diis_old));
+// One whole iteration on the context's stream: save the amplitudes for DIIS,
+// residual, T3 and T1/T2 Jacobi steps, DIIS, energy; the squared norms and the
+// energy are left in scal[0..2] and scal[6] (and copied to out, if given).
+// No host synchronisation and no allocation: safe to record into a graph.
+int enqueue_iteration(cct_ctx* ctx, double* out = nullptr) {
+  const bool use_diis = ctx->diis_on && ctx->diis_space > 0;
+  if (use_diis) RCK(copy_amps_to(ctx, ctx->diis_old));
   RCK(enqueue_residual(ctx, CCT_TERM_ALL, true));
   HIPCK(jacobi_t1t2(ctx->t1, ctx->r1, ctx->t2, ctx->r2, ctx->eps, ctx->o, ctx->v, ctx->s));
+  mark(ctx, PH_DIIS);
+  if (use_diis) RCK(diis_step(ctx));
+  RCK(enqueue_energy(ctx, out));
+  mark(ctx, PH_N);
   return CCT_OK;
 }
 
-// Host part after enqueue_iteration: norms, DIIS extrapolation, energy.
+// Read back the norms and energy of an enqueued iteration (one copy, one
+// synchronisation) and check them.
 int finish_iteration(cct_ctx* ctx, double* e, double norms[3]) {
-  const bool use_diis = ctx->diis_on && ctx->diis_space > 0;
-  double nr[3];
-  RCK(finish_residual(ctx, nr));
-  mark(ctx, PH_DIIS);
-  if (use_diis) RCK(diis_step(ctx));
-  double en = 0.0;
-  RCK(energy_dev(ctx, &en));
-  mark(ctx, PH_N);
+  double h[7];
+  HIPCK(hipMemcpyAsync(h, ctx->scal, 7 * sizeof(double), hipMemcpyDeviceToHost, ctx->s));
+  HIPCK(hipStreamSynchronize(ctx->s));
   if (ctx->events) {
-    float msv = 0.f;
-    if (hipEventSynchronize(ctx->ev[PH_N]) == hipSuccess &&
-        hipEventElapsedTime(&msv, ctx->ev[PH_DIIS], ctx->ev[PH_N]) == hipSuccess)
-      ctx->ms[PH_DIIS] = msv;
+    for (int i = 0; i < PH_N; ++i) {
+      float msv = 0.f;
+      if (hipEventElapsedTime(&msv, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) ctx->ms[i] = msv;
+    }
+    for (int i = 0; i + 1 < ctx->lad_nev; i += 2) {
+      float msv = 0.f;
+      if (hipEventElapsedTime(&msv, ctx->lad_ev[i], ctx->lad_ev[i + 1]) == hipSuccess) ctx->lad_ms += msv;
+    }
   }
-  if (e) *e = en;
-  if (norms) for (int i = 0; i < 3; ++i) norms[i] = nr[i];
-  return CCT_OK;
+  ctx->have_res = true;
+  if (e) *e = h[6];
+  if (norms) for (int i = 0; i < 3; ++i) norms[i] = h[i];
+  for (int i = 0; i < 3; ++i) RCK(finite_or_err(ctx, h[i]));
+  return finite_or_err(ctx, h[6]);
 }
 
 int update(cct_ctx* ctx, double* e, double norms[3]) {
@@ -2293,7 +2235,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
       ctx->tol = std::atof(val.c_str());
       if (!(ctx->tol > 0)) { delete ctx; return CCT_EINVAL; }
     }
-    if (ctx->diis_space < 0 || ctx->diis_space > 64 || ctx->diis_start < 1 || ctx->ws_gb < 0) {
+    if (ctx->diis_space < 0 || ctx->diis_space > DIIS_MAX || ctx->diis_start < 1 || ctx->ws_gb < 0) {
       delete ctx;
       return CCT_EINVAL;
     }
@@ -2310,7 +2252,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   fixed += (long long)v * v * v * v + o2v2 + ov;
   const int M = ctx->diis_on ? ctx->diis_space : 0;
   const long long dlen = ov + o2v2 + ctx->ntri * diis_block(ctx);
-  fixed += (long long)(2 * M + 1) * dlen;
+  fixed += (long long)(2 * M + 2) * dlen;
   // workspace: enough for every job in one batch (two unpacked/contracted
   // slabs per slot, o^2 slots for the rings), capped by the option
   // the split ladder needs W+- (about v^4/2) and, per packed block, its split
@@ -2328,6 +2270,7 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     delete ctx;
     return CCT_EDEVICE;
   }
+
   // workspace: everything in one batch if it fits, else what is left of the
   // device after the fixed allocations (minus a margin), capped by the option
   const double margin = 2e9;
@@ -2358,14 +2301,16 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
   AL(red, ctx->red_n);
   ctx->diis_len = diis_len(ctx);
   if (M > 0) {
+    const long long nchunk = diis_chunks(diis_args(ctx));
     AL(diis_old, ctx->diis_len);
-    for (int k = 0; k < M && rc == CCT_OK; ++k) {
-      double *a = nullptr, *b = nullptr;
-      rc = dalloc(ctx, &a, ctx->diis_len);
-      if (rc == CCT_OK) rc = dalloc(ctx, &b, ctx->diis_len);
-      ctx->dvec.push_back(a);
-      ctx->derr.push_back(b);
-    }
+    AL(diis_new, ctx->diis_len);
+    AL(dvecs, (long long)M * ctx->diis_len);
+    AL(derrs, (long long)M * ctx->diis_len);
+    AL(diis_part, (long long)(M + 1) * nchunk);
+    AL(diis_d, M + 1);
+    AL(diis_B, (long long)M * M);
+    AL(diis_coef, M);
+    if (rc == CCT_OK) rc = dalloc_t(ctx, &ctx->diis_st, DIIS_STATE);
   }
 #undef AL
   if (rc == CCT_OK) {
@@ -2387,9 +2332,9 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (fill(ctx->t1, 0.0, ov, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
     if (fill(ctx->t2, 0.0, o2v2, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
     if (fill(ctx->t3, 0.0, t3n, ctx->s) != hipSuccess) rc = CCT_EDEVICE;
+    if (rc == CCT_OK && diis_reset(ctx) != CCT_OK) rc = CCT_EDEVICE;
     if (hipStreamSynchronize(ctx->s) != hipSuccess) rc = CCT_EDEVICE;
   }
-  diis_reset(ctx);
   if (rc != CCT_OK) {
     cct_destroy(ctx);
     return rc;
@@ -2445,8 +2390,8 @@ int cct_init_mp2(cct_ctx* ctx) {
   HIPCK(fill(ctx->t2, 0.0, ov * ov, ctx->s));
   HIPCK(fill(ctx->t3, 0.0, ctx->ntri * ctx->v3, ctx->s));
   HIPCK(jacobi_t1t2(ctx->t1, ctx->zero_r1, ctx->t2, ctx->vbare, ctx->eps, ctx->o, ctx->v, ctx->s));
+  RCK(diis_reset(ctx));
   HIPCK(hipStreamSynchronize(ctx->s));
-  diis_reset(ctx);
   return CCT_OK;
 }
 
@@ -2457,8 +2402,8 @@ int cct_set_amplitudes(cct_ctx* ctx, const double* t1, const double* t2, const d
   HIPCK(hipMemcpyAsync(ctx->t2, t2, ov * ov * 8, hipMemcpyHostToDevice, ctx->s));
   if (t3p) HIPCK(hipMemcpyAsync(ctx->t3, t3p, ctx->ntri * ctx->v3 * 8, hipMemcpyHostToDevice, ctx->s));
   else HIPCK(fill(ctx->t3, 0.0, ctx->ntri * ctx->v3, ctx->s));
+  RCK(diis_reset(ctx));
   HIPCK(hipStreamSynchronize(ctx->s));
-  diis_reset(ctx);
   return CCT_OK;
 }
 
@@ -2570,12 +2515,12 @@ int cct_get_counters(cct_ctx* ctx, double* macs_by_term, double* ms_by_phase, in
 // ===========================================================================
 // Batches of independent systems
 //
-// Each system is an ordinary context.  The device part of an iteration
-// (amplitude save for DIIS, residual, T3 and T1/T2 Jacobi steps) of every
-// system is recorded once into a HIP graph, forked over a few streams so
-// that independent systems can overlap, and replayed once per iteration:
-// one graph launch per batch residual.  The host part (norm read-back, DIIS
-// extrapolation, energy) follows per system after the replay.
+// Each system is an ordinary context.  One whole iteration of every system
+// (amplitude save for DIIS, residual, T3 and T1/T2 Jacobi steps, DIIS on the
+// device, energy) is recorded once into a HIP graph, forked over a few
+// streams so that independent systems can overlap, and replayed once per
+// iteration; each system's squared norms and energy land in one device
+// array, read back with a single copy and synchronisation per replay.
 // ===========================================================================
 struct cct_batch {
   std::vector<cct_ctx*> sys;
@@ -2586,14 +2531,19 @@ struct cct_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = true;
+  double* dout = nullptr;  // [nsys][4]: |R1|^2, |R2|^2, |R3|^2, energy of the last iteration
+  cct_alloc_fn alloc_fn = nullptr;
+  cct_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   std::string err;
 };
 
 namespace {
 
 int batch_enqueue_all(cct_batch* b) {
-  for (cct_ctx* c : b->sys) {
-    const int rc = enqueue_iteration(c);
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    cct_ctx* c = b->sys[i];
+    const int rc = enqueue_iteration(c, b->dout + 4 * i);
     if (rc != CCT_OK) {
       b->err = c->err;
       return rc;
@@ -2652,6 +2602,10 @@ void cct_batch_destroy(cct_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (cct_ctx* c : b->sys) cct_destroy(c);
+  if (b->dout) {
+    if (b->free_fn) b->free_fn(b->dout, b->alloc_user);
+    else (void)hipFree(b->dout);
+  }
   for (hipEvent_t e : b->join)
     if (e) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
@@ -2682,7 +2636,18 @@ int cct_batch_create(int nsys, const int* nocc, const int* nvir, const int* naux
   if (nstreams < 1 || nstreams > 16) return CCT_EINVAL;
   cct_batch* b = new cct_batch();
   b->use_graph = use_graph;
+  b->alloc_fn = alloc;
+  b->free_fn = free_fn;
+  b->alloc_user = alloc_user;
   int rc = CCT_OK;
+  {
+    const size_t bytes = sizeof(double) * 4 * (size_t)nsys;
+    void* p = nullptr;
+    if (alloc) p = alloc(bytes, alloc_user);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (!p) rc = CCT_ENOMEM;
+    b->dout = (double*)p;
+  }
   for (int i = 0; i < nstreams && rc == CCT_OK; ++i) {
     hipStream_t s = nullptr;
     if (i == 0 && hip_stream) {
@@ -2754,6 +2719,7 @@ int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms) {
     }
   if (b->use_graph && !b->exec) RCK(batch_capture(b));
   const int ns = (int)b->sys.size();
+  std::vector<double> h((size_t)4 * ns);
   for (int it = 0; it < niter; ++it) {
     if (b->use_graph) {
       const hipError_t e = hipGraphLaunch(b->exec, b->streams[0]);
@@ -2761,23 +2727,33 @@ int cct_batch_iterate(cct_batch* b, int niter, double* e_corr, double* norms) {
         b->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
         return CCT_EDEVICE;
       }
-      if (hipStreamSynchronize(b->streams[0]) != hipSuccess) {
-        b->err = "stream synchronisation after graph launch failed";
-        return CCT_EDEVICE;
-      }
     } else {
       RCK(batch_enqueue_all(b));
+      // the eager launches of the other streams join the first before the read-back
+      for (size_t i = 1; i < b->streams.size(); ++i)
+        if (hipEventRecord(b->join[i], b->streams[i]) != hipSuccess ||
+            hipStreamWaitEvent(b->streams[0], b->join[i], 0) != hipSuccess) {
+          b->err = "stream join failed";
+          return CCT_EDEVICE;
+        }
+    }
+    if (hipMemcpyAsync(h.data(), b->dout, sizeof(double) * h.size(), hipMemcpyDeviceToHost, b->streams[0]) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->streams[0]) != hipSuccess) {
+      b->err = "read-back after the batch iteration failed";
+      return CCT_EDEVICE;
     }
     for (int s = 0; s < ns; ++s) {
-      double e = 0.0, nr[3] = {0, 0, 0};
-      const int rc = finish_iteration(b->sys[s], &e, nr);
-      if (rc != CCT_OK) {
-        b->err = "system " + std::to_string(s) + ": " + b->sys[s]->err;
-        return rc;
-      }
-      if (e_corr) e_corr[s] = e;
+      b->sys[s]->have_res = true;
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(h[4 * s + k])) {
+          b->err = "system " + std::to_string(s) + ": non-finite residual norm or energy";
+          b->sys[s]->err = "non-finite residual norm or energy";
+          return CCT_ENUMERIC;
+        }
+      if (e_corr) e_corr[s] = h[4 * s + 3];
       if (norms)
-        for (int k = 0; k < 3; ++k) norms[3 * s + k] = nr[k];
+        for (int k = 0; k < 3; ++k) norms[3 * s + k] = h[4 * s + k];
     }
   }
   return CCT_OK;

@@ -230,6 +230,32 @@ hipError_t add_diag_rows(double* Y, const double* X, int nb, int nf, int nq, lon
                          long long sq, long long xf, double alpha, hipStream_t s);
 // out[i] += sum_r in[r * n + i] for r = 0..rows-1 (fixed order).
 hipError_t add_rows(const double* in, int rows, long long n, double* out, hipStream_t s);
+// DIIS on the device.  The history holds M slots of L doubles (vecs, errs);
+// the first n12 elements of a vector are T1/T2 (weight 1), the rest packed T3
+// blocks of bs elements (weight tri[t].w, the orderings of block t).
+// st (DIIS_STATE ints): [0] next slot, [1] vectors held, [2] slot of the newest,
+// [3] 1 if the last step extrapolated, [4] vectors in that solve, [5..] their
+// slots, oldest first.
+constexpr int DIIS_MAX = 64;
+constexpr int DIIS_STATE = 5 + DIIS_MAX;
+struct DiisArgs {
+  long long L, n12, bs;
+  const int4* tri;
+  int ntri, M, start;
+};
+// Overlap chunks of one step (size of the partial-sum scratch: (M + 1) x chunks).
+long long diis_chunks(const DiisArgs& a);
+// One DIIS step on the Jacobi vector vnew (old: the amplitudes before the
+// step): overlaps of e = vnew - old with the history, the bordered solve
+// (a singular system drops the oldest vector for good), e and vnew enter the
+// history, and vnew becomes the extrapolated vector when the solve succeeded.
+// part: (M + 1) x diis_chunks doubles, d: M + 1, B: M x M, coef: M.
+hipError_t diis_device_step(double* vnew, const double* old, double* vecs, double* errs, double* part, double* d,
+                            double* B, int* st, double* coef, const DiisArgs& a, hipStream_t s);
+// Empty history (a kernel, so that it may sit in a recorded graph).
+hipError_t diis_device_reset(int* st, hipStream_t s);
+// scal[6] = scal[4] + 2 scal[5]; out (may be null) receives scal[0..2], scal[6].
+hipError_t energy_scalars(double* scal, double* out, hipStream_t s);
 // Jacobi update of T1 / T2 with denominators built from eps.
 hipError_t jacobi_t1t2(double* t1, const double* r1, double* t2, const double* r2, const double* eps, int o, int v,
                        hipStream_t s);

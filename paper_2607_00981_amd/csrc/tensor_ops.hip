@@ -964,4 +964,224 @@ hipError_t add_pair_diag(double* W, const double* F, long long ldF, int nx, doub
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// DIIS on the device (Sec. "Distributed DIIS"): the history, its overlap
+// matrix and its bookkeeping stay in device memory, so that one iteration
+// (residual, Jacobi step, extrapolation, energy) runs without the host and
+// can be recorded into a graph and replayed.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int DIIS_CH = TPB * 16;  // elements per overlap chunk
+
+__device__ __forceinline__ void diis_chunk(const DiisArgs& a, long long c, long long& lo, long long& hi, double& w) {
+  const long long nc12 = (a.n12 + DIIS_CH - 1) / DIIS_CH;
+  if (c < nc12) {
+    lo = c * DIIS_CH;
+    hi = lo + DIIS_CH < a.n12 ? lo + DIIS_CH : a.n12;
+    w = 1.0;
+    return;
+  }
+  const long long nct = (a.bs + DIIS_CH - 1) / DIIS_CH;
+  const long long t = (c - nc12) / nct, q = (c - nc12) - t * nct;
+  lo = a.n12 + t * a.bs + q * DIIS_CH;
+  const long long end = a.n12 + (t + 1) * a.bs;
+  hi = lo + DIIS_CH < end ? lo + DIIS_CH : end;
+  w = (double)a.tri[t].w;
+}
+
+// part[j][c] = w_c sum over chunk c of e_new * errs[j] (j < M), or e_new^2 (j = M),
+// with e_new = vnew - old.
+__global__ void diis_overlap_kernel(const double* __restrict__ vnew, const double* __restrict__ old,
+                                    const double* __restrict__ errs, DiisArgs a, long long nchunk,
+                                    double* __restrict__ part) {
+  __shared__ double red[TPB];
+  const long long c = blockIdx.x;
+  const int j = blockIdx.y;
+  long long lo, hi;
+  double w;
+  diis_chunk(a, c, lo, hi, w);
+  const double* ej = errs + (long long)j * a.L;
+  double acc = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += TPB) {
+    const double e = vnew[i] - old[i];
+    acc += e * (j < a.M ? ej[i] : e);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[(long long)j * nchunk + c] = w * s;
+}
+
+__global__ void diis_finalize_kernel(const double* __restrict__ part, long long nchunk, double* __restrict__ d) {
+  __shared__ double red[TPB];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < nchunk; i += TPB) acc += part[(long long)j * nchunk + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) d[j] = s;
+}
+
+// One thread: enter the new overlaps into B, advance the ring, solve the
+// bordered system over the vectors held (oldest first) by LU with partial
+// pivoting; a singular system drops the oldest vector for good and retries.
+__global__ void diis_solve_kernel(const double* __restrict__ d, double* __restrict__ B, int* __restrict__ st,
+                                  double* __restrict__ coef, int M, int start) {
+  __shared__ double A[(DIIS_MAX + 1) * (DIIS_MAX + 1)];
+  __shared__ double rhs[DIIS_MAX + 1], x[DIIS_MAX + 1];
+  __shared__ int order[DIIS_MAX];
+  if (threadIdx.x != 0) return;
+  const int k = st[0];
+  const int n_new = st[1] + 1 < M ? st[1] + 1 : M;
+  for (int idx = 0; idx < n_new; ++idx) order[idx] = (k - n_new + 1 + idx + M) % M;
+  for (int idx = 0; idx < n_new; ++idx) {
+    const int j = order[idx];
+    const double b = (j == k) ? d[M] : d[j];
+    B[k * M + j] = b;
+    B[j * M + k] = b;
+  }
+  st[0] = (k + 1) % M;
+  st[1] = n_new;
+  st[2] = k;
+  st[3] = 0;
+  st[4] = 0;
+  if (n_new < start) return;
+  int first = 0;
+  while (true) {
+    const int m = n_new - first, N = m + 1;
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < m; ++c) A[r * N + c] = B[order[first + r] * M + order[first + c]];
+    for (int r = 0; r < m; ++r) {
+      A[r * N + m] = -1.0;
+      A[m * N + r] = -1.0;
+      rhs[r] = 0.0;
+    }
+    A[m * N + m] = 0.0;
+    rhs[m] = -1.0;
+    double amax = 0.0;
+    for (int i = 0; i < N * N; ++i) amax = fmax(amax, fabs(A[i]));
+    bool singular = false;
+    for (int c = 0; c < N && !singular; ++c) {
+      int pr = c;
+      for (int r = c + 1; r < N; ++r)
+        if (fabs(A[r * N + c]) > fabs(A[pr * N + c])) pr = r;
+      const double pv = fabs(A[pr * N + c]);
+      if (pv <= 1e-300 || pv < 1e-25 * amax) {
+        singular = true;
+        break;
+      }
+      if (pr != c) {
+        for (int q = 0; q < N; ++q) {
+          const double t = A[pr * N + q];
+          A[pr * N + q] = A[c * N + q];
+          A[c * N + q] = t;
+        }
+        const double t = rhs[pr];
+        rhs[pr] = rhs[c];
+        rhs[c] = t;
+      }
+      for (int r = c + 1; r < N; ++r) {
+        const double f = A[r * N + c] / A[c * N + c];
+        for (int q = c; q < N; ++q) A[r * N + q] -= f * A[c * N + q];
+        rhs[r] -= f * rhs[c];
+      }
+    }
+    if (!singular) {
+      for (int r = N - 1; r >= 0; --r) {
+        double acc = rhs[r];
+        for (int q = r + 1; q < N; ++q) acc -= A[r * N + q] * x[q];
+        x[r] = acc / A[r * N + r];
+        if (!isfinite(x[r])) singular = true;
+      }
+    }
+    if (!singular) {
+      for (int idx = 0; idx < m; ++idx) {
+        coef[idx] = x[idx];
+        st[5 + idx] = order[first + idx];
+      }
+      st[4] = m;
+      st[3] = 1;
+      return;
+    }
+    if (m <= 1) return;
+    ++first;
+    st[1] -= 1;
+  }
+}
+
+// The new vector and its error enter the slot the solve assigned.
+__global__ void diis_push_kernel(const double* __restrict__ vnew, const double* __restrict__ old,
+                                 double* __restrict__ vecs, double* __restrict__ errs, long long L,
+                                 const int* __restrict__ st) {
+  const long long base = (long long)st[2] * L;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (long long)gridDim.x * blockDim.x) {
+    const double vn = vnew[i];
+    vecs[base + i] = vn;
+    errs[base + i] = vn - old[i];
+  }
+}
+
+// vnew = sum_idx coef[idx] vecs[slot idx] (oldest first) when the solve
+// succeeded; otherwise vnew keeps the Jacobi vector.
+__global__ void diis_extrapolate_kernel(double* __restrict__ vnew, const double* __restrict__ vecs, long long L,
+                                        const int* __restrict__ st, const double* __restrict__ coef) {
+  if (st[3] == 0) return;
+  const int m = st[4];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int idx = 0; idx < m; ++idx) acc = fma(coef[idx], vecs[(long long)st[5 + idx] * L + i], acc);
+    vnew[i] = acc;
+  }
+}
+
+__global__ void diis_reset_kernel(int* __restrict__ st, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) st[i] = 0;
+}
+
+// scal[6] = scal[4] + 2 scal[5] (the energy); out[0..3] = scal[0..2], scal[6].
+__global__ void energy_scalars_kernel(double* __restrict__ scal, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double e = scal[4] + 2.0 * scal[5];
+  scal[6] = e;
+  if (out) {
+    out[0] = scal[0];
+    out[1] = scal[1];
+    out[2] = scal[2];
+    out[3] = e;
+  }
+}
+
+}  // namespace
+
+long long diis_chunks(const DiisArgs& a) {
+  const long long nc12 = (a.n12 + DIIS_CH - 1) / DIIS_CH;
+  if (a.L <= a.n12 || a.bs <= 0) return nc12;
+  return nc12 + (long long)a.ntri * ((a.bs + DIIS_CH - 1) / DIIS_CH);
+}
+
+hipError_t diis_device_step(double* vnew, const double* old, double* vecs, double* errs, double* part, double* d,
+                            double* B, int* st, double* coef, const DiisArgs& a, hipStream_t s) {
+  if (a.M < 1 || a.M > DIIS_MAX || a.L <= 0) return hipErrorInvalidValue;
+  const long long nc = diis_chunks(a);
+  if (nc > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(diis_overlap_kernel, dim3((unsigned)nc, (unsigned)(a.M + 1)), dim3(TPB), 0, s,
+                     (const double*)vnew, old, (const double*)errs, a, nc, part);
+  hipLaunchKernelGGL(diis_finalize_kernel, dim3((unsigned)(a.M + 1)), dim3(TPB), 0, s, (const double*)part, nc, d);
+  hipLaunchKernelGGL(diis_solve_kernel, dim3(1), dim3(64), 0, s, (const double*)d, B, st, coef, a.M, a.start);
+  hipLaunchKernelGGL(diis_push_kernel, dim3(blocks_for(a.L, TPB * 4)), dim3(TPB), 0, s, (const double*)vnew, old,
+                     vecs, errs, a.L, (const int*)st);
+  hipLaunchKernelGGL(diis_extrapolate_kernel, dim3(blocks_for(a.L, TPB * 4)), dim3(TPB), 0, s, vnew,
+                     (const double*)vecs, a.L, (const int*)st, (const double*)coef);
+  return hipGetLastError();
+}
+
+hipError_t diis_device_reset(int* st, hipStream_t s) {
+  hipLaunchKernelGGL(diis_reset_kernel, dim3(1), dim3(64), 0, s, st, DIIS_STATE);
+  return hipGetLastError();
+}
+
+hipError_t energy_scalars(double* scal, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(energy_scalars_kernel, dim3(1), dim3(64), 0, s, scal, out);
+  return hipGetLastError();
+}
+
 }  // namespace cct

@@ -1,0 +1,70 @@
+"""GPU: the quadruples ladder on compact T4 (cct_quad_*) against the RCCSDTQ
+oracle, through the C ABI.
+
+The oracle's particle-particle ladder term of Eq. resi-rccsdtq on the full
+tensor, passed through the 24-permutation operator and restricted to the
+stored blocks i <= j <= k <= l, is compared element by element with the
+six-term compact evaluation on the GPU.  Inputs: W^{ab}_{ef} random with the
+symmetry W^{ab}_{ef} = W^{ba}_{fe}, T4 column-symmetric random (every
+stored block, repeated occupied indices included).  Shapes: odd v (the
+strided FP64 kernel), even v (the K-contiguous matrix-core kernel), ragged
+tiles.  Tolerances: FP64 1e-12 of the largest element; FP32 2e-6 and
+split-BF16 5e-5 (operand rounding 2^-24 and about 2^-17, as for R3).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rccsdtq as Q4
+from paper_2607_00981_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 5e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _inputs(o, v, seed):
+    rng = np.random.default_rng(seed)
+    W = rng.normal(0.0, 0.1, (v, v, v, v))
+    W = 0.5 * (W + W.transpose(1, 0, 3, 2))
+    t4 = Q4.perm_sym4(rng.normal(0.0, 0.01, (o, o, o, o, v, v, v, v))) / 24.0
+    return W, Q4.pack_t4(t4), t4
+
+
+@pytest.mark.parametrize("o,v,seed", [(2, 5, 1), (3, 4, 2), (4, 6, 3), (2, 9, 4), (3, 10, 5)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_quad_ladder_matches_oracle(prec, o, v, seed):
+    say(f"[quad ladder] prec={prec} o={o} v={v}")
+    W, t4p, t4 = _inputs(o, v, seed)
+    ref = Q4.pack_t4(Q4.perm_sym4(Q4.pp_term(W, t4)))
+    with binding.Quad(o, v, precision=prec, opts={"timers": True}) as q:
+        q.set(W, t4p)
+        got, n2 = q.ladder()
+        macs, ms = q.counters()
+    scale = float(np.abs(ref).max())
+    err = float(np.abs(got - ref).max())
+    say(f"  max err {err:.3e} of {scale:.3e}")
+    assert scale > 0.0 and err <= TOL[prec] * scale
+    w = np.array([len(set(__import__("itertools").permutations(b))) for b in Q4.packed_list4(o)], dtype=float)
+    assert abs(n2 - float(np.sum(w[:, None, None, None, None] * got * got))) <= 1e-10 * max(n2, 1e-300)
+    assert macs["ladder"] == 6 * len(t4p) * v ** 6
+
+
+def test_quad_errors_and_index():
+    lib = binding.load()
+    assert binding.quad_count(3) == 15
+    assert lib.cct_quad_packed_index(3, 0, 0, 1, 2) == 2
+    assert lib.cct_quad_packed_index(3, 0, 1, 0, 2) == -1
+    with binding.Quad(2, 3) as q:
+        with pytest.raises(binding.CCTError) as e:
+            q.ladder()
+        assert e.value.code == binding.CCT_ESTATE
+    h = binding.C.c_void_p()
+    assert lib.cct_quad_create(0, 3, 0, None, None, None, None, None, binding.C.byref(h)) == binding.CCT_EINVAL
