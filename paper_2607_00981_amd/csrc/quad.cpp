@@ -322,7 +322,7 @@ int cct_quad_ladder(cct_quad* q, double* r4p, double* norm2) {
       t_gemm += b;
     }
   }
-  q->macs = 6.0 * (double)q->nq * (double)q->v4 * (double)q->v4;
+  q->macs = 6.0 * (double)q->nq * (double)q->v4 * (double)q->v * (double)q->v;  // 6 nq v^4 outputs x v^2
   q->ms[0] = t_rel;
   q->ms[1] = t_gemm;
   double h = 0.0;

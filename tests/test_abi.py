@@ -99,3 +99,19 @@ def test_q_task_count_reproduces_the_papers_printed_counts():
     for v, blk, n, tasks in rows:
         assert math.ceil(v / blk) == n
         assert binding.q_task_count(n) == tasks
+
+
+def test_quad_packed_index_matches_enumeration():
+    """cct_quad_packed_index / cct_quad_count (host only) against the
+    lexicographic enumeration of i <= j <= k <= l."""
+    from oracle import rccsdtq as Q4
+
+    lib = binding.load()
+    for o in (1, 2, 3, 5):
+        lst = Q4.packed_list4(o)
+        assert binding.quad_count(o) == len(lst) == o * (o + 1) * (o + 2) * (o + 3) // 24
+        for n, q in enumerate(lst):
+            assert lib.cct_quad_packed_index(o, *q) == n
+    assert lib.cct_quad_packed_index(3, 0, 1, 0, 2) == -1
+    assert lib.cct_quad_packed_index(3, 0, 0, 1, 3) == -1
+    assert binding.quad_count(-1) == -1

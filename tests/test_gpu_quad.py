@@ -57,11 +57,8 @@ def test_quad_ladder_matches_oracle(prec, o, v, seed):
     assert macs["ladder"] == 6 * len(t4p) * v ** 6
 
 
-def test_quad_errors_and_index():
+def test_quad_errors():
     lib = binding.load()
-    assert binding.quad_count(3) == 15
-    assert lib.cct_quad_packed_index(3, 0, 0, 1, 2) == 2
-    assert lib.cct_quad_packed_index(3, 0, 1, 0, 2) == -1
     with binding.Quad(2, 3) as q:
         with pytest.raises(binding.CCTError) as e:
             q.ladder()
