@@ -172,6 +172,19 @@ int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters
  * cct_set_fock / cct_set_eri_df.  Synchronous (returns after the stream has
  * drained). */
 int cct_energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap);
+/* cct_energy_q without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same evaluation, arguments and results as
+ * cct_energy_q, with every per-call buffer taken from a fixed 256 MiB device
+ * scratch array that the library holds on each GPU it runs on until the
+ * process ends (looked up once per device on the first call there).  No
+ * hipMalloc, hipFree or allocating library call.  Systems whose (Q) buffers
+ * exceed 256 MiB (about nocc = 4, nvir = 20; the need grows as o^2 v^4 and
+ * with the v^4 task blocks) are refused with CCT_ENOMEM and a message giving
+ * the need, before any device work.  Every call on a GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (two threads, two contexts) race and
+ * must be serialised by the caller; each call initialises what it reads. */
+int cct_energy_q_noalloc(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap);
 /* Number of (Q) tasks, i <= j <= k <= l < nocc: nocc(nocc+1)(nocc+2)(nocc+3)/24
  * (-1 for nocc < 0). */
 int64_t cct_q_task_count(int nocc);

@@ -73,6 +73,7 @@ def load(path: str | None = None):
         "cct_update": (C.c_int, [vp, dp, dp]),
         "cct_energy": (C.c_int, [vp, dp]),
         "cct_energy_q": (C.c_int, [vp, dp, dp, C.c_int64]),
+        "cct_energy_q_noalloc": (C.c_int, [vp, dp, dp, C.c_int64]),
         "cct_q_task_count": (C.c_int64, [C.c_int]),
         "cct_solve": (C.c_int, [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int)]),
         "cct_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
@@ -242,6 +243,15 @@ class Engine:
         nt = q_task_count(self.o)
         et = np.zeros(max(nt, 1)) if tasks else None
         self._check(self.lib.cct_energy_q(self.h, C.byref(e), _ptr(et), nt if tasks else 0))
+        return (e.value, et[:nt]) if tasks else e.value
+
+    def energy_q_noalloc(self, tasks=False):
+        """energy_q with every buffer taken from the library's fixed device
+        scratch (no allocation; small systems only)."""
+        e = C.c_double()
+        nt = q_task_count(self.o)
+        et = np.zeros(max(nt, 1)) if tasks else None
+        self._check(self.lib.cct_energy_q_noalloc(self.h, C.byref(e), _ptr(et), nt if tasks else 0))
         return (e.value, et[:nt]) if tasks else e.value
 
     def solve(self, max_iter=100, tol=None):

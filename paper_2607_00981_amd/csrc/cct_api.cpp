@@ -27,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,7 @@ struct cct_ctx {
   long long ntri = 0, v3 = 0;
   Prec prec = Prec::F64;
   hipStream_t s = nullptr;
+  int dev = 0;  // the HIP device current at cct_create (the stream's device)
   int diis_space = 8, diis_start = 2;
   bool diis_on = true, diis_t3 = true;
   int diis_sv = 0;  // T3 in DIIS: the sub-cube a, b, c < diis_sv of every block (0: all of T3)
@@ -1526,18 +1528,34 @@ DT Vview(cct_ctx* c, double* base, const char* blk) {
   return t;
 }
 
+// Device buffers of one (Q) evaluation: from the caller's allocator or
+// hipMalloc (returned when the evaluation ends), or carved from a fixed
+// device region (base != nullptr: nothing is allocated; `used` counts the
+// bytes asked for, also past `cap`, so that the caller can report the need
+// before any device work has started).
 struct QMem {
   cct_ctx* c;
   std::vector<void*> ps;
-  explicit QMem(cct_ctx* cc) : c(cc) {}
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  explicit QMem(cct_ctx* cc, char* region = nullptr, size_t region_bytes = 0)
+      : c(cc), base(region), cap(region_bytes) {}
   ~QMem() {
-    if (!ps.empty()) (void)hipStreamSynchronize(c->s);
+    if (!ps.empty() || used) (void)hipStreamSynchronize(c->s);
     for (void* p : ps) dev_free(c, p);
   }
+  bool fits() const { return used <= cap; }
   template <typename T>
   int get(T** p, long long n) {
+    const size_t bytes = (size_t)std::max<long long>(n, 1) * sizeof(T);
+    if (base) {
+      const size_t at = (used + 255) & ~(size_t)255;
+      used = at + bytes;
+      *p = used <= cap ? (T*)(base + at) : nullptr;
+      return CCT_OK;
+    }
     void* q = nullptr;
-    RCK(dev_alloc(c, &q, (size_t)std::max<long long>(n, 1) * sizeof(T)));
+    RCK(dev_alloc(c, &q, bytes));
     ps.push_back(q);
     *p = (T*)q;
     return CCT_OK;
@@ -1546,7 +1564,10 @@ struct QMem {
 
 long long q_task_count(int o) { return (long long)o * (o + 1) * (o + 2) * (o + 3) / 24; }
 
-int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
+// region / region_bytes: a fixed device region to take every buffer from
+// (no allocation); nullptr: the context's allocator, or hipMalloc.
+int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap, char* region = nullptr,
+             size_t region_bytes = 0) {
   const int o = ctx->o, v = ctx->v, n = ctx->n;
   const long long naux = ctx->naux, n2 = (long long)n * n, n4 = n2 * n2;
   const long long v2 = (long long)v * v, v3 = v2 * v, v4 = v3 * v, o2 = (long long)o * o;
@@ -1565,7 +1586,7 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   const long long T4 = tiled_len(v);
   const long long need = n4 + v4 + (long long)o * v3 + o2 * o * v + o2 * v2 + o2 * v4 + 2 * o2 * o2 * v2 +
                          o2 * o * v3 + 50 * v4 + (tl ? 48 * T4 : 0) + ntask + 1 + arena_n;
-  if (!ctx->alloc_fn) {
+  if (!ctx->alloc_fn && !region) {
     size_t fr = 0, tot = 0;
     HIPCK(hipMemGetInfo(&fr, &tot));
     if ((double)need * 8.0 + 256e6 > (double)fr) {
@@ -1574,7 +1595,7 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
       return CCT_ENOMEM;
     }
   }
-  QMem mem(ctx);
+  QMem mem(ctx, region, region_bytes);
   double *Vb, *VVVV, *VVVO, *VOOO, *VVOO, *Wv, *g, *Wo, *T3u, *Xb, *Gb, *Rb, *Ab, *et, *ar;
   int2* slots;
   RCK(mem.get(&Vb, n4));
@@ -1599,6 +1620,11 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap) {
   if (tl) {
     RCK(mem.get(&XT, 24 * T4));
     RCK(mem.get(&GT, 24 * T4));
+  }
+  if (!mem.fits()) {  // nothing has been launched yet
+    ctx->err = "energy_q: this system needs " + std::to_string(mem.used >> 20) + " MiB of device scratch, the " +
+               "fixed scratch region holds " + std::to_string(mem.cap >> 20) + " MiB";
+    return CCT_ENOMEM;
   }
   Arena qa;
   qa.init((char*)ar, (size_t)arena_n * 8);
@@ -2156,6 +2182,41 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
   return CCT_OK;
 }
 
+// --- fixed device scratch of the no-allocation (Q) entry point -------------
+// One file-scope device array, one copy per GPU, held until the process ends.
+// Its name is a host-side stand-in in host code: the device address of each
+// GPU's copy is looked up once per device (with that device current) and kept;
+// kernels and copies only ever receive that address.
+constexpr size_t kQScratchBytes = (size_t)256 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kQScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(cct_ctx* ctx, void** out) {
+  if (ctx->dev < 0 || ctx->dev >= kMaxDevices) {
+    ctx->err = "scratch: device index out of range";
+    return CCT_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[ctx->dev]) {
+    int cur = 0;
+    HIPCK(hipGetDevice(&cur));
+    if (cur != ctx->dev) HIPCK(hipSetDevice(ctx->dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != ctx->dev) HIPCK(hipSetDevice(cur));
+    if (e != hipSuccess || !p) {
+      ctx->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return CCT_EDEVICE;
+    }
+    g_scratch_addr[ctx->dev] = p;
+  }
+  *out = g_scratch_addr[ctx->dev];
+  return CCT_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2270,7 +2331,15 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     delete ctx;
     return CCT_EDEVICE;
   }
-
+  {
+    hipDevice_t d = 0;
+    const hipError_t e = ctx->s ? hipStreamGetDevice(ctx->s, &d) : hipGetDevice(&d);
+    if (e != hipSuccess) {
+      delete ctx;
+      return CCT_EDEVICE;
+    }
+    ctx->dev = (int)d;
+  }
   // workspace: everything in one batch if it fits, else what is left of the
   // device after the fixed allocations (minus a margin), capped by the option
   const double margin = 2e9;
@@ -2455,6 +2524,14 @@ int cct_energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap) {
   if (!ctx || !e_q || (e_tasks && cap < 0)) return CCT_EINVAL;
   if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
   return energy_q(ctx, e_q, e_tasks, (long long)cap);
+}
+
+int cct_energy_q_noalloc(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap) {
+  if (!ctx || !e_q || (e_tasks && cap < 0)) return CCT_EINVAL;
+  if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
+  void* region = nullptr;
+  RCK(scratch_address(ctx, &region));
+  return energy_q(ctx, e_q, e_tasks, (long long)cap, (char*)region, kQScratchBytes);
 }
 
 int64_t cct_q_task_count(int nocc) { return nocc < 0 ? -1 : (int64_t)q_task_count(nocc); }
