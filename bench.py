@@ -347,16 +347,22 @@ def run_batched(binding, niter, modes, tune_ms=0.0, graph=True, streams=4):
             "note": f"dE: energy after {niter} iterations minus the {modes[0]} batch's, per system"}
 
 
-def run_accuracy(binding, modes, tol=1e-8, max_iter=150):
-    """Converged energy per mode on o=10 v=90 with variance-scaled integrals:
-    FP64 runs DIIS to |R| < tol; each other mode runs as many iterations; dE
-    is measured against the FP64 energy."""
-    s = ci.make_named("o10v90-scaled")
+def run_accuracy(binding, modes, tol=1e-8, max_iter=150, workload="o10v90-scaled", iters=None, ref_energy=None):
+    """Converged energy per mode: the first mode runs DIIS to |R| < tol (or
+    exactly `iters` iterations); each other mode runs as many iterations; dE
+    is measured against the first mode's energy, or against `ref_energy`
+    (an FP64 energy after the same number of iterations from an earlier run)."""
+    s = ci.make_named(workload)
     o, v, naux = s["o"], s["v"], s["naux"]
-    out = {"workload": "o=10 v=90 naux=200 seed 2, B entries N(0, 0.05 sqrt(48/naux)), DIIS on T1/T2/T3, "
-                       f"FP64 to |R| < {tol:g}, other modes the same number of iterations"}
-    e_ref, n_iter = None, max_iter
+    base, _, variant = workload.partition("-")
+    sigma = ci.variant_sigma(variant, naux)
+    stop = f"exactly {iters} iterations" if iters else f"the first mode to |R| < {tol:g}"
+    out = {"workload": f"o={o} v={v} naux={naux} seed {s['seed']}, B entries N(0, {sigma:.6g}), DIIS on T1/T2, "
+                       f"{stop}, other modes the same number of iterations"}
+    e_ref, n_iter = ref_energy, iters or max_iter
+    fixed = iters is not None or ref_energy is not None
     for prec in modes:
+        traj = []
         with binding.Engine(o, v, naux, precision=prec) as eng:
             eng.set_fock(s["f"])
             eng.set_eri_df(s["B"])
@@ -365,16 +371,21 @@ def run_accuracy(binding, modes, tol=1e-8, max_iter=150):
             for it in range(n_iter):
                 e, nr = eng.update()
                 nrm = float(np.sqrt(nr.sum()))
-                if e_ref is None and nrm < tol:
+                traj.append((e, nrm))
+                log(f"[bench] converge {prec}: iteration {it + 1} E={e:.12f} |R|={nrm:.3e} ({_now() - t0:.1f} s)")
+                if not fixed and e_ref is None and nrm < tol:
                     break
             wall = _now() - t0
-        rec = {"energy": e, "iterations": it + 1, "residual_norm": nrm, "s": wall}
+        rec = {"energy": e, "iterations": it + 1, "residual_norm": nrm, "s": wall,
+               "energies": [x for x, _ in traj], "residual_norms": [y for _, y in traj]}
         if e_ref is None:
             e_ref, n_iter = e, it + 1
         else:
             rec["dE"] = e - e_ref
         out[prec] = rec
-        log(f"[bench] accuracy {prec}: {rec}")
+        log(f"[bench] accuracy {prec}: energy {e!r} after {it + 1} iterations, |R| {nrm:.3e}")
+    if ref_energy is not None:
+        out["reference_energy"] = ref_energy
     return out
 
 
@@ -556,6 +567,14 @@ def main(argv=None, binding=None):
                     help="iterations of the 64-system batch per mode (0 skips it)")
     ap.add_argument("--accuracy", action="store_true",
                     help="also the converged-energy comparison of the modes on o10v90-scaled")
+    ap.add_argument("--converge", default=None, metavar="NAME",
+                    help="only the converged-energy comparison of the modes on this workload (e.g. o20v180-weak)")
+    ap.add_argument("--converge-tol", type=float, default=1e-7, help="|R| at which the first mode stops")
+    ap.add_argument("--converge-max-iter", type=int, default=40)
+    ap.add_argument("--converge-iters", type=int, default=None,
+                    help="run exactly this many iterations in every mode")
+    ap.add_argument("--converge-ref-energy", type=float, default=None,
+                    help="energy of an earlier run after --converge-iters iterations; dE of every mode against it")
     ap.add_argument("--batched-graph", type=int, default=1, help="1: replay a recorded graph, 0: enqueue eagerly")
     ap.add_argument("--batched-streams", type=int, default=4, help="streams the batch's systems are spread over")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -627,10 +646,17 @@ def main(argv=None, binding=None):
         }), flush=True)
         return
 
+    if args.converge:
+        modes = [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision]
+        res = run_accuracy(binding, modes, tol=args.converge_tol, max_iter=args.converge_max_iter,
+                           workload=args.converge, iters=args.converge_iters, ref_energy=args.converge_ref_energy)
+        print(json.dumps({"converge": res, "wall_s": elapsed()}), flush=True)
+        return
+
     budget_end = args.budget_s
     s = ci.make_named(args.workload)
     o, v, naux, seed = s["o"], s["v"], s["naux"], s["seed"]
-    sigma = ci.scaled_sigma(naux) if args.workload.endswith("-scaled") else 0.05
+    sigma = ci.variant_sigma(args.workload.partition("-")[2], naux)
     compare = [m for m in args.compare.split(",") if m and m != args.precision]
     samples = sample_offsets(o, v)
     log(f"[bench] {args.workload}: o={o} v={v} naux={naux} seed={seed} sigma={sigma:.6g} main={args.precision} "
@@ -702,7 +728,7 @@ def main(argv=None, binding=None):
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"RCCSDT iteration o={o} v={v} naux={naux} seed={seed}, B entries N(0, {sigma:.6g}) "
-                               f"({'variance-scaled' if sigma != 0.05 else 'named'} recipe), compact T3 "
+                               f"({args.workload.partition('-')[2] or 'named'} recipe), compact T3 "
                                f"({o*(o+1)*(o+2)//6} triples x {v}^3), MP2 start, one untimed iteration, "
                                f"DIIS on T1/T2",
                    "precision": args.precision},

@@ -24,7 +24,12 @@ grow with naux (0.12 / 0.50 / 1.00 at naux = 48 / 200 / 400) and the larger
 named systems have no coupled-cluster solution reachable from the MP2 guess.
 ``scaled_sigma(naux)`` = 0.05 sqrt(48 / naux) keeps every (pq|rs) at the
 variance of the o=4, v=20 system; the "-scaled" variants of the named
-workloads (``make_named``) use it where a converged energy is needed.
+workloads (``make_named``) use it where a converged energy is needed.  At
+o=20, v=180 even the scaled integrals couple too strongly: the iteration from
+MP2 grows the residual about tenfold per step.  The "-weak" variant divides
+the scaled standard deviation by three (correlation energy about 1 % of the
+scaled one's MP2 value); from MP2 its residual norm falls by a factor of
+about 2.5 per iteration, so a converged energy exists at that size.
 """
 
 from __future__ import annotations
@@ -38,6 +43,7 @@ __all__ = [
     "make_system",
     "make_named",
     "scaled_sigma",
+    "variant_sigma",
     "batched_sizes",
     "random_fock",
     "random_amplitudes",
@@ -61,13 +67,24 @@ def scaled_sigma(naux: int) -> float:
     return 0.05 * float(np.sqrt(48.0 / naux))
 
 
+def variant_sigma(variant: str, naux: int) -> float:
+    """Entry standard deviation of a workload variant: "" (0.05), "scaled"
+    (scaled_sigma) or "weak" (scaled_sigma / 3)."""
+    if variant == "":
+        return 0.05
+    if variant == "scaled":
+        return scaled_sigma(naux)
+    if variant == "weak":
+        return scaled_sigma(naux) / 3.0
+    raise ValueError(f"unknown workload variant {variant!r}")
+
+
 def make_named(name: str) -> dict:
-    """A named workload ("o10v90"), or its variance-scaled variant ("o10v90-scaled")."""
+    """A named workload ("o10v90"), or its variance-scaled ("o10v90-scaled")
+    or weak-coupling ("o20v180-weak") variant."""
     base, _, variant = name.partition("-")
     o, v, naux, seed = CONFIGS[base]
-    if variant not in ("", "scaled"):
-        raise ValueError(f"unknown workload variant {variant!r}")
-    return make_system(o, v, naux, seed, sigma=scaled_sigma(naux) if variant else 0.05)
+    return make_system(o, v, naux, seed, sigma=variant_sigma(variant, naux))
 
 
 def make_system(o: int, v: int, naux: int | None = None, seed: int = 0, sigma: float = 0.05) -> dict:

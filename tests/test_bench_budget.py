@@ -83,6 +83,12 @@ def fake_binding(clock, iter_s, setup_s=12.0, batch_s=6.0):
         def close(self):
             pass
 
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            pass
+
     class Batch:
         def __init__(self, sizes, precision="fp64", opts=None):
             self.n = len(sizes)
@@ -175,3 +181,22 @@ def test_small_request_runs_exactly(sim, capsys):
     assert d["steps"] == 2 and d["warmup"] == 1
     assert b.calls["update"]["fp64"] == 3
     assert set(d["modes"]) == {"fp64", "bf16x3"} and not d["skipped"]
+
+
+def test_converge_leg_stops_at_tolerance_and_matches_iterations(sim, capsys):
+    # the fake squared norms sum to 3e-4 / iteration: |R| < 7e-3 from iteration 7 on
+    d, b, _ = _run(capsys, sim, ["--converge", "o4v20-weak", "--converge-tol", "7e-3", "--compare", "bf16x3"])
+    c = d["converge"]
+    assert c["fp64"]["iterations"] == 7 and c["bf16x3"]["iterations"] == 7
+    assert len(c["fp64"]["energies"]) == 7 and c["fp64"]["residual_norms"][-1] < 7e-3
+    assert c["bf16x3"]["dE"] == pytest.approx(5e-9, abs=1e-12)
+    assert "o=4 v=20 naux=48" in c["workload"]
+
+
+def test_converge_leg_against_a_stored_reference_energy(sim, capsys):
+    d, b, _ = _run(capsys, sim, ["--converge", "o4v20-weak", "--precision", "bf16x3", "--compare", "fp32",
+                                 "--converge-iters", "4", "--converge-ref-energy", "-10.4"])
+    c = d["converge"]
+    assert b.calls["update"] == {"bf16x3": 4, "fp32": 4}
+    assert c["bf16x3"]["dE"] == pytest.approx(5e-9, abs=1e-12)
+    assert c["fp32"]["dE"] == pytest.approx(1e-9, abs=1e-12)
