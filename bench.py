@@ -357,13 +357,16 @@ def run_accuracy(binding, modes, tol=1e-8, max_iter=150, workload="o10v90-scaled
     base, _, variant = workload.partition("-")
     sigma = ci.variant_sigma(variant, naux)
     stop = f"exactly {iters} iterations" if iters else f"the first mode to |R| < {tol:g}"
-    out = {"workload": f"o={o} v={v} naux={naux} seed {s['seed']}, B entries N(0, {sigma:.6g}), DIIS on T1/T2, "
-                       f"{stop}, other modes the same number of iterations"}
+    # T3 in the DIIS history needs 8 stored copies of it: from o = 20 on, T1/T2 only
+    diis_t3 = "none" if o >= 20 else "full"
+    out = {"workload": f"o={o} v={v} naux={naux} seed {s['seed']}, B entries N(0, {sigma:.6g}), DIIS on "
+                       f"{'T1/T2' if diis_t3 == 'none' else 'T1/T2/T3'}, {stop}, other modes the same number of "
+                       "iterations"}
     e_ref, n_iter = ref_energy, iters or max_iter
     fixed = iters is not None or ref_energy is not None
     for prec in modes:
         traj = []
-        with binding.Engine(o, v, naux, precision=prec) as eng:
+        with binding.Engine(o, v, naux, precision=prec, opts={"diis_t3": diis_t3}) as eng:
             eng.set_fock(s["f"])
             eng.set_eri_df(s["B"])
             eng.init_mp2()
