@@ -530,6 +530,43 @@ def run_q(binding, name, reps=2, cpu=True):
     return out
 
 
+QABC = {"workload": "o20v180-weak", "block": 4, "ntasks": 96}
+
+
+def run_q_abc(binding, name, block, ntasks):
+    """E_(Q) in the virtual-tuple order on a sample of its tasks (tile
+    quadruples spread evenly over the task list) at the state after one
+    iteration from MP2: device time of the one-time set-up (integral slices
+    and the T3 transposition) and of the sampled tasks, the executed
+    matrix-core rate, and the full evaluation's time extrapolated from the
+    sample."""
+    s = ci.make_named(name)
+    o, v, naux = s["o"], s["v"], s["naux"]
+    ntot = binding.q_abc_task_count(v, block)
+    n = min(ntasks, ntot)
+    pick = sorted(set(int(round(k * (ntot - 1) / max(n - 1, 1))) for k in range(n)))
+    with binding.Engine(o, v, naux, precision="bf16x3", opts={"diis_t3": "none" if o >= 20 else "full"}) as eng:
+        eng.set_fock(s["f"])
+        eng.set_eri_df(s["B"])
+        eng.init_mp2()
+        eng.update()
+        log(f"[bench] (Q) virtual-tuple order on {name}: {len(pick)} of {ntot} tasks, block {block} ...")
+        t0 = _now()
+        res = eng.energy_q_abc(block, tasks=pick)
+        wall = _now() - t0
+    st = res["stats"]
+    tasks_s = st["tasks_ms"] / 1000.0
+    rate = 2.0 * st["mfma_macs"] / tasks_s / 1e12 if tasks_s > 0 else None
+    out = {"workload": f"{name} (o={o} v={v} naux={naux}), T2/T3 after one iteration from MP2",
+           "block": block, "tasks_total": ntot, "tasks_timed": len(pick), "e_q_sampled_tasks": res["e_q"],
+           "wall_s": wall, "setup_s": st["setup_ms"] / 1000.0, "tasks_s": tasks_s,
+           "s_per_task": tasks_s / len(pick), "mfma_flop": 2.0 * st["mfma_macs"], "valu_flop": 2.0 * st["valu_macs"],
+           "tflops_mfma_over_tasks": rate, "peak": PEAK["fp64"], "frac": rate / PEAK["fp64"] if rate else None,
+           "full_evaluation_s_extrapolated": st["setup_ms"] / 1000.0 + tasks_s * ntot / len(pick)}
+    log(f"[bench] (Q) virtual-tuple order: {out}")
+    return out
+
+
 # ---------------------------------------------------------------------------
 def stored_traffic(prec, workload, kernel):
     """HBM bytes per launch of the ladder GEMM from the committed counter
@@ -587,6 +624,10 @@ def main(argv=None, binding=None):
     ap.add_argument("--panel", type=int, default=8, help="W rows a per rebuilt panel (--slab)")
     ap.add_argument("--q-workload", default="none", metavar="NAME",
                     help="also time the (Q) correction on this workload (e.g. o10v90-scaled)")
+    ap.add_argument("--q-abc", action="store_true",
+                    help="only the (Q) correction in the virtual-tuple order on sampled tasks of o20v180-weak")
+    ap.add_argument("--q-abc-tasks", type=int, default=QABC["ntasks"])
+    ap.add_argument("--q-abc-block", type=int, default=QABC["block"])
     ap.add_argument("--quad", action="store_true",
                     help="only the quadruples ladder on compact T4 (o=6 v=48), every mode")
     args = ap.parse_args(argv)
@@ -609,6 +650,21 @@ def main(argv=None, binding=None):
 
     if binding is None:
         from paper_2607_00981_amd import binding
+
+    if args.q_abc:
+        r = run_q_abc(binding, QABC["workload"], args.q_abc_block, args.q_abc_tasks)
+        print(json.dumps({
+            "metric": "(Q) correction, virtual-tuple order: matrix-core TFLOP/s over the sampled tasks, o=20 v=180",
+            "value": r["tflops_mfma_over_tasks"], "unit": "TFLOP/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1000.0 * r["tasks_s"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"], "block": r["block"]},
+            "q_abc": r,
+            "roofline": {"bound": "mfma", "achieved": r["tflops_mfma_over_tasks"], "peak": r["peak"],
+                         "unit": "TFLOP/s", "frac": r["frac"], "traffic": None,
+                         "kernel": "all kernels of the sampled tasks (matrix-core products, gathers, Wbar builds, "
+                                   "energy)"},
+        }), flush=True)
+        return
 
     if args.quad:
         modes = [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision]

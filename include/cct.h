@@ -189,6 +189,44 @@ int cct_energy_q_noalloc(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap
  * (-1 for nocc < 0). */
 int64_t cct_q_task_count(int nocc);
 
+/* E_(Q) in the virtual-tuple order of the "ABC-based algorithm" section
+ * (Eq. ener-pt-q-abc, with the alternative intermediates of Eq. q_w_alter):
+ * the same correction as cct_energy_q, summed over virtual tuples
+ * a <= b <= c <= d.  The virtual labels are cut into tiles of `block`
+ * (1..16, <= nvir); a task is a tile quadruple tA <= tB <= tC <= tD
+ * (lexicographic order, cct_q_abc_task_count(nvir, block) of them) and
+ * covers every tuple of its box with a <= b <= c <= d.  The call first
+ * transposes the packed T3 to the virtual-triangular layout (blocks
+ * a <= b <= c of o^3 contiguous occupied elements, Fig. q_operation_counts(a)),
+ * then evaluates the listed tasks: tasks (host, ntasks indices) or, with
+ * tasks == NULL, all of them (ntasks ignored).  *e_q: the fixed-order sum
+ * of the evaluated tasks; e_tasks (may be NULL; host, one entry per
+ * evaluated task); e_tuples (may be NULL; host, block^4 entries per task:
+ * the first n0 n1 n2 n3 hold the tuples of the task's box in row-major order
+ * over the four tiles' labels (n_s the tile sizes), each tuple's share of
+ * E_(Q), 0 for tuples outside a <= b <= c <= d or with three equal labels,
+ * the rest 0); stats (may be NULL; 4 entries): device ms of the integral
+ * slices and the T3 transposition, device ms of the tasks, multiply-adds of
+ * the tasks' matrix-core products, multiply-adds of the tasks' Wbar builds.
+ * FP64 whatever the context's precision; T1 does not enter.  Needs about
+ * 8 * (v(v+1)(v+2)/6 o^3 + v^4 + (o + v)^4 + 6 o^2 v^2 + 12 block^2 v o^3
+ * + 36 block^3 o^2 v + 2 block^4 o^4) bytes of device memory (about 90 GB at
+ * o=20, v=180, block 4): taken from the context's workspace when it holds
+ * them (the workspace is idle between iterations), else allocated for the
+ * duration of the call (the caller's allocator, or hipMalloc after a check
+ * of the free memory; CCT_ENOMEM with the need in the message).  CCT_EINVAL
+ * for a bad block or task index; CCT_ESTATE before cct_set_fock /
+ * cct_set_eri_df.  Synchronous. */
+int cct_energy_q_abc(cct_ctx* ctx, int block, const int64_t* tasks, int64_t ntasks, double* e_q, double* e_tasks,
+                     double* e_tuples, double stats[4]);
+/* Tasks of cct_energy_q_abc: T (T + 1) (T + 2) (T + 3) / 24 with
+ * T = ceil(nvir / block) (-1 for nvir < 1 or block < 1). */
+int64_t cct_q_abc_task_count(int nvir, int block);
+/* out[i] = element idx[i] of the packed T3 (element (t, a, b, c) at
+ * ((t v + a) v + b) v + c), i < n; host arrays.  CCT_EINVAL for an index
+ * outside the packed T3.  Synchronous. */
+int cct_gather_t3(cct_ctx* ctx, const int64_t* idx, int64_t n, double* out);
+
 /* Algorithmic multiply-add counts of the last residual per R3 term group
  * (indices as the CCT_TERM_* bit positions, 9 entries) and device time in ms
  * per phase (entries: 0 setup/dressing+CCSD, 1 feedback, 2 PP, 3 rings,

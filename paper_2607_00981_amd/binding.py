@@ -75,6 +75,9 @@ def load(path: str | None = None):
         "cct_energy_q": (C.c_int, [vp, dp, dp, C.c_int64]),
         "cct_energy_q_noalloc": (C.c_int, [vp, dp, dp, C.c_int64]),
         "cct_q_task_count": (C.c_int64, [C.c_int]),
+        "cct_energy_q_abc": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int64), C.c_int64, dp, dp, dp, dp]),
+        "cct_q_abc_task_count": (C.c_int64, [C.c_int, C.c_int]),
+        "cct_gather_t3": (C.c_int, [vp, C.POINTER(C.c_int64), C.c_int64, dp]),
         "cct_solve": (C.c_int, [vp, C.c_int, C.c_double, dp, C.POINTER(C.c_int)]),
         "cct_get_counters": (C.c_int, [vp, dp, dp, C.c_int]),
         "cct_autotune": (C.c_int, [vp, C.c_double, C.POINTER(C.c_int)]),
@@ -139,6 +142,10 @@ def ntri(o):
 
 def q_task_count(o):
     return load().cct_q_task_count(o)
+
+
+def q_abc_task_count(v, block):
+    return load().cct_q_abc_task_count(v, block)
 
 
 class Engine:
@@ -253,6 +260,38 @@ class Engine:
         et = np.zeros(max(nt, 1)) if tasks else None
         self._check(self.lib.cct_energy_q_noalloc(self.h, C.byref(e), _ptr(et), nt if tasks else 0))
         return (e.value, et[:nt]) if tasks else e.value
+
+    def energy_q_abc(self, block, tasks=None, tuples=False):
+        """E_(Q) in the virtual-tuple order over tiles of `block` virtual labels:
+        all tasks (tasks=None) or the listed task indices.  Returns a dict with
+        e_q (the sum over the evaluated tasks), e_tasks, e_tuples (with
+        tuples=True: block^4 values per task) and stats (device ms of the
+        set-up and of the tasks, multiply-adds of the matrix-core products
+        and of the Wbar builds)."""
+        e = C.c_double()
+        if tasks is None:
+            nt = q_abc_task_count(self.v, block)
+            tp, ntp = None, 0
+        else:
+            tl = np.ascontiguousarray(tasks, dtype=np.int64)
+            nt = len(tl)
+            tp, ntp = tl.ctypes.data_as(C.POINTER(C.c_int64)), nt
+        et = np.zeros(max(nt, 1))
+        eu = np.zeros(max(nt, 1) * block ** 4) if tuples else None
+        st = np.zeros(4)
+        self._check(self.lib.cct_energy_q_abc(self.h, block, tp, ntp, C.byref(e), _ptr(et), _ptr(eu), _ptr(st)))
+        out = {"e_q": e.value, "e_tasks": et[:nt],
+               "stats": {"setup_ms": st[0], "tasks_ms": st[1], "mfma_macs": st[2], "valu_macs": st[3]}}
+        if tuples:
+            out["e_tuples"] = eu[: nt * block ** 4].reshape(nt, block ** 4)
+        return out
+
+    def gather_t3(self, idx):
+        """Elements of the packed T3 at the flat indices idx (host int64)."""
+        ix = np.ascontiguousarray(idx, dtype=np.int64).ravel()
+        out = np.zeros(max(len(ix), 1))
+        self._check(self.lib.cct_gather_t3(self.h, ix.ctypes.data_as(C.POINTER(C.c_int64)), len(ix), _ptr(out)))
+        return out[: len(ix)].reshape(np.shape(idx))
 
     def solve(self, max_iter=100, tol=None):
         """Iterate to sqrt(sum |R|^2) < tol (None: the context's "tol" option);

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcct.so")
 
-SOURCES = ["gemm.hip", "tensor_ops.hip", "q_ops.hip", "contract.cpp", "cct_api.cpp", "slab.cpp", "quad.cpp"]
+SOURCES = ["gemm.hip", "tensor_ops.hip", "q_ops.hip", "q_abc.hip", "contract.cpp", "cct_api.cpp", "slab.cpp", "quad.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

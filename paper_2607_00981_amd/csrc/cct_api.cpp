@@ -1880,6 +1880,509 @@ int energy_q(cct_ctx* ctx, double* e_q, double* e_tasks, long long cap, char* re
   return finite_or_err(ctx, *e_q);
 }
 
+// --- perturbative quadruples in the virtual-tuple order --------------------
+// E_(Q) summed over virtual tuples a <= b <= c <= d as in Eq. ener-pt-q-abc,
+// with the alternative Wbar intermediates of Eq. q_w_alter (Sec. "ABC-based
+// algorithm").  The virtual labels are cut into tiles of nb; a task is a tile
+// quadruple tA <= tB <= tC <= tD and covers the dense box of tuples
+// tau = (a, b, c, d), a in tA, ..., d in tD (the four "slots").  In the frame
+// of tau (occupied index i_s paired with the label tau_s) the task
+// accumulates
+//   Xt[tau](i) = the sum over the 24 simultaneous column permutations of X,
+//   Yt[tau](i) = the same sum of Y,
+// without forming any ordered tuple's block: two permutations that differ
+// by a column symmetry of a term's factors (T3 in two columns, Wbar^{vvv}_{voo}
+// in (jb)(kc), Wbar^{vvo}_{ooo} in (ia)(jb)) give equal terms, so each kind of
+// term reduces to 12 distinct contractions of weight 2, and those sharing
+// the slots of the output rows are one matrix-core product with concatenated
+// K segments (X1: 4 products of K = 3v, X2: 6 of K = 2o, Y1: 6 of K = 2v,
+// Y2: 4 of K = 3o).  Then R = Xt + Yt is the full permutation sum of X + Y at
+// tau, U = S(R) / eps with S the spin summation, and tau contributes
+// (Xt + Vt, U) / |Stab(tau)| (Vt the six distinct rank-one V terms); only
+// tuples with a <= b <= c <= d count, so every orbit is counted once.
+long long q_abc_tiles(int v, int nb) { return (v + nb - 1) / nb; }
+long long q_abc_task_count(int v, int nb) {
+  const long long t = q_abc_tiles(v, nb);
+  return t * (t + 1) * (t + 2) * (t + 3) / 24;
+}
+
+int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, double* e_q, double* e_tasks,
+                 double* e_tuples, double* stats) {
+  const int o = ctx->o, v = ctx->v, n = ctx->n;
+  if (nb < 1 || nb > 16 || nb > v) {
+    ctx->err = "energy_q_abc: block must be in [1, min(16, nvir)]";
+    return CCT_EINVAL;
+  }
+  const long long ntile = q_abc_tiles(v, nb), ntot = q_abc_task_count(v, nb);
+  if (!tasks) ntasks = ntot;
+  if (ntasks < 0) return CCT_EINVAL;
+  std::vector<long long> tlist((size_t)ntasks);
+  for (long long i = 0; i < ntasks; ++i) {
+    tlist[(size_t)i] = tasks ? (long long)tasks[i] : i;
+    if (tlist[(size_t)i] < 0 || tlist[(size_t)i] >= ntot) {
+      ctx->err = "energy_q_abc: task index " + std::to_string(tlist[(size_t)i]) + " outside [0, " +
+                 std::to_string(ntot) + ")";
+      return CCT_EINVAL;
+    }
+  }
+  // task index -> tile quadruple (lexicographic over t0 <= t1 <= t2 <= t3)
+  std::vector<std::array<int, 4>> quad;
+  quad.reserve((size_t)ntot);
+  for (int a = 0; a < ntile; ++a)
+    for (int b = a; b < ntile; ++b)
+      for (int c = b; c < ntile; ++c)
+        for (int d = c; d < ntile; ++d) quad.push_back({a, b, c, d});
+  const long long naux = ctx->naux, n2 = (long long)n * n, n4 = n2 * n2;
+  const long long o2 = (long long)o * o, o3 = o2 * o, o4 = o2 * o2, v2 = (long long)v * v, o2v = o2 * v;
+  const long long nvt = (long long)v * (v + 1) * (v + 2) / 6;
+  const long long b2 = (long long)nb * nb, b3 = b2 * nb, b4 = b2 * b2;
+  const long long nchunk = (o4 + 2047) / 2048;
+  // the T3 transposition works on cubes of 16^3 labels, A <= B <= C
+  std::vector<int4> units;
+  const int ncb = (v + 15) / 16;
+  for (int a = 0; a < ncb; ++a)
+    for (int b = a; b < ncb; ++b)
+      for (int c = b; c < ncb; ++c) units.push_back(int4{a, b, c, 0});
+  const long long nunit = (long long)units.size();
+  const long long ntup = e_tuples ? b4 * ntasks : b4;
+  const long long need = nvt * o3 + v2 * v2 + v2 * v * o + 2 * (long long)v * o3 + 3 * o2 * v2 + o4 +
+                         3 * o2 * v2 + 12 * b2 * v * o3 + 12 * b3 * o3 + 36 * b3 * o2v + 12 * b2 * o4 +
+                         2 * b4 * o4 + b4 * nchunk + ntup + ntasks + 2 * nunit + 64 * 256;
+  const double peak_gb = (double)(need + n4) * 8.0 / 1e9;
+  // buffers from the context's workspace when it holds them, else from one
+  // allocation for the duration of the call
+  const size_t bytes = (size_t)(need + n4) * 8 + (size_t)64 * 256 * 64;
+  Arena own_arena;
+  Arena* ar = &ctx->ws;
+  struct Own {
+    cct_ctx* c;
+    void* p = nullptr;
+    ~Own() {
+      if (p) {
+        (void)hipStreamSynchronize(c->s);
+        dev_free(c, p);
+      }
+    }
+  } own{ctx};
+  if ((double)ctx->ws.available() < (double)bytes) {
+    if (!ctx->alloc_fn) {
+      size_t fr = 0, tot = 0;
+      HIPCK(hipMemGetInfo(&fr, &tot));
+      if ((double)bytes + 256e6 > (double)fr) {
+        ctx->err = "energy_q_abc: needs " + std::to_string(peak_gb) + " GB; the context workspace holds " +
+                   std::to_string(ctx->ws.available() / 1e9) + " GB and the device has " + std::to_string(fr / 1e9) +
+                   " GB free";
+        return CCT_ENOMEM;
+      }
+    }
+    RCK(dev_alloc(ctx, &own.p, bytes));
+    own_arena.init((char*)own.p, bytes);
+    ar = &own_arena;
+  }
+  struct Mark {
+    Arena& a;
+    size_t m;
+    ~Mark() { a.reset(m); }
+  } mark{*ar, ar->mark()};
+  hipStream_t s = ctx->s;
+  const Prec F = Prec::F64;
+  auto get = [&](long long cnt) { return ar->alloc((size_t)std::max<long long>(cnt, 1)); };
+  double* T3v = get(nvt * o3);
+  double* VVVV = get(v2 * v2);
+  double* VVVO = get(v2 * v * o);  // [x][y][j][e] = v^{xy}_{ej}
+  double* VO1 = get((long long)v * o3);  // [x][i][j][m] = v^{xm}_{ij}
+  double* VO2 = get((long long)v * o3);  // [x][i][j][m] = v^{xm}_{ji}
+  double* Vmyje = get(o2 * v2);  // [m][y][j][e] = v^{my}_{ej}
+  double* Vmxje = get(o2 * v2);  // [m][x][j][e] = v^{mx}_{je}
+  double* Voooo = get(o4);        // [m][n][k][i] = v^{mn}_{ki}
+  double* Vvvoo = get(o2 * v2);   // [x][y][i][j] = v^{xy}_{ij}
+  double* t2R = get(o2 * v2);     // [d][e][i][j] = t_ij^ed
+  double* t2L = get(o2 * v2);     // [x][e][i][j] = t_ij^xe
+  double* t2Q = get(o2 * v2);     // [x][m][y][n] = t_mn^xy
+  double* frag[4][4] = {};
+  for (int r = 0; r < 4; ++r)
+    for (int s0 = 0; s0 < 4; ++s0)
+      if (s0 != r) frag[r][s0] = get(b2 * v * o3);
+  double* x2b[4][4] = {};  // [s1][s0]: the T3 blocks of the X2 term with (s0, s1) on the rows
+  for (int r0 = 0; r0 < 4; ++r0)
+    for (int r1 = r0 + 1; r1 < 4; ++r1) {
+      x2b[r1][r0] = get(b3 * o3);
+      x2b[r0][r1] = get(b3 * o3);
+    }
+  double* Z[4][4][4] = {};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c)
+        if (a != b && b != c && a != c) Z[a][b][c] = get(b3 * o2v);
+  double* Wo[4][4] = {};  // [s3][s2]
+  for (int s3 = 0; s3 < 4; ++s3)
+    for (int s2 = 0; s2 < 4; ++s2)
+      if (s2 != s3) Wo[s3][s2] = get(b2 * o4);
+  auto pid = [](int r0, int r1) { return r0 * 4 + r1; };
+  double* WvS[4][16] = {};  // [s0][pair id of the row slots (r0, r1)]
+  for (int s0 = 0; s0 < 4; ++s0)
+    for (int r0 = 0; r0 < 4; ++r0)
+      for (int r1 = r0 + 1; r1 < 4; ++r1)
+        if (s0 != r0 && s0 != r1) WvS[s0][pid(r0, r1)] = get(b3 * o2v);
+  double* Xt = get(b4 * o4);
+  double* Yt = get(b4 * o4);
+  double* part = get(b4 * nchunk);
+  double* etup = get(ntup);
+  double* etask = get(ntasks);
+  int4* d_units = (int4*)get(2 * nunit);
+  double* Vb = get(n4);
+  if (!Vb || !d_units || !etask || !etup || !part || !Yt || !Xt) {
+    ctx->err = "energy_q_abc: workspace exhausted (" + std::to_string(peak_gb) + " GB needed)";
+    return CCT_ENOMEM;
+  }
+  hipEvent_t ev[4] = {};
+  struct Ev {
+    hipEvent_t* e;
+    ~Ev() {
+      for (int i = 0; i < 4; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } evguard{ev};
+  for (auto& e : ev) HIPCK(hipEventCreate(&e));
+  HIPCK(hipEventRecord(ev[0], s));
+  // bare integrals v^{pq}_{rs} = (pr|qs), then the slices the task products read
+  {
+    GemmArgs ga{};
+    ga.M = (int)n2; ga.N = (int)n2; ga.K = (int)naux; ga.batch = 1;
+    ga.A = ctx->B; ga.am = idx1(1); ga.ak = idx1(n2);
+    ga.B = ctx->B; ga.bk = idx1(n2); ga.bn = idx1(1);
+    ga.C = Vb; ga.cm = idx1(n2); ga.cn = idx1(1);
+    ga.alpha = 1.0; ga.beta = 0.0;
+    ga.a_len = naux * n2; ga.b_len = naux * n2; ga.c_len = n4;
+    HIPCK(gemm(ga, F, s));
+  }
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvvv"), "xyef", 0.0, dense(VVVV, {v, v, v, v}), "xyef"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvvo"), "xyej", 0.0, dense(VVVO, {v, v, o, v}), "xyje"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vooo"), "xmij", 0.0, dense(VO1, {v, o, o, o}), "xijm"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vooo"), "xmji", 0.0, dense(VO2, {v, o, o, o}), "xijm"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "ovvo"), "myej", 0.0, dense(Vmyje, {o, v, o, v}), "myje"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "ovov"), "mxje", 0.0, dense(Vmxje, {o, v, o, v}), "mxje"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "oooo"), "mnki", 0.0, dense(Voooo, {o, o, o, o}), "mnki"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvoo"), "xyij", 0.0, dense(Vvvoo, {v, v, o, o}), "xyij"));
+  {
+    const DT t2 = dense(ctx->t2, {o, o, v, v});
+    STCK(accumulate(s, 1.0, t2, "ijed", 0.0, dense(t2R, {v, v, o, o}), "deij"));
+    STCK(accumulate(s, 1.0, t2, "ijxe", 0.0, dense(t2L, {v, v, o, o}), "xeij"));
+    STCK(accumulate(s, 1.0, t2, "mnxy", 0.0, dense(t2Q, {v, o, v, o}), "xmyn"));
+  }
+  // T3 in the virtual-triangular layout (the one-time transposition of the
+  // compact amplitudes, Fig. q_operation_counts(a))
+  HIPCK(hipMemcpyAsync(d_units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, s));
+  HIPCK(hipStreamSynchronize(s));  // the host table is released below
+  HIPCK(t3v_transpose(ctx->t3, ctx->tbl, T3v, d_units, nunit, o, v, s));
+  HIPCK(fill(etup, 0.0, ntup, s));
+  HIPCK(hipEventRecord(ev[1], s));
+
+  double macs_mfma = 0.0, macs_valu = 0.0;
+  auto run = [&](QGemmArgs& g) -> int {
+    long long batch = 1;
+    for (int d = 0; d < g.nd; ++d) batch *= g.rad[d];
+    long long K = 0;
+    for (int k = 0; k < g.nseg; ++k) K += g.K[k];
+    macs_mfma += (double)g.M * g.N * K * batch;
+    HIPCK(qgemm(g, s));
+    return CCT_OK;
+  };
+  const long long pw[4] = {o3, o2, (long long)o, 1};
+  auto lin = [](long long st) { return Idx4{1, 1, 1, st, 0, 0, 0}; };
+  auto pair_map = [&](int u, int w) { return Idx4{1, 1, o, pw[u], 0, 0, pw[w]}; };       // (i_u, i_w)
+  auto trip_map = [&](int a, int b, int c) { return Idx4{1, o, o, pw[a], 0, pw[b], pw[c]}; };  // (i_a, i_b, i_c)
+
+  for (long long ti = 0; ti < ntasks; ++ti) {
+    const std::array<int, 4>& tq = quad[(size_t)tlist[(size_t)ti]];
+    QSlots sl{};
+    for (int k = 0; k < 4; ++k) {
+      sl.st[k] = tq[k] * nb;
+      sl.n[k] = std::min(nb, v - sl.st[k]);
+    }
+    long long S[4];
+    for (int k = 0; k < 4; ++k) {
+      S[k] = o4;
+      for (int t = k + 1; t < 4; ++t) S[k] *= sl.n[t];
+    }
+    const long long ntau = (long long)sl.n[0] * sl.n[1] * sl.n[2] * sl.n[3];
+    const long long tlen = ntau * o4;
+    // T3 slices: X1 fragments [lx][ly][e][i_u][i_v][i_w] (u < v < w the slots
+    // other than r; column pairs (i_s0, e), (i_x, tau_x), (i_y, tau_y))
+    for (int r = 0; r < 4; ++r) {
+      int oth[3], k = 0;
+      for (int t = 0; t < 4; ++t)
+        if (t != r) oth[k++] = t;
+      for (int a = 0; a < 3; ++a) {
+        const int s0 = oth[a], x = oth[a == 0 ? 1 : 0], y = oth[a == 2 ? 1 : 2];
+        T3Gather g{};
+        g.o = o; g.v = v; g.nd = 2; g.ne = v;
+        g.rad[0] = sl.n[x]; g.rad[1] = sl.n[y];
+        g.st[0] = sl.st[x]; g.st[1] = sl.st[y];
+        auto pos = [&](int sl_) { return sl_ == oth[0] ? 0 : (sl_ == oth[1] ? 1 : 2); };
+        g.lab[0] = 3; g.ax[0] = pos(s0);
+        g.lab[1] = 0; g.ax[1] = pos(x);
+        g.lab[2] = 1; g.ax[2] = pos(y);
+        HIPCK(t3v_gather(T3v, frag[r][s0], g, s));
+      }
+    }
+    // X2 blocks [l_s1][l_c0][l_c1][m][i_c0][i_c1], column pairs (m, tau_s1),
+    // (i_c0, tau_c0), (i_c1, tau_c1), for the rows (s0, s1)
+    for (int r0 = 0; r0 < 4; ++r0)
+      for (int r1 = r0 + 1; r1 < 4; ++r1) {
+        int cc[2], k = 0;
+        for (int t = 0; t < 4; ++t)
+          if (t != r0 && t != r1) cc[k++] = t;
+        for (int w = 0; w < 2; ++w) {
+          const int s1 = w == 0 ? r1 : r0, s0 = w == 0 ? r0 : r1;
+          T3Gather g{};
+          g.o = o; g.v = v; g.nd = 3; g.ne = 1;
+          g.rad[0] = sl.n[s1]; g.rad[1] = sl.n[cc[0]]; g.rad[2] = sl.n[cc[1]];
+          g.st[0] = sl.st[s1]; g.st[1] = sl.st[cc[0]]; g.st[2] = sl.st[cc[1]];
+          for (int c = 0; c < 3; ++c) {
+            g.lab[c] = c;
+            g.ax[c] = c;
+          }
+          HIPCK(t3v_gather(T3v, x2b[s1][s0], g, s));
+        }
+      }
+    // Z_abc[la][lb][lc][j][k][e] = 1/2 sum_f v^{xy}_{ef} t_jk^{fz}
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        for (int c = 0; c < 4; ++c) {
+          if (a == b || b == c || a == c) continue;
+          QGemmArgs g{};
+          g.M = (int)(sl.n[c] * o2); g.N = v; g.nseg = 1; g.K[0] = v;
+          g.nd = 2; g.rad[0] = sl.n[a]; g.rad[1] = sl.n[b];
+          g.akm = true; g.bkn = false;
+          g.a[0].p = t2L + (long long)sl.st[c] * o2; g.a[0].ld = (long long)v * o2; g.a[0].len = o2 * v2 - (long long)sl.st[c] * o2;
+          g.b[0].p = VVVV + ((long long)sl.st[a] * v + sl.st[b]) * v2; g.b[0].ld = v;
+          g.b[0].sd[0] = (long long)v * v2; g.b[0].sd[1] = v2;
+          g.b[0].len = v2 * v2 - ((long long)sl.st[a] * v + sl.st[b]) * v2;
+          g.C = Z[a][b][c]; g.cm = lin(v); g.cn = lin(1);
+          g.sc[0] = (long long)sl.n[b] * sl.n[c] * o2v; g.sc[1] = (long long)sl.n[c] * o2v;
+          g.c_len = b3 * o2v;
+          g.alpha = 0.5; g.accumulate = 0;
+          RCK(run(g));
+        }
+    // Wbar^{vvv}_{voo} for x in slot s0, (y, z) in the row slots (r0, r1)
+    for (int s0 = 0; s0 < 4; ++s0)
+      for (int r0 = 0; r0 < 4; ++r0)
+        for (int r1 = r0 + 1; r1 < 4; ++r1) {
+          if (s0 == r0 || s0 == r1) continue;
+          HIPCK(q_wv_build(WvS[s0][pid(r0, r1)], Z[s0][r0][r1], Z[s0][r1][r0], Vmyje, Vmxje, ctx->t2, o, v, sl.st[s0],
+                           sl.n[s0], sl.st[r0], sl.n[r0], sl.st[r1], sl.n[r1], s));
+          macs_valu += 4.0 * o * sl.n[s0] * sl.n[r0] * sl.n[r1] * o2v;
+        }
+    // Wbar^{vvo}_{ooo} for (x, y) in slots (s0 < s1), rows = the slots other than s3
+    for (int s3 = 0; s3 < 4; ++s3)
+      for (int s2 = 0; s2 < 4; ++s2) {
+        if (s2 == s3) continue;
+        int rs[3], k = 0, p01[2], kk = 0;
+        for (int t = 0; t < 4; ++t)
+          if (t != s3) rs[k++] = t;
+        for (int t = 0; t < 4; ++t)
+          if (t != s3 && t != s2) p01[kk++] = t;
+        auto pos = [&](int sl_) { return sl_ == rs[0] ? 0 : (sl_ == rs[1] ? 1 : 2); };
+        const int rowpos[3] = {pos(p01[0]), pos(p01[1]), pos(s2)};
+        HIPCK(q_wo_build(Wo[s3][s2], Voooo, ctx->t2, o, v, sl.st[p01[0]], sl.n[p01[0]], sl.st[p01[1]], sl.n[p01[1]],
+                         rowpos, s));
+        macs_valu += 2.0 * o * sl.n[p01[0]] * sl.n[p01[1]] * o4;
+      }
+    // X1: per row slot r, K segments over s0 (the slot whose label is summed)
+    for (int r = 0; r < 4; ++r) {
+      int oth[3], k = 0;
+      for (int t = 0; t < 4; ++t)
+        if (t != r) oth[k++] = t;
+      QGemmArgs g{};
+      g.nseg = 3; g.nd = 3;
+      for (int d = 0; d < 3; ++d) {
+        g.rad[d] = sl.n[oth[d]];
+        g.sc[d] = S[oth[d]];
+      }
+      const bool sw = r == 3;  // the unit-stride axis i_3 on the rows side
+      for (int a = 0; a < 3; ++a) {
+        const int s0 = oth[a];
+        const int xd = a == 0 ? 1 : 0, yd = a == 2 ? 1 : 2;  // digits of x and y
+        QgOperand V{}, Fr{};
+        V.p = VVVO + ((long long)sl.st[s0] * v + sl.st[r]) * o * v;
+        V.ld = v;
+        V.sd[a] = v2 * o;
+        V.len = v2 * v * o - ((long long)sl.st[s0] * v + sl.st[r]) * o * v;
+        Fr.p = frag[r][s0];
+        Fr.ld = o3;
+        Fr.sd[xd] = (long long)sl.n[oth[yd]] * v * o3;
+        Fr.sd[yd] = (long long)v * o3;
+        Fr.len = b2 * v * o3;
+        g.K[a] = v;
+        g.a[a] = sw ? Fr : V;
+        g.b[a] = sw ? V : Fr;
+      }
+      const Idx4 rowm = Idx4{1, 1, o, S[r], 0, 0, pw[r]};
+      const Idx4 colm = trip_map(oth[0], oth[1], oth[2]);
+      g.akm = sw; g.bkn = !sw;
+      g.M = (int)(sw ? o3 : sl.n[r] * o);
+      g.N = (int)(sw ? sl.n[r] * o : o3);
+      g.cm = sw ? colm : rowm;
+      g.cn = sw ? rowm : colm;
+      g.C = Xt; g.c_len = tlen;
+      g.alpha = 1.0; g.accumulate = r == 0 ? 0 : 1;
+      RCK(run(g));
+    }
+    // X2: per row pair (r0, r1), segments (s0, s1) = (r0, r1) and (r1, r0)
+    for (int r0 = 0; r0 < 4; ++r0)
+      for (int r1 = r0 + 1; r1 < 4; ++r1) {
+        int cc[2], k = 0;
+        for (int t = 0; t < 4; ++t)
+          if (t != r0 && t != r1) cc[k++] = t;
+        QGemmArgs g{};
+        g.nseg = 2; g.nd = 4;
+        for (int d = 0; d < 4; ++d) {
+          g.rad[d] = sl.n[d];
+          g.sc[d] = S[d];
+        }
+        const bool sw = r1 == 3;
+        for (int w = 0; w < 2; ++w) {
+          const int s0 = w == 0 ? r0 : r1, s1 = w == 0 ? r1 : r0;
+          QgOperand A{}, B{};
+          A.p = (w == 0 ? VO1 : VO2) + (long long)sl.st[s0] * o3;
+          A.ld = o;
+          A.sd[s0] = o3;
+          A.len = (long long)v * o3 - (long long)sl.st[s0] * o3;
+          B.p = x2b[s1][s0];
+          B.ld = o2;
+          B.sd[s1] = (long long)sl.n[cc[0]] * sl.n[cc[1]] * o3;
+          B.sd[cc[0]] = (long long)sl.n[cc[1]] * o3;
+          B.sd[cc[1]] = o3;
+          B.len = b3 * o3;
+          g.K[w] = o;
+          g.a[w] = sw ? B : A;
+          g.b[w] = sw ? A : B;
+        }
+        const Idx4 rowm = pair_map(r0, r1), colm = pair_map(cc[0], cc[1]);
+        g.akm = sw; g.bkn = !sw;
+        g.M = (int)o2; g.N = (int)o2;
+        g.cm = sw ? colm : rowm;
+        g.cn = sw ? rowm : colm;
+        g.C = Xt; g.c_len = tlen;
+        g.alpha = -1.0; g.accumulate = 1;
+        RCK(run(g));
+      }
+    // Y1: per column pair (c0, c1), segments (s0, s3) = (c0, c1) and (c1, c0);
+    // rows (l_r0, l_r1, i_r0, i_r1)
+    bool firsty = true;
+    for (int c0 = 0; c0 < 4; ++c0)
+      for (int c1 = c0 + 1; c1 < 4; ++c1) {
+        int rr[2], k = 0;
+        for (int t = 0; t < 4; ++t)
+          if (t != c0 && t != c1) rr[k++] = t;
+        QGemmArgs g{};
+        g.nseg = 2; g.nd = 2;
+        g.rad[0] = sl.n[c0]; g.rad[1] = sl.n[c1];
+        g.sc[0] = S[c0]; g.sc[1] = S[c1];
+        const bool sw = c1 != 3;  // i_3 among the row slots
+        const long long wvb = (long long)sl.n[rr[0]] * sl.n[rr[1]] * o2v;
+        for (int w = 0; w < 2; ++w) {
+          const int s0 = w == 0 ? c0 : c1;
+          QgOperand A{}, B{};
+          A.p = WvS[s0][pid(rr[0], rr[1])];
+          A.ld = v;
+          A.sd[w] = wvb;
+          A.len = (long long)sl.n[s0] * wvb;
+          if (w == 0) {  // t_{i_c0 i_c1}^{e tau_c1}
+            B.p = t2R + (long long)sl.st[c1] * v * o2;
+            B.sd[1] = (long long)v * o2;
+            B.len = o2 * v2 - (long long)sl.st[c1] * v * o2;
+          } else {  // t_{i_c1 i_c0}^{e tau_c0} = t_{i_c0 i_c1}^{tau_c0 e}
+            B.p = t2L + (long long)sl.st[c0] * v * o2;
+            B.sd[0] = (long long)v * o2;
+            B.len = o2 * v2 - (long long)sl.st[c0] * v * o2;
+          }
+          B.ld = o2;
+          g.K[w] = v;
+          g.a[w] = sw ? B : A;
+          g.b[w] = sw ? A : B;
+        }
+        const Idx4 rowm = Idx4{sl.n[rr[1]], o, o, S[rr[0]], S[rr[1]], pw[rr[0]], pw[rr[1]]};
+        const Idx4 colm = pair_map(c0, c1);
+        const long long Mr = (long long)sl.n[rr[0]] * sl.n[rr[1]] * o2;
+        g.akm = sw; g.bkn = !sw;
+        g.M = (int)(sw ? o2 : Mr);
+        g.N = (int)(sw ? Mr : o2);
+        g.cm = sw ? colm : rowm;
+        g.cn = sw ? rowm : colm;
+        g.C = Yt; g.c_len = tlen;
+        g.alpha = 1.0; g.accumulate = firsty ? 0 : 1;
+        firsty = false;
+        RCK(run(g));
+      }
+    // Y2: per column slot s3, segments over s2 (the Wbar^{vvo}_{ooo} pair is
+    // the other two slots)
+    for (int s3 = 0; s3 < 4; ++s3) {
+      int rs[3], k = 0;
+      for (int t = 0; t < 4; ++t)
+        if (t != s3) rs[k++] = t;
+      QGemmArgs g{};
+      g.nseg = 3; g.nd = 3;
+      for (int d = 0; d < 3; ++d) {
+        g.rad[d] = sl.n[rs[d]];
+        g.sc[d] = S[rs[d]];
+      }
+      const bool sw = s3 != 3;
+      for (int a = 0; a < 3; ++a) {
+        const int s2 = rs[a];
+        const int d0 = a == 0 ? 1 : 0, d1 = a == 2 ? 1 : 2;  // digits of the pair (s0 < s1)
+        QgOperand A{}, B{};
+        A.p = Wo[s3][s2];
+        A.ld = o;
+        A.sd[d0] = (long long)sl.n[rs[d1]] * o4;
+        A.sd[d1] = o4;
+        A.len = b2 * o4;
+        B.p = t2Q + (long long)sl.st[s2] * o * v * o + (long long)sl.st[s3] * o;
+        B.ld = (long long)v * o;
+        B.sd[a] = (long long)o * v * o;
+        B.len = o2 * v2 - ((long long)sl.st[s2] * o * v * o + (long long)sl.st[s3] * o);
+        g.K[a] = o;
+        g.a[a] = sw ? B : A;
+        g.b[a] = sw ? A : B;
+      }
+      const Idx4 rowm = trip_map(rs[0], rs[1], rs[2]);
+      const Idx4 colm = Idx4{1, 1, o, S[s3], 0, 0, pw[s3]};
+      g.akm = sw; g.bkn = !sw;
+      g.M = (int)(sw ? sl.n[s3] * o : o3);
+      g.N = (int)(sw ? o3 : sl.n[s3] * o);
+      g.cm = sw ? colm : rowm;
+      g.cn = sw ? rowm : colm;
+      g.C = Yt; g.c_len = tlen;
+      g.alpha = -1.0; g.accumulate = 1;
+      RCK(run(g));
+    }
+    // R = Xt + Yt; energies of the box's tuples
+    HIPCK(q_add(Yt, Xt, tlen, s));
+    HIPCK(q_abc_energy(Xt, Yt, Vvvoo, ctx->t2, ctx->eps, sl, o, v, part, etup + (e_tuples ? ti * b4 : 0),
+                       etask + ti, s));
+  }
+  HIPCK(hipEventRecord(ev[2], s));
+  std::vector<double> h((size_t)ntasks);
+  if (ntasks > 0) HIPCK(hipMemcpyAsync(h.data(), etask, sizeof(double) * ntasks, hipMemcpyDeviceToHost, s));
+  if (e_tuples && ntasks > 0) HIPCK(hipMemcpyAsync(e_tuples, etup, sizeof(double) * b4 * ntasks, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (double x : h) sum += x;
+  if (e_tasks) std::copy(h.begin(), h.end(), e_tasks);
+  *e_q = sum;
+  if (stats) {
+    float t01 = 0.f, t12 = 0.f;
+    HIPCK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+    HIPCK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+    stats[0] = t01;
+    stats[1] = t12;
+    stats[2] = macs_mfma;
+    stats[3] = macs_valu;
+  }
+  return finite_or_err(ctx, sum);
+}
+
 // --- DIIS ---------------------------------------------------------------
 // T3 elements per packed block that take part in DIIS (Sec. "Distributed
 // DIIS": all of T3, none of it, or only the low-energy virtual subspace)
@@ -2535,6 +3038,50 @@ int cct_energy_q_noalloc(cct_ctx* ctx, double* e_q, double* e_tasks, int64_t cap
 }
 
 int64_t cct_q_task_count(int nocc) { return nocc < 0 ? -1 : (int64_t)q_task_count(nocc); }
+
+int64_t cct_q_abc_task_count(int nvir, int block) {
+  if (nvir < 1 || block < 1) return -1;
+  return (int64_t)q_abc_task_count(nvir, block);
+}
+
+int cct_energy_q_abc(cct_ctx* ctx, int block, const int64_t* tasks, int64_t ntasks, double* e_q, double* e_tasks,
+                     double* e_tuples, double stats[4]) {
+  if (!ctx || !e_q || (tasks && ntasks < 0)) return CCT_EINVAL;
+  if (!ctx->have_f || !ctx->have_B) { ctx->err = "integrals not set"; return CCT_ESTATE; }
+  return energy_q_abc(ctx, block, tasks, tasks ? (long long)ntasks : 0, e_q, e_tasks, e_tuples, stats);
+}
+
+int cct_gather_t3(cct_ctx* ctx, const int64_t* idx, int64_t n, double* out) {
+  if (!ctx || n < 0 || (n > 0 && (!idx || !out))) return CCT_EINVAL;
+  const long long len = ctx->ntri * ctx->v3;
+  for (int64_t i = 0; i < n; ++i)
+    if (idx[i] < 0 || idx[i] >= len) {
+      ctx->err = "gather_t3: index " + std::to_string(idx[i]) + " outside the packed T3";
+      return CCT_EINVAL;
+    }
+  // chunks of indices through the workspace
+  const size_t mark = ctx->ws.mark();
+  const long long chunk = std::min<long long>(std::max<long long>(n, 1), 1LL << 24);
+  long long* di = (long long*)ctx->ws.alloc((size_t)chunk);
+  double* dv = ctx->ws.alloc((size_t)chunk);
+  if (!di || !dv) {
+    ctx->ws.reset(mark);
+    ctx->err = "gather_t3: workspace exhausted";
+    return CCT_ENOMEM;
+  }
+  int rc = CCT_OK;
+  for (long long a = 0; a < n && rc == CCT_OK; a += chunk) {
+    const long long m = std::min(chunk, (long long)n - a);
+    if (hipMemcpyAsync(di, idx + a, sizeof(long long) * m, hipMemcpyHostToDevice, ctx->s) != hipSuccess ||
+        gather_idx(ctx->t3, di, m, dv, ctx->s) != hipSuccess ||
+        hipMemcpyAsync(out + a, dv, sizeof(double) * m, hipMemcpyDeviceToHost, ctx->s) != hipSuccess ||
+        hipStreamSynchronize(ctx->s) != hipSuccess)
+      rc = CCT_EDEVICE;
+  }
+  ctx->ws.reset(mark);
+  if (rc != CCT_OK) ctx->err = "gather_t3: device error";
+  return rc;
+}
 
 int cct_solve(cct_ctx* ctx, int max_iter, double tol, double* e_corr, int* iters) {
   if (!ctx || max_iter < 1 || std::isnan(tol)) return CCT_EINVAL;

@@ -306,4 +306,92 @@ static inline long long tiled_len(int v) {
   return nt * nt * nt * nt * 4096;
 }
 
+// --- perturbative quadruples in the virtual-tuple order --------------------
+// Four-level index map: i = ((d0 n1 + d1) n2 + d2) n3 + d3 -> sum_k d_k s_k
+// (n1, n2, n3 >= 1).
+struct Idx4 {
+  int n1, n2, n3;
+  long long s0, s1, s2, s3;
+};
+
+// Segmented, digit-batched FP64 product on the matrix cores:
+//   C[z](m, n) (+)= alpha * sum_s sum_{k < K_s} A_s[z](m, k) B_s[z](k, n)
+// The batch index z (gridDim.z) is split into nd digits of radices rad (the
+// last fastest); each operand of each K segment s sits at base + sum_d
+// digit_d * sd[d].  A_s is K-contiguous ([m][k] at m*ld + k) or, with AKM,
+// M-contiguous ([k][m] at k*ld + m); B_s is N-contiguous ([k][n] at
+// k*ld + n) or, without BKN, K-contiguous ([n][k] at n*ld + k).  C through
+// the four-level maps cm, cn plus sum_d digit_d * sc[d].
+constexpr int QG_MAXSEG = 3, QG_MAXD = 4;
+struct QgOperand {
+  const double* p;
+  long long ld;
+  long long sd[QG_MAXD];
+  long long len;  // elements addressable from p (for the host bounds check)
+};
+struct QGemmArgs {
+  int M, N, nseg, nd;
+  int K[QG_MAXSEG];
+  int rad[QG_MAXD];
+  QgOperand a[QG_MAXSEG], b[QG_MAXSEG];
+  bool akm, bkn;
+  double* C;
+  Idx4 cm, cn;
+  long long sc[QG_MAXD];
+  long long c_len;
+  double alpha;
+  int accumulate;  // 1: C += alpha A B, 0: C = alpha A B
+};
+hipError_t qgemm(const QGemmArgs& g, hipStream_t s);
+
+// T3 in the virtual-triangular layout: block vb(a <= b <= c) (lexicographic)
+// holds t_{ijk}^{abc} for all i, j, k at vb * o^3 + (i o + j) o + k.  Filled
+// from the packed occupied-triangular T3 through the table of ordered
+// triples (tbl[(i o + j) o + k]).  cubes: (A, B, C, 0) with A <= B <= C,
+// every cube of 16^3 labels that holds a canonical triple; ncubes of them.
+hipError_t t3v_transpose(const double* T, const BlockRef* tbl, double* T3v, const int4* cubes, long long ncubes,
+                         int o, int v, hipStream_t s);
+// Gather of T3v slices: out[blk][e][y0][y1][y2], blk over nd label digits
+// (radices rad, first labels st), e over ne values (0..ne-1), y over o^3.
+// Column pair c of t3 takes its virtual label from digit lab[c] (lab[c] == 3:
+// e) and its occupied index from output axis ax[c].
+struct T3Gather {
+  int o, v, nd, ne;
+  int rad[3], st[3];
+  int lab[3], ax[3];
+};
+hipError_t t3v_gather(const double* T3v, double* out, const T3Gather& g, hipStream_t s);
+
+// Slots of one virtual tile task: first label and size of each of the four
+// index ranges.
+struct QSlots {
+  int st[4], n[4];
+};
+// Wbar^{vvo}_{ooo} of Eq. q_w_alter for the label pairs (x, y) of slots
+// (s0, s1) with the occupied indices of slots (s0, s1, s2) in slot order:
+// out[lx][ly][rows][m], rows = the three indices ordered by slot, from
+// Voooo[m][n][k][i] = v^{mn}_{ki} and t2[i][j][a][b].
+hipError_t q_wo_build(double* out, const double* Voooo, const double* t2, int o, int v, int x0, int nx, int y0, int ny,
+                      const int rowpos[3], hipStream_t s);
+// Wbar^{vvv}_{voo} of Eq. q_w_alter for x in slot s0 and (y, z) in slots
+// (r0, r1): out[lx][ly][lz][j][k][e] = Z_xy[z](j, k, e) + Z_xz[y](k, j, e)
+// + the four K = o terms, with Z_ab[c] = 1/2 sum_f v^{ab}_{ef} t_{jk}^{fc}
+// laid out [la][lb][lc][j][k][e] (Zxy: slots (s0, r0, r1), Zxz: (s0, r1, r0)),
+// Vmyje[m][y][j][e] = v^{my}_{ej}, Vmxje[m][x][j][e] = v^{mx}_{je}.
+hipError_t q_wv_build(double* out, const double* Zxy, const double* Zxz, const double* Vmyje, const double* Vmxje,
+                      const double* t2, int o, int v, int x0, int nx, int y0, int ny, int z0, int nz, hipStream_t s);
+// Y += X over n elements.
+hipError_t q_add(double* Y, const double* X, long long n, hipStream_t s);
+// out[i] = src[idx[i]], i < n.
+hipError_t gather_idx(const double* src, const long long* idx, long long n, double* out, hipStream_t s);
+// Energy of the tuples of one task: for every tuple tau of the dense box
+// (slot sizes n[]) with a <= b <= c <= d and no three equal labels,
+//   e_tau = 1/|Stab| sum_i (X[tau](i) + Vs(tau, i)) U(tau, i),
+//   U = (1/den) sum_pi c_pi R[tau](i o pi),
+// R = X + Y (in R), Vs the rank-one terms, den the orbital-energy
+// denominator; other tuples get 0.  etup[tau] (dense order) and etask (the
+// fixed-order sum over the box) are written on the device.
+hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2, const double* eps,
+                        const QSlots& sl, int o, int v, double* part, double* etup, double* etask, hipStream_t s);
+
 }  // namespace cct

@@ -115,3 +115,12 @@ def test_quad_packed_index_matches_enumeration():
     assert lib.cct_quad_packed_index(3, 0, 1, 0, 2) == -1
     assert lib.cct_quad_packed_index(3, 0, 0, 1, 3) == -1
     assert binding.quad_count(-1) == -1
+
+
+def test_q_abc_task_count_is_the_tile_quadruple_count():
+    import itertools
+    for v, nb in ((1, 1), (7, 2), (8, 4), (180, 4), (90, 8), (30, 16)):
+        nt = -(-v // nb)
+        assert binding.q_abc_task_count(v, nb) == sum(1 for _ in itertools.combinations_with_replacement(range(nt), 4))
+    assert binding.q_abc_task_count(0, 4) == -1
+    assert binding.q_abc_task_count(10, 0) == -1
