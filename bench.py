@@ -530,7 +530,7 @@ def run_q(binding, name, reps=2, cpu=True):
     return out
 
 
-QABC = {"workload": "o20v180-weak", "block": 4, "ntasks": 96}
+QABC = {"workload": "o20v180-weak", "block": 6, "ntasks": 24}
 
 
 def run_q_abc(binding, name, block, ntasks):

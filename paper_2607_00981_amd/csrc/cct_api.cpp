@@ -1936,7 +1936,8 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   const long long o2 = (long long)o * o, o3 = o2 * o, o4 = o2 * o2, v2 = (long long)v * v, o2v = o2 * v;
   const long long nvt = (long long)v * (v + 1) * (v + 2) / 6;
   const long long b2 = (long long)nb * nb, b3 = b2 * nb, b4 = b2 * b2;
-  const long long nchunk = (o4 + 2047) / 2048;
+  const std::vector<int> orbits = q_abc_orbits(o);
+  const long long norb = (long long)orbits.size() / 25;
   // the T3 transposition works on cubes of 16^3 labels, A <= B <= C
   std::vector<int4> units;
   const int ncb = (v + 15) / 16;
@@ -1947,7 +1948,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   const long long ntup = e_tuples ? b4 * ntasks : b4;
   const long long need = nvt * o3 + v2 * v2 + v2 * v * o + 2 * (long long)v * o3 + 3 * o2 * v2 + o4 +
                          3 * o2 * v2 + 12 * b2 * v * o3 + 12 * b3 * o3 + 36 * b3 * o2v + 12 * b2 * o4 +
-                         2 * b4 * o4 + b4 * nchunk + ntup + ntasks + 2 * nunit + 64 * 256;
+                         2 * b4 * o4 + b4 * norb + ntup + ntasks + 2 * nunit + (long long)orbits.size() + 64 * 256;
   const double peak_gb = (double)(need + n4) * 8.0 / 1e9;
   // buffers from the context's workspace when it holds them, else from one
   // allocation for the duration of the call
@@ -1994,7 +1995,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   double* VO2 = get((long long)v * o3);  // [x][i][j][m] = v^{xm}_{ji}
   double* Vmyje = get(o2 * v2);  // [m][y][j][e] = v^{my}_{ej}
   double* Vmxje = get(o2 * v2);  // [m][x][j][e] = v^{mx}_{je}
-  double* Voooo = get(o4);        // [m][n][k][i] = v^{mn}_{ki}
+  double* Voooo = get(o4);        // [n][k][i][m] = v^{mn}_{ki}
   double* Vvvoo = get(o2 * v2);   // [x][y][i][j] = v^{xy}_{ij}
   double* t2R = get(o2 * v2);     // [d][e][i][j] = t_ij^ed
   double* t2L = get(o2 * v2);     // [x][e][i][j] = t_ij^xe
@@ -2026,12 +2027,13 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         if (s0 != r0 && s0 != r1) WvS[s0][pid(r0, r1)] = get(b3 * o2v);
   double* Xt = get(b4 * o4);
   double* Yt = get(b4 * o4);
-  double* part = get(b4 * nchunk);
+  double* part = get(b4 * norb);
+  int* d_orb = (int*)get(((long long)orbits.size() + 1) / 2);
   double* etup = get(ntup);
   double* etask = get(ntasks);
   int4* d_units = (int4*)get(2 * nunit);
   double* Vb = get(n4);
-  if (!Vb || !d_units || !etask || !etup || !part || !Yt || !Xt) {
+  if (!Vb || !d_units || !d_orb || !etask || !etup || !part || !Yt || !Xt) {
     ctx->err = "energy_q_abc: workspace exhausted (" + std::to_string(peak_gb) + " GB needed)";
     return CCT_ENOMEM;
   }
@@ -2062,7 +2064,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vooo"), "xmji", 0.0, dense(VO2, {v, o, o, o}), "xijm"));
   STCK(accumulate(s, 1.0, Vview(ctx, Vb, "ovvo"), "myej", 0.0, dense(Vmyje, {o, v, o, v}), "myje"));
   STCK(accumulate(s, 1.0, Vview(ctx, Vb, "ovov"), "mxje", 0.0, dense(Vmxje, {o, v, o, v}), "mxje"));
-  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "oooo"), "mnki", 0.0, dense(Voooo, {o, o, o, o}), "mnki"));
+  STCK(accumulate(s, 1.0, Vview(ctx, Vb, "oooo"), "mnki", 0.0, dense(Voooo, {o, o, o, o}), "nkim"));
   STCK(accumulate(s, 1.0, Vview(ctx, Vb, "vvoo"), "xyij", 0.0, dense(Vvvoo, {v, v, o, o}), "xyij"));
   {
     const DT t2 = dense(ctx->t2, {o, o, v, v});
@@ -2073,7 +2075,8 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   // T3 in the virtual-triangular layout (the one-time transposition of the
   // compact amplitudes, Fig. q_operation_counts(a))
   HIPCK(hipMemcpyAsync(d_units, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, s));
-  HIPCK(hipStreamSynchronize(s));  // the host table is released below
+  HIPCK(hipMemcpyAsync(d_orb, orbits.data(), sizeof(int) * orbits.size(), hipMemcpyHostToDevice, s));
+  HIPCK(hipStreamSynchronize(s));  // the host tables are released below
   HIPCK(t3v_transpose(ctx->t3, ctx->tbl, T3v, d_units, nunit, o, v, s));
   HIPCK(fill(etup, 0.0, ntup, s));
   HIPCK(hipEventRecord(ev[1], s));
@@ -2359,8 +2362,8 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
     }
     // R = Xt + Yt; energies of the box's tuples
     HIPCK(q_add(Yt, Xt, tlen, s));
-    HIPCK(q_abc_energy(Xt, Yt, Vvvoo, ctx->t2, ctx->eps, sl, o, v, part, etup + (e_tuples ? ti * b4 : 0),
-                       etask + ti, s));
+    HIPCK(q_abc_energy(Xt, Yt, Vvvoo, t2R, ctx->eps, sl, o, v, d_orb, (int)norb, part,
+                       etup + (e_tuples ? ti * b4 : 0), etask + ti, s));
   }
   HIPCK(hipEventRecord(ev[2], s));
   std::vector<double> h((size_t)ntasks);

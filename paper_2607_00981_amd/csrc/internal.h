@@ -370,7 +370,7 @@ struct QSlots {
 // Wbar^{vvo}_{ooo} of Eq. q_w_alter for the label pairs (x, y) of slots
 // (s0, s1) with the occupied indices of slots (s0, s1, s2) in slot order:
 // out[lx][ly][rows][m], rows = the three indices ordered by slot, from
-// Voooo[m][n][k][i] = v^{mn}_{ki} and t2[i][j][a][b].
+// Voooo[n][k][i][m] = v^{mn}_{ki} and t2[i][j][a][b].
 hipError_t q_wo_build(double* out, const double* Voooo, const double* t2, int o, int v, int x0, int nx, int y0, int ny,
                       const int rowpos[3], hipStream_t s);
 // Wbar^{vvv}_{voo} of Eq. q_w_alter for x in slot s0 and (y, z) in slots
@@ -384,14 +384,18 @@ hipError_t q_wv_build(double* out, const double* Zxy, const double* Zxz, const d
 hipError_t q_add(double* Y, const double* X, long long n, hipStream_t s);
 // out[i] = src[idx[i]], i < n.
 hipError_t gather_idx(const double* src, const long long* idx, long long n, double* out, hipStream_t s);
-// Energy of the tuples of one task: for every tuple tau of the dense box
+// Energy of the tuples of one task (t2R[b][a][i][j] = t_ij^ab): for every
+// tuple tau of the dense box
 // (slot sizes n[]) with a <= b <= c <= d and no three equal labels,
 //   e_tau = 1/|Stab| sum_i (X[tau](i) + Vs(tau, i)) U(tau, i),
 //   U = (1/den) sum_pi c_pi R[tau](i o pi),
 // R = X + Y (in R), Vs the rank-one terms, den the orbital-energy
 // denominator; other tuples get 0.  etup[tau] (dense order) and etask (the
 // fixed-order sum over the box) are written on the device.
-hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2, const double* eps,
-                        const QSlots& sl, int o, int v, double* part, double* etup, double* etask, hipStream_t s);
+hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2R, const double* eps,
+                        const QSlots& sl, int o, int v, const int* orbits, int norb, double* part, double* etup,
+                        double* etask, hipStream_t s);
+// The block orbits q_abc_energy takes (1 + 24 ints each; size / 25 orbits).
+std::vector<int> q_abc_orbits(int o);
 
 }  // namespace cct

@@ -10,6 +10,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -20,13 +21,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 constexpr int QBK = 16;
 
-__device__ __forceinline__ long long map4(const Idx4& d, long long i) {
-  const long long d3 = i % d.n3;
-  i /= d.n3;
-  const long long d2 = i % d.n2;
-  i /= d.n2;
-  const long long d1 = i % d.n1;
-  return (i / d.n1) * d.s0 + d1 * d.s1 + d2 * d.s2 + d3 * d.s3;
+// Four-level map of an index below 2^31 (32-bit digit arithmetic).
+__device__ __forceinline__ long long map4(const Idx4& d, int i) {
+  const unsigned u = (unsigned)i;
+  const unsigned d3 = u % (unsigned)d.n3, r3 = u / (unsigned)d.n3;
+  const unsigned d2 = r3 % (unsigned)d.n2, r2 = r3 / (unsigned)d.n2;
+  const unsigned d1 = r2 % (unsigned)d.n1, d0 = r2 / (unsigned)d.n1;
+  return (long long)d0 * d.s0 + (long long)d1 * d.s1 + (long long)d2 * d.s2 + (long long)d3 * d.s3;
 }
 
 // blockIdx.x -> output tile; consecutive workgroups go to different XCDs
@@ -50,6 +51,10 @@ __device__ __forceinline__ bool q_tile(int tiles_m, int tiles_n, int& tm, int& t
 
 // Tile BM x BN = (16 TM WM) x (16 TN WN), WM x WN waves; K tiles of 16 over
 // the concatenated segments; LDS double-buffered as [k][m] and [k][n].
+// Each thread's load units keep their offsets inside the operand (set when a
+// segment starts, advanced by one K tile per step), so the main loop does no
+// index arithmetic beyond an add; the epilogue maps its rows and columns
+// once.
 template <int TM, int TN, int WM, int WN, bool AKM, bool BKN, bool VEC>
 __global__ __launch_bounds__(64 * WM * WN) void qgemm_kernel(QGemmArgs g, int tiles_m, int tiles_n, int batch) {
   constexpr int NTH = 64 * WM * WN, BM = 16 * TM * WM, BN = 16 * TN * WN;
@@ -69,98 +74,108 @@ __global__ __launch_bounds__(64 * WM * WN) void qgemm_kernel(QGemmArgs g, int ti
     dig[d] = z % g.rad[d];
     z /= g.rad[d];
   }
-  long long aoff[QG_MAXSEG], boff[QG_MAXSEG];
-  int ktl[QG_MAXSEG];
-  int ntile = 0;
+  const int m0 = tm * BM, n0 = tn * BN;
+  // this thread's load units: position in the tile (row or column, k)
+  int ar[NA], ak[NA], br[NB], bk[NB];
 #pragma unroll
-  for (int s = 0; s < QG_MAXSEG; ++s) {
-    aoff[s] = 0;
-    boff[s] = 0;
-    ktl[s] = 0;
-    if (s < g.nseg) {
-      for (int d = 0; d < g.nd; ++d) {
-        aoff[s] += dig[d] * g.a[s].sd[d];
-        boff[s] += dig[d] * g.b[s].sd[d];
-      }
-      ktl[s] = (g.K[s] + QBK - 1) / QBK;
-      ntile += ktl[s];
+  for (int i = 0; i < NA; ++i) {
+    const int u = tid + i * NTH;
+    if constexpr (AKM) {
+      ak[i] = u / (BM / W);
+      ar[i] = (u % (BM / W)) * W;
+    } else {
+      ar[i] = u / (QBK / W);
+      ak[i] = (u % (QBK / W)) * W;
     }
   }
-  long long coff = 0;
-  for (int d = 0; d < g.nd; ++d) coff += dig[d] * g.sc[d];
-  const int m0 = tm * BM, n0 = tn * BN;
-
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int u = tid + i * NTH;
+    if constexpr (BKN) {
+      bk[i] = u / (BN / W);
+      br[i] = (u % (BN / W)) * W;
+    } else {
+      br[i] = u / (QBK / W);
+      bk[i] = (u % (QBK / W)) * W;
+    }
+  }
+  // segment state
+  int seg = -1, seg_first = 0, seg_k = 0;
+  const double* Ab = nullptr;
+  const double* Bb = nullptr;
+  long long aoff[NA], boff[NB], astep = 0, bstep = 0;
+  int total = 0;
+  for (int s = 0; s < g.nseg; ++s) total += (g.K[s] + QBK - 1) / QBK;
+  auto enter = [&](int s) {
+    seg = s;
+    seg_k = g.K[s];
+    long long ao = 0, bo = 0;
+    for (int d = 0; d < g.nd; ++d) {
+      ao += dig[d] * g.a[s].sd[d];
+      bo += dig[d] * g.b[s].sd[d];
+    }
+    Ab = g.a[s].p + ao;
+    Bb = g.b[s].p + bo;
+    const long long lda = g.a[s].ld, ldb = g.b[s].ld;
+    astep = AKM ? QBK * lda : QBK;
+    bstep = BKN ? QBK * ldb : QBK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      aoff[i] = AKM ? (long long)ak[i] * lda + (m0 + ar[i]) : (long long)(m0 + ar[i]) * lda + ak[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      boff[i] = BKN ? (long long)bk[i] * ldb + (n0 + br[i]) : (long long)(n0 + br[i]) * ldb + bk[i];
+  };
   dbl2 ra[NA], rb[NB];
   bool oa[NA], ob[NB];
+  int kt_in_seg = 0;  // K tile index inside the current segment
   auto load = [&](int t) {
-    int s = 0;
-    while (s + 1 < g.nseg && t >= ktl[s]) t -= ktl[s++];
-    const int k0 = t * QBK, Ks = g.K[s];
-    const double* A = g.a[s].p + aoff[s];
-    const double* B = g.b[s].p + boff[s];
-    const long long lda = g.a[s].ld, ldb = g.b[s].ld;
+    // t runs over the concatenated K tiles; move to the segment holding it
+    if (seg < 0 || t - seg_first >= (seg_k + QBK - 1) / QBK) {
+      int s = seg < 0 ? 0 : seg + 1, first = seg < 0 ? 0 : seg_first + (seg_k + QBK - 1) / QBK;
+      while (s + 1 < g.nseg && t - first >= (g.K[s] + QBK - 1) / QBK) first += (g.K[s++] + QBK - 1) / QBK;
+      seg_first = first;
+      enter(s);
+    }
+    kt_in_seg = t - seg_first;
+    const int k0 = kt_in_seg * QBK;
+    const long long ash = kt_in_seg * astep, bsh = kt_in_seg * bstep;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int u = tid + i * NTH;
-      int row, kk;
-      if constexpr (AKM) {
-        kk = u / (BM / W);
-        row = (u % (BM / W)) * W;
-      } else {
-        row = u / (QBK / W);
-        kk = (u % (QBK / W)) * W;
-      }
-      const int m = m0 + row, k = k0 + kk;
-      oa[i] = u < UA && m < g.M && k < Ks;
-      const long long off = oa[i] ? (AKM ? (long long)k * lda + m : (long long)m * lda + k) : 0;
-      if constexpr (VEC) ra[i] = *(const dbl2*)(A + off);
-      else ra[i].x = A[off];
+      oa[i] = (tid + i * NTH) < UA && m0 + ar[i] < g.M && k0 + ak[i] < seg_k;
+      const double* p = Ab + (oa[i] ? aoff[i] + ash : 0);
+      if constexpr (VEC) ra[i] = *(const dbl2*)p;
+      else ra[i].x = *p;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int u = tid + i * NTH;
-      int col, kk;
-      if constexpr (BKN) {
-        kk = u / (BN / W);
-        col = (u % (BN / W)) * W;
-      } else {
-        col = u / (QBK / W);
-        kk = (u % (QBK / W)) * W;
-      }
-      const int n = n0 + col, k = k0 + kk;
-      ob[i] = u < UB && n < g.N && k < Ks;
-      const long long off = ob[i] ? (BKN ? (long long)k * ldb + n : (long long)n * ldb + k) : 0;
-      if constexpr (VEC) rb[i] = *(const dbl2*)(B + off);
-      else rb[i].x = B[off];
+      ob[i] = (tid + i * NTH) < UB && n0 + br[i] < g.N && k0 + bk[i] < seg_k;
+      const double* p = Bb + (ob[i] ? boff[i] + bsh : 0);
+      if constexpr (VEC) rb[i] = *(const dbl2*)p;
+      else rb[i].x = *p;
     }
   };
   auto store = [&](double* as, double* bs) {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const int u = tid + i * NTH;
-      if (u >= UA) continue;
+      if (tid + i * NTH >= UA) continue;
       if constexpr (AKM) {
-        const int kk = u / (BM / W), row = (u % (BM / W)) * W;
-        as[kk * LA + row] = oa[i] ? ra[i].x : 0.0;
-        if constexpr (VEC) as[kk * LA + row + 1] = oa[i] ? ra[i].y : 0.0;
+        as[ak[i] * LA + ar[i]] = oa[i] ? ra[i].x : 0.0;
+        if constexpr (VEC) as[ak[i] * LA + ar[i] + 1] = oa[i] ? ra[i].y : 0.0;
       } else {
-        const int row = u / (QBK / W), kk = (u % (QBK / W)) * W;
-        as[kk * LA + row] = oa[i] ? ra[i].x : 0.0;
-        if constexpr (VEC) as[(kk + 1) * LA + row] = oa[i] ? ra[i].y : 0.0;
+        as[ak[i] * LA + ar[i]] = oa[i] ? ra[i].x : 0.0;
+        if constexpr (VEC) as[(ak[i] + 1) * LA + ar[i]] = oa[i] ? ra[i].y : 0.0;
       }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int u = tid + i * NTH;
-      if (u >= UB) continue;
+      if (tid + i * NTH >= UB) continue;
       if constexpr (BKN) {
-        const int kk = u / (BN / W), col = (u % (BN / W)) * W;
-        bs[kk * LB + col] = ob[i] ? rb[i].x : 0.0;
-        if constexpr (VEC) bs[kk * LB + col + 1] = ob[i] ? rb[i].y : 0.0;
+        bs[bk[i] * LB + br[i]] = ob[i] ? rb[i].x : 0.0;
+        if constexpr (VEC) bs[bk[i] * LB + br[i] + 1] = ob[i] ? rb[i].y : 0.0;
       } else {
-        const int col = u / (QBK / W), kk = (u % (QBK / W)) * W;
-        bs[kk * LB + col] = ob[i] ? rb[i].x : 0.0;
-        if constexpr (VEC) bs[(kk + 1) * LB + col] = ob[i] ? rb[i].y : 0.0;
+        bs[bk[i] * LB + br[i]] = ob[i] ? rb[i].x : 0.0;
+        if constexpr (VEC) bs[(bk[i] + 1) * LB + br[i]] = ob[i] ? rb[i].y : 0.0;
       }
     }
   };
@@ -172,14 +187,35 @@ __global__ __launch_bounds__(64 * WM * WN) void qgemm_kernel(QGemmArgs g, int ti
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  if (ntile > 0) {
+  if (total > 0) {
     load(0);
     store(As[0], Bs[0]);
   }
+  // output rows and columns of this lane
+  long long coff = 0;
+  for (int d = 0; d < g.nd; ++d) coff += dig[d] * g.sc[d];
+  long long cof[TN];
+  bool cin[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn0 + j * 16 + (lane & 15);
+    cin[j] = n < g.N;
+    cof[j] = cin[j] ? map4(g.cn, n) : 0;
+  }
+  double* rowp[TM][4];
+  bool rin[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm0 + i * 16 + 4 * r + lane / 16;
+      rin[i][r] = m < g.M;
+      rowp[i][r] = g.C + coff + (rin[i][r] ? map4(g.cm, m) : 0);
+    }
   __syncthreads();
-  for (int t = 0; t < ntile; ++t) {
+  for (int t = 0; t < total; ++t) {
     const int cur = t & 1;
-    if (t + 1 < ntile) load(t + 1);
+    if (t + 1 < total) load(t + 1);
     const double* as = As[cur];
     const double* bs = Bs[cur];
 #pragma unroll
@@ -195,26 +231,23 @@ __global__ __launch_bounds__(64 * WM * WN) void qgemm_kernel(QGemmArgs g, int ti
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    if (t + 1 < ntile) store(As[cur ^ 1], Bs[cur ^ 1]);
+    if (t + 1 < total) store(As[cur ^ 1], Bs[cur ^ 1]);
     __syncthreads();
   }
-  // accumulator register r of lane l: row 4r + l/16, column l%16
+  // accumulator register r of lane l: row 4r + l/16, column l%16; per
+  // group of 16 rows every load of C is issued before any store
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
+    double cur[4][TN];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm0 + i * 16 + 4 * r + lane / 16;
-      if (m >= g.M) continue;
-      const long long mo = coff + map4(g.cm, m);
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int n = n0 + wn0 + j * 16 + (lane & 15);
-        if (n >= g.N) continue;
-        double* p = g.C + mo + map4(g.cn, n);
-        const double x = g.alpha * acc[i][j][r];
-        *p = g.accumulate ? *p + x : x;
-      }
-    }
+      for (int j = 0; j < TN; ++j) cur[r][j] = (g.accumulate && rin[i][r] && cin[j]) ? rowp[i][r][cof[j]] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (rin[i][r] && cin[j]) rowp[i][r][cof[j]] = cur[r][j] + g.alpha * acc[i][j][r];
   }
 }
 
@@ -235,32 +268,33 @@ hipError_t qlaunch(const QGemmArgs& g, long long batch, hipStream_t s) {
 template <bool AKM, bool BKN, bool VEC>
 hipError_t qdispatch(int cfg, const QGemmArgs& g, long long batch, hipStream_t s) {
   switch (cfg) {
-    case 0: return qlaunch<4, 4, 2, 2, AKM, BKN, VEC>(g, batch, s);   // 128 x 128
-    case 1: return qlaunch<5, 4, 1, 4, AKM, BKN, VEC>(g, batch, s);   // 80 x 256
-    case 2: return qlaunch<4, 5, 4, 1, AKM, BKN, VEC>(g, batch, s);   // 256 x 80
-    case 3: return qlaunch<2, 5, 4, 1, AKM, BKN, VEC>(g, batch, s);   // 128 x 80
-    case 4: return qlaunch<5, 2, 1, 4, AKM, BKN, VEC>(g, batch, s);   // 80 x 128
-    case 5: return qlaunch<5, 5, 1, 2, AKM, BKN, VEC>(g, batch, s);   // 80 x 160
-    case 6: return qlaunch<5, 5, 2, 1, AKM, BKN, VEC>(g, batch, s);   // 160 x 80
+    case 0: return qlaunch<5, 2, 1, 8, AKM, BKN, VEC>(g, batch, s);   // 80 x 256, 8 waves
+    case 1: return qlaunch<2, 5, 8, 1, AKM, BKN, VEC>(g, batch, s);   // 256 x 80, 8 waves
+    case 2: return qlaunch<2, 4, 4, 2, AKM, BKN, VEC>(g, batch, s);   // 128 x 128, 8 waves
+    case 3: return qlaunch<5, 3, 2, 2, AKM, BKN, VEC>(g, batch, s);   // 160 x 96
+    case 4: return qlaunch<3, 5, 2, 2, AKM, BKN, VEC>(g, batch, s);   // 96 x 160
+    case 5: return qlaunch<4, 4, 2, 4, AKM, BKN, VEC>(g, batch, s);   // 128 x 256, 8 waves
+    case 6: return qlaunch<4, 4, 4, 2, AKM, BKN, VEC>(g, batch, s);   // 256 x 128, 8 waves
     default: return qlaunch<2, 2, 2, 2, AKM, BKN, VEC>(g, batch, s);  // 64 x 64
   }
 }
 
-constexpr int QCFG_BM[8] = {128, 80, 256, 128, 80, 80, 160, 64};
-constexpr int QCFG_BN[8] = {128, 256, 80, 80, 128, 160, 80, 64};
+constexpr int QCFG_N = 8;
+constexpr int QCFG_BM[QCFG_N] = {80, 256, 128, 160, 96, 128, 256, 64};
+constexpr int QCFG_BN[QCFG_N] = {256, 80, 128, 96, 160, 256, 128, 64};
 
-// Tile choice: the largest operand reuse (BM BN / (BM + BN)) among the
-// shapes that waste at most 15 % of the padded output, else the best
-// product of reuse and useful fraction.
+// Tile choice: the best operand reuse (BM BN / (BM + BN)) weighted by the
+// square of the useful fraction of the padded output (padding costs both
+// matrix-core time and the loads that feed it).
 int qpick(int M, int N) {
-  int best = 7;
+  int best = QCFG_N - 1;
   double best_score = -1.0;
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < QCFG_N; ++c) {
     const double bm = QCFG_BM[c], bn = QCFG_BN[c];
     const double padded = std::ceil(M / bm) * bm * std::ceil(N / bn) * bn;
     const double useful = (double)M * N / padded;
     const double reuse = bm * bn / (bm + bn);
-    const double score = (useful >= 0.85 ? 1.0 : useful) * reuse;
+    const double score = useful * useful * reuse;
     if (score > best_score) {
       best_score = score;
       best = c;
@@ -332,50 +366,58 @@ __global__ __launch_bounds__(256) void t3v_transpose_kernel(const double* __rest
   }
 }
 
+// One workgroup per output block (label digits, e): the column pairs are
+// ordered by virtual label once, which fixes the source block and the
+// stride of each output axis inside it; the threads then copy the o^3
+// block (reads stay inside one 8 o^3-byte block of T3v).
 __global__ __launch_bounds__(256) void t3v_gather_kernel(const double* __restrict__ T3v, double* __restrict__ out,
-                                                         T3Gather g, long long total) {
+                                                         T3Gather g) {
   const long long o3 = (long long)g.o * g.o * g.o;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const long long q = idx % o3;
-    long long r = idx / o3;
-    const int e = (int)(r % g.ne);
-    r /= g.ne;
-    int dig[3] = {0, 0, 0};
-    for (int d = g.nd - 1; d >= 0; --d) {
-      dig[d] = (int)(r % g.rad[d]);
-      r /= g.rad[d];
-    }
-    const int y[3] = {(int)(q / (g.o * g.o)), (int)((q / g.o) % g.o), (int)(q % g.o)};
-    int lab[3], occ[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      lab[c] = g.lab[c] == 3 ? e : g.st[g.lab[c]] + dig[g.lab[c]];
-      occ[c] = y[g.ax[c]];
-    }
-    // order the column pairs by virtual label (ties: equal values by column symmetry)
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2 - i; ++j)
-        if (lab[j] > lab[j + 1]) {
-          const int tl = lab[j], to = occ[j];
-          lab[j] = lab[j + 1];
-          occ[j] = occ[j + 1];
-          lab[j + 1] = tl;
-          occ[j + 1] = to;
-        }
-    out[idx] = T3v[vtri(lab[0], lab[1], lab[2], g.v) * o3 + ((long long)occ[0] * g.o + occ[1]) * g.o + occ[2]];
+  const int e = (int)(blockIdx.x % g.ne);
+  long long r = blockIdx.x / g.ne;
+  int dig[3] = {0, 0, 0};
+  for (int d = g.nd - 1; d >= 0; --d) {
+    dig[d] = (int)(r % g.rad[d]);
+    r /= g.rad[d];
   }
+  int lab[3], ax[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lab[c] = g.lab[c] == 3 ? e : g.st[g.lab[c]] + dig[g.lab[c]];
+    ax[c] = g.ax[c];
+  }
+  // order the column pairs by virtual label (ties: equal values by column symmetry)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2 - i; ++j)
+      if (lab[j] > lab[j + 1]) {
+        const int tl = lab[j], ta = ax[j];
+        lab[j] = lab[j + 1];
+        ax[j] = ax[j + 1];
+        lab[j + 1] = tl;
+        ax[j + 1] = ta;
+      }
+  // sorted position k of the source block holds the occupied index of output axis ax[k]
+  long long st[3];
+  st[ax[0]] = (long long)g.o * g.o;
+  st[ax[1]] = g.o;
+  st[ax[2]] = 1;
+  const double* src = T3v + vtri(lab[0], lab[1], lab[2], g.v) * o3;
+  double* dst = out + (long long)blockIdx.x * o3;
+  const int o = g.o, o2 = o * o;
+  for (int q = threadIdx.x; q < (int)o3; q += blockDim.x)
+    dst[q] = src[(q / o2) * st[0] + ((q / o) % o) * st[1] + (q % o) * st[2]];
 }
 
 // Wbar_{ijk}^{xym} (alternative form) = -1/2 sum_n (v^{mn}_{ki} t_{nj}^{xy} + v^{mn}_{kj} t_{ni}^{yx})
 // for x = x0 + lx, y = y0 + ly; element [lx][ly][rows][m] with the row index
-// holding i, j, k at the positions rowpos[0..2].
-__global__ __launch_bounds__(256) void q_wo_kernel(double* __restrict__ out, const double* __restrict__ Voooo,
+// holding i, j, k at the positions rowpos[0..2].  VT[n][k][i][m] = v^{mn}_{ki}
+// (m fastest, as the output).
+__global__ __launch_bounds__(256) void q_wo_kernel(double* __restrict__ out, const double* __restrict__ VT,
                                                    const double* __restrict__ t2, int o, int v, int x0, int nx,
                                                    int y0, int ny, int p0, int p1, int p2, long long total) {
-  const long long o2 = (long long)o * o, vv = (long long)v * v;
+  const long long vv = (long long)v * v;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int m = (int)(idx % o);
@@ -392,11 +434,92 @@ __global__ __launch_bounds__(256) void q_wo_kernel(double* __restrict__ out, con
     const int x = x0 + lx, y = y0 + ly;
     double s = 0.0;
     for (int n = 0; n < o; ++n) {
-      const double* vr = Voooo + ((long long)m * o + n) * o2 + (long long)k * o;
-      s += vr[i] * t2[((long long)n * o + j) * vv + (long long)x * v + y] +
-           vr[j] * t2[((long long)n * o + i) * vv + (long long)y * v + x];
+      const double* vr = VT + ((long long)n * o + k) * o * o + m;
+      s += vr[(long long)i * o] * t2[((long long)n * o + j) * vv + (long long)x * v + y] +
+           vr[(long long)j * o] * t2[((long long)n * o + i) * vv + (long long)y * v + x];
     }
     out[idx] = -0.5 * s;
+  }
+}
+
+// Wbar_{ejk}^{xyz} in two passes for o <= QW_OMAX: pass A writes the two
+// Z terms and the two K = o terms that do not involve k (v^{my}_{ej},
+// v^{mx}_{je} held in registers across the k loop); pass B adds the two that
+// do not involve j (v^{mz}_{ek}, v^{mx}_{ke} held across the j loop).  One
+// workgroup per (lx, ly, lz, j) (pass A) or (lx, ly, lz, k) (pass B), the
+// threads over e; the T2 factors of the workgroup's labels are staged in LDS
+// and read as broadcasts.
+constexpr int QW_OMAX = 32;
+__global__ __launch_bounds__(256) void q_wv_a_kernel(double* __restrict__ out, const double* __restrict__ Zxy,
+                                                     const double* __restrict__ Zxz, const double* __restrict__ Vmyje,
+                                                     const double* __restrict__ Vmxje, const double* __restrict__ t2,
+                                                     int o, int v, int x0, int ny, int y0, int nz, int z0) {
+  __shared__ double ta[QW_OMAX * QW_OMAX], tb[QW_OMAX * QW_OMAX];
+  const long long ov = (long long)o * v, vv = (long long)v * v, o2v = (long long)o * ov;
+  int r = blockIdx.x;
+  const int j = r % o;
+  r /= o;
+  const int lz = r % nz;
+  r /= nz;
+  const int ly = r % ny, lx = r / ny;
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+  for (int q = threadIdx.x; q < o * o; q += blockDim.x) {  // [m][k]
+    const long long row = (long long)q * vv;               // (m o + k) vv
+    ta[q] = t2[row + (long long)x * v + z];
+    tb[q] = t2[row + (long long)y * v + z];
+  }
+  __syncthreads();
+  const long long bxy = (((long long)lx * ny + ly) * nz + lz) * o2v, bxz = (((long long)lx * nz + lz) * ny + ly) * o2v;
+  for (int e = threadIdx.x; e < v; e += blockDim.x) {
+    double u1[QW_OMAX], u2[QW_OMAX];
+#pragma unroll
+    for (int m = 0; m < QW_OMAX; ++m) {
+      u1[m] = m < o ? Vmyje[((long long)m * v + y) * ov + (long long)j * v + e] : 0.0;
+      u2[m] = m < o ? Vmxje[((long long)m * v + x) * ov + (long long)j * v + e] : 0.0;
+    }
+    for (int k = 0; k < o; ++k) {
+      double s = Zxy[bxy + ((long long)j * o + k) * v + e] + Zxz[bxz + ((long long)k * o + j) * v + e];
+#pragma unroll
+      for (int m = 0; m < QW_OMAX; ++m)
+        if (m < o) s -= u1[m] * ta[m * o + k] + u2[m] * tb[m * o + k];
+      out[bxy + ((long long)j * o + k) * v + e] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void q_wv_b_kernel(double* __restrict__ out, const double* __restrict__ Vmyje,
+                                                     const double* __restrict__ Vmxje, const double* __restrict__ t2,
+                                                     int o, int v, int x0, int ny, int y0, int nz, int z0) {
+  __shared__ double ta[QW_OMAX * QW_OMAX], tb[QW_OMAX * QW_OMAX];
+  const long long ov = (long long)o * v, vv = (long long)v * v, o2v = (long long)o * ov;
+  int r = blockIdx.x;
+  const int k = r % o;
+  r /= o;
+  const int lz = r % nz;
+  r /= nz;
+  const int ly = r % ny, lx = r / ny;
+  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+  for (int q = threadIdx.x; q < o * o; q += blockDim.x) {  // [m][j]
+    const long long row = (long long)q * vv;
+    ta[q] = t2[row + (long long)x * v + y];
+    tb[q] = t2[row + (long long)z * v + y];
+  }
+  __syncthreads();
+  const long long b = (((long long)lx * ny + ly) * nz + lz) * o2v;
+  for (int e = threadIdx.x; e < v; e += blockDim.x) {
+    double w1[QW_OMAX], w2[QW_OMAX];
+#pragma unroll
+    for (int m = 0; m < QW_OMAX; ++m) {
+      w1[m] = m < o ? Vmyje[((long long)m * v + z) * ov + (long long)k * v + e] : 0.0;
+      w2[m] = m < o ? Vmxje[((long long)m * v + x) * ov + (long long)k * v + e] : 0.0;
+    }
+    for (int j = 0; j < o; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < QW_OMAX; ++m)
+        if (m < o) s += w1[m] * ta[m * o + j] + w2[m] * tb[m * o + j];
+      out[b + ((long long)j * o + k) * v + e] -= s;
+    }
   }
 }
 
@@ -447,63 +570,100 @@ __global__ __launch_bounds__(256) void q_add_kernel(double* __restrict__ Y, cons
 struct QPerms {
   int p[24][4];
   double c[24];
+  int w[24][4];  // in-block offset of the permuted element: sum_m j_m w[p][m]
 };
 
-constexpr int QE_CHUNK = 2048;  // occupied quadruples per workgroup
-
+// The occupied index space o^4 is cut into blocks of bs^4 (bs <= 5, nbk
+// blocks per axis); the axis permutations act on whole blocks, so each orbit
+// of blocks (at most 24) is closed under them.  One workgroup takes one
+// tuple and one orbit: it stages R on the orbit's blocks in LDS (each element
+// read once) and evaluates U = S(R) / den there, so the 24 permuted reads of
+// the spin summation are LDS reads.
+constexpr int QE_BS = 4, QE_MAXB = 24;
 __global__ __launch_bounds__(256) void q_abc_energy_kernel(const double* __restrict__ X, const double* __restrict__ R,
                                                            const double* __restrict__ Vvvoo,
-                                                           const double* __restrict__ t2,
-                                                           const double* __restrict__ eps, QSlots sl, QPerms P, int o,
-                                                           int v, int nchunk, double* __restrict__ part) {
+                                                           const double* __restrict__ t2R,
+                                                           const double* __restrict__ eps, QSlots sl, QPerms P,
+                                                           const int* __restrict__ orbits, int norb, int bs, int o,
+                                                           int v, double* __restrict__ part) {
+  __shared__ double Rl[QE_MAXB * QE_BS * QE_BS * QE_BS * QE_BS];
   __shared__ double red[256];
-  const int chunk = blockIdx.x % nchunk;
-  const int tau = blockIdx.x / nchunk;
-  int l[4], lab[4];
+  __shared__ unsigned char smap[QE_MAXB][24];  // slot of block(slot) o pi
+  __shared__ int btab[QE_MAXB];
+  const int orb = blockIdx.x % norb;
+  const int tau = blockIdx.x / norb;
+  int lab[4];
   {
     int r = tau;
     for (int s = 3; s >= 0; --s) {
-      l[s] = r % sl.n[s];
+      lab[s] = sl.st[s] + r % sl.n[s];
       r /= sl.n[s];
     }
-    for (int s = 0; s < 4; ++s) lab[s] = sl.st[s] + l[s];
   }
   const bool canon = lab[0] <= lab[1] && lab[1] <= lab[2] && lab[2] <= lab[3] &&
                      !(lab[0] == lab[1] && lab[1] == lab[2]) && !(lab[1] == lab[2] && lab[2] == lab[3]);
+  if (!canon) {
+    if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
+    return;
+  }
+  const int* ob = orbits + orb * (QE_MAXB + 1);
+  const int nblk = ob[0];
+  if ((int)threadIdx.x < nblk) btab[threadIdx.x] = ob[1 + threadIdx.x];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nblk * 24; e += blockDim.x) {
+    const int sidx = e / 24, p = e % 24;
+    const int b = btab[sidx];
+    const int d[4] = {b & 255, (b >> 8) & 255, (b >> 16) & 255, (b >> 24) & 255};
+    const int t = d[P.p[p][0]] | (d[P.p[p][1]] << 8) | (d[P.p[p][2]] << 16) | (d[P.p[p][3]] << 24);
+    int k = 0;
+    while (k < nblk && btab[k] != t) ++k;
+    smap[sidx][p] = (unsigned char)k;
+  }
+  const long long o2 = (long long)o * o, o4 = o2 * o2;
+  const double* x = X + (long long)tau * o4;
+  const double* rr = R + (long long)tau * o4;
+  const int bs2 = bs * bs, bs4 = bs2 * bs2;
+  for (int e = threadIdx.x; e < nblk * bs4; e += blockDim.x) {
+    const int sidx = e / bs4, w = e % bs4;
+    const int b = btab[sidx];
+    const int i0 = (b & 255) * bs + w / (bs2 * bs), i1 = ((b >> 8) & 255) * bs + (w / bs2) % bs;
+    const int i2 = ((b >> 16) & 255) * bs + (w / bs) % bs, i3 = ((b >> 24) & 255) * bs + w % bs;
+    Rl[e] = (i0 < o && i1 < o && i2 < o && i3 < o) ? rr[((long long)i0 * o + i1) * o2 + (long long)i2 * o + i3] : 0.0;
+  }
+  __syncthreads();
+  const double ev = eps[o + lab[0]] + eps[o + lab[1]] + eps[o + lab[2]] + eps[o + lab[3]];
   double acc = 0.0;
-  if (canon) {
-    const long long o2 = (long long)o * o, o4 = o2 * o2, vv = (long long)v * v;
-    const double* x = X + (long long)tau * o4;
-    const double* rr = R + (long long)tau * o4;
-    const double ev = eps[o + lab[0]] + eps[o + lab[1]] + eps[o + lab[2]] + eps[o + lab[3]];
-    const long long st[4] = {o2 * o, o2, (long long)o, 1};
-    const long long q0 = (long long)chunk * QE_CHUNK;
-    const long long q1 = min(q0 + (long long)QE_CHUNK, o4);
-    for (long long q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-      const int i[4] = {(int)(q / (o2 * o)), (int)((q / o2) % o), (int)((q / o) % o), (int)(q % o)};
-      double u = 0.0;
+  for (int e = threadIdx.x; e < nblk * bs4; e += blockDim.x) {
+    const int sidx = e / bs4, w = e % bs4;
+    const int b = btab[sidx];
+    const int j[4] = {w / (bs2 * bs), (w / bs2) % bs, (w / bs) % bs, w % bs};
+    const int i[4] = {(b & 255) * bs + j[0], ((b >> 8) & 255) * bs + j[1], ((b >> 16) & 255) * bs + j[2],
+                      ((b >> 24) & 255) * bs + j[3]};
+    if (i[0] >= o || i[1] >= o || i[2] >= o || i[3] >= o) continue;
+    double u = 0.0;
 #pragma unroll 4
-      for (int p = 0; p < 24; ++p)
-        u += P.c[p] * rr[i[P.p[p][0]] * st[0] + i[P.p[p][1]] * st[1] + i[P.p[p][2]] * st[2] + i[P.p[p][3]]];
-      const double den = eps[i[0]] + eps[i[1]] + eps[i[2]] + eps[i[3]] - ev;
-      // sum over the six splits {s0 < s1} | {s2 < s3} of v^{..}_{..} t_{..}^{..}
-      double vs = 0.0;
-#pragma unroll
-      for (int s0 = 0; s0 < 4; ++s0)
-#pragma unroll
-        for (int s1 = s0 + 1; s1 < 4; ++s1) {
-          int s2 = -1, s3 = -1;
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (t != s0 && t != s1) {
-              if (s2 < 0) s2 = t;
-              else s3 = t;
-            }
-          vs += Vvvoo[((long long)lab[s0] * v + lab[s1]) * o2 + (long long)i[s0] * o + i[s1]] *
-                t2[((long long)i[s2] * o + i[s3]) * vv + (long long)lab[s2] * v + lab[s3]];
-        }
-      acc += (x[q] + vs) * (u / den);
+    for (int p = 0; p < 24; ++p) {
+      const int jj = j[0] * P.w[p][0] + j[1] * P.w[p][1] + j[2] * P.w[p][2] + j[3] * P.w[p][3];
+      u += P.c[p] * Rl[smap[sidx][p] * bs4 + jj];
     }
+    const double den = eps[i[0]] + eps[i[1]] + eps[i[2]] + eps[i[3]] - ev;
+    // sum over the six splits {s0 < s1} | {s2 < s3} of v^{..}_{..} t_{..}^{..}
+    double vs = 0.0;
+#pragma unroll
+    for (int s0 = 0; s0 < 4; ++s0)
+#pragma unroll
+      for (int s1 = s0 + 1; s1 < 4; ++s1) {
+        int s2 = -1, s3 = -1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t != s0 && t != s1) {
+            if (s2 < 0) s2 = t;
+            else s3 = t;
+          }
+        vs += Vvvoo[((long long)lab[s0] * v + lab[s1]) * o2 + (long long)i[s0] * o + i[s1]] *
+              t2R[((long long)lab[s3] * v + lab[s2]) * o2 + (long long)i[s2] * o + i[s3]];
+      }
+    acc += (x[((long long)i[0] * o + i[1]) * o2 + (long long)i[2] * o + i[3]] + vs) * (u / den);
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -621,7 +781,11 @@ hipError_t qgemm(const QGemmArgs& g, hipStream_t s) {
     for (int d = 0; d < g.nd; ++d) hi += (long long)(g.rad[d] - 1) * g.sc[d];
     if (g.c_len > 0 && hi >= g.c_len) return hipErrorInvalidValue;
   }
-  const int cfg = qpick(g.M, g.N);
+  // short contractions are bound by the update of C: small tiles, several
+  // workgroups per compute unit
+  long long ktot = 0;
+  for (int sg = 0; sg < g.nseg; ++sg) ktot += g.K[sg];
+  const int cfg = ktot <= 64 ? QCFG_N - 1 : qpick(g.M, g.N);
   if (g.akm && !g.bkn) return vec ? qdispatch<true, false, true>(cfg, g, batch, s) : qdispatch<true, false, false>(cfg, g, batch, s);
   if (!g.akm && g.bkn) return vec ? qdispatch<false, true, true>(cfg, g, batch, s) : qdispatch<false, true, false>(cfg, g, batch, s);
   return hipErrorInvalidValue;  // the two mirrored layouts are the ones used
@@ -641,10 +805,11 @@ hipError_t t3v_transpose(const double* T, const BlockRef* tbl, double* T3v, cons
 }
 
 hipError_t t3v_gather(const double* T3v, double* out, const T3Gather& g, hipStream_t s) {
-  long long total = (long long)g.o * g.o * g.o * g.ne;
-  for (int d = 0; d < g.nd; ++d) total *= g.rad[d];
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(t3v_gather_kernel, dim3(grid_for(total)), dim3(256), 0, s, T3v, out, g, total);
+  long long nblk = g.ne;
+  for (int d = 0; d < g.nd; ++d) nblk *= g.rad[d];
+  if (nblk <= 0 || g.o <= 0) return hipSuccess;
+  if (nblk > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(t3v_gather_kernel, dim3((unsigned)nblk), dim3(256), 0, s, T3v, out, g);
   return hipGetLastError();
 }
 
@@ -663,6 +828,16 @@ hipError_t q_wv_build(double* out, const double* Zxy, const double* Zxz, const d
                       const double* t2, int o, int v, int x0, int nx, int y0, int ny, int z0, int nz, hipStream_t s) {
   const long long total = (long long)nx * ny * nz * o * o * v;
   if (total <= 0) return hipSuccess;
+  if (o <= QW_OMAX) {
+    const unsigned nblk = (unsigned)((long long)nx * ny * nz * o);  // (lx, ly, lz, j) and (lx, ly, lz, k)
+    const unsigned nth = (unsigned)std::min(256, ((v + 63) / 64) * 64);
+    hipLaunchKernelGGL(q_wv_a_kernel, dim3(nblk), dim3(nth), 0, s, out, Zxy, Zxz, Vmyje, Vmxje, t2, o, v, x0, ny, y0,
+                       nz, z0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(q_wv_b_kernel, dim3(nblk), dim3(nth), 0, s, out, Vmyje, Vmxje, t2, o, v, x0, ny, y0, nz, z0);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(q_wv_kernel, dim3(grid_for(total)), dim3(256), 0, s, out, Zxy, Zxz, Vmyje, Vmxje, t2, o, v, x0,
                      nx, y0, ny, z0, nz, total);
   return hipGetLastError();
@@ -680,18 +855,18 @@ hipError_t gather_idx(const double* src, const long long* idx, long long n, doub
   return hipGetLastError();
 }
 
-hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2, const double* eps,
-                        const QSlots& sl, int o, int v, double* part, double* etup, double* etask, hipStream_t s) {
-  const long long o4 = (long long)o * o * o * o;
-  const int nchunk = (int)((o4 + QE_CHUNK - 1) / QE_CHUNK);
+hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2R, const double* eps,
+                        const QSlots& sl, int o, int v, const int* orbits, int norb, double* part, double* etup,
+                        double* etask, hipStream_t s) {
   const long long ntau = (long long)sl.n[0] * sl.n[1] * sl.n[2] * sl.n[3];
   if (ntau <= 0) return hipSuccess;
-  if (ntau * nchunk > INT_MAX) return hipErrorInvalidValue;
+  if (ntau * norb > INT_MAX) return hipErrorInvalidValue;
+  const int nbk = (o + QE_BS - 1) / QE_BS, bs = (o + nbk - 1) / nbk;
   QPerms P{};
   int np = 0;
   int p[4] = {0, 1, 2, 3};
   do {
-    // cycle type from the number of fixed points and the cycle structure
+    // cycle type from the longest cycle and the number of cycles
     int seen[4] = {0, 0, 0, 0}, longest = 0, cycles = 0;
     for (int k = 0; k < 4; ++k) {
       if (seen[k]) continue;
@@ -710,15 +885,41 @@ hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, c
     else if (longest == 3) c = 4.0;                   // three-cycle
     else c = -2.0;                                    // four-cycle
     for (int k = 0; k < 4; ++k) P.p[np][k] = p[k];
+    // (j o pi)_k = j_{p[k]} sits at sum_k j_{p[k]} bs^(3-k): digit m = p[k] weighs bs^(3-k)
+    for (int k = 0; k < 4; ++k) {
+      int w = 1;
+      for (int t = k + 1; t < 4; ++t) w *= bs;
+      P.w[np][p[k]] = w;
+    }
     P.c[np] = c;
     ++np;
   } while (std::next_permutation(p, p + 4));
-  hipLaunchKernelGGL(q_abc_energy_kernel, dim3((unsigned)(ntau * nchunk)), dim3(256), 0, s, X, R, Vvvoo, t2, eps, sl, P,
-                     o, v, nchunk, part);
+  hipLaunchKernelGGL(q_abc_energy_kernel, dim3((unsigned)(ntau * norb)), dim3(256), 0, s, X, R, Vvvoo, t2R, eps, sl, P,
+                     orbits, norb, bs, o, v, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(q_abc_reduce_kernel, dim3(1), dim3(256), 0, s, part, sl, (int)ntau, nchunk, etup, etask);
+  hipLaunchKernelGGL(q_abc_reduce_kernel, dim3(1), dim3(256), 0, s, part, sl, (int)ntau, norb, etup, etask);
   return hipGetLastError();
+}
+
+// Orbits of the occupied blocks under the axis permutations (see
+// q_abc_energy_kernel): per orbit 1 + 24 ints, the block count and the
+// blocks packed as b0 | b1 << 8 | b2 << 16 | b3 << 24.
+std::vector<int> q_abc_orbits(int o) {
+  const int nbk = (o + QE_BS - 1) / QE_BS;
+  std::vector<int> out;
+  for (int a = 0; a < nbk; ++a)
+    for (int b = a; b < nbk; ++b)
+      for (int c = b; c < nbk; ++c)
+        for (int d = c; d < nbk; ++d) {
+          int q[4] = {a, b, c, d};
+          std::vector<int> blocks;
+          do blocks.push_back(q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24));
+          while (std::next_permutation(q, q + 4));
+          out.push_back((int)blocks.size());
+          for (int k = 0; k < QE_MAXB; ++k) out.push_back(k < (int)blocks.size() ? blocks[k] : -1);
+        }
+  return out;
 }
 
 }  // namespace cct
