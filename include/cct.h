@@ -105,7 +105,10 @@ typedef void (*cct_free_fn)(void* ptr, void* user);
  * unpacked slab in one batch, limited by free device memory), "timers"
  * (true: per-phase device times for cct_get_counters), "ladder_split"
  * (true by default: the symmetric/antisymmetric ladder; false: the direct
- * form).  alloc/free_fn/alloc_user: the caller's device allocator (see
+ * form), "lp_block_k" (>= 0, default 1024: in the split-BF16 mode the
+ * ladder and ring operands whose contracted length is at least this are
+ * stored with hi and lo interleaved by blocks of 32; a storage layout only,
+ * the results do not depend on it).  alloc/free_fn/alloc_user: the caller's device allocator (see
  * cct_alloc_fn), or both NULL.  hip_stream: a hipStream_t or NULL.  The
  * memory plan is checked against free device memory here; CCT_ENOMEM if it
  * does not fit (or if the caller's allocator returns NULL). */

@@ -100,6 +100,7 @@ struct cct_ctx {
   long long* vpair_src = nullptr;  // (y*v + z)*v^2 for the virtual pairs y <= z (ladder W rows)
   int2* vpair_yz = nullptr;        // (y, z) of the virtual pairs y <= z
   bool ladder_split = true;        // symmetric / antisymmetric split of the ladder
+  long long lp_block_k = 1024;     // split-BF16 ladder/ring operands with K >= this are stored by blocks of 32
   double* red = nullptr;  // reduction scratch
   long long red_n = 0;
   double* scal = nullptr;  // device scalars
@@ -389,10 +390,10 @@ int build_plans(cct_ctx* ctx) {
   for (int kind = 0; kind < 3; ++kind) {
     Job& J = ctx->ring[kind];
     J.nslot_total = (int)J.slots.size();
-    // per slot: the unpacked operand U (rows padded by <= 8) and the products Z,
+    // per slot: the unpacked operand U (rows padded by < 32) and the products Z,
     // each in its working format (FP64; FP32 U and FP64 Z; split-BF16 U and FP32 Z)
     const long long ring_slot = ctx->prec == Prec::F64 ? 2 * ov3 : (ctx->prec == Prec::F32 ? ov3 + ov3 / 2 : ov3);
-    J.per_batch = slots_per_batch(budget, ring_slot + 8 * v2, J.nslot_total);
+    J.per_batch = slots_per_batch(budget, ring_slot + 16 * v2, J.nslot_total);
     const double cf = ring_coef[kind];
     RCK(build_job(ctx, J, ov3, [&](int t) {
       std::vector<Contrib> cs;
@@ -883,6 +884,20 @@ int feedback(cct_ctx* ctx) {
 // (hi, lo); both take four bytes per element.
 int lp_fmt(Prec p) { return p == Prec::F32 ? OUT_F32 : OUT_BF16X2; }
 void* alloc_lp(Arena& ws, long long n) { return ws.alloc((size_t)((n + 1) / 2)); }
+// Operands of the split ladder and the rings (K = the contracted length):
+// split-BF16 rows with K >= lp_block_k (a context option, 1024 by default)
+// are stored by blocks of 32 and padded to 32, so that hi and lo of 32 values
+// share one 128-byte line and each K tile of the GEMM reads whole lines;
+// shorter ones as two planes padded to 8; FP32 rows padded to 4, FP64 to 2.
+bool lp_blocked(const cct_ctx* ctx, long long K) { return ctx->prec == Prec::BF16X3 && K >= ctx->lp_block_k; }
+int lp_fmt_gemm(const cct_ctx* ctx, long long K) {
+  const Prec p = ctx->prec;
+  return p == Prec::F64 ? OUT_F64 : (p == Prec::F32 ? OUT_F32 : (lp_blocked(ctx, K) ? OUT_BF16X2I : OUT_BF16X2));
+}
+long long lp_kpad(const cct_ctx* ctx, long long K) {
+  const Prec p = ctx->prec;
+  return p == Prec::F64 ? 2 : (p == Prec::F32 ? 4 : (lp_blocked(ctx, K) ? 32 : 8));
+}
 
 // Ladder with operands stored in the working precision: W converted once,
 // then per chunk of blocks the three K-contiguous views of T3 (plain,
@@ -946,9 +961,10 @@ int r3_pp_split(cct_ctx* ctx) {
   const long long v2 = (long long)v * v, v3 = ctx->v3, nt = ctx->ntri;
   const long long P = (long long)v * (v + 1) / 2, Q = (long long)v * (v - 1) / 2;
   const bool f64 = ctx->prec == Prec::F64;
-  const int w = f64 ? 2 : (ctx->prec == Prec::F32 ? 4 : 8);
+  // one format for both products (it follows the longer K)
+  const long long w = lp_kpad(ctx, P);
   const long long pp = round_up(P, w), pq = round_up(std::max<long long>(Q, 1), w);
-  const int fmt = f64 ? OUT_F64 : lp_fmt(ctx->prec);
+  const int fmt = lp_fmt_gemm(ctx, P);
   const long long esz = f64 ? 8 : 4;  // bytes per stored operand element (hi+lo BF16: 2 x 2)
   Arena& ws = ctx->ws;
   const size_t mk0 = ws.mark();
@@ -992,6 +1008,7 @@ int r3_pp_split(cct_ctx* ctx) {
       else g.C = (double*)C;
       g.cm = cm; g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
       g.a_len = a_len; g.b_len = b_len; g.c_len = c_len; g.variant = ctx->tune_ladder;
+      g.il = fmt == OUT_BF16X2I;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     }
     return CCT_OK;
@@ -1198,8 +1215,8 @@ int r3_rings(cct_ctx* ctx, int kind) {
   const bool lp = ctx->prec != Prec::F64;
   // K = (l,d) padded with zeros to the vector width of the working precision,
   // so that every shape runs on the K-contiguous kernels
-  const long long kp = round_up(ov, lp ? (ctx->prec == Prec::F32 ? 4 : 8) : 2);
-  const int fmt = lp ? lp_fmt(ctx->prec) : OUT_F64;
+  const long long kp = round_up(ov, lp_kpad(ctx, ov));
+  const int fmt = lp_fmt_gemm(ctx, ov);
   // A[(p,x)][(l,d)] = Wbar^{lx}_{dp} (ring A) or Wbar^{lx}_{pd} (rings B, C), row-major [p][x][l][d]
   const double* Aw = kind == 0 ? ctx->Wb1 : ctx->Wb2;
   const size_t mk0 = ws.mark();
@@ -1247,6 +1264,7 @@ int r3_rings(cct_ctx* ctx, int kind) {
       g.alpha = 1.0; g.beta = 0.0;
       g.a_len = ov * kp; g.b_len = ulen; g.c_len = zlen;
       g.variant = ctx->tune_rings;
+      g.il = fmt == OUT_BF16X2I;
       HIPCK(gemm_nt_lp(g, ctx->prec, ctx->s));
     } else {
       NtArgs g{};
@@ -2602,7 +2620,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
   // padded to the vector width; direct: N = K = v^2)
   const bool split = ctx->ladder_split && v >= 2;
   const long long vp = (long long)v * (v + 1) / 2;
-  const long long lN = split ? vp : v2, lK = split ? round_up(vp, f64 ? 2 : (ctx->prec == Prec::F32 ? 4 : 8)) : v2;
+  const long long lN = split ? vp : v2, lK = split ? round_up(vp, lp_kpad(ctx, vp)) : v2;
   const bool lad_lp = !f64, lad_nt = f64 && (split || !(v2 & 1));
   if ((lad_lp || lad_nt) && lN * lK <= v4) {
     const long long M = std::min(ctx->ntri * v, ctx->ntri * ctx->v3 / lK);
@@ -2625,7 +2643,8 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
       void* Al = alloc_lp(ws, Mt * lK);
       void* Bl = alloc_lp(ws, lN * lK);
       if (!Al || !Bl) { ctx->err = "workspace exhausted (autotune)"; return CCT_ENOMEM; }
-      const int fmt = lp_fmt(ctx->prec);
+      // the operand format of the ladder form in use
+      const int fmt = split ? lp_fmt_gemm(ctx, vp) : lp_fmt(ctx->prec);
       HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * lK}, Mt * lK, ctx->s));
       HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, lN * lK}, lN * lK, ctx->s));
       ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3},
@@ -2635,6 +2654,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
         g.A = Al; g.lda = lK; g.a_plane = Mt * lK; g.B = Bl; g.ldb = lK; g.b_plane = lN * lK;
         g.C = C; g.cm = idx1(lN); g.cn = idx1(1); g.alpha = 1.0; g.beta = 0.0;
         g.a_len = Mt * lK; g.b_len = lN * lK; g.c_len = Mt * lN; g.variant = var;
+        g.il = fmt == OUT_BF16X2I;
         return gemm_nt_lp(g, ctx->prec, ctx->s);
       });
     }
@@ -2644,8 +2664,8 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
   // most 8), in the padded shape the ring contraction uses
   if (!ctx->ring[0].batches.empty()) {
     const bool ring_lp = !f64;
-    const long long kp = round_up(ov, ring_lp ? (ctx->prec == Prec::F32 ? 4 : 8) : 2);
-    const int fmt = ring_lp ? lp_fmt(ctx->prec) : OUT_F64;
+    const long long kp = round_up(ov, lp_kpad(ctx, ov));
+    const int fmt = lp_fmt_gemm(ctx, ov);
     const int S = std::min(8, ctx->ring[0].per_batch);
     const long long ulen = S * v2 * kp;
     const size_t mk = ws.mark();
@@ -2667,6 +2687,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
         g.B = U; g.ldb = kp; g.b_batch = v2 * kp; g.b_plane = ulen;
         g.C = Z; g.cm = idx1(v2); g.cn = idx1(1); g.c_batch = ov3; g.alpha = 1.0; g.beta = 0.0;
         g.a_len = ov * kp; g.b_len = ulen; g.c_len = S * ov3; g.variant = var;
+        g.il = fmt == OUT_BF16X2I;
         return gemm_nt_lp(g, ctx->prec, ctx->s);
       }
       NtArgs g{};
@@ -2798,6 +2819,10 @@ int cct_create(int nocc, int nvir, int naux, cct_precision prec, const char* opt
     if (json_find(js, "workspace_gb", val)) ctx->ws_gb = std::atof(val.c_str());
     if (json_find(js, "timers", val)) ctx->events = (val == "true" || val == "1");
     if (json_find(js, "ladder_split", val)) ctx->ladder_split = (val == "true" || val == "1");
+    if (json_find(js, "lp_block_k", val)) {
+      ctx->lp_block_k = std::atoll(val.c_str());
+      if (ctx->lp_block_k < 0) { delete ctx; return CCT_EINVAL; }
+    }
     if (json_find(js, "tol", val)) {
       ctx->tol = std::atof(val.c_str());
       if (!(ctx->tol > 0)) { delete ctx; return CCT_EINVAL; }

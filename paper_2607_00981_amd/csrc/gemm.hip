@@ -744,9 +744,18 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64>
+// LDS rows of the split-BF16 kernel hold one K tile (32 values, four 16-byte
+// segments) unpadded; segment q of row r sits at position q ^ ((r >> 1) & 3).
+// On gfx950 this is free of bank conflicts for both 16-byte accesses the
+// kernel makes: the fragment reads (16 consecutive rows, one segment per 16
+// lanes) and the tile stores (4 rows x 4 segments per 16 lanes).  Rows padded
+// to 40 values conflict on both (2x the LDS cycles per instruction).
+__device__ __forceinline__ int lp_swz(int row, int q) { return row * 32 + 8 * (q ^ ((row >> 1) & 3)); }
+
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64, int PF>
 __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
-  constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LK = KB + 8;
+  static_assert(PF == 1 || PF == 2, "one or two load stages");
+  constexpr int NTH = 64 * WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32, LK = KB;
   constexpr int SA = BM * (KB / 8) / NTH, SB = BN * (KB / 8) / NTH;  // 16-byte segments per plane per thread
   __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM * LK];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN * LK];
@@ -790,100 +799,106 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
 #pragma unroll
         for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
   }
-  u32x4 rah[SA], ral[SA], rbh[SB], rbl[SB];
-  bool oa[SA], ob[SB];
+  // PF register stages of global loads.  With two, the tile of K step t + 1
+  // waits in one while the loads of step t + 2 are in flight into the other,
+  // so each global load has two K steps of matrix-core work to arrive in.
+  struct Stage {
+    u32x4 ah[SA], al[SA], bh[SB], bl[SB];
+    bool oa[SA], ob[SB];
+  };
+  Stage S0, S1;
   const int nk = (g.K + KB - 1) / KB;
-  auto load = [&](int k0) {
+  // planar operands: K tile t starts t * 32 elements into the row; blocked
+  // (hi 32, lo 32) operands: t * 64, with the lo values 32 further on
+  const int kmul = g.il ? 2 : 1;
+  auto load = [&](Stage& st, int k0) {
     if constexpr (VEC) {
 #pragma unroll
       for (int i = 0; i < SA; ++i) {
-        oa[i] = va[i] && (k0 + ka[i] < g.K);
-        const __bf16* p = pa[i] + (oa[i] ? k0 : 0);
-        rah[i] = *(const u32x4*)p;
-        ral[i] = *(const u32x4*)(p + g.a_plane);
+        st.oa[i] = va[i] && (k0 + ka[i] < g.K);
+        const __bf16* p = pa[i] + (st.oa[i] ? kmul * k0 : 0);
+        st.ah[i] = *(const u32x4*)p;
+        st.al[i] = *(const u32x4*)(p + g.a_plane);
       }
 #pragma unroll
       for (int i = 0; i < SB; ++i) {
-        ob[i] = vb[i] && (k0 + kb[i] < g.K);
-        const __bf16* p = pb[i] + (ob[i] ? k0 : 0);
-        rbh[i] = *(const u32x4*)p;
-        rbl[i] = *(const u32x4*)(p + g.b_plane);
+        st.ob[i] = vb[i] && (k0 + kb[i] < g.K);
+        const __bf16* p = pb[i] + (st.ob[i] ? kmul * k0 : 0);
+        st.bh[i] = *(const u32x4*)p;
+        st.bl[i] = *(const u32x4*)(p + g.b_plane);
       }
     } else {
       // any K, leading dimension and alignment: element loads, masked per element
       const __bf16 z = (__bf16)0.f;
 #pragma unroll
       for (int i = 0; i < SA; ++i) {
-        oa[i] = true;
+        st.oa[i] = true;
         __bf16 h[8], l[8];
-        const __bf16* p = pa[i] + k0;
+        const __bf16* p = pa[i] + kmul * k0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const bool ok = va[i] && k0 + ka[i] + q < g.K;
           h[q] = ok ? p[q] : z;
           l[q] = ok ? p[q + g.a_plane] : z;
         }
-        __builtin_memcpy(&rah[i], h, 16);
-        __builtin_memcpy(&ral[i], l, 16);
+        __builtin_memcpy(&st.ah[i], h, 16);
+        __builtin_memcpy(&st.al[i], l, 16);
       }
 #pragma unroll
       for (int i = 0; i < SB; ++i) {
-        ob[i] = true;
+        st.ob[i] = true;
         __bf16 h[8], l[8];
-        const __bf16* p = pb[i] + k0;
+        const __bf16* p = pb[i] + kmul * k0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const bool ok = vb[i] && k0 + kb[i] + q < g.K;
           h[q] = ok ? p[q] : z;
           l[q] = ok ? p[q + g.b_plane] : z;
         }
-        __builtin_memcpy(&rbh[i], h, 16);
-        __builtin_memcpy(&rbl[i], l, 16);
+        __builtin_memcpy(&st.bh[i], h, 16);
+        __builtin_memcpy(&st.bl[i], l, 16);
       }
     }
   };
   const u32x4 zero4 = {0u, 0u, 0u, 0u};
-  auto store = [&](int buf) {
+  auto store = [&](const Stage& st, int buf) {
 #pragma unroll
     for (int i = 0; i < SA; ++i) {
-      *(u32x4*)&As[buf][0][rowa[i] * LK + ka[i]] = oa[i] ? rah[i] : zero4;
-      *(u32x4*)&As[buf][1][rowa[i] * LK + ka[i]] = oa[i] ? ral[i] : zero4;
+      const int at = lp_swz(rowa[i], ka[i] / 8);
+      *(u32x4*)&As[buf][0][at] = st.oa[i] ? st.ah[i] : zero4;
+      *(u32x4*)&As[buf][1][at] = st.oa[i] ? st.al[i] : zero4;
     }
 #pragma unroll
     for (int i = 0; i < SB; ++i) {
-      *(u32x4*)&Bs[buf][0][rowb[i] * LK + kb[i]] = ob[i] ? rbh[i] : zero4;
-      *(u32x4*)&Bs[buf][1][rowb[i] * LK + kb[i]] = ob[i] ? rbl[i] : zero4;
+      const int at = lp_swz(rowb[i], kb[i] / 8);
+      *(u32x4*)&Bs[buf][0][at] = st.ob[i] ? st.bh[i] : zero4;
+      *(u32x4*)&Bs[buf][1][at] = st.ob[i] ? st.bl[i] : zero4;
     }
   };
-  load(0);
-  store(0);
-  __syncthreads();
-  const int kq = 8 * (lane / 16);
+  const int kq = lane / 16;  // the lane's 16-byte segment of the K tile
   f4 acc[TM][TN];
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * KB);
+  // one K step out of LDS buffer cur: all B fragments of the wave, then one A
+  // fragment at a time; each accumulator takes its three products (lo*hi,
+  // hi*lo, hi*hi, in that order) TN launches apart
+  auto compute = [&](int kt, int cur) {
     if (kt == 0 || (ACC64 && kt % LP_FLUSH == 0)) {
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    // all B fragments of the wave, then one A fragment at a time: each
-    // accumulator takes its three products (lo*hi, hi*lo, hi*hi, in that
-    // order) TN launches apart
     bf8 bh[TN], bl[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int col = wn0 + j * 16 + (lane & 15);
-      bh[j] = *(const bf8*)&Bs[cur][0][col * LK + kq];
-      bl[j] = *(const bf8*)&Bs[cur][1][col * LK + kq];
+      bh[j] = *(const bf8*)&Bs[cur][0][lp_swz(col, kq)];
+      bl[j] = *(const bf8*)&Bs[cur][1][lp_swz(col, kq)];
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int row = wm0 + i * 16 + (lane & 15);
-      const bf8 ah = *(const bf8*)&As[cur][0][row * LK + kq];
-      const bf8 al = *(const bf8*)&As[cur][1][row * LK + kq];
+      const bf8 ah = *(const bf8*)&As[cur][0][lp_swz(row, kq)];
+      const bf8 al = *(const bf8*)&As[cur][1][lp_swz(row, kq)];
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
 #pragma unroll
@@ -901,8 +916,44 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
             for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
       }
     }
-    if (kt + 1 < nk) store(cur ^ 1);
+  };
+  // K step t sits in LDS buffer t & 1.
+  if constexpr (PF == 1) {
+    // one stage: the loads of step t + 1 fly during step t's products
+    load(S0, 0);
+    store(S0, 0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk) load(S0, (kt + 1) * KB);
+      compute(kt, kt & 1);
+      if (kt + 1 < nk) store(S0, (kt + 1) & 1);
+      __syncthreads();
+    }
+  } else {
+    // two stages: on entry to step t the tile of step t + 1 is in S1 (t even)
+    // or S0 (t odd) and the loads of step t + 2 are in flight into the other;
+    // after step t's products the waiting stage goes to LDS and is refilled
+    // with step t + 3
+    load(S0, 0);
+    if (nk > 1) load(S1, KB);
+    store(S0, 0);
+    if (nk > 2) load(S0, 2 * KB);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      compute(kt, 0);
+      if (kt + 1 < nk) {
+        store(S1, 1);
+        if (kt + 3 < nk) load(S1, (kt + 3) * KB);
+      }
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      compute(kt + 1, 1);
+      if (kt + 2 < nk) {
+        store(S0, 0);
+        if (kt + 4 < nk) load(S0, (kt + 4) * KB);
+      }
+      __syncthreads();
+    }
   }
   const long long coff = (long long)b * g.c_batch;
 #pragma unroll
@@ -927,7 +978,7 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
     }
 }
 
-template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64 = true>
+template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64 = true, int PF = 2>
 hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
   const long long nb = (long long)tiles_m * tiles_n;
@@ -937,23 +988,40 @@ hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   if (prec == Prec::F32)
     hipLaunchKernelGGL((gemm_lp_f32_kernel<BM, BN, WM, WN, OCC, VEC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
   else
-    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC, VEC, ACC64>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m,
-                       tiles_n);
+    hipLaunchKernelGGL((gemm_lp_bf16x3_kernel<BM, BN, WM, WN, OCC, VEC, ACC64, PF>), grid, dim3(64 * WM * WN), 0, s, g,
+                       tiles_m, tiles_n);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (prec == Prec::F64 || g.K <= 0) return hipErrorInvalidValue;
-  if (prec == Prec::BF16X3 && (g.a_plane <= 0 || g.b_plane <= 0)) return hipErrorInvalidValue;
+hipError_t gemm_nt_lp(const NtLpArgs& g_in, Prec prec, hipStream_t s) {
+  if (g_in.M <= 0 || g_in.N <= 0 || g_in.batch <= 0) return hipSuccess;
+  if (prec == Prec::F64 || g_in.K <= 0) return hipErrorInvalidValue;
+  NtLpArgs g = g_in;
+  if (g.il) {
+    // blocked split-BF16 operands (OUT_BF16X2I): the caller's strides and
+    // lengths count logical elements; rows, batch strides and lengths have to
+    // hold whole blocks of 32, and the stored rows are twice as long
+    if (prec != Prec::BF16X3 || g.lda % 32 || g.ldb % 32 || g.a_batch % 32 || g.b_batch % 32 || g.a_len % 32 ||
+        g.b_len % 32)
+      return hipErrorInvalidValue;
+  } else if (prec == Prec::BF16X3 && (g.a_plane <= 0 || g.b_plane <= 0)) {
+    return hipErrorInvalidValue;
+  }
   // FP32 output only where it is exact: FP32 accumulation (split BF16), no read of C
   if (g.C32 && (prec != Prec::BF16X3 || g.beta != 0.0 || g.alpha != 1.0)) return hipErrorInvalidValue;
   const long long nb = g.batch - 1;
   if (g.a_len > 0 && nb * g.a_batch + (long long)(g.M - 1) * g.lda + g.K > g.a_len) return hipErrorInvalidValue;
   if (g.b_len > 0 && nb * g.b_batch + (long long)(g.N - 1) * g.ldb + g.K > g.b_len) return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  if (g.il) {
+    g.lda *= 2;
+    g.ldb *= 2;
+    g.a_batch *= 2;
+    g.b_batch *= 2;
+    g.a_plane = g.b_plane = 32;
+  }
   // 16-byte vector loads need K, leading dimensions, batch strides and planes
   // in multiples of the vector width and 16-byte aligned bases
   const int w = prec == Prec::F32 ? 4 : 8;
@@ -988,11 +1056,13 @@ hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
     const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
     variant = t2x2 >= 256 ? 4 : (t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3));
   }
+  // the 256 x 256 tile keeps one load stage (two need more than the 256
+  // registers a wave has at two waves per SIMD)
   switch (variant) {
-    case 4: return launch_lp<256, 256, 2, 4, 1, true, false>(g, prec, s);
-    case 1: return launch_lp<256, 128, 4, 2, 1, true, false>(g, prec, s);
-    case 2: return launch_lp<128, 128, 2, 4, 2, true, false>(g, prec, s);
-    default: return launch_lp<64, 64, 2, 2, 2, true, false>(g, prec, s);
+    case 4: return launch_lp<256, 256, 2, 4, 1, true, false, 1>(g, prec, s);
+    case 1: return launch_lp<256, 128, 4, 2, 1, true, false, 2>(g, prec, s);
+    case 2: return launch_lp<128, 128, 2, 4, 2, true, false, 2>(g, prec, s);
+    default: return launch_lp<64, 64, 2, 2, 2, true, false, 2>(g, prec, s);
   }
 }
 

@@ -91,8 +91,12 @@ struct BlockRef {
 
 // Element formats of operands written by the bandwidth kernels:
 //   OUT_F64: double; OUT_F32: float; OUT_BF16X2: two bf16 planes (hi at
-//   out[i], lo at out[plane + i], hi = bf16(x), lo = bf16(x - hi)).
-enum OutFmt { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2 };
+//   out[i], lo at out[plane + i], hi = bf16(x), lo = bf16(x - hi));
+//   OUT_BF16X2I: the same pair stored by blocks of 32 consecutive elements,
+//   the block's 32 hi values then its 32 lo values (hi of element i at
+//   out[2i - i % 32], lo 32 further on), so that one 128-byte line holds both
+//   halves of 32 values of a row whose length is a multiple of 32.
+enum OutFmt { OUT_F64 = 0, OUT_F32 = 1, OUT_BF16X2 = 2, OUT_BF16X2I = 3 };
 struct OutSpec {
   void* p;
   int fmt;
@@ -148,6 +152,8 @@ struct NtLpArgs {
   long long a_len, b_len, c_len;
   int variant;  // tile variant (0 = size-based default)
   float* C32;   // split BF16 only: FP32 output here instead of C (exact: the accumulation is FP32; beta 0)
+  int il;       // split BF16 only: A and B stored as OUT_BF16X2I (planes unused; logical strides and lengths,
+                // multiples of 32)
 };
 hipError_t gemm_nt_lp(const NtLpArgs& g, Prec prec, hipStream_t s);
 

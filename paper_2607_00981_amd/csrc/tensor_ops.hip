@@ -29,8 +29,9 @@ __device__ __forceinline__ void put_out(const OutSpec& o, long long i, double x)
   } else {
     const __bf16 hi = (__bf16)(float)x;
     const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
-    ((__bf16*)o.p)[i] = hi;
-    ((__bf16*)o.p)[o.plane + i] = lo;
+    const long long h = o.fmt == OUT_BF16X2I ? 2 * i - (i & 31) : i;
+    ((__bf16*)o.p)[h] = hi;
+    ((__bf16*)o.p)[o.fmt == OUT_BF16X2I ? h + 32 : o.plane + i] = lo;
   }
 }
 

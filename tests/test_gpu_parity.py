@@ -282,24 +282,28 @@ def test_ladder_split_matches_direct(prec, o, v, ws):
 
 
 TILE_VARIANTS = {"fp64": (1, 2, 3, 4), "fp32": (1, 2, 3), "bf16x3": (1, 2, 3, 4)}
+CASES = [(p, x, False) for p, vs in TILE_VARIANTS.items() for x in vs] + [("bf16x3", x, True) for x in (1, 2, 3, 4)]
 
 
-@pytest.mark.parametrize("prec,var", [(p, x) for p, vs in TILE_VARIANTS.items() for x in vs])
-def test_every_tile_variant_matches_oracle(prec, var, tmp_path, monkeypatch):
+@pytest.mark.parametrize("prec,var,blocked", CASES)
+def test_every_tile_variant_matches_oracle(prec, var, blocked, tmp_path, monkeypatch):
     """Each GEMM tile variant, forced for the ladder and the rings through the
     tuning cache, on a shape whose GEMMs all end in ragged tiles (v = 30:
-    465 pairs, o v = 90, 10 packed blocks)."""
+    465 pairs, o v = 90, 10 packed blocks).  blocked: the split-BF16 ladder
+    and ring operands in the layout interleaved by blocks of 32 (forced at
+    this size through lp_block_k = 0; K padded to 480, 448 and 96)."""
     import json
 
     o, v, seed = 3, 30, 23
     cache = tmp_path / "tune.json"
     cache.write_text(json.dumps({f"o{o}_v{v}_{prec}_ladder_split": var, f"o{o}_v{v}_{prec}_rings": var}))
     monkeypatch.setenv("CCT_TUNE_CACHE", str(cache))
-    say(f"[tile variant] prec={prec} variant={var}")
+    say(f"[tile variant] prec={prec} variant={var} blocked={blocked}")
     f, B = _system(o, v, seed)
     t1, t2, t3p = _amps(o, v, seed)
     e1, e2, e3 = _oracle_residual(f, B, o, t1, t2, t3p)
-    with _engine(o, v, B.shape[0], f, B, precision=prec) as eng:
+    opts = {"lp_block_k": 0} if blocked else None
+    with _engine(o, v, B.shape[0], f, B, precision=prec, opts=opts) as eng:
         eng.set_amplitudes(t1, t2, t3p)
         g1, g2, g3, _ = eng.residual()
     rel = 1e-11 if prec == "fp64" else MIXED_TOL[prec]
@@ -307,6 +311,31 @@ def test_every_tile_variant_matches_oracle(prec, var, tmp_path, monkeypatch):
         ok, err, scale = _close(a, b, r)
         say(f"  {name}: max err {err:.3e} scale {scale:.3e}")
         assert ok, f"{prec} variant {var} {name}: max err {err:.3e} (scale {scale:.3e})"
+
+
+@pytest.mark.parametrize("o,v", [(3, 33), (4, 20)])
+def test_blocked_split_bf16_layout_is_a_storage_layout_only(o, v):
+    """The split-BF16 residual with the ladder and ring operands interleaved
+    by blocks of 32 (lp_block_k = 0) equals the one with two planes
+    (lp_block_k above every K) element for element: both feed the same
+    products to the same accumulators in the same K order; only the zero
+    padding of K differs (8 against 32), and adding exact zeros changes no
+    FP32 sum.  v = 33: ragged pair tiles, K = 561 / 528 pairs; o v = 99 and
+    80 ring columns."""
+    seed = 70 + v
+    say(f"[blocked layout] o={o} v={v}")
+    f, B = _system(o, v, seed)
+    t1, t2, t3p = _amps(o, v, seed)
+    out = []
+    for k in (0, 1 << 40):
+        with _engine(o, v, B.shape[0], f, B, precision="bf16x3", opts={"lp_block_k": k}) as eng:
+            eng.set_amplitudes(t1, t2, t3p)
+            out.append(eng.residual())
+    for name, a, b in zip(("R1", "R2", "R3"), out[0][:3], out[1][:3]):
+        d = float(np.abs(a - b).max())
+        say(f"  {name}: max |blocked - planar| {d:.3e}")
+        assert np.array_equal(a, b), f"{name} differs by {d:.3e}"
+    assert np.abs(out[0][2]).max() > 1e-6
 
 
 @pytest.mark.parametrize("mode", ["subspace:10", "none"])
