@@ -18,9 +18,16 @@ spinorb   Equation-free brute force in determinant space: FCI, spin-orbital
           projective CC through exp(-T) H exp(T), and the spin-free <->
           spin-orbital amplitude maps (Appendix A spin-free formalism and the
           closed-shell T3 reconstruction formula of the UCCSDT appendix).
-elements  Element-by-element evaluation of R3 for sampled outputs at sizes
-          where the full tensor does not fit in host memory.
+blocks    Block- and element-level evaluation of R3 (one output block, or
+          sampled output elements, by the term definitions) at sizes where the
+          full T3 does not fit in host memory.
 counts    Closed-form multiply-add counts of the compact contractions
           (Sec. "Total cost of RCCSDT contractions" and the RCCSDT operation
           count table).
+rccsdt_q  The perturbative quadruples correction E_(Q) (Appendix "(Q) energy
+          correction"), on full tensors and per occupied or virtual tuple.
+rccsdtq   RCCSDTQ on full tensors (Appendix "RCCSDTQ"): the quadruples
+          residual, the T4 terms of R2 and R3, the T4 projector.
+time_oracle  Wall-clock timing of the oracle on the named workloads (the
+          benchmark's CPU baseline figures).
 """
