@@ -2647,7 +2647,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
       const int fmt = split ? lp_fmt_gemm(ctx, vp) : lp_fmt(ctx->prec);
       HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * lK}, Mt * lK, ctx->s));
       HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, lN * lK}, lN * lK, ctx->s));
-      ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3},
+      ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{1, 2, 3},
                               [&](int var) {
         NtLpArgs g{};
         g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
@@ -2678,7 +2678,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     else HIPCK(fill((double*)U, 0.01, ulen, ctx->s));
     HIPCK(copy_pad_rows(ctx->Wb1, ov, ov, OutSpec{Al, fmt, ov * kp}, kp, ctx->s));
     const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{1, 2, 3, 4}
-                                        : (ctx->prec == Prec::BF16X3 ? std::vector<int>{4, 1, 2, 3} : std::vector<int>{1, 2, 3});
+                                        : (ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{1, 2, 3});
     ctx->tune_rings = pick(ring_cands, [&](int var) {
       if (ring_lp) {
         NtLpArgs g{};

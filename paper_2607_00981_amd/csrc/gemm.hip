@@ -978,6 +978,152 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
     }
 }
 
+// One 16-byte-per-lane copy from global memory into LDS (the 64 lanes fill
+// 1 KB from LDS byte address lds, lane i at lds + 16 i).  Written out rather
+// than through the compiler builtin: the builtin makes the compiler wait for
+// every such copy in flight before any later LDS read, including the reads of
+// the other buffer that the copies are meant to overlap.  The instruction has
+// no register results; its completion is counted by vmcnt, and the kernel
+// below waits for it (s_waitcnt vmcnt(0)) before the barrier that ends each
+// K step and before anything reads the copied tile.
+__device__ __forceinline__ void lds_copy16(const void* src, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds) : "memory", "m0");
+}
+__device__ __forceinline__ unsigned lds_addr(const __bf16* p) {
+  return (unsigned)(size_t)(__attribute__((address_space(3))) const void*)p;
+}
+
+// The split-BF16 kernel with the operand tiles copied from global memory
+// straight into LDS (16 bytes per lane, no register staging and no LDS store
+// instructions), for K a multiple of 32, two tile buffers.  Each wave copies
+// whole 1 KB chunks of a tile (16 rows of one plane); lane s of a chunk lands
+// at byte 16 s of it, i.e. in row s / 4 at segment position s % 4, so the lane
+// fetches the logical segment (s % 4) ^ ((row >> 1) & 3) that the swizzled
+// layout keeps there.  Rows past the matrix are read from row 0 (finite
+// values whose products go to outputs that are not stored).  FP32
+// accumulation over the whole K.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 1) void gemm_lp_bf16x3_dl_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NW = WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32;
+  constexpr int CA = 2 * BM / 16, CB = 2 * BN / 16;  // 1 KB chunks per K tile (both planes)
+  static_assert(CA % NW == 0 && CB % NW == 0, "whole chunks per wave");
+  constexpr int PA = CA / NW, PB = CB / NW;  // chunks per wave per step
+  constexpr int ABUF = 2 * BM * KB, BBUF = 2 * BN * KB;  // elements per buffer (planes hi, lo)
+  __shared__ __attribute__((aligned(1024))) __bf16 As[2 * ABUF];
+  __shared__ __attribute__((aligned(1024))) __bf16 Bs[2 * BBUF];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const int wave = tid / 64, lane = tid & 63;
+  const __bf16* A = (const __bf16*)g.A + (long long)b * g.a_batch;
+  const __bf16* B = (const __bf16*)g.B + (long long)b * g.b_batch;
+  const int kmul = g.il ? 2 : 1;
+  // per chunk: the lane's source (K step 0) and the chunk's LDS byte address
+  // in buffer 0 (wave-uniform)
+  const __bf16* sa[PA];
+  const __bf16* sb[PB];
+  unsigned la[PA], lb[PB];
+  const unsigned as0 = lds_addr(As), bs0 = lds_addr(Bs);
+#pragma unroll
+  for (int j = 0; j < PA; ++j) {
+    const int c = wave + NW * j, pl = c / (BM / 16), cc = c % (BM / 16);
+    const int row = cc * 16 + lane / 4, q = (lane % 4) ^ ((row >> 1) & 3);
+    const int m = tm * BM + row;
+    sa[j] = A + (long long)(m < g.M ? m : 0) * g.lda + 8 * q + (pl ? g.a_plane : 0);
+    la[j] = __builtin_amdgcn_readfirstlane(as0 + 2u * (unsigned)(pl * BM * KB + cc * 16 * KB));
+  }
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    const int c = wave + NW * j, pl = c / (BN / 16), cc = c % (BN / 16);
+    const int row = cc * 16 + lane / 4, q = (lane % 4) ^ ((row >> 1) & 3);
+    const int n = tn * BN + row;
+    sb[j] = B + (long long)(n < g.N ? n : 0) * g.ldb + 8 * q + (pl ? g.b_plane : 0);
+    lb[j] = __builtin_amdgcn_readfirstlane(bs0 + 2u * (unsigned)(pl * BN * KB + cc * 16 * KB));
+  }
+  const int nk = g.K / KB;
+  auto issue = [&](int kt, int buf) {
+    const long long k0 = (long long)kmul * kt * KB;
+    const unsigned da = buf * (2u * ABUF), db = buf * (2u * BBUF);  // bytes
+#pragma unroll
+    for (int j = 0; j < PA; ++j) lds_copy16(sa[j] + k0, la[j] + da);
+#pragma unroll
+    for (int j = 0; j < PB; ++j) lds_copy16(sb[j] + k0, lb[j] + db);
+  };
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  const int kq = lane / 16;
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](const __bf16* Ac, const __bf16* Bc) {
+    bf8 bh[TN], bl[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = wn0 + j * 16 + (lane & 15);
+      bh[j] = *(const bf8*)&Bc[lp_swz(col, kq)];
+      bl[j] = *(const bf8*)&Bc[BN * KB + lp_swz(col, kq)];
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm0 + i * 16 + (lane & 15);
+      const bf8 ah = *(const bf8*)&Ac[lp_swz(row, kq)];
+      const bf8 al = *(const bf8*)&Ac[BM * KB + lp_swz(row, kq)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  // Step t multiplies out of buffer t & 1 while the copies of step t + 1 fill
+  // the other (last read in step t - 1, before the barrier); each wave then
+  // waits for its own copies, and the barrier for everyone's.
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+    compute(As + cur * ABUF, Bs + cur * BBUF);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        const double x = g.alpha * (double)acc[i][j][r];
+        if (g.C32) {
+          g.C32[mo + map2(g.cn, n)] = (float)x;
+          continue;
+        }
+        double* p = g.C + mo + map2(g.cn, n);
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_lp_dl(const NtLpArgs& g, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  hipLaunchKernelGGL((gemm_lp_bf16x3_dl_kernel<BM, BN, WM, WN>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int WM, int WN, int OCC, bool VEC, bool ACC64 = true, int PF = 2>
 hipError_t launch_lp(const NtLpArgs& g, Prec prec, hipStream_t s) {
   const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
@@ -1054,11 +1200,14 @@ hipError_t gemm_nt_lp(const NtLpArgs& g_in, Prec prec, hipStream_t s) {
     const long long t2x2 = (long long)((g.M + 255) / 256) * ((g.N + 255) / 256) * g.batch;
     const long long t256 = (long long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch;
     const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-    variant = t2x2 >= 256 ? 4 : (t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3));
+    variant = t2x2 >= 256 ? (g.K % 32 == 0 ? 5 : 4) : (t256 >= 256 ? 1 : (t128 >= 256 ? 2 : 3));
   }
   // the 256 x 256 tile keeps one load stage (two need more than the 256
-  // registers a wave has at two waves per SIMD)
+  // registers a wave has at two waves per SIMD); variant 5 is the same tile
+  // with the operands copied straight into LDS, where K is a multiple of 32
+  if (variant == 5 && g.K % 32 != 0) variant = 4;
   switch (variant) {
+    case 5: return launch_lp_dl<256, 256, 2, 4>(g, s);
     case 4: return launch_lp<256, 256, 2, 4, 1, true, false, 1>(g, prec, s);
     case 1: return launch_lp<256, 128, 4, 2, 1, true, false, 2>(g, prec, s);
     case 2: return launch_lp<128, 128, 2, 4, 2, true, false, 2>(g, prec, s);
