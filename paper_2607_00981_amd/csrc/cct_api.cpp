@@ -2099,14 +2099,39 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   HIPCK(fill(etup, 0.0, ntup, s));
   HIPCK(hipEventRecord(ev[1], s));
 
+  // Two streams per task: the X chain (T3 gathers, X1, X2 into Xt) on the
+  // context's stream, the Y chain (Z, Wbar^{vvv}, Wbar^{vvo}, Y1, Y2 into Yt)
+  // on a side stream, so that the bandwidth-bound passes of one chain overlap
+  // the matrix-core products of the other; the side stream joins before
+  // R = Xt + Yt.  (Default priority, created for the call.)
+  struct Side {
+    hipStream_t st = nullptr;
+    hipEvent_t ready = nullptr, ydone = nullptr, added = nullptr;
+    ~Side() {
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+      for (hipEvent_t e : {ready, ydone, added})
+        if (e) (void)hipEventDestroy(e);
+    }
+  } side;
+  HIPCK(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
+  HIPCK(hipEventCreateWithFlags(&side.ready, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&side.ydone, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&side.added, hipEventDisableTiming));
+  hipStream_t sy = side.st;
+  HIPCK(hipEventRecord(side.ready, s));
+  HIPCK(hipStreamWaitEvent(sy, side.ready, 0));
+
   double macs_mfma = 0.0, macs_valu = 0.0;
-  auto run = [&](QGemmArgs& g) -> int {
+  auto run = [&](QGemmArgs& g, hipStream_t st) -> int {
     long long batch = 1;
     for (int d = 0; d < g.nd; ++d) batch *= g.rad[d];
     long long K = 0;
     for (int k = 0; k < g.nseg; ++k) K += g.K[k];
     macs_mfma += (double)g.M * g.N * K * batch;
-    HIPCK(qgemm(g, s));
+    HIPCK(qgemm(g, st));
     return CCT_OK;
   };
   const long long pw[4] = {o3, o2, (long long)o, 1};
@@ -2184,7 +2209,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
           g.sc[0] = (long long)sl.n[b] * sl.n[c] * o2v; g.sc[1] = (long long)sl.n[c] * o2v;
           g.c_len = b3 * o2v;
           g.alpha = 0.5; g.accumulate = 0;
-          RCK(run(g));
+          RCK(run(g, sy));
         }
     // Wbar^{vvv}_{voo} for x in slot s0, (y, z) in the row slots (r0, r1)
     for (int s0 = 0; s0 < 4; ++s0)
@@ -2192,7 +2217,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         for (int r1 = r0 + 1; r1 < 4; ++r1) {
           if (s0 == r0 || s0 == r1) continue;
           HIPCK(q_wv_build(WvS[s0][pid(r0, r1)], Z[s0][r0][r1], Z[s0][r1][r0], Vmyje, Vmxje, ctx->t2, o, v, sl.st[s0],
-                           sl.n[s0], sl.st[r0], sl.n[r0], sl.st[r1], sl.n[r1], s));
+                           sl.n[s0], sl.st[r0], sl.n[r0], sl.st[r1], sl.n[r1], sy));
           macs_valu += 4.0 * o * sl.n[s0] * sl.n[r0] * sl.n[r1] * o2v;
         }
     // Wbar^{vvo}_{ooo} for (x, y) in slots (s0 < s1), rows = the slots other than s3
@@ -2207,7 +2232,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         auto pos = [&](int sl_) { return sl_ == rs[0] ? 0 : (sl_ == rs[1] ? 1 : 2); };
         const int rowpos[3] = {pos(p01[0]), pos(p01[1]), pos(s2)};
         HIPCK(q_wo_build(Wo[s3][s2], Voooo, ctx->t2, o, v, sl.st[p01[0]], sl.n[p01[0]], sl.st[p01[1]], sl.n[p01[1]],
-                         rowpos, s));
+                         rowpos, sy));
         macs_valu += 2.0 * o * sl.n[p01[0]] * sl.n[p01[1]] * o4;
       }
     // X1: per row slot r, K segments over s0 (the slot whose label is summed)
@@ -2248,7 +2273,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
       g.cn = sw ? rowm : colm;
       g.C = Xt; g.c_len = tlen;
       g.alpha = 1.0; g.accumulate = r == 0 ? 0 : 1;
-      RCK(run(g));
+      RCK(run(g, s));
     }
     // X2: per row pair (r0, r1), segments (s0, s1) = (r0, r1) and (r1, r0)
     for (int r0 = 0; r0 < 4; ++r0)
@@ -2287,10 +2312,12 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         g.cn = sw ? rowm : colm;
         g.C = Xt; g.c_len = tlen;
         g.alpha = -1.0; g.accumulate = 1;
-        RCK(run(g));
+        RCK(run(g, s));
       }
     // Y1: per column pair (c0, c1), segments (s0, s3) = (c0, c1) and (c1, c0);
-    // rows (l_r0, l_r1, i_r0, i_r1)
+    // rows (l_r0, l_r1, i_r0, i_r1).  Yt (which holds R after the add) is
+    // overwritten only after the last task's energy has read it.
+    if (ti > 0) HIPCK(hipStreamWaitEvent(sy, side.added, 0));
     bool firsty = true;
     for (int c0 = 0; c0 < 4; ++c0)
       for (int c1 = c0 + 1; c1 < 4; ++c1) {
@@ -2335,7 +2362,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         g.C = Yt; g.c_len = tlen;
         g.alpha = 1.0; g.accumulate = firsty ? 0 : 1;
         firsty = false;
-        RCK(run(g));
+        RCK(run(g, sy));
       }
     // Y2: per column slot s3, segments over s2 (the Wbar^{vvo}_{ooo} pair is
     // the other two slots)
@@ -2376,12 +2403,15 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
       g.cn = sw ? rowm : colm;
       g.C = Yt; g.c_len = tlen;
       g.alpha = -1.0; g.accumulate = 1;
-      RCK(run(g));
+      RCK(run(g, sy));
     }
     // R = Xt + Yt; energies of the box's tuples
-    HIPCK(q_add(Yt, Xt, tlen, s));
+    HIPCK(hipEventRecord(side.ydone, sy));
+    HIPCK(hipStreamWaitEvent(s, side.ydone, 0));
+    HIPCK(q_add(Yt, Xt, tlen, s));  // R = Xt + Yt, in Yt
     HIPCK(q_abc_energy(Xt, Yt, Vvvoo, t2R, ctx->eps, sl, o, v, d_orb, (int)norb, part,
                        etup + (e_tuples ? ti * b4 : 0), etask + ti, s));
+    HIPCK(hipEventRecord(side.added, s));  // Yt free for the next task's Y chain
   }
   HIPCK(hipEventRecord(ev[2], s));
   std::vector<double> h((size_t)ntasks);
