@@ -43,6 +43,21 @@ __device__ __forceinline__ long long map2(const Idx2& d, int i) {
   return (long long)hi * d.s_hi + (long long)lo * d.s_lo;
 }
 
+// One 16-byte-per-lane copy from global memory into LDS (the 64 lanes fill
+// 1 KB from LDS byte address lds, lane i at lds + 16 i).  Written out rather
+// than through the compiler builtin: the builtin makes the compiler wait for
+// every such copy in flight before any later LDS read, including the reads of
+// the other buffer that the copies are meant to overlap.  The instruction has
+// no register results; its completion is counted by vmcnt, and the kernels
+// that use it wait for it (s_waitcnt vmcnt(0)) before the barrier that ends
+// each K step, i.e. before anything reads the copied tile.
+__device__ __forceinline__ void lds_copy16(const void* src, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds) : "memory", "m0");
+}
+__device__ __forceinline__ unsigned lds_addr(const __bf16* p) {
+  return (unsigned)(size_t)(__attribute__((address_space(3))) const void*)p;
+}
+
 // Position of the tile handled by this workgroup.  Consecutive workgroup ids
 // land on different XCDs (round robin over 8); remap so that each XCD gets a
 // contiguous range of the tile order, and order tiles in groups of GM tile
@@ -539,6 +554,123 @@ hipError_t launch_nt(const NtArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The NT kernel with the operand tiles copied from global memory straight
+// into LDS (no register staging, no LDS stores), for K a multiple of BK = 16
+// and both operands K-contiguous.  An LDS row holds one K tile of one matrix
+// row: 16 doubles as eight 16-byte pairs, pair p at slot p ^ ((row >> 1) & 7).
+// The 16 x 16 x 4 fragment reads (16 consecutive rows at one k per 16 lanes)
+// then fall on distinct banks.  Each wave copies whole 1 KB chunks (8 rows);
+// lane s of a chunk lands in row s / 8 at slot s % 8 and fetches the pair that
+// the swizzle keeps there.  Rows past the matrix are read from row 0 (finite
+// values whose products go to outputs that are not stored).  Two buffers; the
+// copies of step t + 1 fly while step t is multiplied.
+__device__ __forceinline__ int nt_swz(int row, int k) { return row * BK + 2 * ((k >> 1) ^ ((row >> 1) & 7)) + (k & 1); }
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 1) void gemm_nt_f64_dl_kernel(NtArgs g, int tiles_m, int tiles_n) {
+  constexpr int NW = WM * WN, TM = BM / WM / 16, TN = BN / WN / 16;
+  constexpr int CA = BM / 8, CB = BN / 8;  // 1 KB chunks per K tile
+  static_assert(CA % NW == 0 && CB % NW == 0, "whole chunks per wave");
+  constexpr int PA = CA / NW, PB = CB / NW;
+  constexpr int ABUF = BM * BK, BBUF = BN * BK;  // doubles per buffer
+  __shared__ __attribute__((aligned(1024))) double As[2 * ABUF];
+  __shared__ __attribute__((aligned(1024))) double Bs[2 * BBUF];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const int wave = tid / 64, lane = tid & 63;
+  const double* A = g.A + (long long)b * g.a_batch;
+  const double* B = g.B + (long long)b * g.b_batch;
+  const double* sa[PA];
+  const double* sb[PB];
+  unsigned la[PA], lb[PB];
+  const unsigned as0 = (unsigned)(size_t)(__attribute__((address_space(3))) const void*)As;
+  const unsigned bs0 = (unsigned)(size_t)(__attribute__((address_space(3))) const void*)Bs;
+#pragma unroll
+  for (int j = 0; j < PA; ++j) {
+    const int c = wave + NW * j, row = c * 8 + lane / 8, kp = (lane % 8) ^ ((row >> 1) & 7);
+    const int m = tm * BM + row;
+    sa[j] = A + (long long)(m < g.M ? m : 0) * g.lda + 2 * kp;
+    la[j] = __builtin_amdgcn_readfirstlane(as0 + 8u * (unsigned)(c * 8 * BK));
+  }
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    const int c = wave + NW * j, row = c * 8 + lane / 8, kp = (lane % 8) ^ ((row >> 1) & 7);
+    const int n = tn * BN + row;
+    sb[j] = B + (long long)(n < g.N ? n : 0) * g.ldb + 2 * kp;
+    lb[j] = __builtin_amdgcn_readfirstlane(bs0 + 8u * (unsigned)(c * 8 * BK));
+  }
+  auto issue = [&](int kt, int buf) {
+    const long long k0 = (long long)kt * BK;
+    const unsigned da = buf * (8u * ABUF), db = buf * (8u * BBUF);  // bytes
+#pragma unroll
+    for (int j = 0; j < PA; ++j) lds_copy16(sa[j] + k0, la[j] + da);
+#pragma unroll
+    for (int j = 0; j < PB; ++j) lds_copy16(sb[j] + k0, lb[j] + db);
+  };
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nk = g.K / BK;
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+    const double* as = As + cur * ABUF;
+    const double* bs = Bs + cur * BBUF;
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = as[nt_swz(wm0 + i * 16 + (lane & 15), kr)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = bs[nt_swz(wn0 + j * 16 + (lane & 15), kr)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+  // epilogue: accumulator register r of lane l holds row 4r + l/16, column l%16
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * r + lane / 16;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * acc[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WM, int WN>
+hipError_t launch_nt_dl(const NtArgs& g, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  hipLaunchKernelGGL((gemm_nt_f64_dl_kernel<BM, BN, WM, WN>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
@@ -577,7 +709,13 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
       if (score > best) { best = score; variant = c.var; }
     }
   }
+  // variant 9: the 128 x 256 tile with the operands copied straight into LDS
+  // (both operands K-contiguous, K a multiple of 16); the default in its place
+  const bool dl_ok = !g.b_kn && g.K % BK == 0;
+  if (g.variant == 0 && variant == 1 && dl_ok) variant = 9;
+  if (variant == 9 && !dl_ok) variant = 1;
   switch (variant) {
+    case 9: return launch_nt_dl<128, 256, 2, 4>(g, s);
     case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
     case 2: return launch_nt<256, 128, 4, 2, 2>(g, s);
     case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);
@@ -976,21 +1114,6 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_bf16x3_kernel(NtLpA
         *p = (g.beta == 0.0) ? x : x + g.beta * *p;
       }
     }
-}
-
-// One 16-byte-per-lane copy from global memory into LDS (the 64 lanes fill
-// 1 KB from LDS byte address lds, lane i at lds + 16 i).  Written out rather
-// than through the compiler builtin: the builtin makes the compiler wait for
-// every such copy in flight before any later LDS read, including the reads of
-// the other buffer that the copies are meant to overlap.  The instruction has
-// no register results; its completion is counted by vmcnt, and the kernel
-// below waits for it (s_waitcnt vmcnt(0)) before the barrier that ends each
-// K step and before anything reads the copied tile.
-__device__ __forceinline__ void lds_copy16(const void* src, unsigned lds) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds) : "memory", "m0");
-}
-__device__ __forceinline__ unsigned lds_addr(const __bf16* p) {
-  return (unsigned)(size_t)(__attribute__((address_space(3))) const void*)p;
 }
 
 // The split-BF16 kernel with the operand tiles copied from global memory
