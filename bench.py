@@ -191,9 +191,13 @@ NT_TILES = {0: "size-based", 1: "<128,256,2,4,2>", 2: "<256,128,4,2,2>", 3: "<64
 LP_TILES = {"fp32": {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>"},
             "bf16x3": {0: "size-based", 1: "<256,128,4,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>",
                        4: "<256,256,2,4,1>"}}
+# tile variants whose operand tiles are copied straight into LDS (their own kernels)
+DL_KERNELS = {("fp64", 9): "gemm_nt_f64_dl_kernel<128,256,2,4>", ("bf16x3", 5): "gemm_lp_bf16x3_dl_kernel<256,256,2,4>"}
 
 
 def kernel_name(prec, variant):
+    if (prec, variant) in DL_KERNELS:
+        return DL_KERNELS[(prec, variant)]
     if prec == "fp64":
         return "gemm_nt_f64_kernel" + NT_TILES.get(variant, str(variant))
     return f"gemm_lp_{prec.replace('fp32', 'f32')}_kernel" + LP_TILES[prec].get(variant, str(variant))
