@@ -888,8 +888,8 @@ void* alloc_lp(Arena& ws, long long n) { return ws.alloc((size_t)((n + 1) / 2));
 // split-BF16 rows with K >= lp_block_k (a context option, 1024 by default)
 // are stored by blocks of 32 and padded to 32, so that hi and lo of 32 values
 // share one 128-byte line and each K tile of the GEMM reads whole lines;
-// shorter ones as two planes padded to 8; FP32 rows padded to 4; FP64 rows to
-// 16 (one K tile of the FP64 kernels, which then copy whole tiles).
+// shorter ones as two planes padded to 8; FP32 rows padded to 32 and FP64
+// rows to 16 (one K tile of those kernels, which then copy whole tiles).
 bool lp_blocked(const cct_ctx* ctx, long long K) { return ctx->prec == Prec::BF16X3 && K >= ctx->lp_block_k; }
 int lp_fmt_gemm(const cct_ctx* ctx, long long K) {
   const Prec p = ctx->prec;
@@ -897,7 +897,7 @@ int lp_fmt_gemm(const cct_ctx* ctx, long long K) {
 }
 long long lp_kpad(const cct_ctx* ctx, long long K) {
   const Prec p = ctx->prec;
-  return p == Prec::F64 ? 16 : (p == Prec::F32 ? 4 : (lp_blocked(ctx, K) ? 32 : 8));
+  return p == Prec::F64 ? 16 : (p == Prec::F32 ? 32 : (lp_blocked(ctx, K) ? 32 : 8));
 }
 
 // Ladder with operands stored in the working precision: W converted once,
@@ -2678,7 +2678,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
       const int fmt = split ? lp_fmt_gemm(ctx, vp) : lp_fmt(ctx->prec);
       HIPCK(convert(ctx->t3, OutSpec{Al, fmt, Mt * lK}, Mt * lK, ctx->s));
       HIPCK(convert(ctx->Wvvvv, OutSpec{Bl, fmt, lN * lK}, lN * lK, ctx->s));
-      ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{1, 2, 3},
+      ctx->tune_ladder = pick(ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{5, 1, 2, 3},
                               [&](int var) {
         NtLpArgs g{};
         g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
@@ -2709,7 +2709,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     else HIPCK(fill((double*)U, 0.01, ulen, ctx->s));
     HIPCK(copy_pad_rows(ctx->Wb1, ov, ov, OutSpec{Al, fmt, ov * kp}, kp, ctx->s));
     const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{9, 1, 2, 3, 4}
-                                        : (ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{1, 2, 3});
+                                        : (ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{5, 1, 2, 3});
     ctx->tune_rings = pick(ring_cands, [&](int var) {
       if (ring_lp) {
         NtLpArgs g{};

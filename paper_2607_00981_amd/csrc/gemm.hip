@@ -882,6 +882,138 @@ __global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_kernel(NtLpArgs
     }
 }
 
+// The FP32 kernel with the operand tiles copied from global memory straight
+// into LDS (no register staging, no LDS stores), for K a multiple of 32.  An
+// LDS row holds one K tile of one matrix row: 32 floats as eight 16-byte
+// slots, slot p at position p ^ ((row >> 1) & 7); the 16 x 16 x 4 fragment
+// reads (16 consecutive rows per 16 lanes, k = lane / 16 within a group of 4)
+// then fall on 64 distinct banks.  Each wave copies whole 1 KB chunks (8 rows);
+// lane s of a chunk lands in row s / 8 at position s % 8 and fetches the slot
+// that the swizzle keeps there.  Rows past the matrix are read from row 0
+// (their outputs are not stored).  FP32 accumulation over LP_FLUSH K tiles,
+// then FP64, as in the register-staged kernel.
+__device__ __forceinline__ int f32_swz(int row, int k) { return row * 32 + 4 * ((k >> 2) ^ ((row >> 1) & 7)) + (k & 3); }
+
+template <int BM, int BN, int WM, int WN, int OCC>
+__global__ __launch_bounds__(64 * WM * WN, OCC) void gemm_lp_f32_dl_kernel(NtLpArgs g, int tiles_m, int tiles_n) {
+  constexpr int NW = WM * WN, TM = BM / WM / 16, TN = BN / WN / 16, KB = 32;
+  constexpr int CA = BM / 8, CB = BN / 8;  // 1 KB chunks per K tile
+  static_assert(CA % NW == 0 && CB % NW == 0, "whole chunks per wave");
+  constexpr int PA = CA / NW, PB = CB / NW;
+  constexpr int ABUF = BM * KB, BBUF = BN * KB;  // floats per buffer
+  __shared__ __attribute__((aligned(1024))) float As[2 * ABUF];
+  __shared__ __attribute__((aligned(1024))) float Bs[2 * BBUF];
+  int tm, tn;
+  if (!tile_coords(tiles_m, tiles_n, tm, tn)) return;
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const int wave = tid / 64, lane = tid & 63;
+  const float* A = (const float*)g.A + (long long)b * g.a_batch;
+  const float* B = (const float*)g.B + (long long)b * g.b_batch;
+  const float* sa[PA];
+  const float* sb[PB];
+  unsigned la[PA], lb[PB];
+  const unsigned as0 = (unsigned)(size_t)(__attribute__((address_space(3))) const void*)As;
+  const unsigned bs0 = (unsigned)(size_t)(__attribute__((address_space(3))) const void*)Bs;
+#pragma unroll
+  for (int j = 0; j < PA; ++j) {
+    const int c = wave + NW * j, row = c * 8 + lane / 8, kp = (lane % 8) ^ ((row >> 1) & 7);
+    const int m = tm * BM + row;
+    sa[j] = A + (long long)(m < g.M ? m : 0) * g.lda + 4 * kp;
+    la[j] = __builtin_amdgcn_readfirstlane(as0 + 4u * (unsigned)(c * 8 * KB));
+  }
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    const int c = wave + NW * j, row = c * 8 + lane / 8, kp = (lane % 8) ^ ((row >> 1) & 7);
+    const int n = tn * BN + row;
+    sb[j] = B + (long long)(n < g.N ? n : 0) * g.ldb + 4 * kp;
+    lb[j] = __builtin_amdgcn_readfirstlane(bs0 + 4u * (unsigned)(c * 8 * KB));
+  }
+  auto issue = [&](int kt, int buf) {
+    const long long k0 = (long long)kt * KB;
+    const unsigned da = buf * (4u * ABUF), db = buf * (4u * BBUF);  // bytes
+#pragma unroll
+    for (int j = 0; j < PA; ++j) lds_copy16(sa[j] + k0, la[j] + da);
+#pragma unroll
+    for (int j = 0; j < PB; ++j) lds_copy16(sb[j] + k0, lb[j] + db);
+  };
+  const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+  double out[TM][TN][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[i][j][r] = 0.0;
+  f4 acc[TM][TN];
+  const int nk = g.K / KB;
+  issue(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+    const float* as = As + cur * ABUF;
+    const float* bs = Bs + cur * BBUF;
+    if (kt % LP_FLUSH == 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int kr = ks * 4 + lane / 16;
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = as[f32_swz(wm0 + i * 16 + (lane & 15), kr)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = bs[f32_swz(wn0 + j * 16 + (lane & 15), kr)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt % LP_FLUSH == LP_FLUSH - 1 || kt + 1 == nk) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[i][j][r] += (double)acc[i][j][r];
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  }
+  const long long coff = (long long)b * g.c_batch;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = tm * BM + wm0 + i * 16 + 4 * (lane / 16) + r;
+      if (m >= g.M) continue;
+      const long long mo = coff + map2(g.cm, m);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = tn * BN + wn0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+        double* p = g.C + mo + map2(g.cn, n);
+        const double x = g.alpha * out[i][j][r];
+        *p = (g.beta == 0.0) ? x : x + g.beta * *p;
+      }
+    }
+}
+
+template <int BM, int BN, int WM, int WN, int OCC>
+hipError_t launch_lp_f32_dl(const NtLpArgs& g, hipStream_t s) {
+  const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
+  const long long nb = (long long)tiles_m * tiles_n;
+  const long long grid_x = ((nb + 7) / 8) * 8;
+  if (grid_x > INT_MAX || g.batch > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)grid_x, 1, (unsigned)g.batch);
+  hipLaunchKernelGGL((gemm_lp_f32_dl_kernel<BM, BN, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
 // LDS rows of the split-BF16 kernel hold one K tile (32 values, four 16-byte
 // segments) unpadded; segment q of row r sits at position q ^ ((r >> 1) & 3).
 // On gfx950 this is free of bank conflicts for both 16-byte accesses the
@@ -1305,11 +1437,14 @@ hipError_t gemm_nt_lp(const NtLpArgs& g_in, Prec prec, hipStream_t s) {
     int variant = g.variant;
     if (variant == 0) {
       // 128 x 128 tiles of 8 waves (64 x 32 each, two waves per SIMD) once
-      // there are enough of them; 64 x 64 below that
+      // there are enough of them, with the operands copied straight into LDS
+      // where K is a multiple of 32; 64 x 64 below that
       const long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-      variant = t128 >= 256 ? 2 : 3;
+      variant = t128 >= 256 ? (g.K % 32 == 0 ? 5 : 2) : 3;
     }
+    if (variant == 5 && g.K % 32 != 0) variant = 2;
     switch (variant) {
+      case 5: return launch_lp_f32_dl<128, 128, 2, 4, 2>(g, s);
       case 1: return launch_lp<128, 128, 2, 2, 1, true, true>(g, prec, s);
       case 2: return launch_lp<128, 128, 2, 4, 2, true, true>(g, prec, s);
       default: return launch_lp<64, 64, 2, 2, 2, true, true>(g, prec, s);
