@@ -157,6 +157,14 @@ void ladder_maps(int v, Idx2 cm[3], Idx2 cn[3]) {
   cn[2] = idx1(1);
 }
 
+// Format of the ladder operands (views and W panel) in the mixed modes: FP32,
+// or split BF16 interleaved by blocks of 32 when the rows (v^2 values) hold
+// whole blocks, else as two planes.
+int ladder_fmt(const cct_slab* sl) {
+  const long long v2 = (long long)sl->v * sl->v;
+  return sl->prec == Prec::F32 ? OUT_F32 : (v2 % 32 == 0 ? OUT_BF16X2I : OUT_BF16X2);
+}
+
 // Relabelled copies of the slab's T3: views[term] = [t][x][(d,e)] with x the
 // free axis of that term, in the working precision (FP64 terms 0 and 1 only;
 // term 2 reads T3 itself in FP64).
@@ -164,7 +172,7 @@ int build_views(cct_slab* sl) {
   const int v = sl->v;
   const long long v2 = (long long)v * v, v3 = sl->v3, nb = sl->count;
   if (lp_ok(sl)) {
-    const int fmt = sl->prec == Prec::F32 ? OUT_F32 : OUT_BF16X2;
+    const int fmt = ladder_fmt(sl);
     char* base = (char*)sl->views;
     for (int term = 0; term < 3; ++term) {
       void* dst = base + (size_t)term * nb * v3 * 4;
@@ -275,8 +283,7 @@ int slab_pp(cct_slab* sl) {
     const long long prow = (long long)na * v;  // W rows (a, b) of this panel
     if (sl->timers) (void)hipEventRecord(e0, sl->s);
     RCK_(build_panel(sl, a0, na));
-    if (lp) SHIP(convert(sl->Wp, OutSpec{sl->Wl, sl->prec == Prec::F32 ? OUT_F32 : OUT_BF16X2, prow * v2},
-                         prow * v2, sl->s));
+    if (lp) SHIP(convert(sl->Wp, OutSpec{sl->Wl, ladder_fmt(sl), prow * v2}, prow * v2, sl->s));
     if (sl->timers) (void)hipEventRecord(e1, sl->s);
     for (int term = 0; term < 3; ++term) {
       // panel rows (y,z) = (a0 + r / v, r % v): offset of the output by a0 along y
@@ -289,6 +296,7 @@ int slab_pp(cct_slab* sl) {
         g.C = sl->r3 + coff; g.cm = cm[term]; g.cn = cn[term];
         g.alpha = 1.0; g.beta = 1.0;
         g.a_len = nb * v3; g.b_len = prow * v2; g.c_len = nb * v3 - coff;
+        g.il = ladder_fmt(sl) == OUT_BF16X2I;
         SHIP(gemm_nt_lp(g, sl->prec, sl->s));
       } else if (nt) {
         NtArgs g{};
