@@ -67,6 +67,18 @@ constexpr int UT = 16;
 constexpr int UP_Z = UT + 1;            // pitch of y rows in the LDS tile
 constexpr int UP_X = UT * UP_Z + 1;     // pitch of x planes
 
+// Tile of this workgroup.  Workgroups go to the eight XCDs in turn, so tile
+// k * per + i runs on XCD k: each XCD takes a contiguous range of tiles, and
+// neighbouring tiles, which share the 128-byte lines that a row of v values
+// leaves partly used when v is not a multiple of 16, meet in one L2 instead
+// of fetching (and writing) the same lines from two.  The grid's x extent is
+// 8 per; workgroups past the last tile return at once.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+inline unsigned xcd_grid(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
+
 template <bool DUAL>
 __global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restrict__ T,
                                                            const BlockRef* __restrict__ tbl,
@@ -82,9 +94,16 @@ __global__ __launch_bounds__(256) void unpack_tiled_kernel(const double* __restr
   const int f1 = (a.nfree == 2) ? fc - f0 * o : 0;
   const int2 fx = slots[slot];
   const int ids[4] = {fx.x, fx.y, f0, f1};
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(nt * nt * nt);
+  if (tile >= nt * nt * nt) return;
   const int t2 = tile % nt, t1 = (tile / nt) % nt, t0 = tile / (nt * nt);
-  const int base[3] = {t0 * UT, t1 * UT, t2 * UT};  // x, y, z origins
+  // the fastest tile digit runs along the output's unit-stride axis
+  const int wf = a.fast == 0 ? 2 : (a.fast == 1 ? 1 : 0);
+  int tb[3];
+  tb[wf] = t2;
+  tb[(wf + 1) % 3] = t1;
+  tb[(wf + 2) % 3] = t0;
+  const int base[3] = {tb[0] * UT, tb[1] * UT, tb[2] * UT};  // x, y, z origins
   const long long obase = (long long)slot * a.s_slot + (long long)f0 * a.s_free[0] + (long long)f1 * a.s_free[1];
   for (int t = 0; t < a.nterms; ++t) {
     const UnpackTerm& tm = a.terms[t];
@@ -174,7 +193,8 @@ __global__ __launch_bounds__(256) void fold_tiled_kernel(double* __restrict__ R,
   const FoldTask tk = tasks[blockIdx.y];
   const long long v2 = (long long)v * v;
   double* Rt = R + (long long)tk.t * bs;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(nt * nt * nt);
+  if (tile >= nt * nt * nt) return;
   const int t2 = tile % nt, t1 = (tile / nt) % nt, t0 = tile / (nt * nt);
   const int base[3] = {t0 * UT, t1 * UT, t2 * UT};  // a, b, c origins
 #pragma unroll
@@ -509,7 +529,7 @@ hipError_t unpack_t3_fmt(const double* T, const BlockRef* tbl, const int2* slots
   if (ny > 65535) return hipErrorInvalidValue;
   if (a.nterms < 1 || a.nterms > 6) return hipErrorInvalidValue;
   const int nt = (a.v + UT - 1) / UT;
-  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ny);
+  dim3 grid(xcd_grid(nt * nt * nt), (unsigned)ny);
   hipLaunchKernelGGL(unpack_tiled_kernel<false>, grid, dim3(TPB), 0, s, T, tbl, slots, out, out, a, nt);
   return hipGetLastError();
 }
@@ -522,7 +542,7 @@ hipError_t unpack_t3_dual(const double* T, const BlockRef* tbl, const int2* slot
   if (ny > 65535) return hipErrorInvalidValue;
   if (a.nterms < 1 || a.nterms > 6) return hipErrorInvalidValue;
   const int nt = (a.v + UT - 1) / UT;
-  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ny);
+  dim3 grid(xcd_grid(nt * nt * nt), (unsigned)ny);
   hipLaunchKernelGGL(unpack_tiled_kernel<true>, grid, dim3(TPB), 0, s, T, tbl, slots, out, out2, a, nt);
   return hipGetLastError();
 }
@@ -537,7 +557,7 @@ hipError_t fold_r3(double* R, long long bs, int v, const double* Z, const FoldTa
   if (ntasks <= 0) return hipSuccess;
   if (ntasks > 65535) return hipErrorInvalidValue;
   const int nt = (v + UT - 1) / UT;
-  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ntasks);
+  dim3 grid(xcd_grid(nt * nt * nt), (unsigned)ntasks);
   hipLaunchKernelGGL(fold_tiled_kernel<double>, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
   return hipGetLastError();
 }
@@ -547,7 +567,7 @@ hipError_t fold_r3(double* R, long long bs, int v, const float* Z, const FoldTas
   if (ntasks <= 0) return hipSuccess;
   if (ntasks > 65535) return hipErrorInvalidValue;
   const int nt = (v + UT - 1) / UT;
-  dim3 grid((unsigned)(nt * nt * nt), (unsigned)ntasks);
+  dim3 grid(xcd_grid(nt * nt * nt), (unsigned)ntasks);
   hipLaunchKernelGGL(fold_tiled_kernel<float>, grid, dim3(TPB), 0, s, R, bs, v, Z, tasks, contribs, nt);
   return hipGetLastError();
 }
