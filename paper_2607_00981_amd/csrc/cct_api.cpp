@@ -503,7 +503,7 @@ int build_plans(cct_ctx* ctx) {
   for (Job* J : {&ctx->feed1}) {
     for (int f = 0; f < o; ++f) J->slots.push_back(int2{f, 0});
     J->nslot_total = o;
-    J->per_batch = slots_per_batch(budget, 2 * o2v3, o);
+    J->per_batch = slots_per_batch(budget, 2 * o2v3 + (long long)o * o * v2, o);  // UA, UB, one X2 partial
     const int S = J->per_batch;
     for (int b = 0; b * S < o; ++b) {
       Batch B;
@@ -857,10 +857,26 @@ int feedback(cct_ctx* ctx) {
       HIPCK(unpack_t3_dual(ctx->t3, ctx->tbl, b.d_slots, OutSpec{UA, OUT_F64, 0}, OutSpec{UB, OUT_F64, 0}, ua, s));
     }
     const long long KA = (long long)S * v2, KB = (long long)S * ov;
-    // X2[(i,j,a)][b] += UA[(i,j,a)][K] VbT[b][f0.. K]
-    RCK(nt_or_generic(ctx, (int)((long long)o * o * v), v, KA, UA, KA, slab, VbT + (long long)f0 * v2,
-                      (long long)o * v2, (long long)o * v3 - (long long)f0 * v2, ctx->X2, idx1(v), idx1(1), o2v2,
-                      1.0, 1.0));
+    // X2[(i,j,a)][b] += UA[(i,j,a)][K] VbT[b][f0.. K].  With v^2 a multiple of
+    // 16 the product is batched over the S slots (K = v^2 each, one partial
+    // per slot, then summed into X2): N = v is a single tile column, so one
+    // product over the whole K would give too few tiles to fill the chip.
+    double* Xp = (v2 % 16 == 0 && S > 1) ? ws.alloc((size_t)(S * o2v2)) : nullptr;
+    if (Xp) {
+      NtArgs g{};
+      g.M = (int)((long long)o * o * v); g.N = v; g.K = (int)v2; g.batch = S;
+      g.A = UA; g.lda = KA; g.a_batch = v2;
+      g.B = VbT + (long long)f0 * v2; g.ldb = (long long)o * v2; g.b_batch = v2;
+      g.C = Xp; g.cm = idx1(v); g.cn = idx1(1); g.c_batch = o2v2;
+      g.alpha = 1.0; g.beta = 0.0;
+      g.a_len = slab; g.b_len = (long long)o * v3 - (long long)f0 * v2; g.c_len = S * o2v2;
+      HIPCK(gemm_nt(g, Prec::F64, s));
+      for (int k = 0; k < S; ++k) HIPCK(axpby(1.0, Xp + (long long)k * o2v2, 1.0, ctx->X2, o2v2, s));
+    } else {
+      RCK(nt_or_generic(ctx, (int)((long long)o * o * v), v, KA, UA, KA, slab, VbT + (long long)f0 * v2,
+                        (long long)o * v2, (long long)o * v3 - (long long)f0 * v2, ctx->X2, idx1(v), idx1(1), o2v2,
+                        1.0, 1.0));
+    }
     // W^{al}_{ij}: C[l][(i,j,a)] = VeT[l][f0.. K] UA[(i,j,a)][K], stored [a][l][i][j]
     RCK(nt_or_generic(ctx, o, (int)((long long)o * o * v), KA, VeT + (long long)f0 * v2, (long long)o * v2,
                       o2v2 - (long long)f0 * v2, UA, KA, slab, ctx->Wvooo, idx1((long long)o * o),
@@ -2103,8 +2119,8 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   // Two streams per task: the X chain (T3 gathers, X1, X2 into Xt) on the
   // context's stream, the Y chain (Z, Wbar^{vvv}, Wbar^{vvo}, Y1, Y2 into Yt)
   // on a side stream, so that the bandwidth-bound passes of one chain overlap
-  // the matrix-core products of the other; the side stream joins before
-  // R = Xt + Yt.  (Default priority, created for the call.)
+  // the matrix-core products of the other; the side stream joins before the
+  // energy, which forms R = Xt + Yt.  (Default priority, created for the call.)
   struct Side {
     hipStream_t st = nullptr;
     hipEvent_t ready = nullptr, ydone = nullptr, added = nullptr;
@@ -2316,8 +2332,8 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
         RCK(run(g, s));
       }
     // Y1: per column pair (c0, c1), segments (s0, s3) = (c0, c1) and (c1, c0);
-    // rows (l_r0, l_r1, i_r0, i_r1).  Yt (which holds R after the add) is
-    // overwritten only after the last task's energy has read it.
+    // rows (l_r0, l_r1, i_r0, i_r1).  Yt is overwritten only after the
+    // previous task's energy has read it.
     if (ti > 0) HIPCK(hipStreamWaitEvent(sy, side.added, 0));
     bool firsty = true;
     for (int c0 = 0; c0 < 4; ++c0)
@@ -2406,13 +2422,12 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
       g.alpha = -1.0; g.accumulate = 1;
       RCK(run(g, sy));
     }
-    // R = Xt + Yt; energies of the box's tuples
+    // energies of the box's tuples (R = Xt + Yt formed inside)
     HIPCK(hipEventRecord(side.ydone, sy));
     HIPCK(hipStreamWaitEvent(s, side.ydone, 0));
-    HIPCK(q_add(Yt, Xt, tlen, s));  // R = Xt + Yt, in Yt
     HIPCK(q_abc_energy(Xt, Yt, Vvvoo, t2R, ctx->eps, sl, o, v, d_orb, (int)norb, part,
                        etup + (e_tuples ? ti * b4 : 0), etask + ti, s));
-    HIPCK(hipEventRecord(side.added, s));  // Yt free for the next task's Y chain
+    HIPCK(hipEventRecord(side.added, s));  // Yt read: free for the next task's Y chain
   }
   HIPCK(hipEventRecord(ev[2], s));
   std::vector<double> h((size_t)ntasks);
@@ -2662,7 +2677,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     // operands: T3 and W read as Mt x lK and lN x lK matrices (values only
     // matter for timing; both fit inside the stored arrays)
     if (lad_nt) {
-      ctx->tune_ladder = pick({9, 1, 2, 3, 4}, [&](int var) {
+      ctx->tune_ladder = pick({9, 10, 1, 2, 3, 4}, [&](int var) {
         NtArgs g{};
         g.M = (int)Mt; g.N = (int)lN; g.K = (int)lK; g.batch = 1;
         g.A = ctx->t3; g.lda = lK; g.B = ctx->Wvvvv; g.ldb = lK;
@@ -2708,7 +2723,7 @@ int autotune(cct_ctx* ctx, double budget_ms, double* spent) {
     if (ring_lp) HIPCK(convert(ctx->t3, OutSpec{U, fmt, ulen}, std::min<long long>(ulen, ctx->ntri * ctx->v3), ctx->s));
     else HIPCK(fill((double*)U, 0.01, ulen, ctx->s));
     HIPCK(copy_pad_rows(ctx->Wb1, ov, ov, OutSpec{Al, fmt, ov * kp}, kp, ctx->s));
-    const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{9, 1, 2, 3, 4}
+    const std::vector<int> ring_cands = !ring_lp ? std::vector<int>{9, 10, 1, 2, 3, 4}
                                         : (ctx->prec == Prec::BF16X3 ? std::vector<int>{5, 4, 1, 2, 3} : std::vector<int>{5, 1, 2, 3});
     ctx->tune_rings = pick(ring_cands, [&](int var) {
       if (ring_lp) {

@@ -690,17 +690,24 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
                                    g.b_len)
     return hipErrorInvalidValue;
   if (g.c_len > 0 && nb * g.c_batch + idx_max(g.cm, g.M) + idx_max(g.cn, g.N) >= g.c_len) return hipErrorInvalidValue;
+  // variants 9, 10 and 11: the 128 x 256, 192 x 256 and 128 x 192 tiles with
+  // the operands copied straight into LDS (both operands K-contiguous, K a
+  // multiple of 16)
+  const bool dl_ok = !g.b_kn && g.K % BK == 0;
   int variant = g.variant;
   if (variant == 0) {
     // score each tile shape by the fraction of its MFMA work that lands inside
     // the matrix (skinny M or N wastes most of a large tile), by how well its
     // tile count fills the chip (two workgroups on each of 256 CUs), and by
-    // the measured relative speed of the shape on full tiles
+    // the measured relative speed of the shape on full tiles (an M or N of
+    // v = 180 virtual labels fills 94 % of 192, 70 % of 256)
     struct Cand { int var, bm, bn; double speed; };
-    const Cand cands[6] = {{1, 128, 256, 1.00}, {2, 256, 128, 1.00}, {4, 128, 128, 0.96},
-                           {3, 64, 64, 0.86},   {5, 256, 32, 0.80},  {6, 32, 256, 0.80}};
+    const Cand cands[9] = {{9, 128, 256, 1.10}, {10, 192, 256, 1.10}, {11, 128, 192, 1.10},
+                           {1, 128, 256, 1.00}, {2, 256, 128, 1.00},  {4, 128, 128, 0.96},
+                           {3, 64, 64, 0.86},   {5, 256, 32, 0.80},   {6, 32, 256, 0.80}};
     double best = -1.0;
     for (const Cand& c : cands) {
+      if (c.var >= 9 && !dl_ok) continue;
       const long long tm = (g.M + c.bm - 1) / c.bm, tn = (g.N + c.bn - 1) / c.bn;
       const double used = ((double)g.M / (double)(tm * c.bm)) * ((double)g.N / (double)(tn * c.bn));
       const double tiles = (double)(tm * tn * g.batch);
@@ -709,13 +716,11 @@ hipError_t gemm_nt(const NtArgs& g, Prec prec, hipStream_t s) {
       if (score > best) { best = score; variant = c.var; }
     }
   }
-  // variant 9: the 128 x 256 tile with the operands copied straight into LDS
-  // (both operands K-contiguous, K a multiple of 16); the default in its place
-  const bool dl_ok = !g.b_kn && g.K % BK == 0;
-  if (g.variant == 0 && variant == 1 && dl_ok) variant = 9;
-  if (variant == 9 && !dl_ok) variant = 1;
+  if (variant >= 9 && variant <= 11 && !dl_ok) variant = 1;
   switch (variant) {
     case 9: return launch_nt_dl<128, 256, 2, 4>(g, s);
+    case 10: return launch_nt_dl<192, 256, 2, 4>(g, s);
+    case 11: return launch_nt_dl<128, 192, 2, 4>(g, s);
     case 1: return launch_nt<128, 256, 2, 4, 2>(g, s);
     case 2: return launch_nt<256, 128, 4, 2, 2>(g, s);
     case 3: return launch_nt<64, 64, 2, 2, 2>(g, s);

@@ -386,8 +386,6 @@ hipError_t q_wo_build(double* out, const double* Voooo, const double* t2, int o,
 // Vmyje[m][y][j][e] = v^{my}_{ej}, Vmxje[m][x][j][e] = v^{mx}_{je}.
 hipError_t q_wv_build(double* out, const double* Zxy, const double* Zxz, const double* Vmyje, const double* Vmxje,
                       const double* t2, int o, int v, int x0, int nx, int y0, int ny, int z0, int nz, hipStream_t s);
-// Y += X over n elements.
-hipError_t q_add(double* Y, const double* X, long long n, hipStream_t s);
 // out[i] = src[idx[i]], i < n.
 hipError_t gather_idx(const double* src, const long long* idx, long long n, double* out, hipStream_t s);
 // Energy of the tuples of one task (t2R[b][a][i][j] = t_ij^ab): for every
@@ -395,10 +393,10 @@ hipError_t gather_idx(const double* src, const long long* idx, long long n, doub
 // (slot sizes n[]) with a <= b <= c <= d and no three equal labels,
 //   e_tau = 1/|Stab| sum_i (X[tau](i) + Vs(tau, i)) U(tau, i),
 //   U = (1/den) sum_pi c_pi R[tau](i o pi),
-// R = X + Y (in R), Vs the rank-one terms, den the orbital-energy
+// R = X + Y (formed in the kernel), Vs the rank-one terms, den the orbital-energy
 // denominator; other tuples get 0.  etup[tau] (dense order) and etask (the
 // fixed-order sum over the box) are written on the device.
-hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2R, const double* eps,
+hipError_t q_abc_energy(const double* X, const double* Y, const double* Vvvoo, const double* t2R, const double* eps,
                         const QSlots& sl, int o, int v, const int* orbits, int norb, double* part, double* etup,
                         double* etask, hipStream_t s);
 // The block orbits q_abc_energy takes (1 + 24 ints each; size / 25 orbits).

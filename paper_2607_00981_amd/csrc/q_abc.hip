@@ -557,12 +557,6 @@ __global__ __launch_bounds__(256) void q_wv_kernel(double* __restrict__ out, con
   }
 }
 
-__global__ __launch_bounds__(256) void q_add_kernel(double* __restrict__ Y, const double* __restrict__ X,
-                                                    long long n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    Y[i] += X[i];
-}
-
 // The spin summation 2 (2 - P_cd)(2 - P_bc - P_bd)(2 - P_ab - P_ac - P_ad),
 // multiplied out, is a class function of the permutation group: 16 on the
 // identity, -8 on transpositions, 4 on three-cycles and on double
@@ -576,11 +570,11 @@ struct QPerms {
 // The occupied index space o^4 is cut into blocks of bs^4 (bs <= 5, nbk
 // blocks per axis); the axis permutations act on whole blocks, so each orbit
 // of blocks (at most 24) is closed under them.  One workgroup takes one
-// tuple and one orbit: it stages R on the orbit's blocks in LDS (each element
-// read once) and evaluates U = S(R) / den there, so the 24 permuted reads of
-// the spin summation are LDS reads.
+// tuple and one orbit: it stages R = X + Y on the orbit's blocks in LDS (each
+// element of X and Y read once) and evaluates U = S(R) / den there, so the 24
+// permuted reads of the spin summation are LDS reads.
 constexpr int QE_BS = 4, QE_MAXB = 24;
-__global__ __launch_bounds__(256) void q_abc_energy_kernel(const double* __restrict__ X, const double* __restrict__ R,
+__global__ __launch_bounds__(256) void q_abc_energy_kernel(const double* __restrict__ X, const double* __restrict__ Y,
                                                            const double* __restrict__ Vvvoo,
                                                            const double* __restrict__ t2R,
                                                            const double* __restrict__ eps, QSlots sl, QPerms P,
@@ -621,14 +615,15 @@ __global__ __launch_bounds__(256) void q_abc_energy_kernel(const double* __restr
   }
   const long long o2 = (long long)o * o, o4 = o2 * o2;
   const double* x = X + (long long)tau * o4;
-  const double* rr = R + (long long)tau * o4;
+  const double* yy = Y + (long long)tau * o4;
   const int bs2 = bs * bs, bs4 = bs2 * bs2;
   for (int e = threadIdx.x; e < nblk * bs4; e += blockDim.x) {
     const int sidx = e / bs4, w = e % bs4;
     const int b = btab[sidx];
     const int i0 = (b & 255) * bs + w / (bs2 * bs), i1 = ((b >> 8) & 255) * bs + (w / bs2) % bs;
     const int i2 = ((b >> 16) & 255) * bs + (w / bs) % bs, i3 = ((b >> 24) & 255) * bs + w % bs;
-    Rl[e] = (i0 < o && i1 < o && i2 < o && i3 < o) ? rr[((long long)i0 * o + i1) * o2 + (long long)i2 * o + i3] : 0.0;
+    const long long at = ((long long)i0 * o + i1) * o2 + (long long)i2 * o + i3;
+    Rl[e] = (i0 < o && i1 < o && i2 < o && i3 < o) ? x[at] + yy[at] : 0.0;
   }
   __syncthreads();
   const double ev = eps[o + lab[0]] + eps[o + lab[1]] + eps[o + lab[2]] + eps[o + lab[3]];
@@ -843,19 +838,13 @@ hipError_t q_wv_build(double* out, const double* Zxy, const double* Zxz, const d
   return hipGetLastError();
 }
 
-hipError_t q_add(double* Y, const double* X, long long n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(q_add_kernel, dim3(grid_for(n)), dim3(256), 0, s, Y, X, n);
-  return hipGetLastError();
-}
-
 hipError_t gather_idx(const double* src, const long long* idx, long long n, double* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(gather_idx_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, idx, n, out);
   return hipGetLastError();
 }
 
-hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, const double* t2R, const double* eps,
+hipError_t q_abc_energy(const double* X, const double* Y, const double* Vvvoo, const double* t2R, const double* eps,
                         const QSlots& sl, int o, int v, const int* orbits, int norb, double* part, double* etup,
                         double* etask, hipStream_t s) {
   const long long ntau = (long long)sl.n[0] * sl.n[1] * sl.n[2] * sl.n[3];
@@ -894,7 +883,7 @@ hipError_t q_abc_energy(const double* X, const double* R, const double* Vvvoo, c
     P.c[np] = c;
     ++np;
   } while (std::next_permutation(p, p + 4));
-  hipLaunchKernelGGL(q_abc_energy_kernel, dim3((unsigned)(ntau * norb)), dim3(256), 0, s, X, R, Vvvoo, t2R, eps, sl, P,
+  hipLaunchKernelGGL(q_abc_energy_kernel, dim3((unsigned)(ntau * norb)), dim3(256), 0, s, X, Y, Vvvoo, t2R, eps, sl, P,
                      orbits, norb, bs, o, v, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -281,7 +281,7 @@ def test_ladder_split_matches_direct(prec, o, v, ws):
     assert macs["PP"] == 3 * ntri * v ** 5
 
 
-TILE_VARIANTS = {"fp64": (1, 2, 3, 4, 9), "fp32": (1, 2, 3, 5), "bf16x3": (1, 2, 3, 4, 5)}
+TILE_VARIANTS = {"fp64": (1, 2, 3, 4, 9, 10, 11), "fp32": (1, 2, 3, 5), "bf16x3": (1, 2, 3, 4, 5)}
 CASES = [(p, x, False) for p, vs in TILE_VARIANTS.items() for x in vs] + [("bf16x3", x, True) for x in (1, 2, 3, 4, 5)]
 
 
