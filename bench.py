@@ -192,8 +192,9 @@ LP_TILES = {"fp32": {0: "size-based", 1: "<128,128,2,2,1>", 2: "<128,128,2,4,2>"
             "bf16x3": {0: "size-based", 1: "<256,128,4,2,1>", 2: "<128,128,2,4,2>", 3: "<64,64,2,2,2>",
                        4: "<256,256,2,4,1>"}}
 # tile variants whose operand tiles are copied straight into LDS (their own kernels)
-DL_KERNELS = {("fp64", 9): "gemm_nt_f64_dl_kernel<128,256,2,4>", ("bf16x3", 5): "gemm_lp_bf16x3_dl_kernel<256,256,2,4>",
-              ("fp32", 5): "gemm_lp_f32_dl_kernel<128,128,2,4,2>"}
+DL_KERNELS = {("fp64", 9): "gemm_nt_f64_dl_kernel<128,256,2,4>", ("fp64", 10): "gemm_nt_f64_dl_kernel<192,256,2,4>",
+              ("fp64", 11): "gemm_nt_f64_dl_kernel<128,192,2,4>",
+              ("bf16x3", 5): "gemm_lp_bf16x3_dl_kernel<256,256,2,4>", ("fp32", 5): "gemm_lp_f32_dl_kernel<128,128,2,4,2>"}
 
 
 def kernel_name(prec, variant):
