@@ -738,6 +738,20 @@ __device__ __forceinline__ long long pidx(int d, int e, int v) {  // d <= e
 __device__ __forceinline__ long long qidx(int d, int e, int v) {  // d < e
   return (long long)d * (v - 1) - (long long)d * (d - 1) / 2 + (e - d - 1);
 }
+// Row and tile pair of this workgroup.  The grid's x extent is rows x P with
+// P = 8 ceil(npair / 8) workgroups per row; workgroups go to the eight XCDs
+// in turn, and the tile pairs of a row are dealt to them in contiguous
+// ranges (pair k per + i on XCD k), so tiles next to each other in a row,
+// which share the 128-byte lines that rows of v values leave partly used,
+// run on one XCD at about the same time.  tp < 0: no tile.
+__device__ __forceinline__ long long pair_row_tile(int nt, int& tp) {
+  const int npair = nt * (nt + 1) / 2, per = (npair + 7) / 8, P = 8 * per;
+  const long long r = blockIdx.x / P;
+  const int t = (int)(blockIdx.x - r * P);
+  tp = (t % 8) * per + t / 8;
+  if (tp >= npair) tp = -1;
+  return r;
+}
 __device__ __forceinline__ void tile_pair(int idx, int nt, int& Dt, int& Et) {  // Dt <= Et
   Dt = 0;
   while (idx >= nt - Dt) {
@@ -752,10 +766,12 @@ __global__ __launch_bounds__(256) void pair_split_kernel(const double* __restric
                                                          OutSpec plus, long long pitch_p, OutSpec minus,
                                                          long long pitch_m, double diag_scale, int nt) {
   __shared__ double T1[PS][PS + 1], T2[PS][PS + 1];
-  const long long r = blockIdx.x;
+  int tp;
+  const long long r = pair_row_tile(nt, tp);
+  if (tp < 0) return;
   const double* M = in + (src ? src[r] : imap(rmap, r));
   int Dt, Et;
-  tile_pair(blockIdx.y, nt, Dt, Et);
+  tile_pair(tp, nt, Dt, Et);
   for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
     const int i = e / PS, j = e % PS;
     const int d1 = Dt * PS + i, e1 = Et * PS + j;
@@ -774,7 +790,7 @@ __global__ __launch_bounds__(256) void pair_split_kernel(const double* __restric
     if (d < f) put_out(minus, r * pitch_m + qidx(d, f, v), a - b);
   }
   // zero the padding columns of this row once
-  if (blockIdx.y == 0) {
+  if (tp == 0) {
     for (long long c = P + threadIdx.x; c < pitch_p; c += blockDim.x) put_out(plus, r * pitch_p + c, 0.0);
     for (long long c = Q + threadIdx.x; c < pitch_m; c += blockDim.x) put_out(minus, r * pitch_m + c, 0.0);
   }
@@ -787,12 +803,14 @@ __global__ __launch_bounds__(256) void pair_combine_rows_kernel(const CT* __rest
                                                                 long long pitch_m, int v, double* __restrict__ R,
                                                                 Idx2 cmap, long long sy, long long sz, int nt) {
   __shared__ double U[PS][PS + 1];
-  const long long r = blockIdx.x;
+  int tp;
+  const long long r = pair_row_tile(nt, tp);
+  if (tp < 0) return;
   double* Rr = R + imap(cmap, r);
   const CT* cp = Cp + r * pitch_p;
   const CT* cq = Cm + r * pitch_m;
   int Yt, Zt;
-  tile_pair(blockIdx.y, nt, Yt, Zt);
+  tile_pair(tp, nt, Yt, Zt);
   for (int e = threadIdx.x; e < PS * PS; e += blockDim.x) {
     const int i = e / PS, j = e % PS;
     const int y = Yt * PS + i, z = Zt * PS + j;
@@ -846,9 +864,9 @@ hipError_t pair_split(const double* in, Idx2 rmap, const long long* src, long lo
                       hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   const int nt = (v + PS - 1) / PS;
-  const int npair = nt * (nt + 1) / 2;
-  if (rows > INT_MAX || npair > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pair_split_kernel, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, in, rmap, src, sd, v,
+  const long long P = 8LL * ((nt * (nt + 1) / 2 + 7) / 8);
+  if (rows * P > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pair_split_kernel, dim3((unsigned)(rows * P)), dim3(TPB), 0, s, in, rmap, src, sd, v,
                      plus, pitch_p, minus, pitch_m, diag_scale, nt);
   return hipGetLastError();
 }
@@ -858,9 +876,9 @@ hipError_t combine_rows_t(const CT* Cp, const CT* Cm, long long pitch_p, long lo
                           double* R, Idx2 cmap, long long sy, long long sz, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   const int nt = (v + PS - 1) / PS;
-  const int npair = nt * (nt + 1) / 2;
-  if (rows > INT_MAX || npair > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pair_combine_rows_kernel<CT>, dim3((unsigned)rows, (unsigned)npair), dim3(TPB), 0, s, Cp, Cm,
+  const long long P = 8LL * ((nt * (nt + 1) / 2 + 7) / 8);
+  if (rows * P > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pair_combine_rows_kernel<CT>, dim3((unsigned)(rows * P)), dim3(TPB), 0, s, Cp, Cm,
                      pitch_p, pitch_m, v, R, cmap, sy, sz, nt);
   return hipGetLastError();
 }
