@@ -2123,20 +2123,20 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
   // energy, which forms R = Xt + Yt.  (Default priority, created for the call.)
   struct Side {
     hipStream_t st = nullptr;
-    hipEvent_t ready = nullptr, ydone = nullptr, added = nullptr;
+    hipEvent_t ready = nullptr, ydone = nullptr, yfree = nullptr;
     ~Side() {
       if (st) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
       }
-      for (hipEvent_t e : {ready, ydone, added})
+      for (hipEvent_t e : {ready, ydone, yfree})
         if (e) (void)hipEventDestroy(e);
     }
   } side;
   HIPCK(hipStreamCreateWithFlags(&side.st, hipStreamNonBlocking));
   HIPCK(hipEventCreateWithFlags(&side.ready, hipEventDisableTiming));
   HIPCK(hipEventCreateWithFlags(&side.ydone, hipEventDisableTiming));
-  HIPCK(hipEventCreateWithFlags(&side.added, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&side.yfree, hipEventDisableTiming));
   hipStream_t sy = side.st;
   HIPCK(hipEventRecord(side.ready, s));
   HIPCK(hipStreamWaitEvent(sy, side.ready, 0));
@@ -2334,7 +2334,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
     // Y1: per column pair (c0, c1), segments (s0, s3) = (c0, c1) and (c1, c0);
     // rows (l_r0, l_r1, i_r0, i_r1).  Yt is overwritten only after the
     // previous task's energy has read it.
-    if (ti > 0) HIPCK(hipStreamWaitEvent(sy, side.added, 0));
+    if (ti > 0) HIPCK(hipStreamWaitEvent(sy, side.yfree, 0));
     bool firsty = true;
     for (int c0 = 0; c0 < 4; ++c0)
       for (int c1 = c0 + 1; c1 < 4; ++c1) {
@@ -2427,7 +2427,7 @@ int energy_q_abc(cct_ctx* ctx, int nb, const int64_t* tasks, long long ntasks, d
     HIPCK(hipStreamWaitEvent(s, side.ydone, 0));
     HIPCK(q_abc_energy(Xt, Yt, Vvvoo, t2R, ctx->eps, sl, o, v, d_orb, (int)norb, part,
                        etup + (e_tuples ? ti * b4 : 0), etask + ti, s));
-    HIPCK(hipEventRecord(side.added, s));  // Yt read: free for the next task's Y chain
+    HIPCK(hipEventRecord(side.yfree, s));  // Yt read: free for the next task's Y chain
   }
   HIPCK(hipEventRecord(ev[2], s));
   std::vector<double> h((size_t)ntasks);
